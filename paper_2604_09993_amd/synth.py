@@ -1,0 +1,303 @@
+"""Seeded synthetic models and node data for the interval discretization.
+
+This module only builds *inputs*: planar multibody model descriptions and
+random node states, FOH control coefficients, dilations and parameters with
+the shapes and value ranges of the legged-locomotion workloads of the paper
+(Sec. VI: monoped, five-link biped on a sinusoid, HalfCheetah; plus a 13-body
+quadruped-shaped chain).  It holds none of the method's arithmetic: no
+dynamics, no Jacobians, no integration.  Both the HIP path (through the C-ABI)
+and the CPU oracle consume what it returns.
+
+Conventions (shared by every consumer, stated once here):
+
+* bodies b = 0..nb-1 in maximal coordinates, pose q_b = (x_b, y_b, theta_b),
+  velocity v_b = (xdot_b, ydot_b, omega_b) (Sec. II, maximal coordinates);
+* augmented state x~ = (q_0..q_{nb-1}, v_0..v_{nb-1}, y_cc_0..y_cc_{nc-1},
+  y_ctcs): n = 6 nb body states, n_y = nc + 1 integral states;
+* control u = (tau_0..tau_{nj-1}, lam_0x, lam_0y, ..., [lam_n_i, lam_t+_i,
+  lam_t-_i]_i): m = 3 nj + 3 nc (joint torques, world-frame joint forces,
+  normal and split-friction contact forces);
+* parameters p = (mu, e, m_0..m_{nb-1});
+* node arrays are node-major here: X[N+1, n~], U[N+1, m], s[N].
+
+Topology family: every model is a torso (body 0) carrying ``legs`` legs of
+``depth`` links each; leg l, link d is body 1 + l*depth + d; joint index
+equals child body - 1; the contact of leg l sits at the distal tip of its
+last link (for depth 0 the contacts sit on the torso itself).
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+GRAVITY = 9.81
+STIFFNESS = 1.0      # N m / rad, joint stiffness (value not given in the paper)
+DAMPING = 0.1        # N m s / rad, joint damping (value not given in the paper)
+SIN_AMPLITUDE = 0.05  # m, sinusoidal terrain amplitude (value not given)
+SIN_WAVENUMBER = 2.0 * np.pi  # rad / m
+MU = 0.8
+RESTITUTION = 0.2
+
+
+@dataclasses.dataclass
+class Model:
+    """Planar maximal-coordinate model description (host data only)."""
+    name: str
+    legs: int
+    depth: int
+    link_length: np.ndarray          # [nb]
+    joint_parent: np.ndarray         # [nj] int32
+    joint_child: np.ndarray          # [nj] int32
+    anchor_parent: np.ndarray        # [nj, 2] body frame of the parent
+    anchor_child: np.ndarray         # [nj, 2] body frame of the child
+    stiffness: np.ndarray            # [nj]
+    damping: np.ndarray              # [nj]
+    contact_body: np.ndarray         # [nc] int32
+    contact_point: np.ndarray        # [nc, 2] body frame
+    gravity: float
+    terrain_amplitude: float         # 0 => flat ground
+    terrain_wavenumber: float
+    masses: np.ndarray               # [nb] default mass parameters
+    torque_sigma: float
+
+    @property
+    def nb(self) -> int:
+        return int(self.link_length.shape[0])
+
+    @property
+    def nj(self) -> int:
+        return int(self.joint_parent.shape[0])
+
+    @property
+    def nc(self) -> int:
+        return int(self.contact_body.shape[0])
+
+    @property
+    def n(self) -> int:
+        return 6 * self.nb
+
+    @property
+    def ny(self) -> int:
+        return self.nc + 1
+
+    @property
+    def nx(self) -> int:
+        """Augmented state size n~ = n + n_y."""
+        return self.n + self.ny
+
+    @property
+    def m(self) -> int:
+        return 3 * self.nj + 3 * self.nc
+
+    @property
+    def n_params(self) -> int:
+        return self.nb + 2
+
+    def params(self, mu: float = MU, e: float = RESTITUTION) -> np.ndarray:
+        return np.concatenate([[mu, e], self.masses]).astype(np.float64)
+
+
+def _rod_y(length: float) -> tuple:
+    """Proximal and distal anchors of a rod along the body y axis."""
+    return np.array([0.0, 0.5 * length]), np.array([0.0, -0.5 * length])
+
+
+def legged_model(name: str, legs: int, depth: int, rng: np.random.Generator,
+                 length_range=(0.3, 0.5), mass_range=(1.0, 5.0),
+                 torque_sigma: float = 5.0, torso: str = "vertical",
+                 terrain: str = "flat", hip_x=None,
+                 stiffness: float = STIFFNESS, damping: float = DAMPING,
+                 gravity: float = GRAVITY) -> Model:
+    """Torso + ``legs`` legs of ``depth`` rod links, seeded sizes and masses."""
+    nb = 1 + legs * depth
+    L = rng.uniform(*length_range, size=nb)
+    masses = rng.uniform(*mass_range, size=nb)
+    jp, jc, ap, ac = [], [], [], []
+    for leg in range(legs):
+        for d in range(depth):
+            child = 1 + leg * depth + d
+            if d == 0:
+                parent = 0
+                if torso == "vertical":
+                    anchor_p = np.array([0.0, -0.5 * L[0]])
+                else:
+                    xs = hip_x if hip_x is not None else np.linspace(-0.5, 0.5, legs)
+                    anchor_p = np.array([xs[leg] * L[0], 0.0])
+            else:
+                parent = child - 1
+                anchor_p = _rod_y(L[parent])[1]
+            jp.append(parent)
+            jc.append(child)
+            ap.append(anchor_p)
+            ac.append(_rod_y(L[child])[0])
+    cb, cp = [], []
+    for leg in range(legs):
+        if depth == 0:
+            cb.append(0)
+            cp.append(np.zeros(2))
+        else:
+            body = 1 + leg * depth + depth - 1
+            cb.append(body)
+            cp.append(_rod_y(L[body])[1])
+    nj = len(jp)
+    nc = len(cb)
+    A = SIN_AMPLITUDE if terrain == "sinusoid" else 0.0
+    return Model(
+        name=name, legs=legs, depth=depth,
+        link_length=L.astype(np.float64),
+        joint_parent=np.asarray(jp, dtype=np.int32).reshape(nj),
+        joint_child=np.asarray(jc, dtype=np.int32).reshape(nj),
+        anchor_parent=np.asarray(ap, dtype=np.float64).reshape(nj, 2),
+        anchor_child=np.asarray(ac, dtype=np.float64).reshape(nj, 2),
+        stiffness=np.full(nj, stiffness, dtype=np.float64),
+        damping=np.full(nj, damping, dtype=np.float64),
+        contact_body=np.asarray(cb, dtype=np.int32).reshape(nc),
+        contact_point=np.asarray(cp, dtype=np.float64).reshape(nc, 2),
+        gravity=float(gravity), terrain_amplitude=float(A),
+        terrain_wavenumber=float(SIN_WAVENUMBER if A != 0.0 else 0.0),
+        masses=masses.astype(np.float64), torque_sigma=float(torque_sigma))
+
+
+def make_hopper(rng):
+    """2-body hopper (torso + one leg link), one foot contact, flat ground."""
+    return legged_model("hopper", 1, 1, rng, (0.3, 0.5), (1.0, 5.0), 5.0, "vertical")
+
+
+def make_biped5(rng):
+    """5-body planar biped (torso + two 2-link legs) on the sinusoidal surface."""
+    return legged_model("biped5", 2, 2, rng, (0.3, 0.5), (1.0, 5.0), 5.0, "vertical",
+                        terrain="sinusoid")
+
+
+def make_cheetah7(rng):
+    """HalfCheetah-shaped chain: horizontal torso + two 3-link legs, 2 feet."""
+    return legged_model("cheetah7", 2, 3, rng, (0.1, 0.5), (1.0, 7.0), 20.0,
+                        "horizontal", hip_x=[-0.5, 0.5])
+
+
+def make_quad13(rng):
+    """Quadruped-shaped chain: horizontal torso + four 3-link legs, 4 feet."""
+    return legged_model("quad13", 4, 3, rng, (0.1, 0.5), (1.0, 7.0), 20.0,
+                        "horizontal", hip_x=[-0.5, -1.0 / 6.0, 1.0 / 6.0, 0.5])
+
+
+def make_free_body(rng, gravity=GRAVITY):
+    """Single free body, no joints, no contacts (ballistic case)."""
+    return legged_model("free1", 0, 0, rng, (0.3, 0.5), (1.0, 5.0), 5.0,
+                        gravity=gravity)
+
+
+def make_point_contact(rng, terrain="flat", gravity=GRAVITY):
+    """Single body with one contact at its centre of mass."""
+    return legged_model("point1", 1, 0, rng, (0.3, 0.5), (1.0, 5.0), 5.0,
+                        terrain=terrain, gravity=gravity)
+
+
+MODEL_MAKERS = {
+    "hopper": make_hopper,
+    "biped5": make_biped5,
+    "cheetah7": make_cheetah7,
+    "quad13": make_quad13,
+    "free1": make_free_body,
+    "point1": make_point_contact,
+}
+
+
+def _rot(th):
+    c, s = np.cos(th), np.sin(th)
+    return np.array([[c, -s], [s, c]])
+
+
+def _place(model: Model, x0: float, y0: float, th0: float, joint_angles: np.ndarray):
+    """Body poses for given torso pose and relative joint angles (joints closed)."""
+    nb = model.nb
+    pos = np.zeros((nb, 2))
+    th = np.zeros(nb)
+    pos[0] = (x0, y0)
+    th[0] = th0
+    for j in range(model.nj):  # parents always precede children in this family
+        p, c = int(model.joint_parent[j]), int(model.joint_child[j])
+        th[c] = th[p] + joint_angles[j]
+        hinge = pos[p] + _rot(th[p]) @ model.anchor_parent[j]
+        pos[c] = hinge - _rot(th[c]) @ model.anchor_child[j]
+    return pos, th
+
+
+def _lowest_clearance(model: Model, pos, th):
+    """Smallest vertical gap between a contact point and the terrain."""
+    gaps = []
+    for i in range(model.nc):
+        b = int(model.contact_body[i])
+        P = pos[b] + _rot(th[b]) @ model.contact_point[i]
+        ground = model.terrain_amplitude * np.sin(model.terrain_wavenumber * P[0])
+        gaps.append(P[1] - ground)
+    return min(gaps) if gaps else None
+
+
+def gen_nodes(model: Model, N: int, rng: np.random.Generator,
+              vel_sigma: float = 0.5, joint_force_sigma: float = 10.0,
+              contact_range=(0.0, 30.0), T: float = 1.0):
+    """Seeded node data for one trajectory with N intervals (N+1 nodes).
+
+    Returns a dict with X[N+1, n~], U[N+1, m], s[N], p[P] (float64, node-major).
+    Poses come from forward placement of random joint angles U(-0.5, 0.5), so
+    joints are closed at the nodes; the torso height is shifted so the lowest
+    contact sits U(-0.02, 0.10) m above the terrain; every velocity component
+    is N(0, vel_sigma); integral states are zero.
+    """
+    nb, nj, nc = model.nb, model.nj, model.nc
+    X = np.zeros((N + 1, model.nx))
+    for k in range(N + 1):
+        x0 = rng.uniform(-0.5, 0.5)
+        th0 = rng.uniform(-0.2, 0.2)
+        ja = rng.uniform(-0.5, 0.5, size=nj)
+        pos, th = _place(model, x0, 0.0, th0, ja)
+        gap = _lowest_clearance(model, pos, th)
+        target = rng.uniform(-0.02, 0.10)
+        if gap is None:
+            shift = 1.0
+        else:
+            shift = target - gap
+        pos[:, 1] += shift
+        q = np.column_stack([pos[:, 0], pos[:, 1], th]).reshape(-1)
+        v = rng.normal(0.0, vel_sigma, size=3 * nb)
+        X[k, :3 * nb] = q
+        X[k, 3 * nb:6 * nb] = v
+    U = np.zeros((N + 1, model.m))
+    U[:, :nj] = rng.normal(0.0, model.torque_sigma, size=(N + 1, nj))
+    U[:, nj:3 * nj] = rng.normal(0.0, joint_force_sigma, size=(N + 1, 2 * nj))
+    U[:, 3 * nj:] = rng.uniform(*contact_range, size=(N + 1, 3 * nc))
+    s = rng.uniform(0.5, 2.0, size=N) * T / N
+    return {"X": X, "U": U, "s": s, "p": model.params()}
+
+
+# Workload recipes (model, N, substeps) of the benchmark configurations.
+CONFIGS = {
+    1: dict(model="hopper", N=20, K=10),
+    2: dict(model="cheetah7", N=50, K=20),
+    3: dict(model="cheetah7", N=50, K=20, ckpt=5),
+    5: dict(model="quad13", N=200, K=20, batch=64),
+}
+
+
+def make_config(config_id: int, traj_id: int = 0):
+    """Model and node data for a configuration, seeded by (config_id, traj_id)."""
+    cfg = CONFIGS[config_id]
+    rng = np.random.default_rng([config_id, traj_id])
+    model = MODEL_MAKERS[cfg["model"]](rng)
+    data = gen_nodes(model, cfg["N"], rng)
+    return model, data, cfg["K"]
+
+
+def mixed_batch(n_traj: int = 256, seed: int = 4):
+    """Uneven batch: 50% hopper / 30% cheetah7 / 20% biped5, N~U{20..100}, K~U{10..30}."""
+    rng = np.random.default_rng([seed, 0])
+    kinds = rng.choice(["hopper", "cheetah7", "biped5"], size=n_traj, p=[0.5, 0.3, 0.2])
+    out = []
+    for t, kind in enumerate(kinds):
+        r = np.random.default_rng([seed, t + 1])
+        model = MODEL_MAKERS[kind](r)
+        N = int(r.integers(20, 101))
+        K = int(r.integers(10, 31))
+        out.append((model, gen_nodes(model, N, r), K))
+    return out
