@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Discretized intervals/s of the CI-SCvx linearize-and-discretize step on one MI355X.
+
+Workload: HalfCheetah-shaped planar chain (7 bodies, 6 joints, 2 contacts;
+nx = 45, m = 24), N = 50 intervals, K = 20 RK4 substeps, FP64, synthetic
+seeded node data (inputs resident in HBM before timing).  One step = one call
+of cis_discretize over all 50 intervals (A, B-, B+, S, defects, F~).
+
+Prints one JSON line.  Extra fields: the FP32 form of the same step, the
+parity error of the timed output against the CPU oracle, the roofline of the
+dominant kernel (k_discretize) and the CPU oracle baseline.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s (AMD published)
+PEAK_FP32_VALU = 157.3e12
+
+
+def algorithmic_flops_per_interval(model, K):
+    """Per-interval FLOPs of the sparse method: K [8 nnz(J) c + 14 nx c + 4 phi_fJ].
+
+    nnz(J) = 2 n_q + 2 n_b + 4 n_j + 4 n_c (flat ground), c = n + 2m + 1 tangent
+    columns, phi_fJ = per-stage right-hand side + Jacobian cost (0.3k hopper,
+    0.7k biped5, 1k cheetah7, 2k quad13).
+    """
+    nb, nj, nc = model.nb, model.nj, model.nc
+    nnz = 2 * 3 * nb + 2 * nb + 4 * nj + 4 * nc
+    c = model.n + 2 * model.m + 1
+    phi = {2: 300, 5: 700, 7: 1000, 13: 2000}.get(nb, 1000)
+    return K * (8 * nnz * c + 14 * model.nx * c + 4 * phi)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus must be 1 (no multi-GPU path in this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2604_09993_amd import _lib, api, synth
+
+    model, data, K = synth.make_config(2)
+    N = data["s"].shape[0]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cm = api.CisModel(model)
+    lib = _lib.load(build_if_missing=False)
+
+    def prepare(dtype):
+        X = api.to_device_soa(data["X"], dev, dtype)
+        U = api.to_device_soa(data["U"], dev, dtype)
+        s = torch.tensor(data["s"], device=dev, dtype=dtype)
+        p = torch.tensor(data["p"], device=dev, dtype=dtype)
+        kw = dict(device=dev, dtype=dtype)
+        nx, m = cm.nx, cm.m
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw), xprop=torch.empty((nx, N), **kw))
+        api.discretize_into(cm, X, U, s, p, K, out)   # validates shapes once
+        stream = torch.cuda.current_stream()
+        sh = _lib.Shape(N, K, api._dtype_code(dtype), 0, X.stride(0), N)
+        argv = [cm.handle, ctypes.byref(sh)] + [ctypes.c_void_p(t.data_ptr()) for t in
+                (X, U, s, p, out["A"], out["Bm"], out["Bp"], out["S"], out["d"], out["xprop"])]
+        argv.append(ctypes.c_void_p(stream.cuda_stream))
+        fn = lib.cis_discretize
+
+        def launch():
+            st = fn(*argv)
+            if st != 0:
+                _lib.check(st)
+        keep = (X, U, s, p, sh)
+        return launch, out, stream, keep
+
+    def timed(launch, stream, steps, warmup):
+        for _ in range(warmup):
+            launch()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / steps, wall
+
+    launch64, out64, stream, keep64 = prepare(torch.float64)
+    ms64, wall64 = timed(launch64, stream, args.steps, args.warmup)
+    launch32, out32, _, keep32 = prepare(torch.float32)
+    ms32, _ = timed(launch32, stream, args.steps, args.warmup)
+
+    flops = algorithmic_flops_per_interval(model, K) * N
+    achieved = flops / (ms64 * 1e-3)
+    line = {
+        "metric": "discretized intervals/s (x+STM+B±) at 1e-10 rel vs oracle",
+        "value": N / (ms64 * 1e-3),
+        "unit": "intervals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cheetah7 planar chain (7 bodies, 6 joints, 2 contacts), "
+                               "N=50 intervals, K=20 RK4 substeps, FP64 forward",
+                   "N": N, "substeps": K, "nx": cm.nx, "m": cm.m},
+        "fp32": {"value": N / (ms32 * 1e-3), "unit": "intervals/s", "ms_per_step": ms32},
+        "roofline": {"bound": "alu", "kernel": "k_discretize<double, Topo<2,3>>",
+                     "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "algorithmic_flop_per_launch": flops},
+        "wall_s_timed_region": wall64,
+    }
+    if not args.no_cpu_baseline:
+        # CPU-baseline leg: the plain FP64 oracle on the host cores, on the same
+        # seeded inputs; its result also gives the parity of the timed outputs.
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import PHI32, PHI64, block_err
+        ref = oracle.discretize(model, data["X"], data["U"], data["s"], data["p"], K)
+        v64 = api.as_interval_major(out64)
+        line["max_rel_err_vs_oracle"] = max(
+            block_err(v64[k].double().cpu().numpy(), ref[k], PHI64)
+            for k in ("A", "Bm", "Bp", "S", "d", "xprop"))
+        r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+        ref32 = oracle.discretize(model, r32(data["X"]), r32(data["U"]), r32(data["s"]),
+                                  r32(data["p"]), K)
+        v32 = api.as_interval_major(out32)
+        line["fp32"]["max_rel_err_vs_oracle_normwise"] = max(
+            block_err(v32[k].double().cpu().numpy(), ref32[k], PHI32)
+            for k in ("A", "Bm", "Bp", "S", "d", "xprop"))
+        ncores = os.cpu_count() or 1
+        ncores = min(ncores, 16)
+        reps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            oracle.discretize(model, data["X"], data["U"], data["s"], data["p"], K, nthreads=ncores)
+            reps += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": reps * N / dt, "unit": "intervals/s", "cores": ncores,
+                                "kind": "oracle",
+                                "sample": f"{reps} repetitions of the same 50-interval workload "
+                                          f"({reps * N} intervals, {dt:.1f} s, OpenMP over intervals)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * cis.h - C ABI of the MI355X (gfx950) interval linearize-and-discretize
+ * library for contact-implicit continuous-time successive convexification
+ * (CI-SCvx, arxiv 2604.09993).
+ *
+ * What is computed (paper references are to arxiv 2604.09993):
+ *  For every interval k = 0..N-1 between trajectory nodes, the time-dilated
+ *  augmented system x~' = s (f(x,u), Omega(x,u)) on tau in [0,1]
+ *  (Sec. IV-B, eq. aug-dynamics) with first-order-hold controls
+ *  u(tau) = (1-tau) U_k + tau U_{k+1} (Sec. IV-B parameterization, Sec. VI) is
+ *  integrated by classical RK4 with K uniform substeps, starting at node X_k.
+ *  f is planar maximal-coordinate multibody dynamics with joint forces and
+ *  normal/split-friction contact forces (Sec. II-A, eq. ct-dynamics); Omega
+ *  holds the integral cross-complementarity integrands (Sec. III, Prop. 1;
+ *  Sec. IV-A eq. aux-dynamics) and one continuous-time constraint-violation
+ *  integrand.  Together with the state, the variational equations are
+ *  integrated through the same RK4 stages (internal numerical
+ *  differentiation, Sec. VI), giving the exact derivatives of the discrete
+ *  map F~_k = F~(X_k, U_k, U_{k+1}, s_k) of eq. intg-aug-sys-param:
+ *     A_k  = dF~_k/dX_k,  Bm_k = dF~_k/dU_k,  Bp_k = dF~_k/dU_{k+1},
+ *     S_k  = dF~_k/ds_k,  defect d_k = F~_k - X_{k+1}  (eq. cito-augdyn).
+ *
+ * Sizes: nb bodies, nj revolute joints, nc contacts;
+ *   n = 6 nb (poses and velocities), n_y = nc + 1 integral states,
+ *   nx = n + n_y (augmented state), m = 3 nj + 3 nc controls
+ *   (joint torques, world-frame joint forces, [lam_n, lam_t+, lam_t-] per
+ *   contact), P = nb + 2 parameters p = (mu, e, m_0 .. m_{nb-1}).
+ * State order: x~ = (x_0,y_0,th_0, .., v_0 .. , y_cc_0 .., y_ctcs).
+ *
+ * Memory layout ("SoA", interval or node index contiguous, all DEVICE
+ * pointers owned by the caller, element type given by cis_shape.dtype):
+ *   X      [nx][ld_node]      node k, component r at X[r*ld_node + k], k <= N
+ *   U      [m][ld_node]
+ *   s      [N]                dilation of interval k (physical length)
+ *   params [P]
+ *   A      [nx][nx][ld_int]   interval k, row r, column c at A[(r*nx+c)*ld_int + k]
+ *   Bm, Bp [nx][m][ld_int]
+ *   S, defect, xprop, seed [nx][ld_int]
+ *   ckpt   [K/C][n][ld_int]   x (without y) at substeps 0, C, 2C, ..
+ *   gX     [nx][ld_node], gU [m][ld_node], gs [N], gparams [P]
+ * ld_node >= N+1 and ld_int >= N.  Every pointer must be aligned to the
+ * element size.
+ *
+ * Concurrency and ownership: no call allocates, frees, copies host<->device or
+ * synchronizes; work is enqueued on `stream` (a hipStream_t; NULL = the
+ * default stream) and errors in device execution surface at the caller's next
+ * synchronization.  A cis_model is an immutable host object and may be used
+ * from several threads and streams at once.  On any returned error nothing
+ * has been enqueued and no output has been written.
+ */
+#ifndef CIS_H
+#define CIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CIS_OK = 0,
+    CIS_ERR_NULL = 1,         /* a required pointer is NULL                  */
+    CIS_ERR_DIM = 2,          /* N, K, ld or checkpoint stride out of range  */
+    CIS_ERR_LAYOUT = 3,       /* pointer not aligned to the element size     */
+    CIS_ERR_DTYPE = 4,        /* unknown dtype or dtype not offered here     */
+    CIS_ERR_WORKSPACE = 5,    /* workspace missing or too small              */
+    CIS_ERR_MODEL = 6,        /* malformed model description                 */
+    CIS_ERR_HIP = 7,          /* the HIP runtime rejected a launch           */
+    CIS_ERR_UNSUPPORTED = 8   /* topology with no compiled kernel            */
+} cis_status;
+
+typedef enum { CIS_F64 = 0, CIS_F32 = 1 } cis_dtype;
+
+typedef struct cis_model cis_model;   /* opaque, immutable after creation */
+
+/*
+ * Host description of a planar multibody model (Sec. II).  All arrays are
+ * HOST pointers, copied by cis_model_create; the caller keeps ownership.
+ * Bodies are rigid rods: I_b = m_b * link_length_b^2 / 12.  Joint j connects
+ * parent body joint_parent[j] at anchor joint_anchor_parent[j] (parent body
+ * frame) to joint_child[j] at joint_anchor_child[j]; its reaction force
+ * lambda_j (world frame) acts +lambda on the parent and -lambda on the child
+ * (grad h^T lambda, eq. ct-dynamics); torque tau_j plus the spring-damper
+ * torque -k (th_c - th_p) - d (w_c - w_p) acts +1x on the child and -1x on
+ * the parent.  Contact i sits at contact_point[i] in the frame of
+ * contact_body[i].  Terrain: h(P) = P_y - A sin(kappa P_x) (A = 0: flat),
+ * signed distance approximated by h/||grad h|| (Sec. VI-B).
+ *
+ * Compiled topologies: a torso (body 0) with L legs of D links, link d of
+ * leg l being body 1 + l*D + d, joint j having child j+1, and the contact of
+ * leg l at the last link of that leg (on the torso when D = 0).  (L, D) in
+ * {(0,0),(1,0),(1,1),(1,2),(2,1),(2,2),(2,3),(4,3)}; other topologies give
+ * CIS_ERR_UNSUPPORTED.
+ */
+typedef struct {
+    int32_t n_bodies, n_joints, n_contacts;
+    const double *link_length;          /* [n_bodies], > 0                   */
+    const int32_t *joint_parent;        /* [n_joints]                        */
+    const int32_t *joint_child;         /* [n_joints]                        */
+    const double *joint_anchor_parent;  /* [n_joints][2]                     */
+    const double *joint_anchor_child;   /* [n_joints][2]                     */
+    const double *joint_stiffness;      /* [n_joints]                        */
+    const double *joint_damping;        /* [n_joints]                        */
+    const int32_t *contact_body;        /* [n_contacts]                      */
+    const double *contact_point;        /* [n_contacts][2]                   */
+    double gravity;                     /* m/s^2, acts along -y              */
+    double terrain_amplitude;           /* A                                 */
+    double terrain_wavenumber;          /* kappa                             */
+} cis_model_desc;
+
+/* Problem shape: N intervals (N+1 nodes), K RK4 substeps per interval. */
+typedef struct {
+    int32_t N;
+    int32_t substeps;        /* 1 <= K <= 4096                               */
+    int32_t dtype;           /* cis_dtype                                    */
+    int32_t reserved;        /* must be 0                                    */
+    int64_t ld_node;         /* >= N + 1                                     */
+    int64_t ld_int;          /* >= N                                         */
+} cis_shape;
+
+/* Library version string (static storage). */
+const char *cis_version(void);
+
+/* Human-readable text of a status code (static storage). */
+const char *cis_status_string(cis_status st);
+
+/* Detail of the last failure on the calling thread (thread-local storage). */
+const char *cis_last_error(void);
+
+/* Validate and copy a model description; *out receives the model.
+ * Errors: CIS_ERR_NULL, CIS_ERR_MODEL, CIS_ERR_UNSUPPORTED. */
+cis_status cis_model_create(const cis_model_desc *desc, cis_model **out);
+
+/* Release a model (NULL is accepted). */
+void cis_model_destroy(cis_model *model);
+
+/* Sizes n, n_y, m, P of a model (any output pointer may be NULL). */
+cis_status cis_model_dims(const cis_model *model, int32_t *n, int32_t *n_y, int32_t *m,
+                          int32_t *n_params);
+
+/*
+ * Linearize and discretize every interval (the per-SCP-iteration hot path,
+ * Sec. VI transcription): writes A, Bm, Bp, S, defect and, if xprop is not
+ * NULL, F~_k.  Inputs X, U, s, params; U may be NULL only when m = 0, and
+ * Bm/Bp likewise.  dtype CIS_F64 or CIS_F32 (all buffers of that type).
+ */
+cis_status cis_discretize(const cis_model *model, const cis_shape *shape, const void *X,
+                          const void *U, const void *s, const void *params, void *A,
+                          void *Bm, void *Bp, void *S, void *defect, void *xprop,
+                          void *stream);
+
+/*
+ * Defects only (no sensitivities): F~_k into xprop (may be NULL), d_k into
+ * defect, and, if ckpt is not NULL, the x part of the state at substeps
+ * 0, C, 2C, .. with C = ckpt_every (C must divide K; ckpt holds K/C slots).
+ * dtype CIS_F64 or CIS_F32.
+ */
+cis_status cis_defects(const cis_model *model, const cis_shape *shape, const void *X,
+                       const void *U, const void *s, const void *params, void *defect,
+                       void *xprop, void *ckpt, int32_t ckpt_every, void *stream);
+
+/* Bytes of device workspace cis_discretize_adjoint needs for this shape. */
+cis_status cis_adjoint_workspace_size(const cis_model *model, const cis_shape *shape,
+                                      size_t *bytes);
+
+/*
+ * Reverse-mode sweep (vector-Jacobian product) of the map
+ * (X, U, s, p) -> F~ for the cotangent seed lambda_k = dJ/dF~_k
+ * (the penalized defect merit of Sec. V is one such J).  Outputs are
+ * overwritten, not accumulated:
+ *   gX_k = A_k^T lambda_k (k < N), gX_N = 0;
+ *   gU_k = Bm_k^T lambda_k + Bp_{k-1}^T lambda_{k-1};
+ *   gs_k = S_k^T lambda_k;  gparams = sum_k (dF~_k/dp)^T lambda_k.
+ * The substep states are recomputed from ckpt (written by cis_defects with
+ * the same ckpt_every).  Reductions over intervals are done in a fixed order
+ * (run-to-run bitwise reproducible).  ws must hold
+ * cis_adjoint_workspace_size bytes.  dtype CIS_F64 only.
+ */
+cis_status cis_discretize_adjoint(const cis_model *model, const cis_shape *shape,
+                                  const void *X, const void *U, const void *s,
+                                  const void *params, const void *ckpt, int32_t ckpt_every,
+                                  const void *seed, void *gX, void *gU, void *gs,
+                                  void *gparams, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CIS_H */

@@ -1,0 +1,107 @@
+"""ctypes binding of libcis.so (argument marshalling only).
+
+Every step of the discretization runs in the HIP kernels behind the C ABI
+declared in include/cis.h; this module only loads the library and describes
+its structs and signatures.  Loading fails loudly when the library is absent
+or cannot be opened: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import build as _build
+
+LIB_PATH = _build.LIB
+
+CIS_OK = 0
+CIS_ERR_NULL = 1
+CIS_ERR_DIM = 2
+CIS_ERR_LAYOUT = 3
+CIS_ERR_DTYPE = 4
+CIS_ERR_WORKSPACE = 5
+CIS_ERR_MODEL = 6
+CIS_ERR_HIP = 7
+CIS_ERR_UNSUPPORTED = 8
+CIS_F64 = 0
+CIS_F32 = 1
+
+# every symbol include/cis.h declares
+EXPORTS = [
+    "cis_version", "cis_status_string", "cis_last_error", "cis_model_create",
+    "cis_model_destroy", "cis_model_dims", "cis_discretize", "cis_defects",
+    "cis_adjoint_workspace_size", "cis_discretize_adjoint",
+]
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_bodies", ctypes.c_int32), ("n_joints", ctypes.c_int32),
+        ("n_contacts", ctypes.c_int32),
+        ("link_length", ctypes.c_void_p), ("joint_parent", ctypes.c_void_p),
+        ("joint_child", ctypes.c_void_p), ("joint_anchor_parent", ctypes.c_void_p),
+        ("joint_anchor_child", ctypes.c_void_p), ("joint_stiffness", ctypes.c_void_p),
+        ("joint_damping", ctypes.c_void_p), ("contact_body", ctypes.c_void_p),
+        ("contact_point", ctypes.c_void_p),
+        ("gravity", ctypes.c_double), ("terrain_amplitude", ctypes.c_double),
+        ("terrain_wavenumber", ctypes.c_double),
+    ]
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("substeps", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ld_node", ctypes.c_int64), ("ld_int", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(build_if_missing: bool = True):
+    """Open libcis.so (building it first only if no library exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise RuntimeError(f"libcis.so not found at {LIB_PATH}; run the package build")
+        _build.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, St = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    lib.cis_version.restype = ctypes.c_char_p
+    lib.cis_version.argtypes = []
+    lib.cis_status_string.restype = ctypes.c_char_p
+    lib.cis_status_string.argtypes = [St]
+    lib.cis_last_error.restype = ctypes.c_char_p
+    lib.cis_last_error.argtypes = []
+    lib.cis_model_create.restype = St
+    lib.cis_model_create.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
+    lib.cis_model_destroy.restype = None
+    lib.cis_model_destroy.argtypes = [P]
+    lib.cis_model_dims.restype = St
+    lib.cis_model_dims.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                   ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.cis_discretize.restype = St
+    lib.cis_discretize.argtypes = [P, ctypes.POINTER(Shape)] + [P] * 11
+    lib.cis_defects.restype = St
+    lib.cis_defects.argtypes = [P, ctypes.POINTER(Shape), P, P, P, P, P, P, P, I32, P]
+    lib.cis_adjoint_workspace_size.restype = St
+    lib.cis_adjoint_workspace_size.argtypes = [P, ctypes.POINTER(Shape),
+                                               ctypes.POINTER(ctypes.c_size_t)]
+    lib.cis_discretize_adjoint.restype = St
+    lib.cis_discretize_adjoint.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, P, I32]
+                                           + [P] * 6 + [ctypes.c_size_t, P])
+    _lib = lib
+    return lib
+
+
+class CisError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"cis status {status}: {detail}")
+        self.status = status
+
+
+def check(status: int) -> None:
+    if status != CIS_OK:
+        lib = load()
+        raise CisError(status, lib.cis_last_error().decode())

@@ -1,0 +1,247 @@
+"""Torch-facing calls of the HIP discretization library.
+
+Tensors live on the GPU in the library's layout (interval or node index
+contiguous, see include/cis.h): X[nx, ld_node], U[m, ld_node], s[N],
+params[P]; outputs come back as A[nx, nx, N], Bm/Bp[nx, m, N], S/d/F~[nx, N].
+``as_interval_major`` gives [N, ...] views.  PyTorch only provides device
+memory and the current stream; every arithmetic step runs in the kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class CisModel:
+    """A model description registered with the library (host object)."""
+
+    def __init__(self, model):
+        lib = _lib.load()
+        self.model = model
+        keep = [
+            np.ascontiguousarray(model.link_length, dtype=np.float64),
+            np.ascontiguousarray(model.joint_parent, dtype=np.int32),
+            np.ascontiguousarray(model.joint_child, dtype=np.int32),
+            np.ascontiguousarray(model.anchor_parent, dtype=np.float64).reshape(-1),
+            np.ascontiguousarray(model.anchor_child, dtype=np.float64).reshape(-1),
+            np.ascontiguousarray(model.stiffness, dtype=np.float64),
+            np.ascontiguousarray(model.damping, dtype=np.float64),
+            np.ascontiguousarray(model.contact_body, dtype=np.int32),
+            np.ascontiguousarray(model.contact_point, dtype=np.float64).reshape(-1),
+        ]
+        ptrs = [k.ctypes.data if k.size else None for k in keep]
+        desc = _lib.ModelDesc(model.nb, model.nj, model.nc, *ptrs, model.gravity,
+                              model.terrain_amplitude, model.terrain_wavenumber)
+        h = ctypes.c_void_p()
+        _lib.check(lib.cis_model_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        dims = [ctypes.c_int32() for _ in range(4)]
+        _lib.check(lib.cis_model_dims(h, *[ctypes.byref(d) for d in dims]))
+        self.n, self.ny, self.m, self.np = [d.value for d in dims]
+        self.nx = self.n + self.ny
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.cis_model_destroy(h)
+            self._h = None
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float64:
+        return _lib.CIS_F64
+    if dtype == torch.float32:
+        return _lib.CIS_F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _shape(X, s, K, ld_int=None):
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be [nx, ld_node] with unit stride along nodes")
+    N = s.shape[0]
+    return _lib.Shape(N, int(K), _dtype_code(X.dtype), 0, X.stride(0),
+                      N if ld_int is None else int(ld_int))
+
+
+def _check_inputs(cm, X, U, s, params):
+    dev = X.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be GPU tensors")
+    for t in (U, s, params):
+        if t is not None and (t.device != dev or t.dtype != X.dtype):
+            raise ValueError("all inputs must share device and dtype")
+    if X.shape[0] != cm.nx or s.dim() != 1 or X.shape[1] < s.shape[0] + 1:
+        raise ValueError("X must be [nx, >= N+1] and s [N]")
+    if cm.m and (U is None or U.shape[0] != cm.m or U.stride(1) != 1 or U.stride(0) != X.stride(0)
+                 or U.shape[1] < s.shape[0] + 1):
+        raise ValueError("U must be [m, >= N+1] with the same ld_node as X")
+    if params.numel() != cm.np or not params.is_contiguous() or not s.is_contiguous():
+        raise ValueError("params must hold P contiguous values and s must be contiguous")
+
+
+def discretize(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None):
+    """A, Bm, Bp, S, defect (and F~) of every interval, written by one kernel launch."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    kw = dict(device=X.device, dtype=X.dtype)
+    out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+               Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+               d=torch.empty((nx, N), **kw))
+    out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+    sh = _shape(X, s, K)
+    lib = _lib.load()
+    _lib.check(lib.cis_discretize(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                  _ptr(params), _ptr(out["A"]), _ptr(out["Bm"] if m else None),
+                                  _ptr(out["Bp"] if m else None), _ptr(out["S"]), _ptr(out["d"]),
+                                  _ptr(out["xprop"]), _stream(stream)))
+    return out
+
+
+def discretize_into(cm, X, U, s, params, K, out, stream=None):
+    """Same as discretize, writing into preallocated outputs (no allocation).
+
+    out holds A[nx, nx, ld], Bm/Bp[nx, m, ld], S/d[nx, ld] and optionally
+    xprop[nx, ld], all contiguous with the same ld >= N.
+    """
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    ld = out["S"].shape[-1]
+    for key, lead in (("A", (nx, nx)), ("Bm", (nx, m)), ("Bp", (nx, m)), ("S", (nx,)),
+                      ("d", (nx,)), ("xprop", (nx,))):
+        t = out.get(key)
+        if t is None and key in ("xprop",):
+            continue
+        if (t is None or not t.is_contiguous() or tuple(t.shape[:-1]) != lead or t.shape[-1] != ld
+                or ld < N or t.dtype != X.dtype or t.device != X.device):
+            raise ValueError(f"output {key} must be a contiguous {lead + (ld,)} tensor, ld >= N")
+    sh = _shape(X, s, K, ld_int=ld)
+    lib = _lib.load()
+    _lib.check(lib.cis_discretize(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                  _ptr(params), _ptr(out["A"]), _ptr(out["Bm"] if cm.m else None),
+                                  _ptr(out["Bp"] if cm.m else None), _ptr(out["S"]), _ptr(out["d"]),
+                                  _ptr(out.get("xprop")), _stream(stream)))
+    return out
+
+
+def defects(cm: CisModel, X, U, s, params, K, *, ckpt_every=None, stream=None):
+    """F~ and defects only; optional substep checkpoints [K/C, n, N] for the adjoint."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx = s.shape[0], cm.nx
+    kw = dict(device=X.device, dtype=X.dtype)
+    out = dict(d=torch.empty((nx, N), **kw), xprop=torch.empty((nx, N), **kw), ckpt=None)
+    C = 0
+    if ckpt_every is not None:
+        C = int(ckpt_every)
+        if C < 1 or K % C:
+            raise ValueError("ckpt_every must divide K")
+        out["ckpt"] = torch.empty((K // C, cm.n, N), **kw)
+    sh = _shape(X, s, K)
+    lib = _lib.load()
+    _lib.check(lib.cis_defects(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                               _ptr(params), _ptr(out["d"]), _ptr(out["xprop"]), _ptr(out["ckpt"]),
+                               C, _stream(stream)))
+    return out
+
+
+def adjoint_workspace_bytes(cm: CisModel, N, K, dtype=torch.float64):
+    sh = _lib.Shape(N, int(K), _dtype_code(dtype), 0, N + 1, N)
+    nbytes = ctypes.c_size_t()
+    _lib.check(_lib.load().cis_adjoint_workspace_size(cm.handle, ctypes.byref(sh),
+                                                      ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def adjoint(cm: CisModel, X, U, s, params, K, ckpt, ckpt_every, seed, *, stream=None):
+    """gX[nx, N+1], gU[m, N+1], gs[N], gp[P] for the cotangent seed[nx, N] of F~."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    kw = dict(device=X.device, dtype=X.dtype)
+    if seed.shape != (nx, N) or not seed.is_contiguous():
+        raise ValueError("seed must be a contiguous [nx, N] tensor")
+    if ckpt is None or ckpt.shape != (K // ckpt_every, cm.n, N) or not ckpt.is_contiguous():
+        raise ValueError("ckpt must come from defects(..., ckpt_every=C) with the same K, C")
+    ld = X.stride(0)
+    gX = torch.empty((nx, ld), **kw)
+    gU = torch.empty((max(m, 1), ld), **kw)
+    gs = torch.empty((N,), **kw)
+    gp = torch.empty((cm.np,), **kw)
+    nbytes = adjoint_workspace_bytes(cm, N, K, X.dtype)
+    ws = torch.empty((max(nbytes, 1),), device=X.device, dtype=torch.uint8)
+    sh = _shape(X, s, K)
+    lib = _lib.load()
+    _lib.check(lib.cis_discretize_adjoint(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                          _ptr(params), _ptr(ckpt), int(ckpt_every), _ptr(seed),
+                                          _ptr(gX), _ptr(gU if m else None), _ptr(gs), _ptr(gp),
+                                          _ptr(ws), nbytes, _stream(stream)))
+    return dict(gX=gX[:, :N + 1], gU=gU[:m, :N + 1], gs=gs, gp=gp)
+
+
+class CisDefects(torch.autograd.Function):
+    """F~ = F~(X, U, s, p) of every interval; backward is the reverse-mode kernel.
+
+    forward(X, U, s, params, cm, K, C) -> F~[nx, N]; substep checkpoints every C
+    substeps are saved and recomputed from in the backward pass.
+    """
+
+    @staticmethod
+    def forward(ctx, X, U, s, params, cm, K, C):
+        out = defects(cm, X.detach(), U.detach(), s.detach(), params.detach(), K, ckpt_every=C)
+        ctx.save_for_backward(X, U, s, params, out["ckpt"])
+        ctx.cm, ctx.K, ctx.C = cm, K, C
+        return out["xprop"]
+
+    @staticmethod
+    def backward(ctx, gF):
+        X, U, s, params, ckpt = ctx.saved_tensors
+        g = adjoint(ctx.cm, X.detach(), U.detach(), s.detach(), params.detach(), ctx.K, ckpt,
+                    ctx.C, gF.contiguous())
+        N = s.shape[0]
+        gX = torch.zeros_like(X)
+        gX[:, :N + 1] = g["gX"]
+        gU = torch.zeros_like(U)
+        if ctx.cm.m:
+            gU[:, :N + 1] = g["gU"]
+        return gX, gU, g["gs"], g["gp"], None, None, None
+
+
+def as_interval_major(out):
+    """[N, ...] views of the outputs (A[N,nx,nx], Bm/Bp[N,nx,m], S/d/F~[N,nx])."""
+    v = {}
+    for key, t in out.items():
+        if t is None:
+            v[key] = None
+        elif t.dim() == 3 and key != "ckpt":
+            v[key] = t.permute(2, 0, 1)
+        elif t.dim() == 2:
+            v[key] = t.t()
+        else:
+            v[key] = t
+    return v
+
+
+def to_device_soa(arr, device="cuda", dtype=torch.float64, ld=None):
+    """Node-major numpy [N+1, c] -> device tensor [c, ld] (node index contiguous)."""
+    arr = np.asarray(arr, dtype=np.float64)
+    t = torch.from_numpy(np.ascontiguousarray(arr.T))
+    if ld is not None and ld > t.shape[1]:
+        pad = torch.zeros((t.shape[0], ld - t.shape[1]), dtype=t.dtype)
+        t = torch.cat([t, pad], dim=1)
+    return t.to(device=device, dtype=dtype).contiguous()

@@ -1,0 +1,459 @@
+// Reverse-mode sweep (vector-Jacobian product) of the discrete RK4 map of
+// every interval, for a cotangent seed lambda_k = dJ/dF~_k; the penalized
+// defect merit of the SCP subproblem (Sec. V) is one such J.
+//
+//   k_adjoint : one wave per interval.  Segments of C substeps are replayed
+//               from the checkpoints (x at substeps 0, C, 2C, ..), the stage
+//               inputs are kept in LDS, and the classical RK4 stages are then
+//               reversed:  kbar_i = h/6 w_i xbar + h a_{i+1} Xbar_{i+1},
+//               Xbar_i = s J_x(X_i)^T kbar_i, xbar <- xbar + sum_i Xbar_i,
+//               with the control, dilation and parameter adjoints gathered
+//               along the way.  The transposed Jacobian product is the
+//               adjoint of the element-parallel forward product: each joint
+//               or contact lane scatters into per-element slots, each body
+//               lane sums its slots (fixed order, no atomics).
+//   k_adjoint_reduce : gU_k = (interval k, left half) + (interval k-1, right
+//               half); gp = sum over intervals in index order; gX_N = 0.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/cis.h"
+#include "cis_host.hpp"
+#include "cis_model.hpp"
+
+namespace cis {
+
+constexpr int CHUNK = 8;   // substeps whose stage inputs are kept in LDS at once
+
+template <class T, class TP>
+struct AdjShared {
+    T hist[CHUNK * 4][TP::NX];          // stage inputs (x part) of the chunk
+    T kb[TP::NXT];                      // kbar of the current stage
+    T xbs[TP::NX];                      // Xbar of the current stage
+    T jslot[cmax(TP::NJ, 1)][8];        // th_p, th_c, w_p, w_c, x_p, x_c, y_p, y_c
+    T cslot[cmax(TP::NC, 1)][6];        // x, y, th, xd, yd, w of the contact body
+    T red[64];
+};
+
+template <class T>
+struct AdjArgs {
+    FwdArgs<T> f;
+    const T* seed;
+    T* gX;
+    T* gs;
+    T* ws_uk;    // [m][N] adjoint of U_k from interval k
+    T* ws_uk1;   // [m][N] adjoint of U_{k+1} from interval k
+    T* ws_p;     // [P][N] parameter adjoint from interval k
+};
+
+// Reverse one RK4 stage at the stage input held in sm.ns (coefficients are
+// recomputed there).  Lanes own rows r = lane, lane + 64.
+template <class T, class TP, class SM>
+__device__ __forceinline__ void reverse_stage(SM& sm, AdjShared<T, TP>& ax,
+                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc, int lane,
+                                              int st, T tau, T (&xbar)[2], T (&xprev)[2],
+                                              T (&xsum)[2], T& sacc, T (&uacc)[3][2], T& muacc,
+                                              T& macc) {
+    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX;
+    constexpr int NXT = TP::NXT, M = TP::M;
+    using C = Coef<TP>;
+    T* cf = sm.coef[0];
+    const T s = sm.s, h = sm.h;
+    // kbar_st = h/6 w_st xbar + h a_{st+1} Xbar_{st+1}
+    const T w = (st == 0 || st == 3) ? T(1) : T(2);
+    const T anext = st == 2 ? h : T(0.5) * h;   // multiplier of k_st in stage st+1's input
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        if (r < NXT) ax.kb[r] = (h / T(6)) * w * xbar[q] + (st < 3 ? anext * xprev[q] : T(0));
+    }
+    nominal_rhs<T, TP, true>(sm, mc, lane, tau, cf);   // ends with a wave sync
+    const T omt = T(1) - tau;
+    const T lc = ax.kb[NX + NC];
+    // phase A: element lanes scatter into their slots; control adjoints
+    if (lane < NJ) {
+        const int j = lane, p = TP::parent(j), c = j + 1;
+        const T gp = ax.kb[NQ + 3 * p + 2], gc = ax.kb[NQ + 3 * c + 2];
+        const T t1 = sm.kc[j][0] * gp - sm.kc[j][2] * gc;
+        const T t2 = sm.kc[j][1] * gp - sm.kc[j][3] * gc;
+        const T* jh = cf + C::JH + 4 * j;
+        ax.jslot[j][0] = -t1 + jh[2] * lc;
+        ax.jslot[j][1] = t1 + jh[3] * lc;
+        ax.jslot[j][2] = -t2;
+        ax.jslot[j][3] = t2;
+        ax.jslot[j][4] = jh[0] * lc;
+        ax.jslot[j][5] = -jh[0] * lc;
+        ax.jslot[j][6] = jh[1] * lc;
+        ax.jslot[j][7] = -jh[1] * lc;
+        const T* gv = cf + C::GV;
+        const T kxp = ax.kb[NQ + 3 * p], kyp = ax.kb[NQ + 3 * p + 1];
+        const T kxc = ax.kb[NQ + 3 * c], kyc = ax.kb[NQ + 3 * c + 1];
+        const int ut = j, ux = NJ + 2 * j, uy = NJ + 2 * j + 1;
+        const T at = gv[(3 * p + 2) * M + ut] * gp + gv[(3 * c + 2) * M + ut] * gc;
+        const T axx = gv[(3 * p) * M + ux] * kxp + gv[(3 * c) * M + ux] * kxc +
+                      gv[(3 * p + 2) * M + ux] * gp + gv[(3 * c + 2) * M + ux] * gc;
+        const T ayy = gv[(3 * p + 1) * M + uy] * kyp + gv[(3 * c + 1) * M + uy] * kyc +
+                      gv[(3 * p + 2) * M + uy] * gp + gv[(3 * c + 2) * M + uy] * gc;
+        uacc[0][0] += omt * at;  uacc[0][1] += tau * at;
+        uacc[1][0] += omt * axx; uacc[1][1] += tau * axx;
+        uacc[2][0] += omt * ayy; uacc[2][1] += tau * ayy;
+    } else if (lane < NJ + NC) {
+        const int i = lane - NJ, b = TP::cbody(i);
+        const T* ct = cf + C::CT + C::NCT * i;
+        const T kx = ax.kb[NQ + 3 * b], ky = ax.kb[NQ + 3 * b + 1], kw = ax.kb[NQ + 3 * b + 2];
+        const T kcc = ax.kb[NX + i];
+        const T pbx = ct[C_FXP] * kx + ct[C_FYP] * ky + ct[C_TP] * kw + ct[C_EPX] * kcc +
+                      ct[C_ZPX] * lc;
+        const T pby = ct[C_EPY] * kcc + ct[C_ZPY] * lc;
+        ax.cslot[i][0] = pbx;
+        ax.cslot[i][1] = pby;
+        ax.cslot[i][2] = -ct[C_AY] * pbx + ct[C_AX] * pby + ct[C_ETH] * kcc;
+        ax.cslot[i][3] = ct[C_EXD] * kcc;
+        ax.cslot[i][4] = ct[C_EYD] * kcc;
+        ax.cslot[i][5] = ct[C_EOM] * kcc;
+        const T* gv = cf + C::GV;
+        const T* gc = cf + C::GC + i * M;
+        const int u0 = 3 * NJ + 3 * i;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int u = u0 + q;
+            const T inst = gv[(3 * b) * M + u] * kx + gv[(3 * b + 1) * M + u] * ky +
+                           gv[(3 * b + 2) * M + u] * kw;
+            const T bar = gc[u] * kcc;
+            uacc[q][0] += omt * inst + bar;
+            uacc[q][1] += tau * inst + bar;
+        }
+        muacc += ct[C_JMU] * kcc;
+    }
+    wave_lds_sync();
+    // phase B: body lanes gather their slots into Xbar of the stage
+    if (lane < NB) {
+        const int b = lane;
+        T xq = T(0), yq = T(0), th = T(0), xd = T(0), yd = T(0), om = T(0);
+        auto as_parent = [&](int j) {
+            th += ax.jslot[j][0];
+            om += ax.jslot[j][2];
+            xq += ax.jslot[j][4];
+            yq += ax.jslot[j][6];
+        };
+        auto as_child = [&](int j) {
+            th += ax.jslot[j][1];
+            om += ax.jslot[j][3];
+            xq += ax.jslot[j][5];
+            yq += ax.jslot[j][7];
+        };
+        auto contact = [&](int i) {
+            xq += ax.cslot[i][0];
+            yq += ax.cslot[i][1];
+            th += ax.cslot[i][2];
+            xd += ax.cslot[i][3];
+            yd += ax.cslot[i][4];
+            om += ax.cslot[i][5];
+        };
+        if (b == 0) {
+#pragma unroll
+            for (int l = 0; l < TP::L; ++l) {
+                if (TP::D > 0) as_parent(l * TP::D);
+                else contact(l);
+            }
+        } else if constexpr (TP::D > 0) {
+            as_child(b - 1);
+            if (b % TP::D != 0) as_parent(b);
+            else contact(b / TP::D - 1);
+        }
+        const T gw = ax.kb[NQ + 3 * b + 2];
+        ax.xbs[3 * b] = xq;
+        ax.xbs[3 * b + 1] = yq;
+        ax.xbs[3 * b + 2] = th + cf[C::CTH + b] * gw;
+        ax.xbs[NQ + 3 * b] = s * ax.kb[3 * b] + xd;
+        ax.xbs[NQ + 3 * b + 1] = s * ax.kb[3 * b + 1] + yd;
+        ax.xbs[NQ + 3 * b + 2] = s * ax.kb[3 * b + 2] + om;
+        // d(s v')/d m_b = -(s/m_b) (v'_x, v'_y + g, w')
+        macc -= s * sm.minv[b] *
+                (sm.fn[NQ + 3 * b] * ax.kb[NQ + 3 * b] +
+                 (sm.fn[NQ + 3 * b + 1] + T(mc.g)) * ax.kb[NQ + 3 * b + 1] +
+                 sm.fn[NQ + 3 * b + 2] * ax.kb[NQ + 3 * b + 2]);
+    }
+    wave_lds_sync();
+    // rows: collect Xbar_i, dilation adjoint F~ . kbar
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        if (r < NX) {
+            const T xb = ax.xbs[r];
+            xsum[q] += xb;
+            xprev[q] = xb;
+        } else {
+            xprev[q] = T(0);
+        }
+        if (r < NXT) {
+            const T F = r < NQ ? sm.ns[NQ + r] : sm.fn[r];
+            sacc += F * ax.kb[r];
+        }
+    }
+    wave_lds_sync();
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(64)
+    k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NX = TP::NX, NXT = TP::NXT;
+    constexpr int M = TP::M;
+    __shared__ Shared<T, TP, 1> sm;
+    __shared__ AdjShared<T, TP> ax;
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const FwdArgs<T>& f = a.f;
+    load_interval<T, TP>(sm, f, mc, k, lane, 64);
+    const T s = sm.s;
+    for (int j = lane; j < NJ; j += 64) {
+        const int p = TP::parent(j), c = j + 1;
+        sm.kc[j][0] = s * T(mc.ks[j]) * sm.iinv[p];
+        sm.kc[j][1] = s * T(mc.ds[j]) * sm.iinv[p];
+        sm.kc[j][2] = s * T(mc.ks[j]) * sm.iinv[c];
+        sm.kc[j][3] = s * T(mc.ds[j]) * sm.iinv[c];
+    }
+    // constant FOH forcing entries of the coefficient buffer (zero elsewhere)
+    for (int e = lane; e < Coef<TP>::SIZE; e += 64) sm.coef[0][e] = T(0);
+    wave_lds_sync();
+    for (int j = lane; j < NJ; j += 64) {
+        const int p = TP::parent(j), c = j + 1;
+        T* gv = sm.coef[0] + Coef<TP>::GV;
+        gv[(3 * p) * M + NJ + 2 * j] = s * sm.minv[p];
+        gv[(3 * p + 1) * M + NJ + 2 * j + 1] = s * sm.minv[p];
+        gv[(3 * c) * M + NJ + 2 * j] = -s * sm.minv[c];
+        gv[(3 * c + 1) * M + NJ + 2 * j + 1] = -s * sm.minv[c];
+        gv[(3 * p + 2) * M + j] = -s * sm.iinv[p];
+        gv[(3 * c + 2) * M + j] = s * sm.iinv[c];
+    }
+    wave_lds_sync();
+
+    const int64_t ldi = f.ldi;
+    T xbar[2], xprev[2], xsum[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        xbar[q] = r < NXT ? a.seed[r * ldi + k] : T(0);
+        xprev[q] = T(0);
+        xsum[q] = T(0);
+    }
+    T sacc = T(0), muacc = T(0), macc = T(0);
+    T uacc[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    const int K = f.K, Cs = f.C;
+    const int nseg = K / Cs;
+    RowState<T> rs;
+    for (int g = nseg - 1; g >= 0; --g) {
+        const int base = g * Cs;
+        for (int c0 = ((Cs - 1) / CHUNK) * CHUNK; c0 >= 0; c0 -= CHUNK) {
+            const int len = (Cs - c0) < CHUNK ? (Cs - c0) : CHUNK;
+            // replay from the checkpoint to the chunk start, then record the chunk
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int r = lane + 64 * q;
+                rs.xb[q] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
+                rs.xa[q] = T(0);
+                if (r < NXT) sm.ns[r] = rs.xb[q];
+            }
+            wave_lds_sync();
+            for (int jj = 0; jj < c0 + len; ++jj) {
+                const int j = base + jj;
+                for (int st = 0; st < 4; ++st) {
+                    if (jj >= c0) {
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const int r = lane + 64 * q;
+                            if (r < NX) ax.hist[(jj - c0) * 4 + st][r] = sm.ns[r];
+                        }
+                    }
+                    const T tau = (T(j) + T(stage_c(st))) / T(K);
+                    nominal_rhs<T, TP, false>(sm, mc, lane, tau, (T*)nullptr);
+                    nominal_update<T, TP, false>(sm, rs, lane, st, (T*)nullptr);
+                }
+            }
+            wave_lds_sync();
+            // reverse the recorded substeps
+            for (int jj = len - 1; jj >= 0; --jj) {
+                const int j = base + c0 + jj;
+                for (int st = 3; st >= 0; --st) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int r = lane + 64 * q;
+                        if (r < NX) sm.ns[r] = ax.hist[jj * 4 + st][r];
+                    }
+                    wave_lds_sync();
+                    const T tau = (T(j) + T(stage_c(st))) / T(K);
+                    reverse_stage<T, TP>(sm, ax, mc, lane, st, tau, xbar, xprev, xsum, sacc,
+                                         uacc, muacc, macc);
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    xbar[q] += xsum[q];
+                    xsum[q] = T(0);
+                    xprev[q] = T(0);
+                }
+            }
+        }
+    }
+    // gX_k = xbar
+    const int64_t ldn = f.ldn;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        if (r < NXT) a.gX[r * ldn + k] = xbar[q];
+    }
+    const int N = f.N;
+    // control adjoints of this interval (left: U_k, right: U_k+1)
+    if (lane < NJ) {
+        const int us[3] = {lane, NJ + 2 * lane, NJ + 2 * lane + 1};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            a.ws_uk[(int64_t)us[q] * N + k] = uacc[q][0];
+            a.ws_uk1[(int64_t)us[q] * N + k] = uacc[q][1];
+        }
+    } else if (lane < NJ + NC) {
+        const int u0 = 3 * NJ + 3 * (lane - NJ);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            a.ws_uk[(int64_t)(u0 + q) * N + k] = uacc[q][0];
+            a.ws_uk1[(int64_t)(u0 + q) * N + k] = uacc[q][1];
+        }
+    }
+    // dilation adjoint: fixed-order sum of the lane partials
+    ax.red[lane] = sacc;
+    wave_lds_sync();
+    if (lane == 0) {
+        T acc = T(0);
+        for (int l = 0; l < 64; ++l) acc += ax.red[l];
+        a.gs[k] = acc;
+    }
+    wave_lds_sync();
+    ax.red[lane] = muacc;
+    wave_lds_sync();
+    if (lane == 0) {
+        T acc = T(0);
+        for (int l = NJ; l < NJ + NC; ++l) acc += ax.red[l];
+        a.ws_p[k] = acc;                 // mu
+        a.ws_p[(int64_t)N + k] = T(0);   // restitution: no dependence on this path
+    }
+    if (lane < NB) a.ws_p[(int64_t)(2 + lane) * N + k] = macc;
+}
+
+// gU, gX_N and gp from the per-interval partials, in a fixed order.
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_adjoint_reduce(const T* ws_uk, const T* ws_uk1, const T* ws_p, T* gU, T* gX, T* gp, int N,
+                     int m, int nxt, int np, int64_t ldn) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nu = (int64_t)m * (N + 1);
+    if (t < nu) {
+        const int c = (int)(t / (N + 1)), k = (int)(t % (N + 1));
+        const T left = k < N ? ws_uk[(int64_t)c * N + k] : T(0);
+        const T right = k > 0 ? ws_uk1[(int64_t)c * N + k - 1] : T(0);
+        gU[(int64_t)c * ldn + k] = left + right;
+    } else if (t < nu + nxt) {
+        gX[(t - nu) * ldn + N] = T(0);
+    } else if (t < nu + nxt + np) {
+        const int c = (int)(t - nu - nxt);
+        T acc = T(0);
+        for (int k = 0; k < N; ++k) acc += ws_p[(int64_t)c * N + k];
+        gp[c] = acc;
+    }
+}
+
+static size_t ws_elems(const cis_model* m, int N) { return (size_t)(2 * m->m + m->np) * N; }
+
+template <int L, int D>
+static cis_status launch_adjoint(const cis_model* m, const cis_shape* sh, const void* X,
+                                 const void* U, const void* s, const void* prm, const void* ckpt,
+                                 int C, const void* seed, void* gX, void* gU, void* gs, void* gp,
+                                 void* ws, hipStream_t stream) {
+    using TP = Topo<L, D>;
+    using T = double;
+    auto mc = make_const<TP::NB, TP::NJ, TP::NC>(m);
+    AdjArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.f.X = (const T*)X;
+    a.f.U = (const T*)U;
+    a.f.s = (const T*)s;
+    a.f.prm = (const T*)prm;
+    a.f.ckpt = (T*)ckpt;
+    a.f.ldn = sh->ld_node;
+    a.f.ldi = sh->ld_int;
+    a.f.N = sh->N;
+    a.f.K = sh->substeps;
+    a.f.C = C;
+    a.seed = (const T*)seed;
+    a.gX = (T*)gX;
+    a.gs = (T*)gs;
+    T* w = (T*)ws;
+    const int N = sh->N;
+    a.ws_uk = w;
+    a.ws_uk1 = w + (size_t)m->m * N;
+    a.ws_p = w + (size_t)2 * m->m * N;
+    void* args[] = {&a, &mc};
+    hipError_t e = hipLaunchKernel((const void*)&k_adjoint<T, TP>, dim3(N), dim3(64), args, 0,
+                                   stream);
+    if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_adjoint launch: %s", hipGetErrorString(e));
+    const int64_t work = (int64_t)m->m * (N + 1) + m->nx + m->np;
+    const int blocks = (int)((work + 255) / 256);
+    const T* wuk = a.ws_uk;
+    const T* wuk1 = a.ws_uk1;
+    const T* wp = a.ws_p;
+    T* gUp = (T*)gU;
+    T* gXp = (T*)gX;
+    T* gpp = (T*)gp;
+    int mm = m->m, nxt = m->nx, np = m->np;
+    int64_t ldn = sh->ld_node;
+    void* rargs[] = {&wuk, &wuk1, &wp, &gUp, &gXp, &gpp, (void*)&N, &mm, &nxt, &np, &ldn};
+    e = hipLaunchKernel((const void*)&k_adjoint_reduce<T>, dim3(blocks), dim3(256), rargs, 0,
+                        stream);
+    if (e != hipSuccess)
+        return fail(CIS_ERR_HIP, "k_adjoint_reduce launch: %s", hipGetErrorString(e));
+    return CIS_OK;
+}
+
+}  // namespace cis
+
+using namespace cis;
+
+extern "C" cis_status cis_adjoint_workspace_size(const cis_model* m, const cis_shape* sh,
+                                                 size_t* bytes) {
+    if (!m || !sh || !bytes) return fail(CIS_ERR_NULL, "cis_adjoint_workspace_size: null argument");
+    if (sh->N < 1) return fail(CIS_ERR_DIM, "cis_adjoint_workspace_size: N=%d must be >= 1", sh->N);
+    *bytes = ws_elems(m, sh->N) * sizeof(double);
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_discretize_adjoint(const cis_model* model, const cis_shape* shape,
+                                             const void* X, const void* U, const void* s,
+                                             const void* params, const void* ckpt,
+                                             int32_t ckpt_every, const void* seed, void* gX,
+                                             void* gU, void* gs, void* gparams, void* ws,
+                                             size_t ws_bytes, void* stream) {
+    cis_status st = check_common(model, shape, X, U, s, params);
+    if (st != CIS_OK) return st;
+    if (shape->dtype != CIS_F64)
+        return fail(CIS_ERR_DTYPE, "cis_discretize_adjoint: only CIS_F64 is offered");
+    if (!ckpt || !seed || !gX || !gs || !gparams || (model->m > 0 && !gU))
+        return fail(CIS_ERR_NULL, "cis_discretize_adjoint: ckpt, seed, gX, gs, gparams (and gU when m > 0) are required");
+    if (ckpt_every < 1 || shape->substeps % ckpt_every != 0)
+        return fail(CIS_ERR_DIM, "cis_discretize_adjoint: ckpt_every=%d must divide K=%d",
+                    ckpt_every, shape->substeps);
+    const size_t need = ws_elems(model, shape->N) * sizeof(double);
+    if (!ws || ws_bytes < need)
+        return fail(CIS_ERR_WORKSPACE, "cis_discretize_adjoint: workspace of %zu bytes needed",
+                    need);
+    const size_t es = sizeof(double);
+    if (!aligned(ckpt, es) || !aligned(seed, es) || !aligned(gX, es) || !aligned(gU, es) ||
+        !aligned(gs, es) || !aligned(gparams, es) || !aligned(ws, es))
+        return fail(CIS_ERR_LAYOUT, "cis_discretize_adjoint: pointer not aligned to 8 bytes");
+    hipStream_t hs = (hipStream_t)stream;
+#define CIS_DISPATCH_ADJ(LL, DD)                                                               \
+    if (model->L == LL && model->D == DD)                                                     \
+        return launch_adjoint<LL, DD>(model, shape, X, U, s, params, ckpt, ckpt_every, seed,   \
+                                      gX, gU, gs, gparams, ws, hs);
+    CIS_TOPOLOGIES(CIS_DISPATCH_ADJ)
+#undef CIS_DISPATCH_ADJ
+    return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_adjoint: topology has no compiled kernel");
+}

@@ -1,0 +1,136 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects malformed arguments before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_09993_amd import _lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cis.h")).read()
+    return sorted(set(re.findall(r"\b(cis_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared_symbols() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.cis_version()
+
+
+def _desc(model):
+    keep = [
+        np.ascontiguousarray(model.link_length, dtype=np.float64),
+        np.ascontiguousarray(model.joint_parent, dtype=np.int32),
+        np.ascontiguousarray(model.joint_child, dtype=np.int32),
+        np.ascontiguousarray(model.anchor_parent, dtype=np.float64).reshape(-1),
+        np.ascontiguousarray(model.anchor_child, dtype=np.float64).reshape(-1),
+        np.ascontiguousarray(model.stiffness, dtype=np.float64),
+        np.ascontiguousarray(model.damping, dtype=np.float64),
+        np.ascontiguousarray(model.contact_body, dtype=np.int32),
+        np.ascontiguousarray(model.contact_point, dtype=np.float64).reshape(-1),
+    ]
+    ptrs = [k.ctypes.data if k.size else None for k in keep]
+    d = _lib.ModelDesc(model.nb, model.nj, model.nc, *ptrs, model.gravity,
+                       model.terrain_amplitude, model.terrain_wavenumber)
+    return d, keep
+
+
+def _create(model):
+    lib = _lib.load()
+    d, keep = _desc(model)
+    h = ctypes.c_void_p()
+    st = lib.cis_model_create(ctypes.byref(d), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("name", ["free1", "point1", "hopper", "biped5", "cheetah7", "quad13"])
+def test_model_create_and_dims(name):
+    lib = _lib.load()
+    model = synth.MODEL_MAKERS[name](np.random.default_rng(0))
+    st, h = _create(model)
+    assert st == _lib.CIS_OK, lib.cis_last_error()
+    dims = [ctypes.c_int32() for _ in range(4)]
+    assert lib.cis_model_dims(h, *[ctypes.byref(x) for x in dims]) == 0
+    assert [x.value for x in dims] == [model.n, model.ny, model.m, model.n_params]
+    lib.cis_model_destroy(h)
+
+
+def test_model_create_rejects_bad_descriptions():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.cis_model_create(None, ctypes.byref(h)) == _lib.CIS_ERR_NULL
+    model = synth.make_cheetah7(np.random.default_rng(0))
+    bad = synth.make_cheetah7(np.random.default_rng(0))
+    bad.link_length = bad.link_length.copy()
+    bad.link_length[2] = -1.0
+    assert _create(bad)[0] == _lib.CIS_ERR_MODEL
+    bad = synth.make_cheetah7(np.random.default_rng(0))
+    bad.joint_parent = bad.joint_parent.copy()
+    bad.joint_parent[3] = 99
+    assert _create(bad)[0] == _lib.CIS_ERR_MODEL
+    bad = synth.make_cheetah7(np.random.default_rng(0))
+    bad.contact_body = bad.contact_body.copy()
+    bad.contact_body[0] = 1              # not a leg tip
+    assert _create(bad)[0] == _lib.CIS_ERR_UNSUPPORTED
+    bad = synth.legged_model("tri", 3, 2, np.random.default_rng(0))   # 3 legs not compiled
+    assert _create(bad)[0] == _lib.CIS_ERR_UNSUPPORTED
+    assert b"legs" in lib.cis_last_error()
+    bad = synth.make_cheetah7(np.random.default_rng(0))
+    bad.gravity = float("nan")
+    assert _create(bad)[0] == _lib.CIS_ERR_MODEL
+    assert _create(model)[0] == _lib.CIS_OK
+
+
+def _call_discretize(h, shape, X=8, U=8, s=8, p=8, outs=(8, 8, 8, 8, 8, 0)):
+    lib = _lib.load()
+    ptr = lambda v: None if v == 0 else ctypes.c_void_p(v)
+    return lib.cis_discretize(h, ctypes.byref(shape) if shape is not None else None, ptr(X), ptr(U),
+                              ptr(s), ptr(p), *[ptr(o) for o in outs], None)
+
+
+def _gpu_visible():
+    import torch
+    return torch.cuda.device_count() > 0
+
+
+@pytest.mark.skipif("_gpu_visible()", reason="uses fake addresses; run only where no GPU exists")
+def test_entry_points_validate_before_launch():
+    """Every rejection returns before any HIP call (fake, never-dereferenced addresses)."""
+    lib = _lib.load()
+    model = synth.make_hopper(np.random.default_rng(0))
+    st, h = _create(model)
+    assert st == 0
+    good = _lib.Shape(5, 4, _lib.CIS_F64, 0, 6, 5)
+    assert _call_discretize(h, None) == _lib.CIS_ERR_NULL
+    assert _call_discretize(None, good) == _lib.CIS_ERR_NULL
+    assert _call_discretize(h, _lib.Shape(0, 4, 0, 0, 6, 5)) == _lib.CIS_ERR_DIM
+    assert _call_discretize(h, _lib.Shape(5, 0, 0, 0, 6, 5)) == _lib.CIS_ERR_DIM
+    assert _call_discretize(h, _lib.Shape(5, 5000, 0, 0, 6, 5)) == _lib.CIS_ERR_DIM
+    assert _call_discretize(h, _lib.Shape(5, 4, 0, 0, 5, 5)) == _lib.CIS_ERR_DIM   # ld_node < N+1
+    assert _call_discretize(h, _lib.Shape(5, 4, 0, 0, 6, 4)) == _lib.CIS_ERR_DIM   # ld_int < N
+    assert _call_discretize(h, _lib.Shape(5, 4, 7, 0, 6, 5)) == _lib.CIS_ERR_DTYPE
+    assert _call_discretize(h, _lib.Shape(5, 4, 0, 1, 6, 5)) == _lib.CIS_ERR_DIM   # reserved
+    assert _call_discretize(h, good, X=0) == _lib.CIS_ERR_NULL
+    assert _call_discretize(h, good, U=0) == _lib.CIS_ERR_NULL                      # m > 0
+    assert _call_discretize(h, good, X=12) == _lib.CIS_ERR_LAYOUT                   # misaligned
+    assert _call_discretize(h, good, outs=(8, 0, 8, 8, 8, 0)) == _lib.CIS_ERR_NULL  # Bm missing
+    assert _call_discretize(h, good, outs=(8, 8, 8, 8, 12, 0)) == _lib.CIS_ERR_LAYOUT
+    # defects: ckpt stride must divide K
+    P = lambda v: ctypes.c_void_p(v)
+    assert lib.cis_defects(h, ctypes.byref(good), P(8), P(8), P(8), P(8), P(8), None, P(8), 3,
+                           None) == _lib.CIS_ERR_DIM
+    assert lib.cis_defects(h, ctypes.byref(good), P(8), P(8), P(8), P(8), None, None, None, 0,
+                           None) == _lib.CIS_ERR_NULL
+    assert lib.cis_status_string(_lib.CIS_ERR_DIM) == b"dimension out of range"
+    lib.cis_model_destroy(h)

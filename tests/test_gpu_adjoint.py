@@ -1,0 +1,170 @@
+"""Reverse-mode kernel vs the oracle's reverse sweep, and through autograd (GPU).
+
+Bar: per-block error <= 1e-10 (phi = 1e-3) for gX, gU, gs and gp against
+oracle.adjoint on the same inputs; dJ/de is exactly 0; central finite
+differences of the merit (h = 1e-6 relative) agree to 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_09993_amd import synth
+from parity import PHI64, TOL64, block_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev_inputs(api, data, dev):
+    X = api.to_device_soa(data["X"], dev)
+    U = api.to_device_soa(data["U"], dev)
+    s = torch.tensor(data["s"], device=dev)
+    p = torch.tensor(data["p"], device=dev)
+    return X, U, s, p
+
+
+def _vec_err(g, o):
+    g = np.asarray(g, dtype=np.float64).reshape(1, -1)
+    o = np.asarray(o, dtype=np.float64).reshape(1, -1)
+    return block_err(g, o, PHI64)
+
+
+def run_adjoint(model, data, K, C, lam):
+    from paper_2604_09993_amd import api
+    dev = torch.device("cuda:0")
+    cm = api.CisModel(model)
+    X, U, s, p = _dev_inputs(api, data, dev)
+    fw = api.defects(cm, X, U, s, p, K, ckpt_every=C)
+    seed = torch.tensor(np.ascontiguousarray(lam.T), device=dev)
+    g = api.adjoint(cm, X, U, s, p, K, fw["ckpt"], C, seed)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in g.items()}
+
+
+def check(model, data, K, C, lam):
+    g = run_adjoint(model, data, K, C, lam)
+    ref = oracle.adjoint(model, data["X"], data["U"], data["s"], data["p"], K, lam)
+    errs = {"gX": block_err(g["gX"].T, ref["gX"], PHI64),
+            "gU": block_err(g["gU"].T, ref["gU"], PHI64) if model.m else 0.0,
+            "gs": _vec_err(g["gs"], ref["gs"]),
+            "gp": _vec_err(g["gp"], ref["gp"])}
+    assert g["gp"][1] == 0.0
+    assert np.all(g["gX"][:, -1] == 0.0)
+    bad = {k: e for k, e in errs.items() if not e <= TOL64}
+    assert not bad, errs
+    return g
+
+
+CASES = [("free1", 3, 4, 2), ("point1", 3, 4, 4), ("hopper", 4, 6, 3), ("biped5", 3, 4, 1),
+         ("cheetah7", 4, 6, 2), ("quad13", 2, 4, 4)]
+
+
+@pytest.mark.parametrize("name,N,K,C", CASES)
+def test_adjoint_matches_oracle(name, N, K, C):
+    _say(f"[gpu] adjoint {name} N={N} K={K} C={C} seed=200")
+    rng = np.random.default_rng(200)
+    model = synth.MODEL_MAKERS[name](rng)
+    data = synth.gen_nodes(model, N, rng, T=0.02 * N * 5)
+    lam = rng.normal(size=(N, model.nx))
+    check(model, data, K, C, lam)
+
+
+def test_adjoint_long_segment_replay():
+    """ckpt_every = K = 20 > the 8-substep LDS chunk: the segment is replayed in chunks."""
+    _say("[gpu] adjoint hopper N=3 K=20 C=20 (chunked replay)")
+    rng = np.random.default_rng(201)
+    model = synth.make_hopper(rng)
+    data = synth.gen_nodes(model, 3, rng, T=0.3)
+    lam = rng.normal(size=(3, model.nx))
+    check(model, data, 20, 20, lam)
+    check(model, data, 20, 10, lam)
+
+
+def _merit_seed(model, d):
+    """R15 merit J = 1/2 sum ||d_k||^2 + sum_k sum_i (F~_k - X_k)_{n+i}: dJ/dF~_k = d_k + [0; 1]."""
+    lam = d.copy()
+    lam[:, model.n:] += 1.0
+    return lam
+
+
+def test_config3_merit_gradients_via_autograd():
+    """Cheetah N=50, K=20, checkpoints every 5 substeps, merit through torch.autograd."""
+    from paper_2604_09993_amd import api
+    _say("[gpu] config 3: cheetah7 N=50 K=20 C=5 adjoint via autograd")
+    model, data, K = synth.make_config(3)
+    C = synth.CONFIGS[3]["ckpt"]
+    dev = torch.device("cuda:0")
+    cm = api.CisModel(model)
+    X, U, s, p = _dev_inputs(api, data, dev)
+    X.requires_grad_(True)
+    U.requires_grad_(True)
+    s.requires_grad_(True)
+    p.requires_grad_(True)
+    N = data["s"].shape[0]
+    F = api.CisDefects.apply(X, U, s, p, cm, K, C)
+    d = F - X[:, 1:N + 1]
+    J = 0.5 * (d[:model.n] ** 2).sum() + 0.5 * (d[model.n:] ** 2).sum() + \
+        (F[model.n:] - X[model.n:, :N]).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    # reference: oracle reverse sweep with dJ/dF~ = d + [0;1], plus the explicit X terms
+    ref_d = oracle.defects(model, data["X"], data["U"], data["s"], data["p"], K)["d"]
+    lam = _merit_seed(model, ref_d)
+    ref = oracle.adjoint(model, data["X"], data["U"], data["s"], data["p"], K, lam)
+    gX = ref["gX"].copy()
+    gX[1:] -= ref_d                      # d_k = F~_k - X_{k+1}
+    gX[:N, model.n:] -= 1.0              # - X_k in the increment term
+    errs = {"gX": block_err(X.grad.t().cpu().numpy(), gX, PHI64),
+            "gU": block_err(U.grad.t().cpu().numpy(), ref["gU"], PHI64),
+            "gs": _vec_err(s.grad.cpu().numpy(), ref["gs"]),
+            "gp": _vec_err(p.grad.cpu().numpy(), ref["gp"])}
+    assert all(e <= TOL64 for e in errs.values()), errs
+    assert p.grad[1].item() == 0.0
+    # FD of the merit w.r.t. mu and two masses on the GPU defects path (h = 1e-6 relative)
+    def merit(pp):
+        with torch.no_grad():
+            out = api.defects(cm, X.detach(), U.detach(), s.detach(), pp, K)
+            dd = out["d"]
+            inc = out["xprop"][model.n:] - X.detach()[model.n:, :N]
+            return float(0.5 * (dd ** 2).sum() + inc.sum())
+    for c in (0, 2, 5):
+        h = 1e-6 * abs(float(p[c]))
+        pp, pm = p.detach().clone(), p.detach().clone()
+        pp[c] += h
+        pm[c] -= h
+        fd = (merit(pp) - merit(pm)) / (2 * h)
+        g = float(p.grad[c])
+        assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (c, fd, g)
+
+
+def test_adjoint_contraction_of_forward_sensitivities():
+    """gX = A^T lam, gs = S^T lam and gU = B-^T lam_k + B+^T lam_k-1 from the GPU forward kernel."""
+    from paper_2604_09993_amd import api
+    _say("[gpu] adjoint vs forward contraction biped5 N=5 K=4")
+    rng = np.random.default_rng(202)
+    model = synth.make_biped5(rng)
+    data = synth.gen_nodes(model, 5, rng, T=0.5)
+    lam = rng.normal(size=(5, model.nx))
+    g = run_adjoint(model, data, 4, 2, lam)
+    dev = torch.device("cuda:0")
+    cm = api.CisModel(model)
+    X, U, s, p = _dev_inputs(api, data, dev)
+    fw = api.as_interval_major(api.discretize(cm, X, U, s, p, 4))
+    A = fw["A"].cpu().numpy()
+    S = fw["S"].cpu().numpy()
+    Bm = fw["Bm"].cpu().numpy()
+    Bp = fw["Bp"].cpu().numpy()
+    gX = np.einsum("kij,ki->kj", A, lam)
+    gU = np.zeros((6, model.m))
+    gU[:5] += np.einsum("kij,ki->kj", Bm, lam)
+    gU[1:] += np.einsum("kij,ki->kj", Bp, lam)
+    assert block_err(g["gX"].T[:5], gX, PHI64) <= 1e-12 * 100
+    assert block_err(g["gU"].T, gU, PHI64) <= 1e-12 * 100
+    assert _vec_err(g["gs"], np.einsum("ki,ki->k", S, lam)) <= 1e-12 * 100
