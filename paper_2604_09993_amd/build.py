@@ -14,7 +14,7 @@ HEADERS = ["cis_model.hpp", "cis_host.hpp", os.path.join("..", "..", "include", 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
-    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    "-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <type_traits>
+#include <utility>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -19,241 +21,398 @@
 namespace cis {
 
 // ---------------------------------------------------------------------------
-// Tangent stage: one column of Z = [Phi_x | B- | B+ | S] per lane.
-// zb: substep base, za: RK4 accumulator, zs: stage input (x rows only; no row
-// of the right-hand side depends on the integral states y), zy: y rows.
-// wbm / wbp / fsel select the forcing of a B-, B+ or S column.
+// Tangent lanes.  Column c of Z = [Phi_x | B- | B+ | S] is spread over G
+// lanes, one per leg: each lane holds the torso rows (replicated, computed
+// identically in the G lanes) and the rows of its own leg.  The only values a
+// lane needs from the other legs are the angle and rate of their first links
+// (hip stiffness and damping on the torso), read with DPP quad permutes.
 // ---------------------------------------------------------------------------
 template <class T, class TP>
-struct Column {
-    T zb[TP::NX], za[TP::NX], zs[TP::NX], zy[TP::NY];
+struct TLane {
+    T zb[6 * TP::LB], za[6 * TP::LB], zs[6 * TP::LB];   // local rows: q(lb,k), v(lb,k)
+    T ycc, yct;                                          // own contact row, violation partial
 };
 
-template <class T, class TP, class SM>
-__device__ __forceinline__ void tangent_stage(const SM& sm, Column<T, TP>& z, const T* cf,
-                                              int st, T tau, T wbm, T wbp, T fsel, int ctrl) {
-    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX, M = TP::M;
-    using C = Coef<TP>;
-    const T s = sm.s, h = sm.h;
-    T kv[3 * NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        kv[3 * b] = T(0);
-        kv[3 * b + 1] = T(0);
-        kv[3 * b + 2] = cf[C::CTH + b] * z.zs[3 * b + 2];
-    }
-    T kct = T(0);
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int p = TP::parent(j), c = j + 1;
-        const T dth = z.zs[3 * c + 2] - z.zs[3 * p + 2];
-        const T dom = z.zs[NQ + 3 * c + 2] - z.zs[NQ + 3 * p + 2];
-        kv[3 * p + 2] += sm.kc[j][0] * dth + sm.kc[j][1] * dom;
-        kv[3 * c + 2] -= sm.kc[j][2] * dth + sm.kc[j][3] * dom;
-        const T* jh = cf + C::JH + 4 * j;
-        kct += jh[0] * (z.zs[3 * p] - z.zs[3 * c]) + jh[1] * (z.zs[3 * p + 1] - z.zs[3 * c + 1]) +
-               jh[2] * z.zs[3 * p + 2] + jh[3] * z.zs[3 * c + 2];
-    }
-    T kcc[cmax(NC, 1)];
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        const int b = TP::cbody(i);
-        const T* ct = cf + C::CT + C::NCT * i;
-        const T dPx = z.zs[3 * b] - ct[C_AY] * z.zs[3 * b + 2];
-        const T dPy = z.zs[3 * b + 1] + ct[C_AX] * z.zs[3 * b + 2];
-        kv[3 * b] += ct[C_FXP] * dPx;
-        kv[3 * b + 1] += ct[C_FYP] * dPx;
-        kv[3 * b + 2] += ct[C_TP] * dPx;
-        kcc[i] = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * z.zs[NQ + 3 * b] +
-                 ct[C_EYD] * z.zs[NQ + 3 * b + 1] + ct[C_EOM] * z.zs[NQ + 3 * b + 2] +
-                 ct[C_ETH] * z.zs[3 * b + 2];
-        kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
-    }
-    // FOH forcing of B-/B+ columns: s (J_u w(tau) + J_ubar / 2)
-    if constexpr (M > 0) {
-        const T wB = wbm * (T(1) - tau) + wbp * tau;
-        const T wC = wbm + wbp;
-#pragma unroll
-        for (int r = 0; r < 3 * NB; ++r) kv[r] += wB * cf[C::GV + r * M + ctrl];
-#pragma unroll
-        for (int i = 0; i < NC; ++i) kcc[i] += wC * cf[C::GC + i * M + ctrl];
-    }
-    // dilation column forcing: F~ at the stage
-#pragma unroll
-    for (int r = 0; r < 3 * NB; ++r) kv[r] += fsel * cf[C::F + NQ + r];
-#pragma unroll
-    for (int i = 0; i < NC; ++i) kcc[i] += fsel * cf[C::F + NX + i];
-    kct += fsel * cf[C::F + NX + NC];
-    // classical RK4 combination
-    const T wk = (st == 0 || st == 3) ? T(1) : T(2);
-    const T an = (st == 2) ? h : T(0.5) * h;
-    const T h6w = (h / T(6)) * wk;
-#pragma unroll
-    for (int r = 0; r < NQ; ++r) {
-        const T kq = s * z.zs[NQ + r] + fsel * cf[C::F + r];
-        if (st == 0) z.za[r] = kq;
-        else z.za[r] += wk * kq;
-        if (st < 3) z.zs[r] = z.zb[r] + an * kq;
-    }
-#pragma unroll
-    for (int r = 0; r < 3 * NB; ++r) {
-        const T kk = kv[r];
-        if (st == 0) z.za[NQ + r] = kk;
-        else z.za[NQ + r] += wk * kk;
-        if (st < 3) z.zs[NQ + r] = z.zb[NQ + r] + an * kk;
-    }
-#pragma unroll
-    for (int i = 0; i < NC; ++i) z.zy[i] += h6w * kcc[i];
-    z.zy[NC] += h6w * kct;
-    if (st == 3) {
-#pragma unroll
-        for (int r = 0; r < NX; ++r) {
-            z.zb[r] += (h / T(6)) * z.za[r];
-            z.zs[r] = z.zb[r];
-        }
+// value of `v` in lane (lane & ~(G-1)) + SRC of the same quad
+template <int G, int SRC>
+__device__ __forceinline__ int dpp_from(int v) {
+    constexpr int p0 = G == 4 ? SRC : SRC, p1 = p0;
+    constexpr int p2 = G == 4 ? SRC : 2 + SRC, p3 = p2;
+    constexpr int ctrl = p0 | (p1 << 2) | (p2 << 4) | (p3 << 6);
+    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+}
+template <int G, int SRC>
+__device__ __forceinline__ double dpp_from(double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    const int2 r = make_int2(dpp_from<G, SRC>(w.x), dpp_from<G, SRC>(w.y));
+    return __builtin_bit_cast(double, r);
+}
+template <int G, int SRC>
+__device__ __forceinline__ float dpp_from(float v) {
+    return __builtin_bit_cast(float, dpp_from<G, SRC>(__builtin_bit_cast(int, v)));
+}
+// value of the leg-SRC lane of this column (the lane's own value when G == 1)
+template <int G, int SRC, class T>
+__device__ __forceinline__ T from_leg(T v) {
+    if constexpr (G == 1) return v;
+    else return dpp_from<G, SRC>(v);
+}
+// sum of v over the G lanes of a column (same order in every lane)
+template <int G, class T>
+__device__ __forceinline__ T column_sum(T v) {
+    if constexpr (G == 1) {
+        return v;
+    } else if constexpr (G == 2) {
+        return dpp_from<2, 0>(v) + dpp_from<2, 1>(v);
+    } else {
+        return (dpp_from<4, 0>(v) + dpp_from<4, 1>(v)) + (dpp_from<4, 2>(v) + dpp_from<4, 3>(v));
     }
 }
 
+template <class T, class TP, int ST>
+__device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T, TP>& z,
+                                              const T* __restrict__ cf, T tau, int leg, T wbm,
+                                              T wbp, T fsel, T fct, int ctrl) {
+    constexpr int LB = TP::LB, D = TP::D, L = TP::L, G = TP::G, NQ = TP::NQ, NX = TP::NX;
+    constexpr int NC = TP::NC, M = TP::M;
+    using C = Coef<TP>;
+    const T s = iv.s, h = iv.h;
+    // global body of local body lb (0 = torso, 1..D = own leg links)
+    auto gb = [&](int lb) { return lb == 0 ? 0 : 1 + leg * D + lb - 1; };
+#define ZQ(lb, k) z.zs[3 * (lb) + (k)]
+#define ZV(lb, k) z.zs[3 * LB + 3 * (lb) + (k)]
+    T kv[3 * LB];
+#pragma unroll
+    for (int lb = 0; lb < LB; ++lb) {
+        kv[3 * lb] = T(0);
+        kv[3 * lb + 1] = T(0);
+        kv[3 * lb + 2] = cf[C::CTH + gb(lb)] * ZQ(lb, 2);
+    }
+    T kct = T(0), kcc = T(0);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (D >= 1) {
+        // hip joints: torso-side stiffness and damping of every leg
+        const T th1 = ZQ(1, 2), w1 = ZV(1, 2);
+        const T th0 = ZQ(0, 2), w0 = ZV(0, 2);
+        [&]<int... Ls>(std::integer_sequence<int, Ls...>) {
+            ((kv[2] += iv.kc[Ls * D][0] * (from_leg<G, Ls>(th1) - th0) +
+                       iv.kc[Ls * D][1] * (from_leg<G, Ls>(w1) - w0)),
+             ...);
+        }(std::make_integer_sequence<int, L>{});
+#pragma unroll
+        for (int lb = 1; lb <= D; ++lb) {
+            const int j = leg * D + lb - 1;
+            const T dth = ZQ(lb, 2) - ZQ(lb - 1, 2);
+            const T dom = ZV(lb, 2) - ZV(lb - 1, 2);
+            if (lb >= 2) kv[3 * (lb - 1) + 2] += iv.kc[j][0] * dth + iv.kc[j][1] * dom;
+            kv[3 * lb + 2] -= iv.kc[j][2] * dth + iv.kc[j][3] * dom;
+            const T* jh = cf + C::JH + 4 * j;
+            kct += jh[0] * (ZQ(lb - 1, 0) - ZQ(lb, 0)) + jh[1] * (ZQ(lb - 1, 1) - ZQ(lb, 1)) +
+                   jh[2] * ZQ(lb - 1, 2) + jh[3] * ZQ(lb, 2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if constexpr (L >= 1) {
+        constexpr int lb = D;   // the contact sits on the last local body
+        const T* ct = cf + C::CT + C::NCT * leg;
+        const T dPx = ZQ(lb, 0) - ct[C_AY] * ZQ(lb, 2);
+        const T dPy = ZQ(lb, 1) + ct[C_AX] * ZQ(lb, 2);
+        kv[3 * lb] += ct[C_FXP] * dPx;
+        kv[3 * lb + 1] += ct[C_FYP] * dPx;
+        kv[3 * lb + 2] += ct[C_TP] * dPx;
+        kcc = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * ZV(lb, 0) + ct[C_EYD] * ZV(lb, 1) +
+              ct[C_EOM] * ZV(lb, 2) + ct[C_ETH] * ZQ(lb, 2);
+        kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // FOH forcing of B-/B+ columns: s (J_u w(tau) + J_ubar / 2); only waves
+    // holding such columns take the branch
+    if constexpr (M > 0) {
+        if (wbm + wbp != T(0)) {
+            const T wB = wbm * (T(1) - tau) + wbp * tau;
+#pragma unroll
+            for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    kv[3 * lb + k] += wB * cf[C::GV + (3 * gb(lb) + k) * M + ctrl];
+            if constexpr (L >= 1) kcc += cf[C::GC + leg * M + ctrl];
+        }
+    }
+    // dilation column forcing: F~ at the stage (q rows below)
+    if (fsel != T(0)) {
+#pragma unroll
+        for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) kv[3 * lb + k] += cf[C::F + NQ + 3 * gb(lb) + k];
+        if constexpr (L >= 1) kcc += cf[C::F + NX + leg];
+        kct += fct * cf[C::F + NX + NC];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // classical RK4 combination (stage ST known at compile time)
+    constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
+    const T an = (ST == 2) ? h : T(0.5) * h;
+#pragma unroll
+    for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int r = 3 * lb + k;
+            T kq = s * z.zs[3 * LB + r];
+            if (fsel != T(0)) kq += cf[C::F + 3 * gb(lb) + k];
+            if (ST == 0) z.za[r] = kq;
+            else z.za[r] += T(WK) * kq;
+            if (ST < 3) z.zs[r] = z.zb[r] + an * kq;
+        }
+#pragma unroll
+    for (int r = 0; r < 3 * LB; ++r) {
+        const T kk = kv[r];
+        if (ST == 0) z.za[3 * LB + r] = kk;
+        else z.za[3 * LB + r] += T(WK) * kk;
+        if (ST < 3) z.zs[3 * LB + r] = z.zb[3 * LB + r] + an * kk;
+    }
+    const T h6 = iv.h6;
+    z.ycc += (h6 * T(WK)) * kcc;
+    z.yct += (h6 * T(WK)) * kct;
+    if (ST == 3) {
+#pragma unroll
+        for (int r = 0; r < 6 * LB; ++r) {
+            z.zb[r] += h6 * z.za[r];
+            z.zs[r] = z.zb[r];
+        }
+    }
+#undef ZQ
+#undef ZV
+}
+
 // ---------------------------------------------------------------------------
-// K2: discretize.  Workgroup = NCW tangent waves + 1 nominal wave.  The
-// nominal wave runs one stage ahead and fills the coefficient buffer of the
-// next stage while the tangent waves consume the current one; one workgroup
-// barrier per stage.
+// K2: discretize.  One workgroup per interval, three wave roles separated by
+// one workgroup barrier per RK stage, each role one stage behind the previous:
+//   state wave      : evaluates the accelerations at stage t and forms the
+//                     input of stage t+1 (the only serial chain);
+//   coefficient wave: full right-hand side and Jacobian nonzeros at stage t-1
+//                     (rotations reused from the state wave), integral rows;
+//   tangent waves   : apply stage t-2 to their columns.
 // ---------------------------------------------------------------------------
+template <class T, class TP>
+struct DiscShared {
+    Interval<T, TP> iv;
+    RhsScratch<T, TP> scS, scC;
+    T xring[4][TP::NX];        // stage inputs from the state wave
+    T csring[4][TP::NB][2];    // their rotations
+    T coef[2][Coef<TP>::SIZE];
+};
+
 template <class T, class TP>
 __global__ void __launch_bounds__(TP::NTHREADS)
     k_discretize(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
-    constexpr int NB = TP::NB, NJ = TP::NJ, NX = TP::NX, NXT = TP::NXT, M = TP::M;
-    constexpr int NY = TP::NY;
+    constexpr int NB = TP::NB, NX = TP::NX, NXT = TP::NXT, M = TP::M, NY = TP::NY;
+    constexpr int NQ = TP::NQ, NC = TP::NC, LB = TP::LB, G = TP::G, D = TP::D, L = TP::L;
     using C = Coef<TP>;
-    __shared__ Shared<T, TP, 2> sm;
+    static_assert(D > 0 || L <= 1, "several contacts on the torso are not laid out");
+    __shared__ DiscShared<T, TP> sh;
     const int k = blockIdx.x;
+    const int grp = blockIdx.y;   // column group of this workgroup
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nth = TP::NTHREADS;
-    load_interval<T, TP>(sm, a, mc, k, tid, nth);
-    // zero both coefficient buffers, then the constant FOH forcing entries
-    for (int e = tid; e < 2 * C::SIZE; e += nth) (&sm.coef[0][0])[e] = T(0);
+    constexpr int nth = TP::NTHREADS;
+    load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
+    for (int e = tid; e < 2 * C::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
     __syncthreads();
-    const T s = sm.s;
-    for (int j = tid; j < NJ; j += nth) {
-        const int p = TP::parent(j), c = j + 1;
-        sm.kc[j][0] = s * T(mc.ks[j]) * sm.iinv[p];
-        sm.kc[j][1] = s * T(mc.ds[j]) * sm.iinv[p];
-        sm.kc[j][2] = s * T(mc.ks[j]) * sm.iinv[c];
-        sm.kc[j][3] = s * T(mc.ds[j]) * sm.iinv[c];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            T* gv = sm.coef[q] + C::GV;
-            gv[(3 * p) * M + NJ + 2 * j] = s * sm.minv[p];
-            gv[(3 * p + 1) * M + NJ + 2 * j + 1] = s * sm.minv[p];
-            gv[(3 * c) * M + NJ + 2 * j] = -s * sm.minv[c];
-            gv[(3 * c + 1) * M + NJ + 2 * j + 1] = -s * sm.minv[c];
-            gv[(3 * p + 2) * M + j] = -s * sm.iinv[p];
-            gv[(3 * c + 2) * M + j] = s * sm.iinv[c];
-        }
-    }
+    coef_constants<T, TP>(sh.iv, sh.coef[0], tid, nth);
+    coef_constants<T, TP>(sh.iv, sh.coef[1], tid, nth);
+    const int nst = 4 * a.K;
+    const int nsteps = nst + 2;
+    const int64_t ldi = a.ldi;
     __syncthreads();
 
-    const bool nominal = wave == TP::NCW;
-    const int nst = 4 * a.K;
-    RowState<T> rs;
-    Column<T, TP> z;
-    const int col = wave * 64 + lane;
-    T wbm = T(0), wbp = T(0), fsel = T(0);
-    int ctrl = 0;
-    if (nominal) {
+    // Each role runs its own loop with the same number of workgroup barriers
+    // (nsteps), so the registers of one role are not live in the others.
+    if (wave == TP::NTW) {
+        // ---------------- state wave: stage t at step t ----------------
+        RowState<T> rs;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int r = lane + 64 * q;
-            rs.xb[q] = r < NXT ? sm.ns[r] : T(0);
             rs.xa[q] = T(0);
+            rs.xb[q] = r < NX ? sh.iv.x0[r] : T(0);
+            if (r < NX) sh.scS.ns[r] = rs.xb[q];
         }
-        nominal_rhs<T, TP, true>(sm, mc, lane, T(0), sm.coef[0]);
-        nominal_update<T, TP, true>(sm, rs, lane, 0, sm.coef[0]);
+        wave_lds_sync();
+        for (int t = 0; t < nsteps; ++t) {
+            if (t < nst) {
+                const int st = t & 3;
+                const T tau = (T(t >> 2) + T(stage_c(st))) / T(a.K);
+                rhs_eval<T, TP, LEAN>(sh.iv, sh.scS, mc, lane, tau, (T*)nullptr);
+                if (lane < NB) {
+                    sh.csring[t & 3][lane][0] = sh.scS.cs[lane][0];
+                    sh.csring[t & 3][lane][1] = sh.scS.cs[lane][1];
+                }
+                rk_rows<T, TP, NX>(sh.iv, sh.scS, rs, lane, st, sh.scS.ns, sh.xring[(t + 1) & 3]);
+            }
+            __syncthreads();
+        }
+        if (grp == 0) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int r = lane + 64 * q;
+                if (r < NX) {
+                    if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
+                    a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
+                }
+            }
+        }
+    } else if (wave == TP::NTW + 1) {
+        // -------- coefficient wave: stage t-1 at step t; integral rows --------
+        RowState<T> rs;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = lane + 64 * q;
+            rs.xa[q] = T(0);
+            rs.xb[q] = (r >= NX && r < NXT) ? sh.iv.x0[r] : T(0);
+        }
+        for (int t = 0; t < nsteps; ++t) {
+            const int tc = t - 1;
+            if (tc >= 0 && tc < nst) {
+                const int st = tc & 3;
+                const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
+                T* cf = sh.coef[tc & 1];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int r = lane + 64 * q;
+                    if (r < NX) sh.scC.ns[r] = tc == 0 ? sh.iv.x0[r] : sh.xring[tc & 3][r];
+                }
+                if (lane < NB) {
+                    sh.scC.cs[lane][0] = sh.csring[tc & 3][lane][0];
+                    sh.scC.cs[lane][1] = sh.csring[tc & 3][lane][1];
+                }
+                wave_lds_sync();
+                rhs_eval<T, TP, EMIT, true>(sh.iv, sh.scC, mc, lane, tau, cf);
+                // F~ for the dilation column, and the integral rows of the nominal state
+                const T s = sh.iv.s, h = sh.iv.h;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int r = lane + 64 * q;
+                    if (r < NXT) {
+                        const T F = r < NQ ? sh.scC.ns[NQ + r] : sh.scC.fn[r];
+                        cf[C::F + r] = F;
+                        if (r >= NX) {
+                            const T kk = s * F;
+                            if (st == 0) rs.xa[q] = kk;
+                            else if (st == 3) rs.xa[q] += kk;
+                            else rs.xa[q] += T(2) * kk;
+                            if (st == 3) rs.xb[q] += sh.iv.h6 * rs.xa[q];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (grp == 0) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int r = lane + 64 * q;
+                if (r >= NX && r < NXT) {
+                    if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
+                    a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
+                }
+            }
+            // A[:, n:] = [0; I]: the integral states feed back into nothing
+            for (int e = lane; e < NXT * NY; e += 64) {
+                const int r = e / NY, c = NX + e % NY;
+                a.A[((int64_t)r * NXT + c) * ldi + k] = (r == c) ? T(1) : T(0);
+            }
+        }
     } else {
+        // ---------------- tangent waves: stage t-2 at step t ----------------
+        const int col = grp * TP::CPG + (wave * 64 + lane) / G;
+        const int leg = G == 1 ? 0 : (lane & (G - 1));
+        T wbm = T(0), wbp = T(0), fsel = T(0);
+        int ctrl = 0;
         if (col >= NX && col < NX + M) { wbm = T(1); ctrl = col - NX; }
         else if (col >= NX + M && col < NX + 2 * M) { wbp = T(1); ctrl = col - NX - M; }
         else if (col == NX + 2 * M) fsel = T(1);
+        const T fct = leg == 0 ? fsel : T(0);
+        auto gbody = [&](int lb) { return lb == 0 ? 0 : 1 + leg * D + lb - 1; };
+        TLane<T, TP> z;
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
-            z.zb[r] = (r == col) ? T(1) : T(0);
+        for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                const int gq = 3 * gbody(lb) + kk;
+                z.zb[3 * lb + kk] = (gq == col) ? T(1) : T(0);
+                z.zb[3 * LB + 3 * lb + kk] = (NQ + gq == col) ? T(1) : T(0);
+            }
+#pragma unroll
+        for (int r = 0; r < 6 * LB; ++r) {
             z.zs[r] = z.zb[r];
             z.za[r] = T(0);
         }
-#pragma unroll
-        for (int i = 0; i < NY; ++i) z.zy[i] = T(0);
-    }
-    __syncthreads();
-    for (int t = 0; t < nst; ++t) {
-        if (nominal) {
-            const int t1 = t + 1;
-            if (t1 < nst) {
-                const int st = t1 & 3;
-                const T tau = (T(t1 >> 2) + T(stage_c(st))) / T(a.K);
-                nominal_rhs<T, TP, true>(sm, mc, lane, tau, sm.coef[t1 & 1]);
-                nominal_update<T, TP, true>(sm, rs, lane, st, sm.coef[t1 & 1]);
-            }
-        } else {
-            const int st = t & 3;
-            const T tau = (T(t >> 2) + T(stage_c(st))) / T(a.K);
-            tangent_stage<T, TP>(sm, z, sm.coef[t & 1], st, tau, wbm, wbp, fsel, ctrl);
-        }
+        z.ycc = T(0);
+        z.yct = T(0);
+        __syncthreads();   // steps 0 and 1: nothing to apply yet
         __syncthreads();
-    }
-    // outputs
-    const int64_t ldi = a.ldi;
-    if (nominal) {
+        // steps 2 .. nst+1 apply stages 0 .. nst-1, unrolled by the 4 RK stages
+        const T Kt = T(a.K);
+        for (int j = 0; j < a.K; ++j) {
+            const T jt = T(j);
+            const T tau0 = jt / Kt, tauh = (jt + T(0.5)) / Kt, tau1 = (jt + T(1)) / Kt;
+            tangent_stage<T, TP, 0>(sh.iv, z, sh.coef[0], tau0, leg, wbm, wbp, fsel, fct, ctrl);
+            __syncthreads();
+            tangent_stage<T, TP, 1>(sh.iv, z, sh.coef[1], tauh, leg, wbm, wbp, fsel, fct, ctrl);
+            __syncthreads();
+            tangent_stage<T, TP, 2>(sh.iv, z, sh.coef[0], tauh, leg, wbm, wbp, fsel, fct, ctrl);
+            __syncthreads();
+            tangent_stage<T, TP, 3>(sh.iv, z, sh.coef[1], tau1, leg, wbm, wbp, fsel, fct, ctrl);
+            __syncthreads();
+        }
+        const T yct = column_sum<G>(z.yct);
+        if (col < TP::NCOL) {
+            T* out;
+            int64_t cstride, c0;   // element (row, column) at out[(row * cstride + c0) * ldi + k]
+            if (col < NX) { out = a.A; cstride = NXT; c0 = col; }
+            else if (col < NX + M) { out = a.Bm; cstride = M; c0 = col - NX; }
+            else if (col < NX + 2 * M) { out = a.Bp; cstride = M; c0 = col - NX - M; }
+            else { out = a.S; cstride = 1; c0 = 0; }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int r = lane + 64 * q;
-            if (r < NXT) {
-                if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
-                a.defect[r * ldi + k] = rs.xb[q] - sm.xk1[r];
+            for (int lb = 0; lb < LB; ++lb) {
+                if (lb == 0 && leg != 0) continue;
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    const int gq = 3 * gbody(lb) + kk;
+                    out[((int64_t)gq * cstride + c0) * ldi + k] = z.zb[3 * lb + kk];
+                    out[((int64_t)(NQ + gq) * cstride + c0) * ldi + k] = z.zb[3 * LB + 3 * lb + kk];
+                }
             }
+            if constexpr (L >= 1) out[((int64_t)(NX + leg) * cstride + c0) * ldi + k] = z.ycc;
+            if (leg == 0) out[((int64_t)(NX + NC) * cstride + c0) * ldi + k] = yct;
         }
-        // A[:, n:] = [0; I]: the integral states feed back into nothing
-        for (int e = lane; e < NXT * NY; e += 64) {
-            const int r = e / NY, c = NX + e % NY;
-            a.A[((int64_t)r * NXT + c) * ldi + k] = (r == c) ? T(1) : T(0);
-        }
-    } else if (col < NX) {
-#pragma unroll
-        for (int r = 0; r < NX; ++r) a.A[((int64_t)r * NXT + col) * ldi + k] = z.zb[r];
-#pragma unroll
-        for (int i = 0; i < NY; ++i) a.A[((int64_t)(NX + i) * NXT + col) * ldi + k] = z.zy[i];
-    } else if (col < NX + 2 * M) {
-        T* B = col < NX + M ? a.Bm : a.Bp;
-        const int c = col < NX + M ? col - NX : col - NX - M;
-#pragma unroll
-        for (int r = 0; r < NX; ++r) B[((int64_t)r * M + c) * ldi + k] = z.zb[r];
-#pragma unroll
-        for (int i = 0; i < NY; ++i) B[((int64_t)(NX + i) * M + c) * ldi + k] = z.zy[i];
-    } else if (col == NX + 2 * M) {
-#pragma unroll
-        for (int r = 0; r < NX; ++r) a.S[(int64_t)r * ldi + k] = z.zb[r];
-#pragma unroll
-        for (int i = 0; i < NY; ++i) a.S[(int64_t)(NX + i) * ldi + k] = z.zy[i];
     }
 }
 
 // ---------------------------------------------------------------------------
-// K1: defects and checkpoints.  One wave per interval (the nominal wave alone).
+// K1: defects and checkpoints.  One wave per interval.
 // ---------------------------------------------------------------------------
+template <class T, class TP>
+struct DefShared {
+    Interval<T, TP> iv;
+    RhsScratch<T, TP> sc;
+};
+
 template <class T, class TP>
 __global__ void __launch_bounds__(64)
     k_defects(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     constexpr int NX = TP::NX, NXT = TP::NXT;
-    __shared__ Shared<T, TP, 0> sm;
+    __shared__ DefShared<T, TP> sh;
     const int k = blockIdx.x;
     const int lane = threadIdx.x;
-    load_interval<T, TP>(sm, a, mc, k, lane, 64);
+    load_interval<T, TP>(sh.iv, a, mc, k, lane, 64);
     RowState<T> rs;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int r = lane + 64 * q;
-        rs.xb[q] = r < NXT ? sm.ns[r] : T(0);
+        rs.xb[q] = r < NXT ? sh.iv.x0[r] : T(0);
         rs.xa[q] = T(0);
+        if (r < NXT) sh.sc.ns[r] = rs.xb[q];
     }
+    wave_lds_sync();
     const int64_t ldi = a.ldi;
     for (int j = 0; j < a.K; ++j) {
         if (a.ckpt && (j % a.C) == 0) {
@@ -266,8 +425,8 @@ __global__ void __launch_bounds__(64)
         }
         for (int st = 0; st < 4; ++st) {
             const T tau = (T(j) + T(stage_c(st))) / T(a.K);
-            nominal_rhs<T, TP, false>(sm, mc, lane, tau, (T*)nullptr);
-            nominal_update<T, TP, false>(sm, rs, lane, st, (T*)nullptr);
+            rhs_eval<T, TP, FULL>(sh.iv, sh.sc, mc, lane, tau, (T*)nullptr);
+            rk_rows<T, TP, NXT>(sh.iv, sh.sc, rs, lane, st, sh.sc.ns, (T*)nullptr);
         }
     }
 #pragma unroll
@@ -275,7 +434,7 @@ __global__ void __launch_bounds__(64)
         const int r = lane + 64 * q;
         if (r < NXT) {
             if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
-            a.defect[r * ldi + k] = rs.xb[q] - sm.xk1[r];
+            a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
         }
     }
 }
@@ -305,7 +464,8 @@ static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, con
                                     const void* U, const void* s, const void* prm, void* A,
                                     void* Bm, void* Bp, void* S, void* d, void* xp,
                                     hipStream_t stream) {
-    using TP = Topo<L, D>;
+    // FP64 columns need about twice the registers of FP32 ones
+    using TP = Topo<L, D, sizeof(T) == 8 ? 2 : 6>;
     auto mc = make_const<TP::NB, TP::NJ, TP::NC>(m);
     FwdArgs<T> a = make_args<T>(sh, X, U, s, prm);
     a.A = (T*)A;
@@ -315,7 +475,7 @@ static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, con
     a.defect = (T*)d;
     a.xprop = (T*)xp;
     void* args[] = {&a, &mc};
-    hipError_t e = hipLaunchKernel((const void*)&k_discretize<T, TP>, dim3(sh->N),
+    hipError_t e = hipLaunchKernel((const void*)&k_discretize<T, TP>, dim3(sh->N, TP::NGRP),
                                    dim3(TP::NTHREADS), args, 0, stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_discretize launch: %s", hipGetErrorString(e));
     return CIS_OK;

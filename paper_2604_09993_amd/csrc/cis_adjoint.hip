@@ -28,6 +28,9 @@ constexpr int CHUNK = 8;   // substeps whose stage inputs are kept in LDS at onc
 
 template <class T, class TP>
 struct AdjShared {
+    Interval<T, TP> iv;
+    RhsScratch<T, TP> sc;
+    T coef[Coef<TP>::SIZE];
     T hist[CHUNK * 4][TP::NX];          // stage inputs (x part) of the chunk
     T kb[TP::NXT];                      // kbar of the current stage
     T xbs[TP::NX];                      // Xbar of the current stage
@@ -47,10 +50,10 @@ struct AdjArgs {
     T* ws_p;     // [P][N] parameter adjoint from interval k
 };
 
-// Reverse one RK4 stage at the stage input held in sm.ns (coefficients are
+// Reverse one RK4 stage at the stage input held in ax.sc.ns (coefficients are
 // recomputed there).  Lanes own rows r = lane, lane + 64.
-template <class T, class TP, class SM>
-__device__ __forceinline__ void reverse_stage(SM& sm, AdjShared<T, TP>& ax,
+template <class T, class TP>
+__device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
                                               const MConst<TP::NB, TP::NJ, TP::NC>& mc, int lane,
                                               int st, T tau, T (&xbar)[2], T (&xprev)[2],
                                               T (&xsum)[2], T& sacc, T (&uacc)[3][2], T& muacc,
@@ -58,25 +61,26 @@ __device__ __forceinline__ void reverse_stage(SM& sm, AdjShared<T, TP>& ax,
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX;
     constexpr int NXT = TP::NXT, M = TP::M;
     using C = Coef<TP>;
-    T* cf = sm.coef[0];
-    const T s = sm.s, h = sm.h;
+    T* cf = ax.coef;
+    const Interval<T, TP>& iv = ax.iv;
+    const T s = iv.s, h = iv.h;
     // kbar_st = h/6 w_st xbar + h a_{st+1} Xbar_{st+1}
     const T w = (st == 0 || st == 3) ? T(1) : T(2);
     const T anext = st == 2 ? h : T(0.5) * h;   // multiplier of k_st in stage st+1's input
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int r = lane + 64 * q;
-        if (r < NXT) ax.kb[r] = (h / T(6)) * w * xbar[q] + (st < 3 ? anext * xprev[q] : T(0));
+        if (r < NXT) ax.kb[r] = iv.h6 * w * xbar[q] + (st < 3 ? anext * xprev[q] : T(0));
     }
-    nominal_rhs<T, TP, true>(sm, mc, lane, tau, cf);   // ends with a wave sync
+    rhs_eval<T, TP, EMIT>(iv, ax.sc, mc, lane, tau, cf);   // ends with a wave sync
     const T omt = T(1) - tau;
     const T lc = ax.kb[NX + NC];
     // phase A: element lanes scatter into their slots; control adjoints
     if (lane < NJ) {
         const int j = lane, p = TP::parent(j), c = j + 1;
         const T gp = ax.kb[NQ + 3 * p + 2], gc = ax.kb[NQ + 3 * c + 2];
-        const T t1 = sm.kc[j][0] * gp - sm.kc[j][2] * gc;
-        const T t2 = sm.kc[j][1] * gp - sm.kc[j][3] * gc;
+        const T t1 = iv.kc[j][0] * gp - iv.kc[j][2] * gc;
+        const T t2 = iv.kc[j][1] * gp - iv.kc[j][3] * gc;
         const T* jh = cf + C::JH + 4 * j;
         ax.jslot[j][0] = -t1 + jh[2] * lc;
         ax.jslot[j][1] = t1 + jh[3] * lc;
@@ -170,10 +174,10 @@ __device__ __forceinline__ void reverse_stage(SM& sm, AdjShared<T, TP>& ax,
         ax.xbs[NQ + 3 * b + 1] = s * ax.kb[3 * b + 1] + yd;
         ax.xbs[NQ + 3 * b + 2] = s * ax.kb[3 * b + 2] + om;
         // d(s v')/d m_b = -(s/m_b) (v'_x, v'_y + g, w')
-        macc -= s * sm.minv[b] *
-                (sm.fn[NQ + 3 * b] * ax.kb[NQ + 3 * b] +
-                 (sm.fn[NQ + 3 * b + 1] + T(mc.g)) * ax.kb[NQ + 3 * b + 1] +
-                 sm.fn[NQ + 3 * b + 2] * ax.kb[NQ + 3 * b + 2]);
+        macc -= s * iv.minv[b] *
+                (ax.sc.fn[NQ + 3 * b] * ax.kb[NQ + 3 * b] +
+                 (ax.sc.fn[NQ + 3 * b + 1] + T(mc.g)) * ax.kb[NQ + 3 * b + 1] +
+                 ax.sc.fn[NQ + 3 * b + 2] * ax.kb[NQ + 3 * b + 2]);
     }
     wave_lds_sync();
     // rows: collect Xbar_i, dilation adjoint F~ . kbar
@@ -188,7 +192,7 @@ __device__ __forceinline__ void reverse_stage(SM& sm, AdjShared<T, TP>& ax,
             xprev[q] = T(0);
         }
         if (r < NXT) {
-            const T F = r < NQ ? sm.ns[NQ + r] : sm.fn[r];
+            const T F = r < NQ ? ax.sc.ns[NQ + r] : ax.sc.fn[r];
             sacc += F * ax.kb[r];
         }
     }
@@ -199,34 +203,15 @@ template <class T, class TP>
 __global__ void __launch_bounds__(64)
     k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NX = TP::NX, NXT = TP::NXT;
-    constexpr int M = TP::M;
-    __shared__ Shared<T, TP, 1> sm;
     __shared__ AdjShared<T, TP> ax;
     const int k = blockIdx.x;
     const int lane = threadIdx.x;
     const FwdArgs<T>& f = a.f;
-    load_interval<T, TP>(sm, f, mc, k, lane, 64);
-    const T s = sm.s;
-    for (int j = lane; j < NJ; j += 64) {
-        const int p = TP::parent(j), c = j + 1;
-        sm.kc[j][0] = s * T(mc.ks[j]) * sm.iinv[p];
-        sm.kc[j][1] = s * T(mc.ds[j]) * sm.iinv[p];
-        sm.kc[j][2] = s * T(mc.ks[j]) * sm.iinv[c];
-        sm.kc[j][3] = s * T(mc.ds[j]) * sm.iinv[c];
-    }
+    load_interval<T, TP>(ax.iv, f, mc, k, lane, 64);
     // constant FOH forcing entries of the coefficient buffer (zero elsewhere)
-    for (int e = lane; e < Coef<TP>::SIZE; e += 64) sm.coef[0][e] = T(0);
+    for (int e = lane; e < Coef<TP>::SIZE; e += 64) ax.coef[e] = T(0);
     wave_lds_sync();
-    for (int j = lane; j < NJ; j += 64) {
-        const int p = TP::parent(j), c = j + 1;
-        T* gv = sm.coef[0] + Coef<TP>::GV;
-        gv[(3 * p) * M + NJ + 2 * j] = s * sm.minv[p];
-        gv[(3 * p + 1) * M + NJ + 2 * j + 1] = s * sm.minv[p];
-        gv[(3 * c) * M + NJ + 2 * j] = -s * sm.minv[c];
-        gv[(3 * c + 1) * M + NJ + 2 * j + 1] = -s * sm.minv[c];
-        gv[(3 * p + 2) * M + j] = -s * sm.iinv[p];
-        gv[(3 * c + 2) * M + j] = s * sm.iinv[c];
-    }
+    coef_constants<T, TP>(ax.iv, ax.coef, lane, 64);
     wave_lds_sync();
 
     const int64_t ldi = f.ldi;
@@ -253,7 +238,7 @@ __global__ void __launch_bounds__(64)
                 const int r = lane + 64 * q;
                 rs.xb[q] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
                 rs.xa[q] = T(0);
-                if (r < NXT) sm.ns[r] = rs.xb[q];
+                if (r < NXT) ax.sc.ns[r] = rs.xb[q];
             }
             wave_lds_sync();
             for (int jj = 0; jj < c0 + len; ++jj) {
@@ -263,12 +248,12 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
                         for (int q = 0; q < 2; ++q) {
                             const int r = lane + 64 * q;
-                            if (r < NX) ax.hist[(jj - c0) * 4 + st][r] = sm.ns[r];
+                            if (r < NX) ax.hist[(jj - c0) * 4 + st][r] = ax.sc.ns[r];
                         }
                     }
                     const T tau = (T(j) + T(stage_c(st))) / T(K);
-                    nominal_rhs<T, TP, false>(sm, mc, lane, tau, (T*)nullptr);
-                    nominal_update<T, TP, false>(sm, rs, lane, st, (T*)nullptr);
+                    rhs_eval<T, TP, LEAN>(ax.iv, ax.sc, mc, lane, tau, (T*)nullptr);
+                    rk_rows<T, TP, NX>(ax.iv, ax.sc, rs, lane, st, ax.sc.ns, (T*)nullptr);
                 }
             }
             wave_lds_sync();
@@ -279,12 +264,12 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         const int r = lane + 64 * q;
-                        if (r < NX) sm.ns[r] = ax.hist[jj * 4 + st][r];
+                        if (r < NX) ax.sc.ns[r] = ax.hist[jj * 4 + st][r];
                     }
                     wave_lds_sync();
                     const T tau = (T(j) + T(stage_c(st))) / T(K);
-                    reverse_stage<T, TP>(sm, ax, mc, lane, st, tau, xbar, xprev, xsum, sacc,
-                                         uacc, muacc, macc);
+                    reverse_stage<T, TP>(ax, mc, lane, st, tau, xbar, xprev, xsum, sacc, uacc,
+                                         muacc, macc);
                 }
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {

@@ -7,17 +7,14 @@
 // kernel argument segment; masses and the friction coefficient are run-time
 // device inputs (they are differentiated).
 //
-// The per-stage work is split in two roles inside one workgroup:
-//  * the nominal wave evaluates the right-hand side of the time-dilated
-//    augmented system (Sec. IV-B) element-parallel: one lane per body for the
-//    rotations, one lane per joint or contact for forces, violation and
-//    cross-complementarity integrands, one lane per body for the Newton-Euler
-//    sums, one lane per state row for the RK4 update.  It also writes the
-//    nonzeros of the Jacobians at the stage state into an LDS coefficient
-//    buffer;
-//  * the tangent waves hold one column of [Phi | B- | B+ | S] per lane in
-//    registers and apply the sparse Jacobian (a hand-written forward-mode
-//    product, coefficients broadcast from LDS) plus the FOH forcing.
+// Right-hand side of the time-dilated augmented system (Sec. IV-B) in three
+// element-parallel steps executed by one wave: one lane per body for the
+// rotations, one lane per joint or contact for forces and integrands, one
+// lane per body for the Newton-Euler sums.  Three depths:
+//   LEAN : accelerations only (what the state recursion needs),
+//   FULL : + cross-complementarity and violation integrands,
+//   EMIT : + every nonzero of dF~/dx, dF~/du, dF~/dubar at the stage, written
+//          into a coefficient buffer read by the tangent lanes.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,21 +27,30 @@ namespace cis {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int even(int a) { return (a + 1) & ~1; }
 
-template <int L_, int D_>
+template <int L_, int D_, int TW_MAX_ = 6>
 struct Topo {
     static constexpr int L = L_, D = D_;
     static constexpr int NB = 1 + L * D, NJ = L * D, NC = L;
     static constexpr int NQ = 3 * NB, NX = 6 * NB, NY = NC + 1, NXT = NX + NY;
     static constexpr int M = 3 * NJ + 3 * NC, P = NB + 2;
-    static constexpr int NCOL = NX + 2 * M + 1;           // tangent columns
-    static constexpr int NCW = (NCOL + 63) / 64;          // tangent waves
-    static constexpr int NTHREADS = 64 * (NCW + 1);       // + one nominal wave
-    static_assert(NXT <= 128, "the nominal wave owns at most two state rows per lane");
+    static constexpr int NCOL = NX + 2 * M + 1;   // tangent columns [Phi_x | B- | B+ | S]
+    static constexpr int G = L > 1 ? L : 1;       // lanes per tangent column (one per leg)
+    static constexpr int LB = D + 1;              // bodies held by one tangent lane
+    static constexpr int NTW_ALL = (NCOL * G + 63) / 64;   // tangent waves per interval
+    // columns are split over NGRP workgroups of at most TW_MAX_ tangent waves
+    // (TW_MAX_ = 6: two waves per SIMD, 256 VGPRs each; TW_MAX_ = 2: one wave
+    // per SIMD and 512 registers, for the FP64 columns)
+    static constexpr int NGRP = (NTW_ALL + TW_MAX_ - 1) / TW_MAX_;
+    static constexpr int NTW = (NTW_ALL + NGRP - 1) / NGRP;  // tangent waves per workgroup
+    static constexpr int CPG = NTW * 64 / G;                  // columns per workgroup
+    static constexpr int NTHREADS = 64 * (NTW + 2);           // + state wave + coefficient wave
+    static_assert(NXT <= 128, "state rows are owned two per lane");
     static_assert(NB < 64 && NJ + NC <= 64, "one lane per body / element");
+    static_assert(G == 1 || G == 2 || G == 4, "legs must map onto a DPP quad");
+    static_assert(NTHREADS <= 512, "at most 8 waves per workgroup");
     __host__ __device__ static constexpr int parent(int j) {
         return D == 0 ? 0 : ((j % D == 0) ? 0 : j);
     }
-    __host__ __device__ static constexpr int child(int j) { return j + 1; }
     __host__ __device__ static constexpr int cbody(int i) { return D * (i + 1); }
 };
 
@@ -63,42 +69,44 @@ struct MConst {
 // Layout of one per-stage coefficient buffer (LDS), in elements.
 template <class TP>
 struct Coef {
-    static constexpr int CTH = 0;                         // [NB] s dT_b/dth_b / I_b
-    static constexpr int JH = even(TP::NB);               // [NJ][4] violation row, joints
-    static constexpr int CT = JH + 4 * TP::NJ;            // [NC][14] contact terms
-    static constexpr int NCT = 14;
-    static constexpr int GV = CT + NCT * TP::NC;          // [3NB][M] s dv'/du
-    static constexpr int GC = GV + 3 * TP::NB * TP::M;    // [NC][M] (s/2) dOmega_cc/dubar
-    static constexpr int F = GC + TP::NC * TP::M;         // [NXT] F~ (unscaled)
+    static constexpr int NCT = 14;                     // per-contact terms
+    static constexpr int CTH = 0;                      // [NB] s dT_b/dth_b / I_b
+    static constexpr int JH = even(TP::NB);            // [NJ][4] violation row, joints
+    static constexpr int CT = JH + 4 * TP::NJ;         // [NC][NCT] contact terms
+    static constexpr int GV = CT + NCT * TP::NC;       // [3NB][M] s dv'/du
+    static constexpr int GC = GV + 3 * TP::NB * TP::M; // [NC][M] (s/2) dOmega_cc/dubar
+    static constexpr int F = GC + TP::NC * TP::M;      // [NXT] F~ (unscaled)
     static constexpr int SIZE = even(F + TP::NXT);
 };
-// per-contact slots inside Coef::CT
-// (C_JMU = s lbar_n |v_t|_s is d(s Omega_cc)/d mu, used by the reverse sweep)
+// per-contact slots (C_JMU = s lbar_n |v_t|_s = d(s Omega_cc)/d mu)
 enum { C_AX = 0, C_AY, C_FXP, C_FYP, C_TP, C_EPX, C_EPY, C_EXD, C_EYD, C_EOM, C_ETH, C_ZPX, C_ZPY,
        C_JMU };
 
-template <class T, class TP, int NBUF = 2>
-struct Shared {
-    using value_type = T;
-    // stage coefficient buffers (double-buffered in the discretize kernel,
-    // one in the reverse sweep, none in the defects-only kernel)
-    T coef[NBUF > 0 ? NBUF : 1][NBUF > 0 ? Coef<TP>::SIZE : 2];
+// Per-interval data shared by every role.
+template <class T, class TP>
+struct Interval {
     T kc[cmax(TP::NJ, 1)][4];                  // s k/I_p, s d/I_p, s k/I_c, s d/I_c
-    T ns[TP::NXT];                             // nominal stage input
-    T fn[TP::NXT];                             // F~ at the stage
-    T cs[TP::NB][2];                           // cos, sin of body angles
-    T slot[cmax(2 * TP::NJ + TP::NC, 1)][4];   // (Fx, Fy, T, dT/dth) per element end
-    T ctp[cmax(TP::NJ + TP::NC, 1)];           // violation integrand parts
     T uk[cmax(TP::M, 1)], uk1[cmax(TP::M, 1)]; // FOH coefficients U_k, U_k+1
+    T x0[TP::NXT];                             // X_k
     T xk1[TP::NXT];                            // X_{k+1}
     T prm[TP::P];                              // (mu, e, masses)
     T minv[TP::NB], iinv[TP::NB];              // 1/m_b, 1/I_b
-    T s, h;                                    // dilation, RK4 step 1/K
+    T s, h, h6;                                // dilation, RK4 step 1/K, h/6
 };
 
-// LDS ordering between lanes of one wave (no s_barrier needed: a wave's LDS
-// instructions execute in order; the fences keep the compiler from moving
-// loads and stores across the point and drain outstanding LDS traffic).
+// Scratch of one right-hand-side evaluation (one per concurrently evaluating wave).
+template <class T, class TP>
+struct RhsScratch {
+    T ns[TP::NXT];                             // evaluation point (x part used)
+    T fn[TP::NXT];                             // F~ rows v, y (q rows are ns[v])
+    T cs[TP::NB][2];                           // cos, sin of body angles
+    T slot[cmax(2 * TP::NJ + TP::NC, 1)][4];   // (Fx, Fy, T, dT/dth) per element end
+    T ctp[cmax(TP::NJ + TP::NC, 1)];           // violation integrand parts
+};
+
+// LDS ordering between lanes of one wave (a wave's LDS instructions execute
+// in order; the fences keep the compiler from moving loads and stores across
+// the point and drain outstanding LDS traffic).
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -111,161 +119,199 @@ __device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }
 __device__ __forceinline__ float sqrt_t(float a) { return sqrtf(a); }
 
 // Pseudo-Huber absolute value with unit steepness (Sec. II notation):
-// |a|_s = sqrt(a^2+1) - 1 (evaluated as a^2/(sqrt(a^2+1)+1)) and its slope.
+// |a|_s = sqrt(a^2+1) - 1 = a^2/(sqrt(a^2+1)+1) and its slope a/sqrt(a^2+1),
+// with one square root and one division.
 template <class T>
 __device__ __forceinline__ void sabs_d(T a, T& val, T& der) {
-    T r = sqrt_t(a * a + T(1));
-    val = a * a / (r + T(1));
-    der = a / r;
+    const T r = sqrt_t(a * a + T(1));
+    const T inv = T(1) / (r * (r + T(1)));
+    val = (a * a) * (r * inv);
+    der = a * ((r + T(1)) * inv);
 }
 
+enum RhsMode { LEAN = 0, FULL = 1, EMIT = 2 };
+
 // ---------------------------------------------------------------------------
-// Nominal wave: one RHS evaluation at the stage input held in sm.ns.
-// Produces sm.fn (F~ without the dilation) and, if EMIT, the Jacobian
-// coefficients of this stage into cf.  Called by all 64 lanes of one wave.
+// One right-hand-side evaluation at sc.ns by the 64 lanes of one wave.
+// If HAVE_CS the rotations sc.cs are already filled in.  Writes sc.fn (v rows
+// always, y rows from FULL on) and, in EMIT mode, the coefficients into cf.
 // ---------------------------------------------------------------------------
-template <class T, class TP, bool EMIT, class SM>
-__device__ __forceinline__ void nominal_rhs(SM& sm,
-                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
-                                            int lane, T tau, T* cf) {
+template <class T, class TP, int MODE, bool HAVE_CS = false>
+__device__ __forceinline__ void rhs_eval(const Interval<T, TP>& iv, RhsScratch<T, TP>& sc,
+                                         const MConst<TP::NB, TP::NJ, TP::NC>& mc, int lane,
+                                         T tau, T* cf) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX, M = TP::M;
     using C = Coef<TP>;
-    const T s = sm.s;
+    const T s = iv.s;
     const T omt = T(1) - tau;
-    // step 1: body rotations
-    if (lane < NB) {
-        T sn, cn;
-        sincos_t(sm.ns[3 * lane + 2], &sn, &cn);
-        sm.cs[lane][0] = cn;
-        sm.cs[lane][1] = sn;
+    if (!HAVE_CS) {
+        if (lane < NB) {
+            T sn, cn;
+            sincos_t(sc.ns[3 * lane + 2], &sn, &cn);
+            sc.cs[lane][0] = cn;
+            sc.cs[lane][1] = sn;
+        }
+        wave_lds_sync();
     }
-    wave_lds_sync();
-    // step 2: joints and contacts, one lane each
+    const bool flat = mc.A == 0.0;
+    // step 2a: element arguments and wrenches (cheap, divergent)
+    T sa0 = T(0), sa1 = T(0);          // smooth-function arguments of this element
+    T apx = T(0), apy = T(0), acx = T(0), acy = T(0);   // joint arms
+    T ax = T(0), ay = T(0), om = T(0), sd = T(0), tx = T(1), ty = T(0), nx = T(0), ny = T(1);
+    T dsd_px = T(0), dsd_py = T(1), dnx = T(0), dny = T(0), ln = T(0), ft = T(0);
+    T lnb = T(0), ltpb = T(0), ltmb = T(0), vt = T(0), Pdx = T(0), Pdy = T(0);
     if (lane < NJ) {
         const int j = lane;
         const int p = TP::parent(j), c = j + 1;
-        const T cp = sm.cs[p][0], sp = sm.cs[p][1], cc = sm.cs[c][0], sc = sm.cs[c][1];
+        const T cp = sc.cs[p][0], sp = sc.cs[p][1], cc = sc.cs[c][0], scc = sc.cs[c][1];
         const T rpx = T(mc.rp[j][0]), rpy = T(mc.rp[j][1]);
         const T rcx = T(mc.rc[j][0]), rcy = T(mc.rc[j][1]);
-        const T apx = cp * rpx - sp * rpy, apy = sp * rpx + cp * rpy;
-        const T acx = cc * rcx - sc * rcy, acy = sc * rcx + cc * rcy;
-        const T hx = sm.ns[3 * p] + apx - sm.ns[3 * c] - acx;
-        const T hy = sm.ns[3 * p + 1] + apy - sm.ns[3 * c + 1] - acy;
-        const T lx = omt * sm.uk[NJ + 2 * j] + tau * sm.uk1[NJ + 2 * j];
-        const T ly = omt * sm.uk[NJ + 2 * j + 1] + tau * sm.uk1[NJ + 2 * j + 1];
-        const T tq = omt * sm.uk[j] + tau * sm.uk1[j];
+        apx = cp * rpx - sp * rpy;
+        apy = sp * rpx + cp * rpy;
+        acx = cc * rcx - scc * rcy;
+        acy = scc * rcx + cc * rcy;
+        const T lx = omt * iv.uk[NJ + 2 * j] + tau * iv.uk1[NJ + 2 * j];
+        const T ly = omt * iv.uk[NJ + 2 * j + 1] + tau * iv.uk1[NJ + 2 * j + 1];
+        const T tq = omt * iv.uk[j] + tau * iv.uk1[j];
         const T k = T(mc.ks[j]), d = T(mc.ds[j]);
-        const T tsd = -k * (sm.ns[3 * c + 2] - sm.ns[3 * p + 2]) -
-                      d * (sm.ns[NQ + 3 * c + 2] - sm.ns[NQ + 3 * p + 2]);
+        const T tsd = -k * (sc.ns[3 * c + 2] - sc.ns[3 * p + 2]) -
+                      d * (sc.ns[NQ + 3 * c + 2] - sc.ns[NQ + 3 * p + 2]);
         const T tt = tq + tsd;
-        sm.slot[2 * j][0] = lx;
-        sm.slot[2 * j][1] = ly;
-        sm.slot[2 * j][2] = (apx * ly - apy * lx) - tt;
-        sm.slot[2 * j][3] = -(apx * lx + apy * ly);
-        sm.slot[2 * j + 1][0] = -lx;
-        sm.slot[2 * j + 1][1] = -ly;
-        sm.slot[2 * j + 1][2] = -(acx * ly - acy * lx) + tt;
-        sm.slot[2 * j + 1][3] = acx * lx + acy * ly;
-        T vx, gx, vy, gy;
-        sabs_d(hx, vx, gx);
-        sabs_d(hy, vy, gy);
-        sm.ctp[j] = vx + vy;
-        if (EMIT) {
-            cf[C::JH + 4 * j + 0] = s * gx;
-            cf[C::JH + 4 * j + 1] = s * gy;
-            cf[C::JH + 4 * j + 2] = s * (gy * apx - gx * apy);
-            cf[C::JH + 4 * j + 3] = s * (gx * acy - gy * acx);
-            const T ip = s * sm.iinv[p], ic = s * sm.iinv[c];
-            cf[C::GV + (3 * p + 2) * M + NJ + 2 * j] = -apy * ip;
-            cf[C::GV + (3 * p + 2) * M + NJ + 2 * j + 1] = apx * ip;
-            cf[C::GV + (3 * c + 2) * M + NJ + 2 * j] = acy * ic;
-            cf[C::GV + (3 * c + 2) * M + NJ + 2 * j + 1] = -acx * ic;
+        sc.slot[2 * j][0] = lx;
+        sc.slot[2 * j][1] = ly;
+        sc.slot[2 * j][2] = (apx * ly - apy * lx) - tt;
+        sc.slot[2 * j][3] = -(apx * lx + apy * ly);
+        sc.slot[2 * j + 1][0] = -lx;
+        sc.slot[2 * j + 1][1] = -ly;
+        sc.slot[2 * j + 1][2] = -(acx * ly - acy * lx) + tt;
+        sc.slot[2 * j + 1][3] = acx * lx + acy * ly;
+        if (MODE >= FULL) {
+            sa0 = sc.ns[3 * p] + apx - sc.ns[3 * c] - acx;          // h_x
+            sa1 = sc.ns[3 * p + 1] + apy - sc.ns[3 * c + 1] - acy;  // h_y
         }
     } else if (lane < NJ + NC) {
         const int i = lane - NJ;
         const int b = TP::cbody(i);
-        const T cn = sm.cs[b][0], sn = sm.cs[b][1];
+        const T cn = sc.cs[b][0], sn = sc.cs[b][1];
         const T rx = T(mc.cr[i][0]), ry = T(mc.cr[i][1]);
-        const T ax = cn * rx - sn * ry, ay = sn * rx + cn * ry;
-        const T Px = sm.ns[3 * b] + ax, Py = sm.ns[3 * b + 1] + ay;
-        const T om = sm.ns[NQ + 3 * b + 2];
-        const T Pdx = sm.ns[NQ + 3 * b] - om * ay, Pdy = sm.ns[NQ + 3 * b + 1] + om * ax;
-        // terrain frame at P (Sec. II contact frame; Sec. VI-B sd = h/||grad h||)
-        const T A = T(mc.A), kap = T(mc.kappa);
-        T sw, cw;
-        sincos_t(kap * Px, &sw, &cw);
-        const T H = Py - A * sw;
-        const T Hx = -A * kap * cw;
-        const T Hxx = A * kap * kap * sw;
-        const T G = sqrt_t(T(1) + Hx * Hx);
-        const T G3 = G * G * G;
-        const T sd = H / G;
-        const T nx = Hx / G, ny = T(1) / G;
-        const T tx = ny, ty = -nx;
-        const T dsd_px = Hx / G - H * Hx * Hxx / G3, dsd_py = T(1) / G;
-        const T dnx = Hxx / G3, dny = -Hx * Hxx / G3;
-        const T dtx = dny, dty = -dnx;
+        ax = cn * rx - sn * ry;
+        ay = sn * rx + cn * ry;
+        const T Px = sc.ns[3 * b] + ax, Py = sc.ns[3 * b + 1] + ay;
+        om = sc.ns[NQ + 3 * b + 2];
+        Pdx = sc.ns[NQ + 3 * b] - om * ay;
+        Pdy = sc.ns[NQ + 3 * b + 1] + om * ax;
+        if (flat) {
+            sd = Py;   // h = P_y, n = (0, 1), t = (1, 0)
+        } else {
+            // terrain frame at P (Sec. II contact frame; Sec. VI-B sd = h/||grad h||)
+            const T A = T(mc.A), kap = T(mc.kappa);
+            T sw, cw;
+            sincos_t(kap * Px, &sw, &cw);
+            const T H = Py - A * sw;
+            const T Hx = -A * kap * cw;
+            const T Hxx = A * kap * kap * sw;
+            const T G = sqrt_t(T(1) + Hx * Hx);
+            const T rG = T(1) / G;
+            const T rG3 = rG * rG * rG;
+            sd = H * rG;
+            nx = Hx * rG;
+            ny = rG;
+            tx = ny;
+            ty = -nx;
+            dsd_px = Hx * rG - H * Hx * Hxx * rG3;
+            dsd_py = rG;
+            dnx = Hxx * rG3;
+            dny = -Hx * Hxx * rG3;
+        }
         const int u0 = 3 * NJ + 3 * i;
-        const T ln = omt * sm.uk[u0] + tau * sm.uk1[u0];
-        const T ltp = omt * sm.uk[u0 + 1] + tau * sm.uk1[u0 + 1];
-        const T ltm = omt * sm.uk[u0 + 2] + tau * sm.uk1[u0 + 2];
-        const T lnb = T(0.5) * (sm.uk[u0] + sm.uk1[u0]);
-        const T ltpb = T(0.5) * (sm.uk[u0 + 1] + sm.uk1[u0 + 1]);
-        const T ltmb = T(0.5) * (sm.uk[u0 + 2] + sm.uk1[u0 + 2]);
-        const T ft = ltp - ltm;
+        ln = omt * iv.uk[u0] + tau * iv.uk1[u0];
+        const T ltp = omt * iv.uk[u0 + 1] + tau * iv.uk1[u0 + 1];
+        const T ltm = omt * iv.uk[u0 + 2] + tau * iv.uk1[u0 + 2];
+        ft = ltp - ltm;
         const T fx = tx * ft + nx * ln, fy = ty * ft + ny * ln;
-        const T vt = tx * Pdx + ty * Pdy;
-        const T mu = sm.prm[0];
-        const T slack = mu * lnb - ltpb - ltmb;
-        T av, dav;
-        sabs_d(vt, av, dav);
-        const T rp = vt > T(0) ? av : T(0);     // ramp_s(v_t)
-        const T rm = vt < T(0) ? av : T(0);     // ramp_s(-v_t)
-        // integral cross-complementarity integrand (pairs of Sec. III)
-        sm.fn[NX + i] = lnb * sd + ltpb * rp + ltmb * rm + slack * av;
-        T as, das;
-        sabs_d(-sd, as, das);
-        sm.ctp[NJ + i] = -sd > T(0) ? as : T(0);   // ramp_s(-sd)
-        sm.slot[2 * NJ + i][0] = fx;
-        sm.slot[2 * NJ + i][1] = fy;
-        sm.slot[2 * NJ + i][2] = ax * fy - ay * fx;
-        sm.slot[2 * NJ + i][3] = -(ax * fx + ay * fy);
-        if (EMIT) {
-            const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) +
-                         slack * dav;
-            const T Dg = -(-sd > T(0) ? das : T(0));
-            const T dfx = dtx * ft + dnx * ln, dfy = dty * ft + dny * ln;
-            const T dvt_px = dtx * Pdx + dty * Pdy;
-            const T im = s * sm.minv[b], ii = s * sm.iinv[b];
-            T* ct = cf + C::CT + C::NCT * i;
-            ct[C_AX] = ax;
-            ct[C_AY] = ay;
-            ct[C_FXP] = dfx * im;
-            ct[C_FYP] = dfy * im;
-            ct[C_TP] = (ax * dfy - ay * dfx) * ii;
-            ct[C_EPX] = s * (lnb * dsd_px + gv * dvt_px);
-            ct[C_EPY] = s * (lnb * dsd_py);
-            ct[C_EXD] = s * (gv * tx);
-            ct[C_EYD] = s * (gv * ty);
-            ct[C_EOM] = s * (gv * (ty * ax - tx * ay));
-            ct[C_ETH] = s * (-gv * om * (tx * ax + ty * ay));
-            ct[C_ZPX] = s * (Dg * dsd_px);
-            ct[C_ZPY] = s * (Dg * dsd_py);
-            ct[C_JMU] = s * (lnb * av);
-            T* gvb = cf + C::GV;
-            gvb[(3 * b) * M + u0] = nx * im;
-            gvb[(3 * b + 1) * M + u0] = ny * im;
-            gvb[(3 * b + 2) * M + u0] = (ax * ny - ay * nx) * ii;
-            gvb[(3 * b) * M + u0 + 1] = tx * im;
-            gvb[(3 * b + 1) * M + u0 + 1] = ty * im;
-            gvb[(3 * b + 2) * M + u0 + 1] = (ax * ty - ay * tx) * ii;
-            gvb[(3 * b) * M + u0 + 2] = -tx * im;
-            gvb[(3 * b + 1) * M + u0 + 2] = -ty * im;
-            gvb[(3 * b + 2) * M + u0 + 2] = -(ax * ty - ay * tx) * ii;
-            T* gcb = cf + C::GC + i * M;
-            gcb[u0] = s * T(0.5) * (sd + mu * av);
-            gcb[u0 + 1] = s * T(0.5) * (rp - av);
-            gcb[u0 + 2] = s * T(0.5) * (rm - av);
+        sc.slot[2 * NJ + i][0] = fx;
+        sc.slot[2 * NJ + i][1] = fy;
+        sc.slot[2 * NJ + i][2] = ax * fy - ay * fx;
+        sc.slot[2 * NJ + i][3] = -(ax * fx + ay * fy);
+        if (MODE >= FULL) {
+            lnb = T(0.5) * (iv.uk[u0] + iv.uk1[u0]);
+            ltpb = T(0.5) * (iv.uk[u0 + 1] + iv.uk1[u0 + 1]);
+            ltmb = T(0.5) * (iv.uk[u0 + 2] + iv.uk1[u0 + 2]);
+            vt = tx * Pdx + ty * Pdy;
+            sa0 = vt;
+            sa1 = -sd;
+        }
+    }
+    if (MODE >= FULL && NJ + NC > 0) {
+        // step 2b: smooth functions, one code path for joints and contacts
+        T v0, d0, v1, d1;
+        sabs_d(sa0, v0, d0);
+        sabs_d(sa1, v1, d1);
+        if (lane < NJ) {
+            const int j = lane;
+            const int p = TP::parent(j), c = j + 1;
+            sc.ctp[j] = v0 + v1;   // |h_x|_s + |h_y|_s
+            if (MODE == EMIT) {
+                cf[C::JH + 4 * j + 0] = s * d0;
+                cf[C::JH + 4 * j + 1] = s * d1;
+                cf[C::JH + 4 * j + 2] = s * (d1 * apx - d0 * apy);
+                cf[C::JH + 4 * j + 3] = s * (d0 * acy - d1 * acx);
+                const T ip = s * iv.iinv[p], ic = s * iv.iinv[c];
+                cf[C::GV + (3 * p + 2) * M + NJ + 2 * j] = -apy * ip;
+                cf[C::GV + (3 * p + 2) * M + NJ + 2 * j + 1] = apx * ip;
+                cf[C::GV + (3 * c + 2) * M + NJ + 2 * j] = acy * ic;
+                cf[C::GV + (3 * c + 2) * M + NJ + 2 * j + 1] = -acx * ic;
+            }
+        } else if (lane < NJ + NC) {
+            const int i = lane - NJ;
+            const int b = TP::cbody(i);
+            const T av = v0, dav = d0;                   // |v_t|_s and its slope
+            const T rp = vt > T(0) ? av : T(0);          // ramp_s(v_t)
+            const T rm = vt < T(0) ? av : T(0);          // ramp_s(-v_t)
+            const T mu = iv.prm[0];
+            const T slack = mu * lnb - ltpb - ltmb;
+            // integral cross-complementarity integrand (pairs of Sec. III)
+            sc.fn[NX + i] = lnb * sd + ltpb * rp + ltmb * rm + slack * av;
+            sc.ctp[NJ + i] = -sd > T(0) ? v1 : T(0);     // ramp_s(-sd)
+            if (MODE == EMIT) {
+                const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) +
+                             slack * dav;
+                const T Dg = -(-sd > T(0) ? d1 : T(0));
+                const T dtx = dny, dty = -dnx;
+                const T dfx = dtx * ft + dnx * ln, dfy = dty * ft + dny * ln;
+                const T dvt_px = dtx * Pdx + dty * Pdy;
+                const T im = s * iv.minv[b], ii = s * iv.iinv[b];
+                T* ct = cf + C::CT + C::NCT * i;
+                ct[C_AX] = ax;
+                ct[C_AY] = ay;
+                ct[C_FXP] = dfx * im;
+                ct[C_FYP] = dfy * im;
+                ct[C_TP] = (ax * dfy - ay * dfx) * ii;
+                ct[C_EPX] = s * (lnb * dsd_px + gv * dvt_px);
+                ct[C_EPY] = s * (lnb * dsd_py);
+                ct[C_EXD] = s * (gv * tx);
+                ct[C_EYD] = s * (gv * ty);
+                ct[C_EOM] = s * (gv * (ty * ax - tx * ay));
+                ct[C_ETH] = s * (-gv * om * (tx * ax + ty * ay));
+                ct[C_ZPX] = s * (Dg * dsd_px);
+                ct[C_ZPY] = s * (Dg * dsd_py);
+                ct[C_JMU] = s * (lnb * av);
+                const int u0 = 3 * NJ + 3 * i;
+                T* gvb = cf + C::GV;
+                gvb[(3 * b) * M + u0] = nx * im;
+                gvb[(3 * b + 1) * M + u0] = ny * im;
+                gvb[(3 * b + 2) * M + u0] = (ax * ny - ay * nx) * ii;
+                gvb[(3 * b) * M + u0 + 1] = tx * im;
+                gvb[(3 * b + 1) * M + u0 + 1] = ty * im;
+                gvb[(3 * b + 2) * M + u0 + 1] = (ax * ty - ay * tx) * ii;
+                gvb[(3 * b) * M + u0 + 2] = -tx * im;
+                gvb[(3 * b + 1) * M + u0 + 2] = -ty * im;
+                gvb[(3 * b + 2) * M + u0 + 2] = -(ax * ty - ay * tx) * ii;
+                T* gcb = cf + C::GC + i * M;
+                gcb[u0] = s * T(0.5) * (sd + mu * av);
+                gcb[u0 + 1] = s * T(0.5) * (rp - av);
+                gcb[u0 + 2] = s * T(0.5) * (rm - av);
+            }
         }
     }
     wave_lds_sync();
@@ -274,10 +320,10 @@ __device__ __forceinline__ void nominal_rhs(SM& sm,
         const int b = lane;
         T Fx = T(0), Fy = T(0), Tq = T(0), dT = T(0);
         auto add = [&](int sl) {
-            Fx += sm.slot[sl][0];
-            Fy += sm.slot[sl][1];
-            Tq += sm.slot[sl][2];
-            dT += sm.slot[sl][3];
+            Fx += sc.slot[sl][0];
+            Fy += sc.slot[sl][1];
+            Tq += sc.slot[sl][2];
+            dT += sc.slot[sl][3];
         };
         if (b == 0) {
 #pragma unroll
@@ -290,16 +336,16 @@ __device__ __forceinline__ void nominal_rhs(SM& sm,
             if (b % TP::D != 0) add(2 * b);
             else add(2 * NJ + b / TP::D - 1);
         }
-        const T mi = sm.minv[b], ii = sm.iinv[b];
-        sm.fn[NQ + 3 * b] = Fx * mi;
-        sm.fn[NQ + 3 * b + 1] = Fy * mi - T(mc.g);
-        sm.fn[NQ + 3 * b + 2] = Tq * ii;
-        if (EMIT) cf[C::CTH + b] = s * dT * ii;
-    } else if (lane == NB) {
+        const T mi = iv.minv[b], ii = iv.iinv[b];
+        sc.fn[NQ + 3 * b] = Fx * mi;
+        sc.fn[NQ + 3 * b + 1] = Fy * mi - T(mc.g);
+        sc.fn[NQ + 3 * b + 2] = Tq * ii;
+        if (MODE == EMIT) cf[C::CTH + b] = s * dT * ii;
+    } else if (MODE >= FULL && lane == NB) {
         T acc = T(0);
 #pragma unroll
-        for (int e = 0; e < NJ + NC; ++e) acc += sm.ctp[e];
-        sm.fn[NX + NC] = acc;
+        for (int e = 0; e < NJ + NC; ++e) acc += sc.ctp[e];
+        sc.fn[NX + NC] = acc;
     }
     wave_lds_sync();
 }
@@ -310,27 +356,27 @@ struct RowState {
     T xb[2], xa[2];
 };
 
-// RK4 update of the nominal state after a stage evaluation.  stage in 0..3.
-// Writes the next stage input into sm.ns (or the new substep state after
-// stage 3) and, if EMIT, F~ into cf.
-template <class T, class TP, bool EMIT, class SM>
-__device__ __forceinline__ void nominal_update(SM& sm, RowState<T>& rs, int lane,
-                                               int stage, T* cf) {
-    constexpr int NXT = TP::NXT, NQ = TP::NQ;
+// RK4 update after evaluating stage `stage` (0..3) at sc.ns, rows r < NROWS
+// (NX for the state recursion alone, NXT with the integral states).  The next
+// stage input (or the new substep state after stage 3) goes to nxt[r] and, if
+// nxt2 is not NULL, to nxt2[r] too.
+template <class T, class TP, int NROWS>
+__device__ __forceinline__ void rk_rows(const Interval<T, TP>& iv, RhsScratch<T, TP>& sc,
+                                        RowState<T>& rs, int lane, int stage, T* nxt, T* nxt2) {
+    constexpr int NQ = TP::NQ;
     T F[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int r = lane + 64 * q;
         F[q] = T(0);
-        if (r < NXT) F[q] = r < NQ ? sm.ns[NQ + r] : sm.fn[r];
+        if (r < NROWS) F[q] = r < NQ ? sc.ns[NQ + r] : sc.fn[r];
     }
     wave_lds_sync();
-    const T s = sm.s, h = sm.h;
+    const T s = iv.s, h = iv.h;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int r = lane + 64 * q;
-        if (r < NXT) {
-            if (EMIT) cf[Coef<TP>::F + r] = F[q];
+        if (r < NROWS) {
             const T kk = s * F[q];
             if (stage == 0) rs.xa[q] = kk;
             else if (stage == 3) rs.xa[q] += kk;
@@ -339,10 +385,11 @@ __device__ __forceinline__ void nominal_update(SM& sm, RowState<T>& rs, int lane
             if (stage == 0 || stage == 1) next = rs.xb[q] + (T(0.5) * h) * kk;
             else if (stage == 2) next = rs.xb[q] + h * kk;
             else {
-                rs.xb[q] += (h / T(6)) * rs.xa[q];
+                rs.xb[q] += iv.h6 * rs.xa[q];
                 next = rs.xb[q];
             }
-            sm.ns[r] = next;
+            nxt[r] = next;
+            if (nxt2 != nullptr) nxt2[r] = next;
         }
     }
     wave_lds_sync();
@@ -370,31 +417,61 @@ struct FwdArgs {
 
 __device__ __forceinline__ double stage_c(int st) { return st == 0 ? 0.0 : (st == 3 ? 1.0 : 0.5); }
 
-// Interval inputs into LDS and per-interval constants.
-template <class T, class TP, class SM>
-__device__ __forceinline__ void load_interval(SM& sm, const FwdArgs<T>& a,
+// Interval inputs into LDS and per-interval constants (all threads of the block).
+template <class T, class TP>
+__device__ __forceinline__ void load_interval(Interval<T, TP>& iv, const FwdArgs<T>& a,
                                               const MConst<TP::NB, TP::NJ, TP::NC>& mc, int k,
                                               int tid, int nth) {
     for (int e = tid; e < TP::NXT; e += nth) {
-        sm.ns[e] = a.X[e * a.ldn + k];
-        sm.xk1[e] = a.X[e * a.ldn + k + 1];
+        iv.x0[e] = a.X[e * a.ldn + k];
+        iv.xk1[e] = a.X[e * a.ldn + k + 1];
     }
     for (int e = tid; e < TP::M; e += nth) {
-        sm.uk[e] = a.U[e * a.ldn + k];
-        sm.uk1[e] = a.U[e * a.ldn + k + 1];
+        iv.uk[e] = a.U[e * a.ldn + k];
+        iv.uk1[e] = a.U[e * a.ldn + k + 1];
     }
-    for (int e = tid; e < TP::P; e += nth) sm.prm[e] = a.prm[e];
+    for (int e = tid; e < TP::P; e += nth) iv.prm[e] = a.prm[e];
     if (tid == 0) {
-        sm.s = a.s[k];
-        sm.h = T(1) / T(a.K);
+        iv.s = a.s[k];
+        iv.h = T(1) / T(a.K);
+        iv.h6 = iv.h / T(6);
     }
     __syncthreads();
     for (int b = tid; b < TP::NB; b += nth) {
-        const T m = sm.prm[2 + b];
-        sm.minv[b] = T(1) / m;
-        sm.iinv[b] = T(1) / (m * T(mc.ipm[b]));
+        const T m = iv.prm[2 + b];
+        iv.minv[b] = T(1) / m;
+        iv.iinv[b] = T(1) / (m * T(mc.ipm[b]));
     }
     __syncthreads();
+    const T s = iv.s;
+    for (int j = tid; j < TP::NJ; j += nth) {
+        const int p = TP::parent(j), c = j + 1;
+        iv.kc[j][0] = s * T(mc.ks[j]) * iv.iinv[p];
+        iv.kc[j][1] = s * T(mc.ds[j]) * iv.iinv[p];
+        iv.kc[j][2] = s * T(mc.ks[j]) * iv.iinv[c];
+        iv.kc[j][3] = s * T(mc.ds[j]) * iv.iinv[c];
+    }
+    __syncthreads();
+}
+
+// Constant FOH forcing entries (s/m and s/I of joint forces and torques) of a
+// zeroed coefficient buffer; called by the lanes tid = 0..nth-1.
+template <class T, class TP>
+__device__ __forceinline__ void coef_constants(const Interval<T, TP>& iv, T* cf, int tid,
+                                               int nth) {
+    using C = Coef<TP>;
+    constexpr int NJ = TP::NJ, M = TP::M;
+    const T s = iv.s;
+    for (int j = tid; j < NJ; j += nth) {
+        const int p = TP::parent(j), c = j + 1;
+        T* gv = cf + C::GV;
+        gv[(3 * p) * M + NJ + 2 * j] = s * iv.minv[p];
+        gv[(3 * p + 1) * M + NJ + 2 * j + 1] = s * iv.minv[p];
+        gv[(3 * c) * M + NJ + 2 * j] = -s * iv.minv[c];
+        gv[(3 * c + 1) * M + NJ + 2 * j + 1] = -s * iv.minv[c];
+        gv[(3 * p + 2) * M + j] = -s * iv.iinv[p];
+        gv[(3 * c + 2) * M + j] = s * iv.iinv[c];
+    }
 }
 
 template <int NB, int NJ, int NC>

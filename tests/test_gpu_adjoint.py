@@ -68,10 +68,13 @@ CASES = [("free1", 3, 4, 2), ("point1", 3, 4, 4), ("hopper", 4, 6, 3), ("biped5"
 
 @pytest.mark.parametrize("name,N,K,C", CASES)
 def test_adjoint_matches_oracle(name, N, K, C):
+    """Intervals of ~0.02 s, as in the configurations.  (With 0.1-0.2 s intervals
+    the light quad13 links tumble and a 1-ulp input perturbation already moves
+    the oracle's own gradients by ~2.5e-10, above the 1e-10 bar.)"""
     _say(f"[gpu] adjoint {name} N={N} K={K} C={C} seed=200")
     rng = np.random.default_rng(200)
     model = synth.MODEL_MAKERS[name](rng)
-    data = synth.gen_nodes(model, N, rng, T=0.02 * N * 5)
+    data = synth.gen_nodes(model, N, rng, T=0.02 * N)
     lam = rng.normal(size=(N, model.nx))
     check(model, data, K, C, lam)
 
@@ -134,14 +137,18 @@ def test_config3_merit_gradients_via_autograd():
             dd = out["d"]
             inc = out["xprop"][model.n:] - X.detach()[model.n:, :N]
             return float(0.5 * (dd ** 2).sum() + inc.sum())
+    # central-difference error bound: 1e-6 relative (truncation at h = 1e-6
+    # relative) plus the rounding of the merit itself, ~ eps |J| / h.
+    J0 = merit(p.detach())
     for c in (0, 2, 5):
-        h = 1e-6 * abs(float(p[c]))
+        h = 1e-6 * abs(float(p.detach()[c]))
         pp, pm = p.detach().clone(), p.detach().clone()
         pp[c] += h
         pm[c] -= h
         fd = (merit(pp) - merit(pm)) / (2 * h)
         g = float(p.grad[c])
-        assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (c, fd, g)
+        tol = 1e-6 * max(1.0, abs(g)) + 64 * 2.2e-16 * abs(J0) / h
+        assert abs(fd - g) <= tol, (c, fd, g, tol, J0)
 
 
 def test_adjoint_contraction_of_forward_sensitivities():
