@@ -107,6 +107,32 @@ def main():
     launch32, out32, _, keep32 = prepare(torch.float32)
     ms32, _ = timed(launch32, stream, args.steps, args.warmup)
 
+    # adjoint form on the same workload (checkpoints every 5 substeps): one
+    # gradient step = forward defects with checkpoints + reverse sweep + reduce
+    C = 5
+    X64, U64, s64, p64 = keep64[:4]
+    fw = api.defects(cm, X64, U64, s64, p64, K, ckpt_every=C)
+    seed = fw["d"].clone()
+    seed[cm.n:] += 1.0          # d(1/2 ||d||^2 + sum of integral increments)/dF~
+    nbytes = api.adjoint_workspace_bytes(cm, N, K)
+    ws = torch.empty((nbytes,), device=dev, dtype=torch.uint8)
+    gX = torch.empty((cm.nx, N + 1), device=dev, dtype=torch.float64)
+    gU = torch.empty((cm.m, N + 1), device=dev, dtype=torch.float64)
+    gs = torch.empty((N,), device=dev, dtype=torch.float64)
+    gp = torch.empty((cm.np,), device=dev, dtype=torch.float64)
+    sh_adj = _lib.Shape(N, K, _lib.CIS_F64, 0, X64.stride(0), N)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    d_fw, xp_fw, ck = fw["d"], fw["xprop"], fw["ckpt"]
+    st_ptr = ctypes.c_void_p(stream.cuda_stream)
+
+    def launch_grad():
+        _lib.check(lib.cis_defects(cm.handle, ctypes.byref(sh_adj), vp(X64), vp(U64), vp(s64), vp(p64),
+                                   vp(d_fw), vp(xp_fw), vp(ck), C, st_ptr))
+        _lib.check(lib.cis_discretize_adjoint(cm.handle, ctypes.byref(sh_adj), vp(X64), vp(U64),
+                                              vp(s64), vp(p64), vp(ck), C, vp(seed), vp(gX),
+                                              vp(gU), vp(gs), vp(gp), vp(ws), nbytes, st_ptr))
+    ms_grad, _ = timed(launch_grad, stream, max(args.steps // 2, 10), args.warmup)
+
     flops = algorithmic_flops_per_interval(model, K) * N
     achieved = flops / (ms64 * 1e-3)
     line = {
@@ -126,6 +152,9 @@ def main():
                                "N=50 intervals, K=20 RK4 substeps, FP64 forward",
                    "N": N, "substeps": K, "nx": cm.nx, "m": cm.m},
         "fp32": {"value": N / (ms32 * 1e-3), "unit": "intervals/s", "ms_per_step": ms32},
+        "adjoint": {"value": N / (ms_grad * 1e-3), "unit": "interval grads/s",
+                    "ms_per_step": ms_grad,
+                    "step": "cis_defects with checkpoints every 5 substeps + cis_discretize_adjoint"},
         "roofline": {"bound": "alu", "kernel": "k_discretize<double, Topo<2,3>>",
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
