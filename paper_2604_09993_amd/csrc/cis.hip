@@ -16,6 +16,7 @@
 
 #include "../../include/cis.h"
 #include "cis_model.hpp"
+#include "cis_body.hpp"
 #include "cis_host.hpp"
 
 namespace cis {
@@ -195,9 +196,12 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 template <class T, class TP>
 struct DiscShared {
     Interval<T, TP> iv;
-    RhsScratch<T, TP> scS, scC;
     T xring[4][TP::NX];        // stage inputs from the state wave
     T csring[4][TP::NB][2];    // their rotations
+    T fring[4][3 * TP::NB];    // their accelerations
+    T pshS[2][TP::NB][4];      // joint-wrench exchange of the state wave
+    T pshC[2][TP::NB][4];      // dT/dth exchange of the coefficient wave
+    T red[TP::NB][2];
     T coef[2][Coef<TP>::SIZE];
 };
 
@@ -227,97 +231,72 @@ __global__ void __launch_bounds__(TP::NTHREADS)
     // (nsteps), so the registers of one role are not live in the others.
     if (wave == TP::NTW) {
         // ---------------- state wave: stage t at step t ----------------
-        RowState<T> rs;
+        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+        BodyRK<T> bs;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int r = lane + 64 * q;
-            rs.xa[q] = T(0);
-            rs.xb[q] = r < NX ? sh.iv.x0[r] : T(0);
-            if (r < NX) sh.scS.ns[r] = rs.xb[q];
+        for (int kk = 0; kk < 3; ++kk) {
+            bs.xb[kk] = sh.iv.x0[3 * c.b + kk];
+            bs.xb[3 + kk] = sh.iv.x0[NQ + 3 * c.b + kk];
         }
-        wave_lds_sync();
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) {
+            bs.xs[kk] = bs.xb[kk];
+            bs.xa[kk] = T(0);
+        }
         for (int t = 0; t < nsteps; ++t) {
             if (t < nst) {
                 const int st = t & 3;
                 const T tau = (T(t >> 2) + T(stage_c(st))) / T(a.K);
-                rhs_eval<T, TP, LEAN>(sh.iv, sh.scS, mc, lane, tau, (T*)nullptr);
-                if (lane < NB) {
-                    sh.csring[t & 3][lane][0] = sh.scS.cs[lane][0];
-                    sh.csring[t & 3][lane][1] = sh.scS.cs[lane][1];
-                }
-                rk_rows<T, TP, NX>(sh.iv, sh.scS, rs, lane, st, sh.scS.ns, sh.xring[(t + 1) & 3]);
+                state_stage<T, TP>(sh.iv, mc, c, bs, sh.pshS[t & 1], st, tau, sh.xring[(t + 1) & 3],
+                                   sh.csring[t & 3], sh.fring[t & 3], lane);
             }
             __syncthreads();
         }
-        if (grp == 0) {
+        if (grp == 0 && lane < NB) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int r = lane + 64 * q;
-                if (r < NX) {
-                    if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
-                    a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
-                }
+            for (int kk = 0; kk < 6; ++kk) {
+                const int r = kk < 3 ? 3 * c.b + kk : NQ + 3 * c.b + kk - 3;
+                if (a.xprop) a.xprop[r * ldi + k] = bs.xb[kk];
+                a.defect[r * ldi + k] = bs.xb[kk] - sh.iv.xk1[r];
             }
         }
     } else if (wave == TP::NTW + 1) {
         // -------- coefficient wave: stage t-1 at step t; integral rows --------
-        RowState<T> rs;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int r = lane + 64 * q;
-            rs.xa[q] = T(0);
-            rs.xb[q] = (r >= NX && r < NXT) ? sh.iv.x0[r] : T(0);
-        }
+        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+        // integral rows: the contact's cc row on its lane, the violation row on lane 0
+        const int ycc_row = NX + c.i;
+        T ycb = c.contact ? sh.iv.x0[ycc_row] : T(0), yca = T(0);
+        T ytb = lane == 0 ? sh.iv.x0[NX + NC] : T(0), yta = T(0);
+        const T s = sh.iv.s;
         for (int t = 0; t < nsteps; ++t) {
             const int tc = t - 1;
             if (tc >= 0 && tc < nst) {
                 const int st = tc & 3;
                 const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
-                T* cf = sh.coef[tc & 1];
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int r = lane + 64 * q;
-                    if (r < NX) sh.scC.ns[r] = tc == 0 ? sh.iv.x0[r] : sh.xring[tc & 3][r];
-                }
-                if (lane < NB) {
-                    sh.scC.cs[lane][0] = sh.csring[tc & 3][lane][0];
-                    sh.scC.cs[lane][1] = sh.csring[tc & 3][lane][1];
-                }
-                wave_lds_sync();
-                rhs_eval<T, TP, EMIT, true>(sh.iv, sh.scC, mc, lane, tau, cf);
-                // F~ for the dilation column, and the integral rows of the nominal state
-                const T s = sh.iv.s, h = sh.iv.h;
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int r = lane + 64 * q;
-                    if (r < NXT) {
-                        const T F = r < NQ ? sh.scC.ns[NQ + r] : sh.scC.fn[r];
-                        cf[C::F + r] = F;
-                        if (r >= NX) {
-                            const T kk = s * F;
-                            if (st == 0) rs.xa[q] = kk;
-                            else if (st == 3) rs.xa[q] += kk;
-                            else rs.xa[q] += T(2) * kk;
-                            if (st == 3) rs.xb[q] += sh.iv.h6 * rs.xa[q];
-                        }
-                    }
-                }
+                T ycc = T(0), yct = T(0);
+                coef_stage<T, TP>(sh.iv, mc, c, tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
+                                  sh.csring[tc & 3], sh.fring[tc & 3], sh.pshC[tc & 1], sh.red, tau,
+                                  sh.coef[tc & 1], ycc, yct, lane);
+                const T wk = (st == 0 || st == 3) ? T(1) : T(2);
+                if (st == 0) { yca = s * ycc; yta = s * yct; }
+                else { yca += wk * s * ycc; yta += wk * s * yct; }
+                if (st == 3) { ycb += sh.iv.h6 * yca; ytb += sh.iv.h6 * yta; }
             }
             __syncthreads();
         }
         if (grp == 0) {
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int r = lane + 64 * q;
-                if (r >= NX && r < NXT) {
-                    if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
-                    a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
-                }
+            if (c.contact) {
+                if (a.xprop) a.xprop[ycc_row * ldi + k] = ycb;
+                a.defect[ycc_row * ldi + k] = ycb - sh.iv.xk1[ycc_row];
+            }
+            if (lane == 0) {
+                if (a.xprop) a.xprop[(NX + NC) * ldi + k] = ytb;
+                a.defect[(NX + NC) * ldi + k] = ytb - sh.iv.xk1[NX + NC];
             }
             // A[:, n:] = [0; I]: the integral states feed back into nothing
             for (int e = lane; e < NXT * NY; e += 64) {
-                const int r = e / NY, c = NX + e % NY;
-                a.A[((int64_t)r * NXT + c) * ldi + k] = (r == c) ? T(1) : T(0);
+                const int r = e / NY, cc = NX + e % NY;
+                a.A[((int64_t)r * NXT + cc) * ldi + k] = (r == cc) ? T(1) : T(0);
             }
         }
     } else {

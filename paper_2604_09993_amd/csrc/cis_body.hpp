@@ -1,0 +1,396 @@
+// Body-lane evaluation of the nominal stages (state recursion and Jacobian
+// coefficients) for the discretize kernel.
+//
+// Lane b < NB of a wave owns body b: its six state rows (x, y, th, xd, yd, w)
+// and the joint whose child it is (joint b-1, for b >= 1) and the contact it
+// carries (the tip of a leg's last link).  Per stage the only cross-lane
+// traffic is the parent's angle and rate (a DPP/bpermute shuffle) and one LDS
+// exchange of the parent-side joint wrench; both rotations a lane needs are
+// evaluated side by side.  Right-hand side as in Sec. II-A (eq. ct-dynamics),
+// Sec. III (integrands) and Sec. IV-B (dilation, FOH); Jacobian nonzeros in
+// the layout of Coef<TP>.
+#pragma once
+#include "cis_model.hpp"
+
+namespace cis {
+
+template <class TP>
+__device__ __forceinline__ int parent_body(int b) {
+    // body b >= 1 is the child of joint b-1; the torso has no parent (0 = itself)
+    if (b == 0 || TP::D == 0) return 0;
+    return ((b - 1) % TP::D) == 0 ? 0 : b - 1;
+}
+template <class TP>
+__device__ __forceinline__ bool has_contact(int b) {
+    if constexpr (TP::D == 0) return b == 0 && TP::L >= 1;
+    else return b >= 1 && ((b - 1) % TP::D) == TP::D - 1;
+}
+template <class TP>
+__device__ __forceinline__ int contact_of(int b) {
+    return TP::D == 0 ? 0 : (b - 1) / TP::D;
+}
+
+__device__ __forceinline__ double shfl_t(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ float shfl_t(float v, int src) { return __shfl(v, src, 64); }
+
+// Constants a body lane keeps in registers for the whole interval.
+template <class T, class TP>
+struct BodyConst {
+    int b, p;                 // own and parent body
+    bool joint, contact;      // has a parent joint, carries a contact
+    int j, i;                 // joint and contact index
+    T rpx, rpy, rcx, rcy;     // joint anchors (parent frame, own frame)
+    T kj, dj;                 // stiffness, damping of the parent joint
+    T rx, ry;                 // contact point
+    T mi, ii;                 // 1/m, 1/I
+    T uk[3], uk1[3];          // joint controls tau, lambda_x, lambda_y at the two nodes
+    T ck[3], ck1[3];          // contact controls lambda_n, lambda_t+, lambda_t-
+};
+
+template <class T, class TP>
+__device__ __forceinline__ BodyConst<T, TP> body_const(const Interval<T, TP>& iv,
+                                                       const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                                       int lane) {
+    constexpr int NB = TP::NB, NJ = TP::NJ;
+    BodyConst<T, TP> c;
+    c.b = lane < NB ? lane : 0;
+    c.p = parent_body<TP>(c.b);
+    c.joint = TP::D >= 1 && lane < NB && c.b >= 1;
+    c.contact = lane < NB && has_contact<TP>(c.b);
+    c.j = c.joint ? c.b - 1 : 0;
+    c.i = c.contact ? contact_of<TP>(c.b) : 0;
+    c.rpx = c.rpy = c.rcx = c.rcy = c.kj = c.dj = c.rx = c.ry = T(0);
+    for (int q = 0; q < 3; ++q) c.uk[q] = c.uk1[q] = c.ck[q] = c.ck1[q] = T(0);
+    if constexpr (NJ > 0) {
+        if (c.joint) {
+            c.rpx = T(mc.rp[c.j][0]);
+            c.rpy = T(mc.rp[c.j][1]);
+            c.rcx = T(mc.rc[c.j][0]);
+            c.rcy = T(mc.rc[c.j][1]);
+            c.kj = T(mc.ks[c.j]);
+            c.dj = T(mc.ds[c.j]);
+            const int us[3] = {c.j, NJ + 2 * c.j, NJ + 2 * c.j + 1};
+            for (int q = 0; q < 3; ++q) {
+                c.uk[q] = iv.uk[us[q]];
+                c.uk1[q] = iv.uk1[us[q]];
+            }
+        }
+    }
+    if constexpr (TP::NC > 0) {
+        if (c.contact) {
+            c.rx = T(mc.cr[c.i][0]);
+            c.ry = T(mc.cr[c.i][1]);
+            for (int q = 0; q < 3; ++q) {
+                c.ck[q] = iv.uk[3 * NJ + 3 * c.i + q];
+                c.ck1[q] = iv.uk1[3 * NJ + 3 * c.i + q];
+            }
+        }
+    }
+    c.mi = iv.minv[c.b];
+    c.ii = iv.iinv[c.b];
+    return c;
+}
+
+// RK4 state of a body lane: base, accumulator, stage input of its six rows
+template <class T>
+struct BodyRK {
+    T xb[6], xa[6], xs[6];
+};
+
+// Terrain frame at the contact point (flat ground when A == 0).
+template <class T>
+struct Frame {
+    T sd, nx, ny, tx, ty, dsd_px, dsd_py, dnx, dny;
+};
+template <class T, class MC>
+__device__ __forceinline__ Frame<T> terrain(const MC& mc, T Px, T Py) {
+    Frame<T> f;
+    if (mc.A == 0.0) {
+        f.sd = Py;
+        f.nx = T(0);
+        f.ny = T(1);
+        f.tx = T(1);
+        f.ty = T(0);
+        f.dsd_px = T(0);
+        f.dsd_py = T(1);
+        f.dnx = T(0);
+        f.dny = T(0);
+    } else {
+        // Sec. II contact frame; Sec. VI-B sd = h / ||grad h||
+        const T A = T(mc.A), kap = T(mc.kappa);
+        T sw, cw;
+        sincos_t(kap * Px, &sw, &cw);
+        const T H = Py - A * sw;
+        const T Hx = -A * kap * cw;
+        const T Hxx = A * kap * kap * sw;
+        const T G = sqrt_t(T(1) + Hx * Hx);
+        const T rG = T(1) / G;
+        const T rG3 = rG * rG * rG;
+        f.sd = H * rG;
+        f.nx = Hx * rG;
+        f.ny = rG;
+        f.tx = f.ny;
+        f.ty = -f.nx;
+        f.dsd_px = Hx * rG - H * Hx * Hxx * rG3;
+        f.dsd_py = rG;
+        f.dnx = Hxx * rG3;
+        f.dny = -Hx * Hxx * rG3;
+    }
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// State wave: one stage.  bs.xs holds the stage input of the lane's body.
+// Writes the next stage input (or the new substep state after stage 3) into
+// bs.xs and into ring[NX], the body rotation into cs_out[NB][2] and the
+// accelerations into fv_out[3 NB].  psh: [NB][4] LDS exchange slot.
+// ---------------------------------------------------------------------------
+template <class T, class TP>
+__device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
+                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                            const BodyConst<T, TP>& c, BodyRK<T>& bs,
+                                            T (*psh)[4], int st, T tau, T* ring, T (*cs_out)[2],
+                                            T* fv_out, int lane) {
+    constexpr int NB = TP::NB, NQ = TP::NQ, D = TP::D, L = TP::L;
+    const T omt = T(1) - tau;
+    const T thp = shfl_t(bs.xs[2], c.p), omp = shfl_t(bs.xs[5], c.p);
+    T sb, cb, sp, cp;
+    sincos_t(bs.xs[2], &sb, &cb);
+    sincos_t(thp, &sp, &cp);
+    T Fx = T(0), Fy = T(0), Tq = T(0);
+    if (c.joint) {
+        const T apx = cp * c.rpx - sp * c.rpy, apy = sp * c.rpx + cp * c.rpy;
+        const T acx = cb * c.rcx - sb * c.rcy, acy = sb * c.rcx + cb * c.rcy;
+        const T tq = omt * c.uk[0] + tau * c.uk1[0];
+        const T lx = omt * c.uk[1] + tau * c.uk1[1];
+        const T ly = omt * c.uk[2] + tau * c.uk1[2];
+        const T tt = tq - c.kj * (bs.xs[2] - thp) - c.dj * (bs.xs[5] - omp);
+        Fx -= lx;
+        Fy -= ly;
+        Tq += -(acx * ly - acy * lx) + tt;
+        psh[c.b][0] = lx;
+        psh[c.b][1] = ly;
+        psh[c.b][2] = (apx * ly - apy * lx) - tt;
+    }
+    if (c.contact) {
+        const T ax = cb * c.rx - sb * c.ry, ay = sb * c.rx + cb * c.ry;
+        const Frame<T> f = terrain<T>(mc, bs.xs[0] + ax, bs.xs[1] + ay);
+        const T ln = omt * c.ck[0] + tau * c.ck1[0];
+        const T ft = (omt * c.ck[1] + tau * c.ck1[1]) - (omt * c.ck[2] + tau * c.ck1[2]);
+        const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
+        Fx += fx;
+        Fy += fy;
+        Tq += ax * fy - ay * fx;
+    }
+    wave_lds_sync();
+    // parent-side wrenches of the children's joints
+    if (lane < NB) {
+        if constexpr (D >= 1) {
+            if (c.b == 0) {
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    Fx += psh[1 + l * D][0];
+                    Fy += psh[1 + l * D][1];
+                    Tq += psh[1 + l * D][2];
+                }
+            } else if (((c.b - 1) % D) < D - 1) {
+                Fx += psh[c.b + 1][0];
+                Fy += psh[c.b + 1][1];
+                Tq += psh[c.b + 1][2];
+            }
+        }
+    }
+    const T fv[3] = {Fx * c.mi, Fy * c.mi - T(mc.g), Tq * c.ii};
+    const T s = iv.s, h = iv.h;
+    const T an = (st == 2) ? h : T(0.5) * h;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const T kk = s * (k < 3 ? bs.xs[3 + k] : fv[k - 3]);
+        if (st == 0) bs.xa[k] = kk;
+        else if (st == 3) bs.xa[k] += kk;
+        else bs.xa[k] += T(2) * kk;
+    }
+    if (lane < NB) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fv_out[3 * c.b + k] = fv[k];
+        cs_out[c.b][0] = cb;
+        cs_out[c.b][1] = sb;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (st < 3) {
+            const T kk = s * (k < 3 ? bs.xs[3 + k] : fv[k - 3]);
+            bs.xs[k] = bs.xb[k] + an * kk;
+        } else {
+            bs.xb[k] += iv.h6 * bs.xa[k];
+            bs.xs[k] = bs.xb[k];
+        }
+    }
+    if (lane < NB) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ring[3 * c.b + k] = bs.xs[k];
+            ring[NQ + 3 * c.b + k] = bs.xs[3 + k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient wave: Jacobian nonzeros and F~ of one stage, given its input
+// state xs[NX], the body rotations cs[NB][2] and accelerations fv[3NB] from
+// the state wave.  Writes cf (layout Coef<TP>) and returns, in the lanes that
+// own them, the integral-row right-hand sides (cc_i on contact lanes, the
+// violation row on lane 0) through ycc / yct.  psh: [NB][4] LDS slot.
+// ---------------------------------------------------------------------------
+template <class T, class TP>
+__device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
+                                           const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                           const BodyConst<T, TP>& c, const T* xs,
+                                           const T (*cs)[2], const T* fv, T (*psh)[4],
+                                           T (*red)[2], T tau, T* cf, T& ycc, T& yct, int lane) {
+    // ycc: cross-complementarity integrand of the lane's contact; yct: the
+    // violation integrand (lane 0).  Both unchanged where not owned.
+    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX, M = TP::M;
+    using C = Coef<TP>;
+    const T s = iv.s, omt = T(1) - tau;
+    const int b = c.b, p = c.p;
+    const T cb = cs[b][0], sb = cs[b][1];
+    // smooth-function arguments: joint h_x, h_y; contact v_t, -sd
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    T apx = T(0), apy = T(0), acx = T(0), acy = T(0), lx = T(0), ly = T(0);
+    if (c.joint) {
+        const T cp = cs[p][0], sp = cs[p][1];
+        apx = cp * c.rpx - sp * c.rpy;
+        apy = sp * c.rpx + cp * c.rpy;
+        acx = cb * c.rcx - sb * c.rcy;
+        acy = sb * c.rcx + cb * c.rcy;
+        lx = omt * c.uk[1] + tau * c.uk1[1];
+        ly = omt * c.uk[2] + tau * c.uk1[2];
+        a0 = xs[3 * p] + apx - xs[3 * b] - acx;
+        a1 = xs[3 * p + 1] + apy - xs[3 * b + 1] - acy;
+    }
+    T ax = T(0), ay = T(0), om = T(0), Pdx = T(0), Pdy = T(0), ln = T(0), ft = T(0);
+    Frame<T> f;
+    f.sd = T(0);
+    f.nx = f.dsd_px = f.dnx = f.dny = f.ty = T(0);
+    f.ny = f.tx = f.dsd_py = T(1);
+    if (c.contact) {
+        ax = cb * c.rx - sb * c.ry;
+        ay = sb * c.rx + cb * c.ry;
+        om = xs[NQ + 3 * b + 2];
+        Pdx = xs[NQ + 3 * b] - om * ay;
+        Pdy = xs[NQ + 3 * b + 1] + om * ax;
+        f = terrain<T>(mc, xs[3 * b] + ax, xs[3 * b + 1] + ay);
+        ln = omt * c.ck[0] + tau * c.ck1[0];
+        ft = (omt * c.ck[1] + tau * c.ck1[1]) - (omt * c.ck[2] + tau * c.ck1[2]);
+        a2 = f.tx * Pdx + f.ty * Pdy;
+        a3 = -f.sd;
+    }
+    T v0, d0, v1, d1, v2, d2, v3, d3;
+    sabs_d(a0, v0, d0);
+    sabs_d(a1, v1, d1);
+    sabs_d(a2, v2, d2);
+    sabs_d(a3, v3, d3);
+    T dTown = T(0), ctp = T(0);
+    if (c.joint) {
+        const int j = c.j;
+        ctp += v0 + v1;   // |h_x|_s + |h_y|_s
+        cf[C::JH + 4 * j + 0] = s * d0;
+        cf[C::JH + 4 * j + 1] = s * d1;
+        cf[C::JH + 4 * j + 2] = s * (d1 * apx - d0 * apy);
+        cf[C::JH + 4 * j + 3] = s * (d0 * acy - d1 * acx);
+        const T ip = s * iv.iinv[p], ic = s * c.ii;
+        cf[C::GV + (3 * p + 2) * M + NJ + 2 * j] = -apy * ip;
+        cf[C::GV + (3 * p + 2) * M + NJ + 2 * j + 1] = apx * ip;
+        cf[C::GV + (3 * b + 2) * M + NJ + 2 * j] = acy * ic;
+        cf[C::GV + (3 * b + 2) * M + NJ + 2 * j + 1] = -acx * ic;
+        dTown += acx * lx + acy * ly;          // child side d(-a_c x lam)/dth
+        psh[b][3] = -(apx * lx + apy * ly);    // parent side d(a_p x lam)/dth_p
+    }
+    if (c.contact) {
+        const int i = c.i;
+        const T lnb = T(0.5) * (c.ck[0] + c.ck1[0]);
+        const T ltpb = T(0.5) * (c.ck[1] + c.ck1[1]);
+        const T ltmb = T(0.5) * (c.ck[2] + c.ck1[2]);
+        const T vt = a2, av = v2, dav = d2;
+        const T rp = vt > T(0) ? av : T(0);
+        const T rm = vt < T(0) ? av : T(0);
+        const T mu = iv.prm[0];
+        const T slack = mu * lnb - ltpb - ltmb;
+        ycc = lnb * f.sd + ltpb * rp + ltmb * rm + slack * av;   // pairs of Sec. III
+        ctp += -f.sd > T(0) ? v3 : T(0);                           // ramp_s(-sd)
+        const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) +
+                     slack * dav;
+        const T Dg = -(-f.sd > T(0) ? d3 : T(0));
+        const T dtx = f.dny, dty = -f.dnx;
+        const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
+        const T dvt_px = dtx * Pdx + dty * Pdy;
+        const T im = s * c.mi, ii = s * c.ii;
+        T* ct = cf + C::CT + C::NCT * i;
+        ct[C_AX] = ax;
+        ct[C_AY] = ay;
+        ct[C_FXP] = dfx * im;
+        ct[C_FYP] = dfy * im;
+        ct[C_TP] = (ax * dfy - ay * dfx) * ii;
+        ct[C_EPX] = s * (lnb * f.dsd_px + gv * dvt_px);
+        ct[C_EPY] = s * (lnb * f.dsd_py);
+        ct[C_EXD] = s * (gv * f.tx);
+        ct[C_EYD] = s * (gv * f.ty);
+        ct[C_EOM] = s * (gv * (f.ty * ax - f.tx * ay));
+        ct[C_ETH] = s * (-gv * om * (f.tx * ax + f.ty * ay));
+        ct[C_ZPX] = s * (Dg * f.dsd_px);
+        ct[C_ZPY] = s * (Dg * f.dsd_py);
+        ct[C_JMU] = s * (lnb * av);
+        const int u0 = 3 * NJ + 3 * i;
+        T* gvb = cf + C::GV;
+        gvb[(3 * b) * M + u0] = f.nx * im;
+        gvb[(3 * b + 1) * M + u0] = f.ny * im;
+        gvb[(3 * b + 2) * M + u0] = (ax * f.ny - ay * f.nx) * ii;
+        gvb[(3 * b) * M + u0 + 1] = f.tx * im;
+        gvb[(3 * b + 1) * M + u0 + 1] = f.ty * im;
+        gvb[(3 * b + 2) * M + u0 + 1] = (ax * f.ty - ay * f.tx) * ii;
+        gvb[(3 * b) * M + u0 + 2] = -f.tx * im;
+        gvb[(3 * b + 1) * M + u0 + 2] = -f.ty * im;
+        gvb[(3 * b + 2) * M + u0 + 2] = -(ax * f.ty - ay * f.tx) * ii;
+        T* gcb = cf + C::GC + i * M;
+        gcb[u0] = s * T(0.5) * (f.sd + mu * av);
+        gcb[u0 + 1] = s * T(0.5) * (rp - av);
+        gcb[u0 + 2] = s * T(0.5) * (rm - av);
+        const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
+        dTown += -(ax * fx + ay * fy);         // d(a x F)/dth at fixed F
+    }
+    if (lane < NB) red[lane][0] = ctp;
+    // F~: q rows are the stage velocities, v rows the state wave's accelerations
+    if (lane < NB) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cf[C::F + 3 * b + k] = xs[NQ + 3 * b + k];
+            cf[C::F + NQ + 3 * b + k] = fv[3 * b + k];
+        }
+    }
+    if (c.contact) cf[C::F + NX + c.i] = ycc;
+    wave_lds_sync();
+    // dT_b/dth_b: own terms plus the parent-side terms of the children's joints
+    if (lane < NB) {
+        T dT = dTown;
+        if constexpr (TP::D >= 1) {
+            if (b == 0) {
+#pragma unroll
+                for (int l = 0; l < TP::L; ++l) dT += psh[1 + l * TP::D][3];
+            } else if (((b - 1) % TP::D) < TP::D - 1) {
+                dT += psh[b + 1][3];
+            }
+        }
+        cf[C::CTH + b] = s * dT * c.ii;
+    }
+    if (lane == 0) {
+        // violation row: sum over bodies of their joint and contact parts
+        T acc = T(0);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) acc += red[e][0];
+        yct = acc;
+        cf[C::F + NX + NC] = acc;
+    }
+}
+
+}  // namespace cis

@@ -113,20 +113,76 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ void sincos_t(double a, double* s, double* c) { sincos(a, s, c); }
-__device__ __forceinline__ void sincos_t(float a, float* s, float* c) { sincosf(a, s, c); }
 __device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }
 __device__ __forceinline__ float sqrt_t(float a) { return sqrtf(a); }
 
+// sin and cos without branches (two evaluations interleave): Cody-Waite
+// reduction r = a - k pi/2 with pi/2 split in three parts (the leading two
+// with 30 significant bits, so k P1 and k P2 are exact for |k| < 2^23; pi
+// from Machin's formula), then the Taylor series of sin and cos on
+// [-pi/4, pi/4] through r^17 and r^18 (truncation below 1e-19), and the
+// quadrant of k.  Arguments beyond 1e5 in any lane take the library routine.
+__device__ __forceinline__ void sincos_cw(double a, double& sa, double& ca) {
+    const double k = rint(a * 0.6366197723675814);
+    double r = fma(-k, 1.570796325802803, a);
+    r = fma(-k, 9.920935791635221e-10, r);
+    r = fma(-k, 5.170182981794105e-19, r);
+    const double z = r * r;
+    double ps = 1.0 / 355687428096000.0;             // 1/17!
+    ps = fma(ps, z, -1.0 / 1307674368000.0);         // 1/15!
+    ps = fma(ps, z, 1.0 / 6227020800.0);             // 1/13!
+    ps = fma(ps, z, -1.0 / 39916800.0);              // 1/11!
+    ps = fma(ps, z, 1.0 / 362880.0);                 // 1/9!
+    ps = fma(ps, z, -1.0 / 5040.0);                  // 1/7!
+    ps = fma(ps, z, 1.0 / 120.0);                    // 1/5!
+    ps = fma(ps, z, -1.0 / 6.0);                     // 1/3!
+    double pc = -1.0 / 6402373705728000.0;           // 1/18!
+    pc = fma(pc, z, 1.0 / 20922789888000.0);         // 1/16!
+    pc = fma(pc, z, -1.0 / 87178291200.0);           // 1/14!
+    pc = fma(pc, z, 1.0 / 479001600.0);              // 1/12!
+    pc = fma(pc, z, -1.0 / 3628800.0);               // 1/10!
+    pc = fma(pc, z, 1.0 / 40320.0);                  // 1/8!
+    pc = fma(pc, z, -1.0 / 720.0);                   // 1/6!
+    pc = fma(pc, z, 1.0 / 24.0);                     // 1/4!
+    const double sr = fma(r * z, ps, r);
+    const double cr = fma(z * z, pc, fma(-0.5, z, 1.0));
+    const int q = (int)k;
+    const double s1 = (q & 1) ? cr : sr;
+    const double c1 = (q & 1) ? sr : cr;
+    sa = (q & 2) ? -s1 : s1;
+    ca = ((q + 1) & 2) ? -c1 : c1;
+}
+__device__ __forceinline__ void sincos_t(double a, double* s, double* c) {
+    if (__any(fabs(a) > 1e5)) {
+        sincos(a, s, c);
+    } else {
+        sincos_cw(a, *s, *c);
+    }
+}
+__device__ __forceinline__ void sincos_t(float a, float* s, float* c) { sincosf(a, s, c); }
+
 // Pseudo-Huber absolute value with unit steepness (Sec. II notation):
-// |a|_s = sqrt(a^2+1) - 1 = a^2/(sqrt(a^2+1)+1) and its slope a/sqrt(a^2+1),
-// with one square root and one division.
-template <class T>
-__device__ __forceinline__ void sabs_d(T a, T& val, T& der) {
-    const T r = sqrt_t(a * a + T(1));
-    const T inv = T(1) / (r * (r + T(1)));
+// |a|_s = sqrt(a^2+1) - 1 = a^2 y/(1 + y) with y = 1/sqrt(a^2+1), and its
+// slope a y.  y and 1/(1+y) start from the hardware reciprocal (square root)
+// estimates and take two Newton steps each (w >= 1, 1 + y in [1, 2]).
+__device__ __forceinline__ void sabs_d(double a, double& val, double& der) {
+    const double w = fma(a, a, 1.0);
+    double y = __builtin_amdgcn_rsq(w);
+    double hw = 0.5 * w;
+    y = y * fma(-hw * y, y, 1.5);
+    y = y * fma(-hw * y, y, 1.5);
+    const double d = 1.0 + y;
+    double q = __builtin_amdgcn_rcp(d);
+    q = q * fma(-d, q, 2.0);
+    q = q * fma(-d, q, 2.0);
+    der = a * y;
+    val = (a * a) * (y * q);
+}
+__device__ __forceinline__ void sabs_d(float a, float& val, float& der) {
+    const float r = sqrtf(a * a + 1.0f);
+    const float inv = 1.0f / (r * (r + 1.0f));
     val = (a * a) * (r * inv);
-    der = a * ((r + T(1)) * inv);
+    der = a * ((r + 1.0f) * inv);
 }
 
 enum RhsMode { LEAN = 0, FULL = 1, EMIT = 2 };

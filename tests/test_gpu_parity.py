@@ -189,8 +189,8 @@ def test_defects_match_discretize_and_oracle():
     ref = oracle.defects(model, data["X"], data["U"], data["s"], data["p"], 4)
     assert block_err(out["d"].t().cpu().numpy(), ref["d"], PHI64) <= TOL64
     assert block_err(out["xprop"].t().cpu().numpy(), ref["xprop"], PHI64) <= TOL64
-    # same nominal arithmetic in both kernels
-    assert torch.equal(out["xprop"], full["xprop"])
+    # the two kernels evaluate the same right-hand side (in different summation orders)
+    assert block_err(out["xprop"].t().cpu().numpy(), full["xprop"].t().cpu().numpy(), PHI64) <= 1e-13
     # checkpoint 0 is the node state; checkpoint 1 is the state after 2 substeps
     ck = out["ckpt"].cpu().numpy()
     np.testing.assert_array_equal(ck[0].T, data["X"][:6, :model.n])
