@@ -183,6 +183,87 @@ cis_status cis_discretize_adjoint(const cis_model *model, const cis_shape *shape
                                   const void *seed, void *gX, void *gU, void *gs,
                                   void *gparams, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of trajectories (multiple shooting over many trajectories at once,
+ * Sec. VI): the per-interval work of every trajectory is put on one device
+ * work list per model, sorted by decreasing substep count, and launched as
+ * one kernel per model; the models' kernels run concurrently when the batch
+ * is replayed as a HIP graph.
+ *
+ * A plan binds the buffers of every trajectory at creation (like the
+ * single-trajectory calls, all device pointers owned by the caller, same
+ * layouts and alignment rules).  Creation is NOT a hot call: it validates,
+ * allocates the plan's device memory (descriptors, work lists, and for the
+ * reverse sweep the checkpoints and partial sums), uploads it, synchronizes
+ * `stream`, and, when asked to tune, times the candidate launch schedules by
+ * running the batch (the outputs are then written).  cis_batch_run and
+ * cis_batch_graph_run are hot calls: no allocation, no synchronization.  A
+ * plan's runs must not overlap each other (they share the plan's device
+ * memory); run them on one stream, or order them.
+ * ------------------------------------------------------------------------ */
+typedef struct cis_batch_plan cis_batch_plan;
+
+/* One trajectory of a batch.  Inputs X, U, s, params and the shape fields
+ * mean what they mean for cis_discretize.  Outputs used by CIS_BATCH_DISCRETIZE:
+ * A, Bm, Bp, S, defect, xprop (xprop may be NULL).  Used by CIS_BATCH_ADJOINT:
+ * defect and xprop (F~ from the forward pass; xprop may be NULL), seed,
+ * gX, gU, gs, gparams (as for cis_discretize_adjoint).  Pointers an operation
+ * does not use may be NULL. */
+typedef struct {
+    const cis_model *model;
+    int32_t N, substeps;
+    int64_t ld_node, ld_int;
+    const void *X, *U, *s, *params;
+    void *A, *Bm, *Bp, *S, *defect, *xprop;
+    const void *seed;
+    void *gX, *gU, *gs, *gparams;
+} cis_traj;
+
+/* Operations a plan can run (bit mask at creation, one value at run time). */
+enum { CIS_BATCH_DISCRETIZE = 1, CIS_BATCH_ADJOINT = 2 };
+
+/* Launch schedule of the discretize kernels, per model.
+ *   CIS_SCHED_GRID       one workgroup per (interval, column group) unit;
+ *   CIS_SCHED_PERSISTENT a resident grid (occupancy x compute units) takes
+ *                        units from a device cursor (reset by the kernel);
+ *   CIS_SCHED_TUNE       time both at creation and keep the faster. */
+enum { CIS_SCHED_GRID = 1, CIS_SCHED_PERSISTENT = 2, CIS_SCHED_TUNE = 3 };
+
+/*
+ * Create a plan for n_traj trajectories (all of one dtype; CIS_BATCH_ADJOINT
+ * needs CIS_F64).  ckpt_every: substeps between the checkpoints of the reverse
+ * sweep; it must divide every trajectory's K, or be 0 to take, per
+ * trajectory, the largest divisor of K not above 8.  graph != 0 also builds
+ * the HIP graphs used by cis_batch_graph_run.
+ * Errors: CIS_ERR_NULL, CIS_ERR_DIM, CIS_ERR_LAYOUT, CIS_ERR_DTYPE,
+ * CIS_ERR_UNSUPPORTED (as for the single-trajectory calls, with the offending
+ * trajectory named by cis_last_error), CIS_ERR_HIP (allocation, upload,
+ * tuning or graph failure).  On error *plan is NULL and nothing is held.
+ */
+cis_status cis_batch_plan_create(const cis_traj *trajs, int32_t n_traj, cis_dtype dtype,
+                                 int32_t ops, int32_t sched, int32_t ckpt_every, int32_t graph,
+                                 void *stream, cis_batch_plan **plan);
+
+/* Enqueue one operation (CIS_BATCH_DISCRETIZE or CIS_BATCH_ADJOINT, which
+ * must have been requested at creation) of every trajectory on `stream`:
+ * the models' launches are issued one after another. */
+cis_status cis_batch_run(cis_batch_plan *plan, int32_t op, void *stream);
+
+/* Same work as cis_batch_run, replayed from the plan's HIP graph, in which
+ * the models' launches are independent nodes (they may run concurrently). */
+cis_status cis_batch_graph_run(cis_batch_plan *plan, int32_t op, void *stream);
+
+/* Description of a plan: number of model groups, and for group g (if
+ * 0 <= g < groups) its trajectories, work items (intervals), units per item,
+ * and the persistent grid size chosen for it (0 = one workgroup per unit).
+ * Any output pointer may be NULL. */
+cis_status cis_batch_plan_info(const cis_batch_plan *plan, int32_t g, int32_t *groups,
+                               int32_t *n_traj, int32_t *n_items, int32_t *units_per_item,
+                               int32_t *persist_blocks);
+
+/* Release a plan (NULL accepted); synchronizes the device first. */
+void cis_batch_plan_destroy(cis_batch_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

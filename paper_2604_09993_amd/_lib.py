@@ -25,12 +25,18 @@ CIS_ERR_HIP = 7
 CIS_ERR_UNSUPPORTED = 8
 CIS_F64 = 0
 CIS_F32 = 1
+CIS_BATCH_DISCRETIZE = 1
+CIS_BATCH_ADJOINT = 2
+CIS_SCHED_GRID = 1
+CIS_SCHED_PERSISTENT = 2
+CIS_SCHED_TUNE = 3
 
 # every symbol include/cis.h declares
 EXPORTS = [
     "cis_version", "cis_status_string", "cis_last_error", "cis_model_create",
     "cis_model_destroy", "cis_model_dims", "cis_discretize", "cis_defects",
-    "cis_adjoint_workspace_size", "cis_discretize_adjoint",
+    "cis_adjoint_workspace_size", "cis_discretize_adjoint", "cis_batch_plan_create",
+    "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
 ]
 
 
@@ -52,6 +58,15 @@ class Shape(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("substeps", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("ld_node", ctypes.c_int64), ("ld_int", ctypes.c_int64)]
+
+
+class Traj(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("N", ctypes.c_int32),
+                ("substeps", ctypes.c_int32), ("ld_node", ctypes.c_int64),
+                ("ld_int", ctypes.c_int64)] + [
+        (name, ctypes.c_void_p) for name in
+        ("X", "U", "s", "params", "A", "Bm", "Bp", "S", "defect", "xprop", "seed",
+         "gX", "gU", "gs", "gparams")]
 
 
 _lib = None
@@ -91,6 +106,17 @@ def load(build_if_missing: bool = True):
     lib.cis_discretize_adjoint.restype = St
     lib.cis_discretize_adjoint.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, P, I32]
                                            + [P] * 6 + [ctypes.c_size_t, P])
+    lib.cis_batch_plan_create.restype = St
+    lib.cis_batch_plan_create.argtypes = [ctypes.POINTER(Traj), I32, I32, I32, I32, I32, I32, P,
+                                          ctypes.POINTER(P)]
+    lib.cis_batch_run.restype = St
+    lib.cis_batch_run.argtypes = [P, I32, P]
+    lib.cis_batch_graph_run.restype = St
+    lib.cis_batch_graph_run.argtypes = [P, I32, P]
+    lib.cis_batch_plan_info.restype = St
+    lib.cis_batch_plan_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 5
+    lib.cis_batch_plan_destroy.restype = None
+    lib.cis_batch_plan_destroy.argtypes = [P]
     _lib = lib
     return lib
 

@@ -60,8 +60,9 @@ class CisModel:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.cis_model_destroy(h)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and lib is not None:
+            lib.cis_model_destroy(h)
             self._h = None
 
 
@@ -245,3 +246,99 @@ def to_device_soa(arr, device="cuda", dtype=torch.float64, ld=None):
         pad = torch.zeros((t.shape[0], ld - t.shape[1]), dtype=t.dtype)
         t = torch.cat([t, pad], dim=1)
     return t.to(device=device, dtype=dtype).contiguous()
+
+
+_SCHED = {"grid": _lib.CIS_SCHED_GRID, "persistent": _lib.CIS_SCHED_PERSISTENT,
+          "tune": _lib.CIS_SCHED_TUNE}
+_OPS = {"discretize": _lib.CIS_BATCH_DISCRETIZE, "adjoint": _lib.CIS_BATCH_ADJOINT}
+
+
+class BatchPlan:
+    """Many trajectories (of one or several models) discretized together.
+
+    ``trajs`` is a list of dicts with keys cm, X, U, s, params, K (inputs laid
+    out as for :func:`discretize`).  The plan allocates, per trajectory, the
+    outputs of the requested operations: A, Bm, Bp, S, d, xprop
+    ("discretize"); d, xprop, seed (zeros, to be filled in place by the
+    caller), gX, gU, gs, gp ("adjoint").  They are in ``self.out[i]`` and stay
+    bound to the plan: each run overwrites them.
+    """
+
+    def __init__(self, trajs, ops=("discretize",), *, sched="tune", ckpt_every=0, graph=True,
+                 stream=None):
+        lib = _lib.load()
+        if not trajs:
+            raise ValueError("a batch needs at least one trajectory")
+        self.ops = 0
+        for o in ops:
+            self.ops |= _OPS[o]
+        dtype = trajs[0]["X"].dtype
+        self.out = []
+        arr = (_lib.Traj * len(trajs))()
+        for i, t in enumerate(trajs):
+            cm, X, U, s, params = t["cm"], t["X"], t.get("U"), t["s"], t["params"]
+            _check_inputs(cm, X, U, s, params)
+            if X.dtype != dtype:
+                raise ValueError("all trajectories of a batch share one dtype")
+            N, nx, m = s.shape[0], cm.nx, cm.m
+            kw = dict(device=X.device, dtype=dtype)
+            o = dict(d=torch.empty((nx, N), **kw), xprop=torch.empty((nx, N), **kw))
+            if self.ops & _lib.CIS_BATCH_DISCRETIZE:
+                o.update(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                         Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw))
+            if self.ops & _lib.CIS_BATCH_ADJOINT:
+                ld = X.stride(0)
+                o.update(seed=torch.zeros((nx, N), **kw), gX=torch.empty((nx, ld), **kw),
+                         gU=torch.empty((max(m, 1), ld), **kw), gs=torch.empty((N,), **kw),
+                         gp=torch.empty((cm.np,), **kw))
+            o["_in"] = (cm, X, U, s, params)   # keep the inputs alive with the plan
+            self.out.append(o)
+            tr = arr[i]
+            tr.model = cm.handle.value
+            tr.N, tr.substeps = N, int(t["K"])
+            tr.ld_node, tr.ld_int = X.stride(0), N
+            for name, ten in (("X", X), ("U", U if m else None), ("s", s), ("params", params)):
+                setattr(tr, name, None if ten is None else ten.data_ptr())
+            for name, key in (("A", "A"), ("Bm", "Bm"), ("Bp", "Bp"), ("S", "S"),
+                              ("defect", "d"), ("xprop", "xprop"), ("seed", "seed"),
+                              ("gX", "gX"), ("gU", "gU"), ("gs", "gs"), ("gparams", "gp")):
+                ten = o.get(key)
+                if key in ("Bm", "Bp", "gU") and m == 0:
+                    ten = None
+                setattr(tr, name, None if ten is None else ten.data_ptr())
+        self._arr = arr
+        h = ctypes.c_void_p()
+        _lib.check(lib.cis_batch_plan_create(arr, len(trajs), _dtype_code(dtype), self.ops,
+                                             _SCHED[sched], int(ckpt_every), int(bool(graph)),
+                                             _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.graph = bool(graph)
+
+    def run(self, op="discretize", *, graph=False, stream=None):
+        """Enqueue one operation over the whole batch (graph replay if graph=True)."""
+        lib = _lib.load()
+        fn = lib.cis_batch_graph_run if graph else lib.cis_batch_run
+        _lib.check(fn(self._h, _OPS[op], _stream(stream)))
+
+    def groups(self):
+        """Per model group: trajectories, items, units per item, persistent grid (0 = grid)."""
+        lib = _lib.load()
+        ng = ctypes.c_int32()
+        _lib.check(lib.cis_batch_plan_info(self._h, -1, ctypes.byref(ng), None, None, None, None))
+        res = []
+        for g in range(ng.value):
+            v = [ctypes.c_int32() for _ in range(4)]
+            _lib.check(lib.cis_batch_plan_info(self._h, g, None, *[ctypes.byref(x) for x in v]))
+            res.append(dict(n_traj=v[0].value, n_items=v[1].value, units_per_item=v[2].value,
+                            persist_blocks=v[3].value))
+        return res
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and lib is not None:
+            lib.cis_batch_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()

@@ -18,6 +18,7 @@
 #include "cis_model.hpp"
 #include "cis_body.hpp"
 #include "cis_host.hpp"
+#include "cis_launch.hpp"
 
 namespace cis {
 
@@ -205,16 +206,15 @@ struct DiscShared {
     T coef[2][Coef<TP>::SIZE];
 };
 
+// Interval k, column group grp, by the whole workgroup.
 template <class T, class TP>
-__global__ void __launch_bounds__(TP::NTHREADS)
-    k_discretize(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+__device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const FwdArgs<T>& a,
+                                                const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                                const int k, const int grp) {
     constexpr int NB = TP::NB, NX = TP::NX, NXT = TP::NXT, M = TP::M, NY = TP::NY;
     constexpr int NQ = TP::NQ, NC = TP::NC, LB = TP::LB, G = TP::G, D = TP::D, L = TP::L;
     using C = Coef<TP>;
     static_assert(D > 0 || L <= 1, "several contacts on the torso are not laid out");
-    __shared__ DiscShared<T, TP> sh;
-    const int k = blockIdx.x;
-    const int grp = blockIdx.y;   // column group of this workgroup
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int nth = TP::NTHREADS;
     load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
@@ -366,6 +366,42 @@ __global__ void __launch_bounds__(TP::NTHREADS)
     }
 }
 
+template <class T, class TP>
+__global__ void __launch_bounds__(TP::NTHREADS)
+    k_discretize(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ DiscShared<T, TP> sh;
+    discretize_item<T, TP>(sh, a, mc, xcd_slot(blockIdx.x, gridDim.x), blockIdx.y);
+}
+
+// K5: a batch of trajectories of one model.  PERSIST = false: one workgroup per
+// work unit (dispatch order follows the cost-sorted list); PERSIST = true: a
+// resident grid draws units from an atomic cursor until the list is empty.
+template <class T, class TP, bool PERSIST>
+__global__ void __launch_bounds__(TP::NTHREADS)
+    k_discretize_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ DiscShared<T, TP> sh;
+    const int total = b.n_items * TP::NGRP;
+    if constexpr (!PERSIST) {
+        int item, grp;
+        unit_item(xcd_slot(blockIdx.x, gridDim.x), b.n_items, TP::NGRP, item, grp);
+        const int2 it = b.items[item];
+        const FwdArgs<T> a = b.descs[it.x];
+        discretize_item<T, TP>(sh, a, mc, it.y, grp);
+    } else {
+        __shared__ int slot;
+        for (;;) {
+            const int u = fetch_unit(b.cursor, &slot);
+            if (u >= total) break;
+            int item, grp;
+            unit_item(u, b.n_items, TP::NGRP, item, grp);
+            const int2 it = b.items[item];
+            const FwdArgs<T> a = b.descs[it.x];
+            discretize_item<T, TP>(sh, a, mc, it.y, grp);
+        }
+        retire_block(b.cursor);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K1: defects and checkpoints.  One wave per interval.
 // ---------------------------------------------------------------------------
@@ -376,11 +412,10 @@ struct DefShared {
 };
 
 template <class T, class TP>
-__global__ void __launch_bounds__(64)
-    k_defects(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+__device__ __forceinline__ void defects_item(DefShared<T, TP>& sh, const FwdArgs<T>& a,
+                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                             const int k) {
     constexpr int NX = TP::NX, NXT = TP::NXT;
-    __shared__ DefShared<T, TP> sh;
-    const int k = blockIdx.x;
     const int lane = threadIdx.x;
     load_interval<T, TP>(sh.iv, a, mc, k, lane, 64);
     RowState<T> rs;
@@ -416,6 +451,22 @@ __global__ void __launch_bounds__(64)
             a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
         }
     }
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(64)
+    k_defects(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ DefShared<T, TP> sh;
+    defects_item<T, TP>(sh, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(64)
+    k_defects_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ DefShared<T, TP> sh;
+    const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
+    const FwdArgs<T> a = b.descs[it.x];
+    defects_item<T, TP>(sh, a, mc, it.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -476,6 +527,83 @@ static cis_status launch_defects(const cis_model* m, const cis_shape* sh, const 
                                    0, stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_defects launch: %s", hipGetErrorString(e));
     return CIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched launch preparation (one model group)
+// ---------------------------------------------------------------------------
+template <class T>
+static BatchArgs<FwdArgs<T>> batch_args(const BatchGroupDev& g) {
+    BatchArgs<FwdArgs<T>> b;
+    b.descs = (const FwdArgs<T>*)g.fdesc;
+    b.items = g.items;
+    b.n_items = g.n_items;
+    b.cursor = g.cursor;
+    return b;
+}
+
+template <class T, int L, int D>
+static cis_status prep_disc_t(const cis_model* m, const BatchGroupDev& g, int persist_blocks,
+                              KLaunch* out) {
+    using TP = Topo<L, D, sizeof(T) == 8 ? 2 : 6>;
+    out->arg(batch_args<T>(g));
+    out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
+    out->block = dim3(TP::NTHREADS);
+    if (persist_blocks > 0) {
+        out->func = (const void*)&k_discretize_batch<T, TP, true>;
+        out->grid = dim3(persist_blocks);
+    } else {
+        out->func = (const void*)&k_discretize_batch<T, TP, false>;
+        out->grid = dim3(g.n_items * TP::NGRP);
+    }
+    return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_discretize_batch: launch record refused");
+}
+
+template <class T, int L, int D>
+static cis_status prep_def_t(const cis_model* m, const BatchGroupDev& g, KLaunch* out) {
+    using TP = Topo<L, D>;
+    out->arg(batch_args<T>(g));
+    out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
+    out->func = (const void*)&k_defects_batch<T, TP>;
+    out->grid = dim3(g.n_items);
+    out->block = dim3(64);
+    return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_defects_batch: launch record refused");
+}
+
+template <class T, int L, int D>
+static int units_t() {
+    return Topo<L, D, sizeof(T) == 8 ? 2 : 6>::NGRP;
+}
+
+cis_status prep_discretize_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
+                                 int persist_blocks, KLaunch* out) {
+#define CIS_PREP_DISC(LL, DD)                                                               \
+    if (m->L == LL && m->D == DD)                                                           \
+        return dtype == CIS_F64 ? prep_disc_t<double, LL, DD>(m, g, persist_blocks, out)    \
+                                : prep_disc_t<float, LL, DD>(m, g, persist_blocks, out);
+    CIS_TOPOLOGIES(CIS_PREP_DISC)
+#undef CIS_PREP_DISC
+    return fail(CIS_ERR_UNSUPPORTED, "prep_discretize_batch: topology has no compiled kernel");
+}
+
+cis_status prep_defects_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
+                              KLaunch* out) {
+#define CIS_PREP_DEF(LL, DD)                                                                \
+    if (m->L == LL && m->D == DD)                                                           \
+        return dtype == CIS_F64 ? prep_def_t<double, LL, DD>(m, g, out)                     \
+                                : prep_def_t<float, LL, DD>(m, g, out);
+    CIS_TOPOLOGIES(CIS_PREP_DEF)
+#undef CIS_PREP_DEF
+    return fail(CIS_ERR_UNSUPPORTED, "prep_defects_batch: topology has no compiled kernel");
+}
+
+int discretize_units_per_item(const cis_model* m, int32_t dtype) {
+#define CIS_UNITS(LL, DD)                                                                   \
+    if (m->L == LL && m->D == DD)                                                           \
+        return dtype == CIS_F64 ? units_t<double, LL, DD>() : units_t<float, LL, DD>();
+    CIS_TOPOLOGIES(CIS_UNITS)
+#undef CIS_UNITS
+    return 0;
 }
 
 }  // namespace cis

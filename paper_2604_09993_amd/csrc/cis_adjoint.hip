@@ -20,6 +20,7 @@
 
 #include "../../include/cis.h"
 #include "cis_host.hpp"
+#include "cis_launch.hpp"
 #include "cis_model.hpp"
 
 namespace cis {
@@ -37,17 +38,6 @@ struct AdjShared {
     T jslot[cmax(TP::NJ, 1)][8];        // th_p, th_c, w_p, w_c, x_p, x_c, y_p, y_c
     T cslot[cmax(TP::NC, 1)][6];        // x, y, th, xd, yd, w of the contact body
     T red[64];
-};
-
-template <class T>
-struct AdjArgs {
-    FwdArgs<T> f;
-    const T* seed;
-    T* gX;
-    T* gs;
-    T* ws_uk;    // [m][N] adjoint of U_k from interval k
-    T* ws_uk1;   // [m][N] adjoint of U_{k+1} from interval k
-    T* ws_p;     // [P][N] parameter adjoint from interval k
 };
 
 // Reverse one RK4 stage at the stage input held in ax.sc.ns (coefficients are
@@ -200,11 +190,10 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
 }
 
 template <class T, class TP>
-__global__ void __launch_bounds__(64)
-    k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+__device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
+                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                             const int k) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NX = TP::NX, NXT = TP::NXT;
-    __shared__ AdjShared<T, TP> ax;
-    const int k = blockIdx.x;
     const int lane = threadIdx.x;
     const FwdArgs<T>& f = a.f;
     load_interval<T, TP>(ax.iv, f, mc, k, lane, 64);
@@ -324,12 +313,28 @@ __global__ void __launch_bounds__(64)
     if (lane < NB) a.ws_p[(int64_t)(2 + lane) * N + k] = macc;
 }
 
+template <class T, class TP>
+__global__ void __launch_bounds__(64)
+    k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ AdjShared<T, TP> ax;
+    adjoint_item<T, TP>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(64)
+    k_adjoint_batch(BatchArgs<AdjArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ AdjShared<T, TP> ax;
+    const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
+    const AdjArgs<T> a = b.descs[it.x];
+    adjoint_item<T, TP>(ax, a, mc, it.y);
+}
+
 // gU, gX_N and gp from the per-interval partials, in a fixed order.
 template <class T>
-__global__ void __launch_bounds__(256)
-    k_adjoint_reduce(const T* ws_uk, const T* ws_uk1, const T* ws_p, T* gU, T* gX, T* gp, int N,
-                     int m, int nxt, int np, int64_t ldn) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adjoint_reduce_part(const T* ws_uk, const T* ws_uk1,
+                                                    const T* ws_p, T* gU, T* gX, T* gp, int N,
+                                                    int m, int nxt, int np, int64_t ldn,
+                                                    int64_t t) {
     const int64_t nu = (int64_t)m * (N + 1);
     if (t < nu) {
         const int c = (int)(t / (N + 1)), k = (int)(t % (N + 1));
@@ -344,6 +349,23 @@ __global__ void __launch_bounds__(256)
         for (int k = 0; k < N; ++k) acc += ws_p[(int64_t)c * N + k];
         gp[c] = acc;
     }
+}
+
+// One workgroup per trajectory of a batch.
+__global__ void __launch_bounds__(256) k_adjoint_reduce_batch(const RedDesc* rd) {
+    const RedDesc r = rd[blockIdx.x];
+    const int64_t work = (int64_t)r.m * (r.N + 1) + r.nxt + r.np;
+    for (int64_t t = threadIdx.x; t < work; t += blockDim.x)
+        adjoint_reduce_part<double>(r.ws_uk, r.ws_uk1, r.ws_p, r.gU, r.gX, r.gp, r.N, r.m, r.nxt,
+                                    r.np, r.ldn, t);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_adjoint_reduce(const T* ws_uk, const T* ws_uk1, const T* ws_p, T* gU, T* gX, T* gp, int N,
+                     int m, int nxt, int np, int64_t ldn) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    adjoint_reduce_part<T>(ws_uk, ws_uk1, ws_p, gU, gX, gp, N, m, nxt, np, ldn, t);
 }
 
 static size_t ws_elems(const cis_model* m, int N) { return (size_t)(2 * m->m + m->np) * N; }
@@ -396,6 +418,38 @@ static cis_status launch_adjoint(const cis_model* m, const cis_shape* sh, const 
     if (e != hipSuccess)
         return fail(CIS_ERR_HIP, "k_adjoint_reduce launch: %s", hipGetErrorString(e));
     return CIS_OK;
+}
+
+template <int L, int D>
+static cis_status prep_adj_t(const cis_model* m, const BatchGroupDev& g, KLaunch* out) {
+    using TP = Topo<L, D>;
+    BatchArgs<AdjArgs<double>> b;
+    b.descs = (const AdjArgs<double>*)g.adesc;
+    b.items = g.items;
+    b.n_items = g.n_items;
+    b.cursor = g.cursor;
+    out->arg(b);
+    out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
+    out->func = (const void*)&k_adjoint_batch<double, TP>;
+    out->grid = dim3(g.n_items);
+    out->block = dim3(64);
+    return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_adjoint_batch: launch record refused");
+}
+
+cis_status prep_adjoint_batch(const cis_model* m, const BatchGroupDev& g, KLaunch* out) {
+#define CIS_PREP_ADJ(LL, DD) \
+    if (m->L == LL && m->D == DD) return prep_adj_t<LL, DD>(m, g, out);
+    CIS_TOPOLOGIES(CIS_PREP_ADJ)
+#undef CIS_PREP_ADJ
+    return fail(CIS_ERR_UNSUPPORTED, "prep_adjoint_batch: topology has no compiled kernel");
+}
+
+cis_status prep_adjoint_reduce_batch(const void* rdesc, int n_traj, KLaunch* out) {
+    out->arg((const RedDesc*)rdesc);
+    out->func = (const void*)&k_adjoint_reduce_batch;
+    out->grid = dim3(n_traj);
+    out->block = dim3(256);
+    return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_adjoint_reduce_batch: launch record refused");
 }
 
 }  // namespace cis

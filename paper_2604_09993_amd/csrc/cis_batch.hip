@@ -1,0 +1,480 @@
+// Batched multiple shooting over many trajectories: plan creation (work
+// lists, descriptors, schedule tuning, HIP graphs) and the hot run calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/cis.h"
+#include "cis_host.hpp"
+#include "cis_launch.hpp"
+#include "cis_model.hpp"
+
+using namespace cis;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Group {
+    const cis_model* model = nullptr;
+    std::vector<int> trajs;    // indices into the plan's trajectory list
+    std::vector<int2> items;   // {group-local trajectory, interval}
+    int units_per_item = 0;
+    int persist_blocks = 0;
+    size_t fdesc_off = 0, ddesc_off = 0, adesc_off = 0, items_off = 0, cursor_off = 0;
+    BatchGroupDev dev{};
+    KLaunch disc, def, adj;
+};
+
+int auto_ckpt(int K) {
+    for (int c = 8; c > 1; --c)
+        if (K % c == 0) return c;
+    return 1;
+}
+
+}  // namespace
+
+struct cis_batch_plan {
+    int device = 0;
+    int32_t dtype = CIS_F64, ops = 0;
+    std::vector<cis_traj> trajs;
+    std::vector<int> ckpt_every;
+    std::vector<size_t> ckpt_off, ws_off;
+    std::vector<Group> groups;
+    size_t rdesc_off = 0;
+    unsigned char* dmem = nullptr;
+    KLaunch red;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+static void plan_free(cis_batch_plan* p) {
+    if (!p) return;
+    for (int i = 0; i < 2; ++i) {
+        if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
+        if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
+    }
+    if (p->dmem) (void)hipFree(p->dmem);
+    delete p;
+}
+
+// Per-trajectory argument checks of one operation.
+static cis_status check_traj(const cis_traj& t, int i, int32_t dtype, int32_t ops) {
+    cis_shape sh;
+    std::memset(&sh, 0, sizeof(sh));
+    sh.N = t.N;
+    sh.substeps = t.substeps;
+    sh.dtype = (cis_dtype)dtype;
+    sh.ld_node = t.ld_node;
+    sh.ld_int = t.ld_int;
+    cis_status st = check_common(t.model, &sh, t.X, t.U, t.s, t.params);
+    if (st != CIS_OK) {
+        char why[256];
+        std::snprintf(why, sizeof(why), "%s", cis_last_error());
+        return fail(st, "trajectory %d: %s", i, why);
+    }
+    const size_t es = elem_size(dtype);
+    const bool hasm = t.model->m > 0;
+    if (ops & CIS_BATCH_DISCRETIZE) {
+        if (!t.A || !t.S || !t.defect || (hasm && (!t.Bm || !t.Bp)))
+            return fail(CIS_ERR_NULL, "trajectory %d: A, S, defect (and Bm, Bp when m > 0) are required", i);
+        if (!aligned(t.A, es) || !aligned(t.S, es) || !aligned(t.defect, es) ||
+            !aligned(t.xprop, es) || !aligned(t.Bm, es) || !aligned(t.Bp, es))
+            return fail(CIS_ERR_LAYOUT, "trajectory %d: output pointer not aligned to %zu bytes", i, es);
+    }
+    if (ops & CIS_BATCH_ADJOINT) {
+        if (!t.defect || !t.seed || !t.gX || !t.gs || !t.gparams || (hasm && !t.gU))
+            return fail(CIS_ERR_NULL, "trajectory %d: defect, seed, gX, gs, gparams (and gU when m > 0) are required", i);
+        if (!aligned(t.defect, es) || !aligned(t.xprop, es) || !aligned(t.seed, es) ||
+            !aligned(t.gX, es) || !aligned(t.gU, es) || !aligned(t.gs, es) || !aligned(t.gparams, es))
+            return fail(CIS_ERR_LAYOUT, "trajectory %d: pointer not aligned to %zu bytes", i, es);
+    }
+    return CIS_OK;
+}
+
+template <class T>
+static FwdArgs<T> fwd_desc(const cis_traj& t) {
+    FwdArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.X = (const T*)t.X;
+    a.U = (const T*)t.U;
+    a.s = (const T*)t.s;
+    a.prm = (const T*)t.params;
+    a.ldn = t.ld_node;
+    a.ldi = t.ld_int;
+    a.N = t.N;
+    a.K = t.substeps;
+    a.C = 1;
+    return a;
+}
+
+// Median time in microseconds of `reps` launches of one group's discretize kernel.
+static float time_launch(KLaunch& l, hipStream_t s, int reps) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    std::vector<float> ts;
+    bool ok = l.launch(s) == hipSuccess;   // warm-up
+    for (int r = 0; ok && r < reps; ++r) {
+        ok = hipEventRecord(e0, s) == hipSuccess && l.launch(s) == hipSuccess &&
+             hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        ts.push_back(ms * 1e3f);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok || ts.empty()) return -1.f;
+    std::sort(ts.begin(), ts.end());
+    return ts[ts.size() / 2];
+}
+
+static cis_status build_graph(cis_batch_plan* p, int op) {
+    const int gi = op == CIS_BATCH_DISCRETIZE ? 0 : 1;
+    hipGraph_t g = nullptr;
+    if (hipGraphCreate(&g, 0) != hipSuccess) return fail(CIS_ERR_HIP, "hipGraphCreate failed");
+    p->graph[gi] = g;
+    std::vector<hipGraphNode_t> tails;
+    for (Group& gr : p->groups) {
+        hipGraphNode_t n0 = nullptr, n1 = nullptr;
+        if (op == CIS_BATCH_DISCRETIZE) {
+            if (gr.disc.node(g, nullptr, 0, &n0) != hipSuccess)
+                return fail(CIS_ERR_HIP, "graph: discretize node refused");
+        } else {
+            if (gr.def.node(g, nullptr, 0, &n0) != hipSuccess ||
+                gr.adj.node(g, &n0, 1, &n1) != hipSuccess)
+                return fail(CIS_ERR_HIP, "graph: defects/adjoint node refused");
+            tails.push_back(n1);
+        }
+    }
+    if (op == CIS_BATCH_ADJOINT) {
+        hipGraphNode_t nr = nullptr;
+        if (p->red.node(g, tails.data(), tails.size(), &nr) != hipSuccess)
+            return fail(CIS_ERR_HIP, "graph: reduction node refused");
+    }
+    hipError_t e = hipGraphInstantiate(&p->exec[gi], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(CIS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_traj,
+                                            cis_dtype dtype, int32_t ops, int32_t sched,
+                                            int32_t ckpt_every, int32_t graph, void* stream,
+                                            cis_batch_plan** out) {
+    if (!out) return fail(CIS_ERR_NULL, "cis_batch_plan_create: plan output is required");
+    *out = nullptr;
+    if (!trajs) return fail(CIS_ERR_NULL, "cis_batch_plan_create: trajs is required");
+    if (n_traj < 1) return fail(CIS_ERR_DIM, "cis_batch_plan_create: n_traj=%d must be >= 1", n_traj);
+    if (dtype != CIS_F64 && dtype != CIS_F32)
+        return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: unknown dtype %d", dtype);
+    if (ops < 1 || ops > 3) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ops=%d is not a mask of operations", ops);
+    if ((ops & CIS_BATCH_ADJOINT) && dtype != CIS_F64)
+        return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: the reverse sweep is offered in CIS_F64 only");
+    if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE)
+        return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched);
+    if (ckpt_every < 0) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ckpt_every=%d < 0", ckpt_every);
+    for (int i = 0; i < n_traj; ++i) {
+        cis_status st = check_traj(trajs[i], i, dtype, ops);
+        if (st != CIS_OK) return st;
+        if ((ops & CIS_BATCH_ADJOINT) && ckpt_every > 0 && trajs[i].substeps % ckpt_every != 0)
+            return fail(CIS_ERR_DIM, "trajectory %d: ckpt_every=%d must divide K=%d", i, ckpt_every,
+                        trajs[i].substeps);
+        if ((int64_t)trajs[i].N > (1 << 30))
+            return fail(CIS_ERR_DIM, "trajectory %d: N too large", i);
+    }
+    cis_batch_plan* p = new cis_batch_plan();
+    p->dtype = dtype;
+    p->ops = ops;
+    p->trajs.assign(trajs, trajs + n_traj);
+    (void)hipGetDevice(&p->device);
+    hipStream_t hs = (hipStream_t)stream;
+
+    // group by model, work items sorted by decreasing K (then trajectory, interval)
+    for (int i = 0; i < n_traj; ++i) {
+        const cis_model* m = trajs[i].model;
+        auto it = std::find_if(p->groups.begin(), p->groups.end(),
+                               [&](const Group& g) { return g.model == m; });
+        if (it == p->groups.end()) {
+            p->groups.emplace_back();
+            p->groups.back().model = m;
+            it = p->groups.end() - 1;
+        }
+        it->trajs.push_back(i);
+    }
+    int64_t total_items = 0;
+    for (Group& g : p->groups) {
+        for (int lt = 0; lt < (int)g.trajs.size(); ++lt)
+            for (int k = 0; k < trajs[g.trajs[lt]].N; ++k) g.items.push_back(make_int2(lt, k));
+        std::stable_sort(g.items.begin(), g.items.end(), [&](const int2& a, const int2& b) {
+            return trajs[g.trajs[a.x]].substeps > trajs[g.trajs[b.x]].substeps;
+        });
+        g.units_per_item = discretize_units_per_item(g.model, dtype);
+        total_items += (int64_t)g.items.size();
+        if ((int64_t)g.items.size() * g.units_per_item > (int64_t)1 << 30) {
+            plan_free(p);
+            return fail(CIS_ERR_DIM, "cis_batch_plan_create: work list too long");
+        }
+    }
+    (void)total_items;
+
+    // device memory: descriptors, work lists, cursors; checkpoints and partials
+    const size_t es = elem_size(dtype);
+    const size_t fsz = dtype == CIS_F64 ? sizeof(FwdArgs<double>) : sizeof(FwdArgs<float>);
+    size_t off = 0;
+    for (Group& g : p->groups) {
+        const size_t nt = g.trajs.size();
+        g.fdesc_off = off;
+        off = align_up(off + nt * fsz);
+        g.ddesc_off = off;
+        off = align_up(off + nt * fsz);
+        g.adesc_off = off;
+        off = align_up(off + nt * sizeof(AdjArgs<double>));
+        g.items_off = off;
+        off = align_up(off + g.items.size() * sizeof(int2));
+        g.cursor_off = off;
+        off = align_up(off + 2 * sizeof(int));
+    }
+    p->rdesc_off = off;
+    off = align_up(off + (ops & CIS_BATCH_ADJOINT ? n_traj * sizeof(RedDesc) : 0));
+    const size_t host_part = off;
+    p->ckpt_every.assign(n_traj, 1);
+    p->ckpt_off.assign(n_traj, 0);
+    p->ws_off.assign(n_traj, 0);
+    if (ops & CIS_BATCH_ADJOINT) {
+        for (int i = 0; i < n_traj; ++i) {
+            const cis_traj& t = trajs[i];
+            const int C = ckpt_every > 0 ? ckpt_every : auto_ckpt(t.substeps);
+            p->ckpt_every[i] = C;
+            p->ckpt_off[i] = off;
+            off = align_up(off + (size_t)(t.substeps / C) * t.model->n * t.ld_int * es);
+            p->ws_off[i] = off;
+            off = align_up(off + (size_t)(2 * t.model->m + t.model->np) * t.N * sizeof(double));
+        }
+    }
+    hipError_t e = hipMalloc((void**)&p->dmem, off);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return fail(CIS_ERR_HIP, "cis_batch_plan_create: hipMalloc(%zu): %s", off, hipGetErrorString(e));
+    }
+    unsigned char* d = p->dmem;
+
+    // host image of the descriptor part
+    std::vector<unsigned char> img(host_part, 0);
+    for (Group& g : p->groups) {
+        for (size_t lt = 0; lt < g.trajs.size(); ++lt) {
+            const int i = g.trajs[lt];
+            const cis_traj& t = trajs[i];
+            if (dtype == CIS_F64) {
+                FwdArgs<double> a = fwd_desc<double>(t);
+                a.A = (double*)t.A;
+                a.Bm = (double*)t.Bm;
+                a.Bp = (double*)t.Bp;
+                a.S = (double*)t.S;
+                a.defect = (double*)t.defect;
+                a.xprop = (double*)t.xprop;
+                std::memcpy(&img[g.fdesc_off + lt * fsz], &a, fsz);
+                FwdArgs<double> f = fwd_desc<double>(t);
+                f.defect = (double*)t.defect;
+                f.xprop = (double*)t.xprop;
+                if (ops & CIS_BATCH_ADJOINT) {
+                    f.ckpt = (double*)(d + p->ckpt_off[i]);
+                    f.C = p->ckpt_every[i];
+                }
+                std::memcpy(&img[g.ddesc_off + lt * fsz], &f, fsz);
+                AdjArgs<double> ad;
+                std::memset(&ad, 0, sizeof(ad));
+                ad.f = f;
+                ad.seed = (const double*)t.seed;
+                ad.gX = (double*)t.gX;
+                ad.gs = (double*)t.gs;
+                if (ops & CIS_BATCH_ADJOINT) {
+                    double* w = (double*)(d + p->ws_off[i]);
+                    ad.ws_uk = w;
+                    ad.ws_uk1 = w + (size_t)t.model->m * t.N;
+                    ad.ws_p = w + (size_t)2 * t.model->m * t.N;
+                }
+                std::memcpy(&img[g.adesc_off + lt * sizeof(ad)], &ad, sizeof(ad));
+            } else {
+                FwdArgs<float> a = fwd_desc<float>(t);
+                a.A = (float*)t.A;
+                a.Bm = (float*)t.Bm;
+                a.Bp = (float*)t.Bp;
+                a.S = (float*)t.S;
+                a.defect = (float*)t.defect;
+                a.xprop = (float*)t.xprop;
+                std::memcpy(&img[g.fdesc_off + lt * fsz], &a, fsz);
+                FwdArgs<float> f = fwd_desc<float>(t);
+                f.defect = (float*)t.defect;
+                f.xprop = (float*)t.xprop;
+                std::memcpy(&img[g.ddesc_off + lt * fsz], &f, fsz);
+            }
+        }
+        if (!g.items.empty())
+            std::memcpy(&img[g.items_off], g.items.data(), g.items.size() * sizeof(int2));
+    }
+    if (ops & CIS_BATCH_ADJOINT) {
+        for (int i = 0; i < n_traj; ++i) {
+            const cis_traj& t = trajs[i];
+            RedDesc r;
+            std::memset(&r, 0, sizeof(r));
+            const double* w = (const double*)(d + p->ws_off[i]);
+            r.ws_uk = w;
+            r.ws_uk1 = w + (size_t)t.model->m * t.N;
+            r.ws_p = w + (size_t)2 * t.model->m * t.N;
+            r.gU = (double*)t.gU;
+            r.gX = (double*)t.gX;
+            r.gp = (double*)t.gparams;
+            r.N = t.N;
+            r.m = t.model->m;
+            r.nxt = t.model->nx;
+            r.np = t.model->np;
+            r.ldn = t.ld_node;
+            std::memcpy(&img[p->rdesc_off + i * sizeof(RedDesc)], &r, sizeof(r));
+        }
+    }
+    e = hipMemcpyAsync(d, img.data(), host_part, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return fail(CIS_ERR_HIP, "cis_batch_plan_create: upload: %s", hipGetErrorString(e));
+    }
+
+    // launch records
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (ncu < 1) ncu = 1;
+    for (Group& g : p->groups) {
+        g.dev.fdesc = d + g.fdesc_off;
+        g.dev.adesc = d + g.adesc_off;
+        g.dev.items = (const int2*)(d + g.items_off);
+        g.dev.n_items = (int)g.items.size();
+        g.dev.cursor = (int*)(d + g.cursor_off);
+        cis_status st;
+        if (ops & CIS_BATCH_DISCRETIZE) {
+            const int units = g.dev.n_items * g.units_per_item;
+            KLaunch probe;
+            st = prep_discretize_batch(g.model, dtype, g.dev, 1, &probe);
+            if (st != CIS_OK) {
+                plan_free(p);
+                return st;
+            }
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, probe.func, probe.block.x, 0) !=
+                    hipSuccess || occ < 1)
+                occ = 1;
+            const int pblocks = std::min(units, occ * ncu);
+            KLaunch grid_l, pers_l;
+            st = prep_discretize_batch(g.model, dtype, g.dev, 0, &grid_l);
+            if (st == CIS_OK) st = prep_discretize_batch(g.model, dtype, g.dev, pblocks, &pers_l);
+            if (st != CIS_OK) {
+                plan_free(p);
+                return st;
+            }
+            int choice = sched == CIS_SCHED_PERSISTENT ? pblocks : 0;
+            if (sched == CIS_SCHED_TUNE) {
+                const float tg = time_launch(grid_l, hs, 3);
+                const float tp = time_launch(pers_l, hs, 3);
+                if (tg < 0.f || tp < 0.f) {
+                    plan_free(p);
+                    return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
+                }
+                choice = tp < tg ? pblocks : 0;
+            }
+            g.persist_blocks = choice;
+            g.disc = choice ? pers_l : grid_l;
+        }
+        if (ops & CIS_BATCH_ADJOINT) {
+            BatchGroupDev dd = g.dev;
+            dd.fdesc = d + g.ddesc_off;
+            st = prep_defects_batch(g.model, dtype, dd, &g.def);
+            if (st == CIS_OK) st = prep_adjoint_batch(g.model, g.dev, &g.adj);
+            if (st != CIS_OK) {
+                plan_free(p);
+                return st;
+            }
+        }
+    }
+    if (ops & CIS_BATCH_ADJOINT) {
+        cis_status st = prep_adjoint_reduce_batch(d + p->rdesc_off, n_traj, &p->red);
+        if (st != CIS_OK) {
+            plan_free(p);
+            return st;
+        }
+    }
+    if (graph) {
+        for (int op : {CIS_BATCH_DISCRETIZE, CIS_BATCH_ADJOINT}) {
+            if (!(ops & op)) continue;
+            cis_status st = build_graph(p, op);
+            if (st != CIS_OK) {
+                plan_free(p);
+                return st;
+            }
+        }
+    }
+    *out = p;
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_run(cis_batch_plan* p, int32_t op, void* stream) {
+    if (!p) return fail(CIS_ERR_NULL, "cis_batch_run: plan is required");
+    if ((op != CIS_BATCH_DISCRETIZE && op != CIS_BATCH_ADJOINT) || !(p->ops & op))
+        return fail(CIS_ERR_DIM, "cis_batch_run: operation %d was not planned", op);
+    hipStream_t hs = (hipStream_t)stream;
+    for (Group& g : p->groups) {
+        hipError_t e;
+        if (op == CIS_BATCH_DISCRETIZE) {
+            e = g.disc.launch(hs);
+        } else {
+            e = g.def.launch(hs);
+            if (e == hipSuccess) e = g.adj.launch(hs);
+        }
+        if (e != hipSuccess) return fail(CIS_ERR_HIP, "cis_batch_run: launch: %s", hipGetErrorString(e));
+    }
+    if (op == CIS_BATCH_ADJOINT) {
+        hipError_t e = p->red.launch(hs);
+        if (e != hipSuccess) return fail(CIS_ERR_HIP, "cis_batch_run: reduction launch: %s", hipGetErrorString(e));
+    }
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_graph_run(cis_batch_plan* p, int32_t op, void* stream) {
+    if (!p) return fail(CIS_ERR_NULL, "cis_batch_graph_run: plan is required");
+    if ((op != CIS_BATCH_DISCRETIZE && op != CIS_BATCH_ADJOINT) || !(p->ops & op))
+        return fail(CIS_ERR_DIM, "cis_batch_graph_run: operation %d was not planned", op);
+    const int gi = op == CIS_BATCH_DISCRETIZE ? 0 : 1;
+    if (!p->exec[gi]) return fail(CIS_ERR_DIM, "cis_batch_graph_run: the plan was created without graphs");
+    hipError_t e = hipGraphLaunch(p->exec[gi], (hipStream_t)stream);
+    if (e != hipSuccess) return fail(CIS_ERR_HIP, "cis_batch_graph_run: %s", hipGetErrorString(e));
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, int32_t* groups,
+                                          int32_t* n_traj, int32_t* n_items,
+                                          int32_t* units_per_item, int32_t* persist_blocks) {
+    if (!p) return fail(CIS_ERR_NULL, "cis_batch_plan_info: plan is required");
+    if (groups) *groups = (int32_t)p->groups.size();
+    if (g < 0 || g >= (int32_t)p->groups.size()) return CIS_OK;
+    const Group& gr = p->groups[g];
+    if (n_traj) *n_traj = (int32_t)gr.trajs.size();
+    if (n_items) *n_items = (int32_t)gr.items.size();
+    if (units_per_item) *units_per_item = gr.units_per_item;
+    if (persist_blocks) *persist_blocks = gr.persist_blocks;
+    return CIS_OK;
+}
+
+extern "C" void cis_batch_plan_destroy(cis_batch_plan* p) {
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+    (void)hipSetDevice(cur);
+}

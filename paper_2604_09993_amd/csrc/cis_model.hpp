@@ -471,6 +471,75 @@ struct FwdArgs {
     int N, K, C;
 };
 
+// Arguments of the reverse sweep of one trajectory.
+template <class T>
+struct AdjArgs {
+    FwdArgs<T> f;
+    const T* seed;
+    T* gX;
+    T* gs;
+    T* ws_uk;    // [m][N] adjoint of U_k from interval k
+    T* ws_uk1;   // [m][N] adjoint of U_{k+1} from interval k
+    T* ws_p;     // [P][N] parameter adjoint from interval k
+};
+
+// Batched launches: one kernel per model over a device work list of
+// (trajectory, interval) items sorted by decreasing cost; `descs` holds the
+// per-trajectory argument blocks (FwdArgs or AdjArgs).
+template <class DESC>
+struct BatchArgs {
+    const DESC* descs;
+    const int2* items;   // {trajectory, interval}
+    int n_items;
+    int* cursor;         // [2] work cursor and finished-block count (persistent launches)
+};
+
+// Workgroups are handed to the 8 XCDs round-robin in dispatch order.  Map
+// dispatch slot w (of n) to a logical index such that, inside every full block
+// of 128 slots, 16 consecutive logical indices fall on one XCD: neighbouring
+// intervals then write their output lines through the same L2.
+__device__ __forceinline__ int xcd_slot(int w, int n) {
+    if (w >= (n & ~127)) return w;
+    const int r = w & 127;
+    return (w & ~127) | ((r & 7) << 4) | (r >> 3);
+}
+
+// Work unit u of a list of n_items items, each split into ngrp column groups:
+// items are taken in blocks of 16, and inside a block all items of group 0
+// come first, then group 1, ...  (a bijection onto [0, n_items * ngrp)).
+__device__ __forceinline__ void unit_item(int u, int n_items, int ngrp, int& item, int& grp) {
+    constexpr int BLK = 16;
+    const int blk = u / (BLK * ngrp);
+    const int base = blk * BLK;
+    const int nb = n_items - base < BLK ? n_items - base : BLK;
+    const int w = u - blk * BLK * ngrp;
+    grp = w / nb;
+    item = base + w % nb;
+}
+
+// Next unit of a persistent workgroup (one atomic per workgroup, broadcast
+// through LDS).  Every thread of the block must call it.
+__device__ __forceinline__ int fetch_unit(int* cursor, int* slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(cursor, 1);
+    __syncthreads();
+    const int u = *slot;
+    __syncthreads();
+    return u;
+}
+
+// Called once by every persistent workgroup after its last fetch: the last one
+// to finish clears the cursor for the next launch (no host-side reset, so the
+// launch can be replayed from a graph).
+__device__ __forceinline__ void retire_block(int* cursor) {
+    if (threadIdx.x == 0) {
+        const unsigned nblk = gridDim.x * gridDim.y;
+        if ((unsigned)atomicAdd(cursor + 1, 1) == nblk - 1) {
+            atomicExch(cursor, 0);
+            atomicExch(cursor + 1, 0);
+        }
+    }
+}
+
 __device__ __forceinline__ double stage_c(int st) { return st == 0 ? 0.0 : (st == 3 ? 1.0 : 0.5); }
 
 // Interval inputs into LDS and per-interval constants (all threads of the block).

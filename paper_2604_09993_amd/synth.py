@@ -289,15 +289,47 @@ def make_config(config_id: int, traj_id: int = 0):
     return model, data, cfg["K"]
 
 
-def mixed_batch(n_traj: int = 256, seed: int = 4):
-    """Uneven batch: 50% hopper / 30% cheetah7 / 20% biped5, N~U{20..100}, K~U{10..30}."""
-    rng = np.random.default_rng([seed, 0])
-    kinds = rng.choice(["hopper", "cheetah7", "biped5"], size=n_traj, p=[0.5, 0.3, 0.2])
+# Model mix of the uneven multi-trajectory batch (trajectories per 256).
+BATCH_MIX = (("hopper", 128), ("cheetah7", 77), ("biped5", 51))
+
+
+def mixed_batch(n_traj: int = 256, seed: int = 4, N_range=(20, 100), K_range=(10, 30)):
+    """Uneven batch over three models: hopper / cheetah7 / biped5 trajectories
+    in the ratio 128 : 77 : 51, N ~ U{N_range}, K ~ U{K_range}.
+
+    One model per kind (seeded by (seed, 0, kind index)); the order of the
+    kinds is shuffled with (seed, 0); trajectory t draws N, K and its nodes
+    from (seed, t + 1).  Returns a list of (model, data, K).
+    """
+    total = sum(c for _, c in BATCH_MIX)
+    counts = [int(round(n_traj * c / total)) for _, c in BATCH_MIX]
+    counts[-1] = n_traj - sum(counts[:-1])
+    models = {kind: MODEL_MAKERS[kind](np.random.default_rng([seed, 0, i]))
+              for i, (kind, _) in enumerate(BATCH_MIX)}
+    kinds = [kind for (kind, _), c in zip(BATCH_MIX, counts) for _ in range(c)]
+    np.random.default_rng([seed, 0]).shuffle(kinds)
     out = []
     for t, kind in enumerate(kinds):
         r = np.random.default_rng([seed, t + 1])
-        model = MODEL_MAKERS[kind](r)
-        N = int(r.integers(20, 101))
-        K = int(r.integers(10, 31))
+        N = int(r.integers(N_range[0], N_range[1] + 1))
+        K = int(r.integers(K_range[0], K_range[1] + 1))
+        model = models[kind]
         out.append((model, gen_nodes(model, N, r), K))
+    return out
+
+
+def config_batch(config_id: int, n_traj=None):
+    """The trajectories of a batched configuration, all of one model.
+
+    Trajectory 0 is make_config(config_id, 0); trajectory t > 0 takes the
+    same model and draws its nodes from (config_id, t).
+    """
+    cfg = CONFIGS[config_id]
+    n_traj = cfg.get("batch", 1) if n_traj is None else n_traj
+    model, data, K = make_config(config_id, 0)
+    out = [(model, data, K)]
+    for t in range(1, n_traj):
+        r = np.random.default_rng([config_id, t])
+        MODEL_MAKERS[cfg["model"]](r)   # same stream position as make_config
+        out.append((model, gen_nodes(model, cfg["N"], r), K))
     return out

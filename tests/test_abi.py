@@ -134,3 +134,90 @@ def test_entry_points_validate_before_launch():
                            None) == _lib.CIS_ERR_NULL
     assert lib.cis_status_string(_lib.CIS_ERR_DIM) == b"dimension out of range"
     lib.cis_model_destroy(h)
+
+
+_LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "cis.h"
+#define F(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("cis_shape size %zu\n", sizeof(cis_shape));
+  F(cis_shape, N) F(cis_shape, substeps) F(cis_shape, dtype) F(cis_shape, ld_node) F(cis_shape, ld_int)
+  printf("cis_model_desc size %zu\n", sizeof(cis_model_desc));
+  F(cis_model_desc, link_length) F(cis_model_desc, contact_point) F(cis_model_desc, gravity)
+  F(cis_model_desc, terrain_wavenumber)
+  printf("cis_traj size %zu\n", sizeof(cis_traj));
+  F(cis_traj, N) F(cis_traj, ld_node) F(cis_traj, X) F(cis_traj, A) F(cis_traj, xprop)
+  F(cis_traj, seed) F(cis_traj, gparams)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of cis_shape, cis_model_desc and cis_traj have the C layout."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                           str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        t, f, v = line.split()
+        got[(t, f)] = int(v)
+    mirrors = {"cis_shape": _lib.Shape, "cis_model_desc": _lib.ModelDesc, "cis_traj": _lib.Traj}
+    for (t, f), v in got.items():
+        cls = mirrors[t]
+        if f == "size":
+            assert ctypes.sizeof(cls) == v, t
+        else:
+            assert getattr(cls, f).offset == v, (t, f)
+
+
+def _traj(h, **kw):
+    t = _lib.Traj()
+    t.model = h.value
+    t.N, t.substeps, t.ld_node, t.ld_int = 5, 4, 6, 5
+    for name in ("X", "U", "s", "params", "A", "Bm", "Bp", "S", "defect", "xprop", "seed",
+                 "gX", "gU", "gs", "gparams"):
+        setattr(t, name, 8)
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+@pytest.mark.skipif("_gpu_visible()", reason="uses fake addresses; run only where no GPU exists")
+def test_batch_plan_validates_before_any_device_call():
+    lib = _lib.load()
+    st, h = _create(synth.make_hopper(np.random.default_rng(0)))
+    assert st == 0
+    plan = ctypes.c_void_p()
+
+    def create(trajs, n=None, dtype=_lib.CIS_F64, ops=_lib.CIS_BATCH_DISCRETIZE,
+               sched=_lib.CIS_SCHED_GRID, ckpt=0):
+        arr = (_lib.Traj * len(trajs))(*trajs)
+        return lib.cis_batch_plan_create(arr, len(trajs) if n is None else n, dtype, ops, sched,
+                                         ckpt, 0, None, ctypes.byref(plan))
+
+    good = _traj(h)
+    assert lib.cis_batch_plan_create(None, 1, 0, 1, 1, 0, 0, None, ctypes.byref(plan)) == _lib.CIS_ERR_NULL
+    assert create([good], n=0) == _lib.CIS_ERR_DIM
+    assert create([good], dtype=9) == _lib.CIS_ERR_DTYPE
+    assert create([good], ops=0) == _lib.CIS_ERR_DIM
+    assert create([good], ops=4) == _lib.CIS_ERR_DIM
+    assert create([good], sched=0) == _lib.CIS_ERR_DIM
+    assert create([good], ops=_lib.CIS_BATCH_ADJOINT, dtype=_lib.CIS_F32) == _lib.CIS_ERR_DTYPE
+    assert create([good, _traj(h, N=0)]) == _lib.CIS_ERR_DIM
+    assert b"trajectory 1" in lib.cis_last_error()
+    assert create([good, _traj(h, A=None)]) == _lib.CIS_ERR_NULL
+    assert create([_traj(h, xprop=12)]) == _lib.CIS_ERR_LAYOUT
+    assert create([_traj(h, seed=None)], ops=_lib.CIS_BATCH_ADJOINT) == _lib.CIS_ERR_NULL
+    assert create([good], ops=_lib.CIS_BATCH_ADJOINT, ckpt=3) == _lib.CIS_ERR_DIM   # 3 does not divide 4
+    assert create([good], ckpt=-1) == _lib.CIS_ERR_DIM
+    assert not plan.value
+    assert lib.cis_batch_run(None, 1, None) == _lib.CIS_ERR_NULL
+    assert lib.cis_batch_graph_run(None, 1, None) == _lib.CIS_ERR_NULL
+    lib.cis_batch_plan_destroy(None)
+    lib.cis_model_destroy(h)
