@@ -200,9 +200,6 @@ struct DiscShared {
     T xring[4][TP::NX];        // stage inputs from the state wave
     T csring[4][TP::NB][2];    // their rotations
     T fring[4][3 * TP::NB];    // their accelerations
-    T pshS[2][TP::NB][4];      // joint-wrench exchange of the state wave
-    T pshC[2][TP::NB][4];      // dT/dth exchange of the coefficient wave
-    T red[TP::NB][2];
     T coef[2][Coef<TP>::SIZE];
 };
 
@@ -247,7 +244,7 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             if (t < nst) {
                 const int st = t & 3;
                 const T tau = (T(t >> 2) + T(stage_c(st))) / T(a.K);
-                state_stage<T, TP>(sh.iv, mc, c, bs, sh.pshS[t & 1], st, tau, sh.xring[(t + 1) & 3],
+                state_stage<T, TP>(sh.iv, mc, c, bs, st, tau, sh.xring[(t + 1) & 3],
                                    sh.csring[t & 3], sh.fring[t & 3], lane);
             }
             __syncthreads();
@@ -275,7 +272,7 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
                 const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
                 T ycc = T(0), yct = T(0);
                 coef_stage<T, TP>(sh.iv, mc, c, tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
-                                  sh.csring[tc & 3], sh.fring[tc & 3], sh.pshC[tc & 1], sh.red, tau,
+                                  sh.csring[tc & 3], sh.fring[tc & 3], tau,
                                   sh.coef[tc & 1], ycc, yct, lane);
                 const T wk = (st == 0 || st == 3) ? T(1) : T(2);
                 if (st == 0) { yca = s * ycc; yta = s * yct; }

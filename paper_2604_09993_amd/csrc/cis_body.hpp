@@ -4,9 +4,11 @@
 // Lane b < NB of a wave owns body b: its six state rows (x, y, th, xd, yd, w)
 // and the joint whose child it is (joint b-1, for b >= 1) and the contact it
 // carries (the tip of a leg's last link).  Per stage the only cross-lane
-// traffic is the parent's angle and rate (a DPP/bpermute shuffle) and one LDS
-// exchange of the parent-side joint wrench; both rotations a lane needs are
-// evaluated side by side.  Right-hand side as in Sec. II-A (eq. ct-dynamics),
+// traffic goes through DPP row shifts and lane reads (all bodies sit in the
+// first row of 16 lanes): a body's parent is the previous lane, or the torso
+// (lane 0) for the first link of a leg; an interior link's child is the next
+// lane, and the torso collects the first links of all legs.  Right-hand side
+// as in Sec. II-A (eq. ct-dynamics),
 // Sec. III (integrands) and Sec. IV-B (dilation, FOH); Jacobian nonzeros in
 // the layout of Coef<TP>.
 #pragma once
@@ -30,12 +32,65 @@ __device__ __forceinline__ int contact_of(int b) {
     return TP::D == 0 ? 0 : (b - 1) / TP::D;
 }
 
-__device__ __forceinline__ double shfl_t(double v, int src) { return __shfl(v, src, 64); }
-__device__ __forceinline__ float shfl_t(float v, int src) { return __shfl(v, src, 64); }
+// DPP row shifts by one lane: prev_lane(v) in lane b is v of lane b-1, next_lane(v) that
+// of lane b+1 (within rows of 16 lanes; the value at a row edge is unspecified).
+template <int CTRL>
+__device__ __forceinline__ int dpp_row(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(dpp_row<CTRL>(w.x), dpp_row<CTRL>(w.y)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+    return __builtin_bit_cast(float, dpp_row<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <class T>
+__device__ __forceinline__ T prev_lane(T v) { return dpp_row<0x111>(v); }   // row_shr:1
+template <class T>
+__device__ __forceinline__ T next_lane(T v) { return dpp_row<0x101>(v); }   // row_shl:1
+
+// value of v in lane `src` (a wave-uniform lane index), in every lane
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(w.x, src),
+                                                __builtin_amdgcn_readlane(w.y, src)));
+}
+__device__ __forceinline__ float lane_value(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+
+// value of v at the parent body of this lane's body (lane 0 gets its own value)
+template <class TP, class T>
+__device__ __forceinline__ T from_parent(T v, bool parent_is_torso) {
+    const T t = lane_value(v, 0);
+    const T q = prev_lane(v);
+    return parent_is_torso ? t : q;
+}
+
+// sum, in the parent lane, of a value held by the child lanes of the joints:
+// interior links take it from the next lane, the torso from the first link of
+// every leg (in leg order).  Lanes without children get 0.
+template <class TP, class T>
+__device__ __forceinline__ T from_children(T v, int b) {
+    if constexpr (TP::D == 0) {
+        return T(0);
+    } else {
+        const T q = next_lane(v);
+        T t = T(0);
+#pragma unroll
+        for (int l = 0; l < TP::L; ++l) t += lane_value(v, 1 + l * TP::D);
+        const bool interior = b >= 1 && (b % TP::D) != 0;   // not a leg tip
+        return b == 0 ? t : (interior ? q : T(0));
+    }
+}
 
 // Constants a body lane keeps in registers for the whole interval.
 template <class T, class TP>
 struct BodyConst {
+    static_assert(TP::NB <= 16, "the bodies must fit one DPP row");
     int b, p;                 // own and parent body
     bool joint, contact;      // has a parent joint, carries a contact
     int j, i;                 // joint and contact index
@@ -143,21 +198,23 @@ __device__ __forceinline__ Frame<T> terrain(const MC& mc, T Px, T Py) {
 // State wave: one stage.  bs.xs holds the stage input of the lane's body.
 // Writes the next stage input (or the new substep state after stage 3) into
 // bs.xs and into ring[NX], the body rotation into cs_out[NB][2] and the
-// accelerations into fv_out[3 NB].  psh: [NB][4] LDS exchange slot.
+// accelerations into fv_out[3 NB].
 // ---------------------------------------------------------------------------
 template <class T, class TP>
 __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
-                                            const BodyConst<T, TP>& c, BodyRK<T>& bs,
-                                            T (*psh)[4], int st, T tau, T* ring, T (*cs_out)[2],
-                                            T* fv_out, int lane) {
-    constexpr int NB = TP::NB, NQ = TP::NQ, D = TP::D, L = TP::L;
+                                            const BodyConst<T, TP>& c, BodyRK<T>& bs, int st,
+                                            T tau, T* ring, T (*cs_out)[2], T* fv_out,
+                                            int lane) {
+    constexpr int NB = TP::NB, NQ = TP::NQ;
     const T omt = T(1) - tau;
-    const T thp = shfl_t(bs.xs[2], c.p), omp = shfl_t(bs.xs[5], c.p);
-    T sb, cb, sp, cp;
+    T sb, cb;
     sincos_t(bs.xs[2], &sb, &cb);
-    sincos_t(thp, &sp, &cp);
+    const bool pt = c.p == 0;
+    const T thp = from_parent<TP>(bs.xs[2], pt), omp = from_parent<TP>(bs.xs[5], pt);
+    const T sp = from_parent<TP>(sb, pt), cp = from_parent<TP>(cb, pt);
     T Fx = T(0), Fy = T(0), Tq = T(0);
+    T wx = T(0), wy = T(0), wt = T(0);   // parent-side wrench of the own joint
     if (c.joint) {
         const T apx = cp * c.rpx - sp * c.rpy, apy = sp * c.rpx + cp * c.rpy;
         const T acx = cb * c.rcx - sb * c.rcy, acy = sb * c.rcx + cb * c.rcy;
@@ -168,9 +225,9 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
         Fx -= lx;
         Fy -= ly;
         Tq += -(acx * ly - acy * lx) + tt;
-        psh[c.b][0] = lx;
-        psh[c.b][1] = ly;
-        psh[c.b][2] = (apx * ly - apy * lx) - tt;
+        wx = lx;
+        wy = ly;
+        wt = (apx * ly - apy * lx) - tt;
     }
     if (c.contact) {
         const T ax = cb * c.rx - sb * c.ry, ay = sb * c.rx + cb * c.ry;
@@ -182,24 +239,10 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
         Fy += fy;
         Tq += ax * fy - ay * fx;
     }
-    wave_lds_sync();
     // parent-side wrenches of the children's joints
-    if (lane < NB) {
-        if constexpr (D >= 1) {
-            if (c.b == 0) {
-#pragma unroll
-                for (int l = 0; l < L; ++l) {
-                    Fx += psh[1 + l * D][0];
-                    Fy += psh[1 + l * D][1];
-                    Tq += psh[1 + l * D][2];
-                }
-            } else if (((c.b - 1) % D) < D - 1) {
-                Fx += psh[c.b + 1][0];
-                Fy += psh[c.b + 1][1];
-                Tq += psh[c.b + 1][2];
-            }
-        }
-    }
+    Fx += from_children<TP>(wx, c.b);
+    Fy += from_children<TP>(wy, c.b);
+    Tq += from_children<TP>(wt, c.b);
     const T fv[3] = {Fx * c.mi, Fy * c.mi - T(mc.g), Tq * c.ii};
     const T s = iv.s, h = iv.h;
     const T an = (st == 2) ? h : T(0.5) * h;
@@ -240,34 +283,35 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
 // state xs[NX], the body rotations cs[NB][2] and accelerations fv[3NB] from
 // the state wave.  Writes cf (layout Coef<TP>) and returns, in the lanes that
 // own them, the integral-row right-hand sides (cc_i on contact lanes, the
-// violation row on lane 0) through ycc / yct.  psh: [NB][4] LDS slot.
+// violation row on lane 0) through ycc / yct.
 // ---------------------------------------------------------------------------
 template <class T, class TP>
 __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                            const BodyConst<T, TP>& c, const T* xs,
-                                           const T (*cs)[2], const T* fv, T (*psh)[4],
-                                           T (*red)[2], T tau, T* cf, T& ycc, T& yct, int lane) {
-    // ycc: cross-complementarity integrand of the lane's contact; yct: the
-    // violation integrand (lane 0).  Both unchanged where not owned.
+                                           const T (*cs)[2], const T* fv, T tau, T* cf, T& ycc,
+                                           T& yct, int lane) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX, M = TP::M;
     using C = Coef<TP>;
     const T s = iv.s, omt = T(1) - tau;
     const int b = c.b, p = c.p;
     const T cb = cs[b][0], sb = cs[b][1];
+    const T xb = xs[3 * b], yb = xs[3 * b + 1];
+    const bool pt = p == 0;
+    const T cp = from_parent<TP>(cb, pt), sp = from_parent<TP>(sb, pt);
+    const T xp = from_parent<TP>(xb, pt), yp = from_parent<TP>(yb, pt);
     // smooth-function arguments: joint h_x, h_y; contact v_t, -sd
     T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
     T apx = T(0), apy = T(0), acx = T(0), acy = T(0), lx = T(0), ly = T(0);
     if (c.joint) {
-        const T cp = cs[p][0], sp = cs[p][1];
         apx = cp * c.rpx - sp * c.rpy;
         apy = sp * c.rpx + cp * c.rpy;
         acx = cb * c.rcx - sb * c.rcy;
         acy = sb * c.rcx + cb * c.rcy;
         lx = omt * c.uk[1] + tau * c.uk1[1];
         ly = omt * c.uk[2] + tau * c.uk1[2];
-        a0 = xs[3 * p] + apx - xs[3 * b] - acx;
-        a1 = xs[3 * p + 1] + apy - xs[3 * b + 1] - acy;
+        a0 = xp + apx - xb - acx;
+        a1 = yp + apy - yb - acy;
     }
     T ax = T(0), ay = T(0), om = T(0), Pdx = T(0), Pdy = T(0), ln = T(0), ft = T(0);
     Frame<T> f;
@@ -280,7 +324,7 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         om = xs[NQ + 3 * b + 2];
         Pdx = xs[NQ + 3 * b] - om * ay;
         Pdy = xs[NQ + 3 * b + 1] + om * ax;
-        f = terrain<T>(mc, xs[3 * b] + ax, xs[3 * b + 1] + ay);
+        f = terrain<T>(mc, xb + ax, yb + ay);
         ln = omt * c.ck[0] + tau * c.ck1[0];
         ft = (omt * c.ck[1] + tau * c.ck1[1]) - (omt * c.ck[2] + tau * c.ck1[2]);
         a2 = f.tx * Pdx + f.ty * Pdy;
@@ -291,7 +335,7 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     sabs_d(a1, v1, d1);
     sabs_d(a2, v2, d2);
     sabs_d(a3, v3, d3);
-    T dTown = T(0), ctp = T(0);
+    T dTown = T(0), ctp = T(0), dTpar = T(0);
     if (c.joint) {
         const int j = c.j;
         ctp += v0 + v1;   // |h_x|_s + |h_y|_s
@@ -305,7 +349,7 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         cf[C::GV + (3 * b + 2) * M + NJ + 2 * j] = acy * ic;
         cf[C::GV + (3 * b + 2) * M + NJ + 2 * j + 1] = -acx * ic;
         dTown += acx * lx + acy * ly;          // child side d(-a_c x lam)/dth
-        psh[b][3] = -(apx * lx + apy * ly);    // parent side d(a_p x lam)/dth_p
+        dTpar = -(apx * lx + apy * ly);        // parent side d(a_p x lam)/dth_p
     }
     if (c.contact) {
         const int i = c.i;
@@ -358,8 +402,8 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         gcb[u0 + 2] = s * T(0.5) * (rm - av);
         const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
         dTown += -(ax * fx + ay * fy);         // d(a x F)/dth at fixed F
+        cf[C::F + NX + i] = ycc;
     }
-    if (lane < NB) red[lane][0] = ctp;
     // F~: q rows are the stage velocities, v rows the state wave's accelerations
     if (lane < NB) {
 #pragma unroll
@@ -368,26 +412,14 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
             cf[C::F + NQ + 3 * b + k] = fv[3 * b + k];
         }
     }
-    if (c.contact) cf[C::F + NX + c.i] = ycc;
-    wave_lds_sync();
     // dT_b/dth_b: own terms plus the parent-side terms of the children's joints
-    if (lane < NB) {
-        T dT = dTown;
-        if constexpr (TP::D >= 1) {
-            if (b == 0) {
+    const T dT = dTown + from_children<TP>(dTpar, b);
+    if (lane < NB) cf[C::CTH + b] = s * dT * c.ii;
+    // violation row: sum over bodies (lane order) of their joint and contact parts
+    T acc = T(0);
 #pragma unroll
-                for (int l = 0; l < TP::L; ++l) dT += psh[1 + l * TP::D][3];
-            } else if (((b - 1) % TP::D) < TP::D - 1) {
-                dT += psh[b + 1][3];
-            }
-        }
-        cf[C::CTH + b] = s * dT * c.ii;
-    }
+    for (int e = 0; e < NB; ++e) acc += lane_value(ctp, e);
     if (lane == 0) {
-        // violation row: sum over bodies of their joint and contact parts
-        T acc = T(0);
-#pragma unroll
-        for (int e = 0; e < NB; ++e) acc += red[e][0];
         yct = acc;
         cf[C::F + NX + NC] = acc;
     }
