@@ -7,6 +7,7 @@
 // The adjoint kernels live in cis_adjoint.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <type_traits>
 #include <utility>
@@ -186,21 +187,33 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 }
 
 // ---------------------------------------------------------------------------
-// K2: discretize.  One workgroup per interval, three wave roles separated by
-// one workgroup barrier per RK stage, each role one stage behind the previous:
-//   state wave      : evaluates the accelerations at stage t and forms the
-//                     input of stage t+1 (the only serial chain);
-//   coefficient wave: full right-hand side and Jacobian nonzeros at stage t-1
-//                     (rotations reused from the state wave), integral rows;
-//   tangent waves   : apply stage t-2 to their columns.
+// K2: discretize.  One workgroup per (interval, column group), three wave roles
+// separated by one workgroup barrier per pipeline step:
+//   state wave        : evaluates the accelerations at stage t and forms the
+//                       input of stage t+1 (the only serial chain);
+//   coefficient waves : full right-hand side and Jacobian nonzeros of stage
+//                       t-1 (rotations reused from the state wave) and the
+//                       integral rows.  With two such waves they take alternate
+//                       stages and each stage spans steps t-1 and t-2;
+//   tangent waves     : apply stage t-LAG to their columns.
 // ---------------------------------------------------------------------------
+// Workgroup layouts of the discretize kernel.  Latency (one trajectory): two
+// coefficient waves; FP64 one tangent wave per workgroup (512 registers per
+// lane, one wave per SIMD), FP32 up to five (two waves per SIMD).  Throughput
+// (batches): one coefficient wave and more tangent waves per workgroup.
+template <class T, int L, int D>
+using LatencyTopo = Topo<L, D, sizeof(T) == 8 ? 1 : 5, 2>;
+template <class T, int L, int D>
+using ThroughputTopo = Topo<L, D, sizeof(T) == 8 ? 2 : 6, 1>;
+
 template <class T, class TP>
 struct DiscShared {
     Interval<T, TP> iv;
     T xring[4][TP::NX];        // stage inputs from the state wave
     T csring[4][TP::NB][2];    // their rotations
     T fring[4][3 * TP::NB];    // their accelerations
-    T coef[2][Coef<TP>::SIZE];
+    T yshare[TP::NY];          // integral-row partial sums of the second coefficient wave
+    T coef[TP::NCOEF][Coef<TP>::SIZE];
 };
 
 // Interval k, column group grp, by the whole workgroup.
@@ -210,17 +223,18 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
                                                 const int k, const int grp) {
     constexpr int NB = TP::NB, NX = TP::NX, NXT = TP::NXT, M = TP::M, NY = TP::NY;
     constexpr int NQ = TP::NQ, NC = TP::NC, LB = TP::LB, G = TP::G, D = TP::D, L = TP::L;
+    constexpr int NCW = TP::NCW, NCOEF = TP::NCOEF, LAG = TP::LAG;
     using C = Coef<TP>;
     static_assert(D > 0 || L <= 1, "several contacts on the torso are not laid out");
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int nth = TP::NTHREADS;
     load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
-    for (int e = tid; e < 2 * C::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
+    for (int e = tid; e < NCOEF * C::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
     __syncthreads();
-    coef_constants<T, TP>(sh.iv, sh.coef[0], tid, nth);
-    coef_constants<T, TP>(sh.iv, sh.coef[1], tid, nth);
+#pragma unroll
+    for (int q = 0; q < NCOEF; ++q) coef_constants<T, TP>(sh.iv, sh.coef[q], tid, nth);
     const int nst = 4 * a.K;
-    const int nsteps = nst + 2;
+    const int nsteps = nst + LAG;
     const int64_t ldi = a.ldi;
     __syncthreads();
 
@@ -249,6 +263,7 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             }
             __syncthreads();
         }
+        if constexpr (NCW > 1) __syncthreads();   // the integral-row hand-over step
         if (grp == 0 && lane < NB) {
 #pragma unroll
             for (int kk = 0; kk < 6; ++kk) {
@@ -257,31 +272,53 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
                 a.defect[r * ldi + k] = bs.xb[kk] - sh.iv.xk1[r];
             }
         }
-    } else if (wave == TP::NTW + 1) {
-        // -------- coefficient wave: stage t-1 at step t; integral rows --------
+    } else if (wave > TP::NTW) {
+        // ---- coefficient waves: stage tc over steps tc+1 .. tc+NCW; integral rows ----
+        const int w = wave - TP::NTW - 1;
         const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
         // integral rows: the contact's cc row on its lane, the violation row on lane 0
         const int ycc_row = NX + c.i;
-        T ycb = c.contact ? sh.iv.x0[ycc_row] : T(0), yca = T(0);
-        T ytb = lane == 0 ? sh.iv.x0[NX + NC] : T(0), yta = T(0);
+        const bool own0 = w == 0;
+        T ycb = (c.contact && own0) ? sh.iv.x0[ycc_row] : T(0), yca = T(0);
+        T ytb = (lane == 0 && own0) ? sh.iv.x0[NX + NC] : T(0), yta = T(0);
         const T s = sh.iv.s;
-        for (int t = 0; t < nsteps; ++t) {
-            const int tc = t - 1;
-            if (tc >= 0 && tc < nst) {
-                const int st = tc & 3;
-                const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
-                T ycc = T(0), yct = T(0);
-                coef_stage<T, TP>(sh.iv, mc, c, tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
-                                  sh.csring[tc & 3], sh.fring[tc & 3], tau,
-                                  sh.coef[tc & 1], ycc, yct, lane);
-                const T wk = (st == 0 || st == 3) ? T(1) : T(2);
-                if (st == 0) { yca = s * ycc; yta = s * yct; }
-                else { yca += wk * s * ycc; yta += wk * s * yct; }
-                if (st == 3) { ycb += sh.iv.h6 * yca; ytb += sh.iv.h6 * yta; }
+        // leading steps before the first stage of this wave
+        for (int t = 0; t < 1 + w; ++t) __syncthreads();
+        for (int tc = w; tc < nst; tc += NCW) {
+            const int st = tc & 3;
+            const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
+            T ycc = T(0), yct = T(0);
+            coef_stage<T, TP, (NCW > 1)>(sh.iv, mc, c, tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
+                                         sh.csring[tc & 3], sh.fring[tc & 3], tau,
+                                         sh.coef[tc & (NCOEF - 1)], ycc, yct, lane);
+            const T wk = (st == 0 || st == 3) ? T(1) : T(2);
+            if (st == w) {   // first stage of the substep handled by this wave
+                yca = wk * s * ycc;
+                yta = wk * s * yct;
+            } else {
+                yca += wk * s * ycc;
+                yta += wk * s * yct;
+            }
+            if (st + NCW > 3) {   // last stage of the substep handled by this wave
+                ycb += sh.iv.h6 * yca;
+                ytb += sh.iv.h6 * yta;
             }
             __syncthreads();
         }
-        if (grp == 0) {
+        // trailing steps: the wave's last stage ends at step nst - NCW + w + NCW
+        for (int t = nst + w + 1; t < nsteps; ++t) __syncthreads();
+        if constexpr (NCW > 1) {
+            if (w == 1) {
+                if (c.contact) sh.yshare[c.i] = ycb;
+                if (lane == 0) sh.yshare[NC] = ytb;
+            }
+            __syncthreads();
+            if (w == 0) {
+                if (c.contact) ycb += sh.yshare[c.i];
+                if (lane == 0) ytb += sh.yshare[NC];
+            }
+        }
+        if (grp == 0 && w == 0) {
             if (c.contact) {
                 if (a.xprop) a.xprop[ycc_row * ldi + k] = ycb;
                 a.defect[ycc_row * ldi + k] = ycb - sh.iv.xk1[ycc_row];
@@ -297,7 +334,7 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             }
         }
     } else {
-        // ---------------- tangent waves: stage t-2 at step t ----------------
+        // ---------------- tangent waves: stage t-LAG at step t ----------------
         const int col = grp * TP::CPG + (wave * 64 + lane) / G;
         const int leg = G == 1 ? 0 : (lane & (G - 1));
         T wbm = T(0), wbp = T(0), fsel = T(0);
@@ -323,9 +360,10 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
         }
         z.ycc = T(0);
         z.yct = T(0);
-        __syncthreads();   // steps 0 and 1: nothing to apply yet
-        __syncthreads();
-        // steps 2 .. nst+1 apply stages 0 .. nst-1, unrolled by the 4 RK stages
+        // steps 0 .. LAG-1: nothing to apply yet
+#pragma unroll
+        for (int t = 0; t < LAG; ++t) __syncthreads();
+        // steps LAG .. nst+LAG-1 apply stages 0 .. nst-1, unrolled by the 4 RK stages
         const T Kt = T(a.K);
         for (int j = 0; j < a.K; ++j) {
             const T jt = T(j);
@@ -334,11 +372,14 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             __syncthreads();
             tangent_stage<T, TP, 1>(sh.iv, z, sh.coef[1], tauh, leg, wbm, wbp, fsel, fct, ctrl);
             __syncthreads();
-            tangent_stage<T, TP, 2>(sh.iv, z, sh.coef[0], tauh, leg, wbm, wbp, fsel, fct, ctrl);
+            tangent_stage<T, TP, 2>(sh.iv, z, sh.coef[2 % NCOEF], tauh, leg, wbm, wbp, fsel, fct,
+                                    ctrl);
             __syncthreads();
-            tangent_stage<T, TP, 3>(sh.iv, z, sh.coef[1], tau1, leg, wbm, wbp, fsel, fct, ctrl);
+            tangent_stage<T, TP, 3>(sh.iv, z, sh.coef[3 % NCOEF], tau1, leg, wbm, wbp, fsel, fct,
+                                    ctrl);
             __syncthreads();
         }
+        if constexpr (NCW > 1) __syncthreads();   // the integral-row hand-over step
         const T yct = column_sum<G>(z.yct);
         if (col < TP::NCOL) {
             T* out;
@@ -486,13 +527,26 @@ static FwdArgs<T> make_args(const cis_shape* sh, const void* X, const void* U, c
     return a;
 }
 
-template <class T, int L, int D>
-static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, const void* X,
-                                    const void* U, const void* s, const void* prm, void* A,
-                                    void* Bm, void* Bp, void* S, void* d, void* xp,
-                                    hipStream_t stream) {
-    // FP64 columns need about twice the registers of FP32 ones
-    using TP = Topo<L, D, sizeof(T) == 8 ? 2 : 6>;
+// Compute units of the current device (cached per device id).
+static int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+template <class T, class TP>
+static cis_status launch_discretize_as(const cis_model* m, const cis_shape* sh, const void* X,
+                                       const void* U, const void* s, const void* prm, void* A,
+                                       void* Bm, void* Bp, void* S, void* d, void* xp,
+                                       hipStream_t stream) {
     auto mc = make_const<TP::NB, TP::NJ, TP::NC>(m);
     FwdArgs<T> a = make_args<T>(sh, X, U, s, prm);
     a.A = (T*)A;
@@ -506,6 +560,20 @@ static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, con
                                    dim3(TP::NTHREADS), args, 0, stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_discretize launch: %s", hipGetErrorString(e));
     return CIS_OK;
+}
+
+// One trajectory: the latency layout while every (interval, column group)
+// workgroup can be resident at once, the throughput layout beyond.
+template <class T, int L, int D>
+static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, const void* X,
+                                    const void* U, const void* s, const void* prm, void* A,
+                                    void* Bm, void* Bp, void* S, void* d, void* xp,
+                                    hipStream_t stream) {
+    using TL = LatencyTopo<T, L, D>;
+    using TT = ThroughputTopo<T, L, D>;
+    if ((int64_t)sh->N * TL::NGRP <= device_cus())
+        return launch_discretize_as<T, TL>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    return launch_discretize_as<T, TT>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
 }
 
 template <class T, int L, int D>
@@ -542,7 +610,7 @@ static BatchArgs<FwdArgs<T>> batch_args(const BatchGroupDev& g) {
 template <class T, int L, int D>
 static cis_status prep_disc_t(const cis_model* m, const BatchGroupDev& g, int persist_blocks,
                               KLaunch* out) {
-    using TP = Topo<L, D, sizeof(T) == 8 ? 2 : 6>;
+    using TP = ThroughputTopo<T, L, D>;
     out->arg(batch_args<T>(g));
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
     out->block = dim3(TP::NTHREADS);
@@ -569,7 +637,7 @@ static cis_status prep_def_t(const cis_model* m, const BatchGroupDev& g, KLaunch
 
 template <class T, int L, int D>
 static int units_t() {
-    return Topo<L, D, sizeof(T) == 8 ? 2 : 6>::NGRP;
+    return ThroughputTopo<T, L, D>::NGRP;
 }
 
 cis_status prep_discretize_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,

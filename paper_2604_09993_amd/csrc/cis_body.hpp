@@ -283,9 +283,10 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
 // state xs[NX], the body rotations cs[NB][2] and accelerations fv[3NB] from
 // the state wave.  Writes cf (layout Coef<TP>) and returns, in the lanes that
 // own them, the integral-row right-hand sides (cc_i on contact lanes, the
-// violation row on lane 0) through ycc / yct.
+// violation row on lane 0) through ycc / yct.  With SPLIT the call contains
+// one workgroup barrier.
 // ---------------------------------------------------------------------------
-template <class T, class TP>
+template <class T, class TP, bool SPLIT = false>
 __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                            const BodyConst<T, TP>& c, const T* xs,
@@ -335,6 +336,9 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     sabs_d(a1, v1, d1);
     sabs_d(a2, v2, d2);
     sabs_d(a3, v3, d3);
+    // SPLIT: the stage spans two pipeline steps; the workgroup barrier between
+    // them is taken here, after the evaluation and before the stores
+    if constexpr (SPLIT) __syncthreads();
     T dTown = T(0), ctp = T(0), dTpar = T(0);
     if (c.joint) {
         const int j = c.j;

@@ -27,7 +27,7 @@ namespace cis {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int even(int a) { return (a + 1) & ~1; }
 
-template <int L_, int D_, int TW_MAX_ = 6>
+template <int L_, int D_, int TW_MAX_ = 6, int NCW_ = 1>
 struct Topo {
     static constexpr int L = L_, D = D_;
     static constexpr int NB = 1 + L * D, NJ = L * D, NC = L;
@@ -43,7 +43,13 @@ struct Topo {
     static constexpr int NGRP = (NTW_ALL + TW_MAX_ - 1) / TW_MAX_;
     static constexpr int NTW = (NTW_ALL + NGRP - 1) / NGRP;  // tangent waves per workgroup
     static constexpr int CPG = NTW * 64 / G;                  // columns per workgroup
-    static constexpr int NTHREADS = 64 * (NTW + 2);           // + state wave + coefficient wave
+    // coefficient waves: with NCW_ = 2 two waves take alternate stages, each
+    // stage spread over two pipeline steps
+    static constexpr int NCW = NCW_;
+    static constexpr int NCOEF = NCW == 1 ? 2 : 4;            // coefficient buffers in flight
+    static constexpr int LAG = NCW + 1;                       // steps from state to tangent
+    static constexpr int NTHREADS = 64 * (NTW + 1 + NCW);     // + state wave + coefficient waves
+    static_assert(NCW == 1 || NCW == 2, "one or two coefficient waves");
     static_assert(NXT <= 128, "state rows are owned two per lane");
     static_assert(NB < 64 && NJ + NC <= 64, "one lane per body / element");
     static_assert(G == 1 || G == 2 || G == 4, "legs must map onto a DPP quad");
