@@ -7,8 +7,10 @@ seeded node data (inputs resident in HBM before timing).  One step = one call
 of cis_discretize over all 50 intervals (A, B-, B+, S, defects, F~).
 
 Prints one JSON line.  Extra fields: the FP32 form of the same step, the
-parity error of the timed output against the CPU oracle, the roofline of the
-dominant kernel (k_discretize) and the CPU oracle baseline.
+adjoint gradient step, batched multiple shooting (256 mixed trajectories;
+64 quad13 trajectories of N = 200), the parity error of the timed output
+against the CPU oracle, the roofline of the dominant kernel (k_discretize)
+and the CPU oracle baseline.
 """
 import argparse
 import ctypes
@@ -38,6 +40,39 @@ def algorithmic_flops_per_interval(model, K):
     return K * (8 * nnz * c + 14 * model.nx * c + 4 * phi)
 
 
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter record, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    from paper_2604_09993_amd.profiling import kernel_sources_sha256
+    if rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return {"fetch_bytes": k["fetch_bytes"], "write_bytes": k["write_bytes"],
+            "total_bytes": k["fetch_bytes"] + k["write_bytes"],
+            "algorithmic_bytes": k.get("algorithmic_bytes"), "source": "profiles/hbm_traffic.json"}
+
+
+def upload_batch(api, batch, dev, dtype):
+    import torch
+    cms, trajs = {}, []
+    for model, data, K in batch:
+        cm = cms.get(id(model)) or cms.setdefault(id(model), api.CisModel(model))
+        N = data["s"].shape[0]
+        trajs.append(dict(cm=cm, K=K, X=api.to_device_soa(data["X"], dev, dtype, ld=N + 1),
+                          U=api.to_device_soa(data["U"], dev, dtype, ld=N + 1),
+                          s=torch.tensor(data["s"], device=dev, dtype=dtype),
+                          params=torch.tensor(data["p"], device=dev, dtype=dtype)))
+    return trajs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--batch-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus must be 1 (no multi-GPU path in this build)",
@@ -102,10 +139,15 @@ def main():
         wall = time.perf_counter() - t0
         return e0.elapsed_time(e1) / steps, wall
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     launch64, out64, stream, keep64 = prepare(torch.float64)
     ms64, wall64 = timed(launch64, stream, args.steps, args.warmup)
+    progress(f"fp64 discretize {ms64:.4f} ms/step")
     launch32, out32, _, keep32 = prepare(torch.float32)
     ms32, _ = timed(launch32, stream, args.steps, args.warmup)
+    progress(f"fp32 discretize {ms32:.4f} ms/step")
 
     # adjoint form on the same workload (checkpoints every 5 substeps): one
     # gradient step = forward defects with checkpoints + reverse sweep + reduce
@@ -132,9 +174,46 @@ def main():
                                               vp(s64), vp(p64), vp(ck), C, vp(seed), vp(gX),
                                               vp(gU), vp(gs), vp(gp), vp(ws), nbytes, st_ptr))
     ms_grad, _ = timed(launch_grad, stream, max(args.steps // 2, 10), args.warmup)
+    progress(f"gradient step {ms_grad:.4f} ms")
 
     flops = algorithmic_flops_per_interval(model, K) * N
     achieved = flops / (ms64 * 1e-3)
+    kname = "k_discretize<double, Topo<2,3,1,2>>"
+
+    batch = {}
+    if not args.no_batch:
+        # multiple shooting over many trajectories: one plan per workload,
+        # replayed as a HIP graph (one kernel per model, run concurrently)
+        for name, make, ops, dtypes in (
+                ("mixed256", lambda: synth.mixed_batch(), ("discretize", "adjoint"),
+                 (torch.float64,)),
+                ("quad13x64", lambda: synth.config_batch(5), ("discretize",),
+                 (torch.float64, torch.float32))):
+            bl = make()
+            nint = sum(d["s"].shape[0] for _, d, _ in bl)
+            bflops = sum(algorithmic_flops_per_interval(m, k) * d["s"].shape[0] for m, d, k in bl)
+            for dt in dtypes:
+                trajs = upload_batch(api, bl, dev, dt)
+                plan = api.BatchPlan(trajs, ops if dt == torch.float64 else ("discretize",),
+                                     sched="tune", graph=True, stream=stream)
+                res = {}
+                for op in (ops if dt == torch.float64 else ("discretize",)):
+                    ms_b, _ = timed(lambda: plan.run(op, graph=True, stream=stream), stream,
+                                    args.batch_steps, 2)
+                    res[op] = {"value": nint / (ms_b * 1e-3),
+                               "unit": "intervals/s" if op == "discretize" else "interval grads/s",
+                               "ms_per_step": ms_b}
+                    if op == "discretize":
+                        peak = PEAK_FP64_VALU if dt == torch.float64 else PEAK_FP32_VALU
+                        res[op]["roofline_frac"] = bflops / (ms_b * 1e-3) / peak
+                key = f"{name}_{'f64' if dt == torch.float64 else 'f32'}"
+                progress(f"batch {key}: " + ", ".join(f"{o} {r['ms_per_step']:.3f} ms"
+                                                      for o, r in res.items()))
+                batch[key] = dict(trajectories=len(bl), intervals=nint, **res,
+                                  groups=plan.groups())
+                plan.close()
+                del trajs
+
     line = {
         "metric": "discretized intervals/s (x+STM+B±) at 1e-10 rel vs oracle",
         "value": N / (ms64 * 1e-3),
@@ -155,10 +234,12 @@ def main():
         "adjoint": {"value": N / (ms_grad * 1e-3), "unit": "interval grads/s",
                     "ms_per_step": ms_grad,
                     "step": "cis_defects with checkpoints every 5 substeps + cis_discretize_adjoint"},
-        "roofline": {"bound": "alu", "kernel": "k_discretize<double, Topo<2,3>>",
+        "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                     "traffic": committed_traffic(kname),
                      "algorithmic_flop_per_launch": flops},
+        "batch": batch,
         "wall_s_timed_region": wall64,
     }
     if not args.no_cpu_baseline:
@@ -187,6 +268,7 @@ def main():
             oracle.discretize(model, data["X"], data["U"], data["s"], data["p"], K, nthreads=ncores)
             reps += 1
         dt = time.perf_counter() - t0
+        progress(f"cpu baseline {reps} repetitions in {dt:.1f} s")
         line["cpu_baseline"] = {"value": reps * N / dt, "unit": "intervals/s", "cores": ncores,
                                 "kind": "oracle",
                                 "sample": f"{reps} repetitions of the same 50-interval workload "

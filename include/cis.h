@@ -183,6 +183,36 @@ cis_status cis_discretize_adjoint(const cis_model *model, const cis_shape *shape
                                   const void *seed, void *gX, void *gU, void *gs,
                                   void *gparams, void *ws, size_t ws_bytes, void *stream);
 
+/* Composition of the substep blocks of cis_discretize_blocked. */
+enum { CIS_COMPOSE_VALU = 0, CIS_COMPOSE_MFMA = 1 };
+
+/* Bytes of device workspace cis_discretize_blocked needs (blocks >= 2 must
+ * divide the substep count). */
+cis_status cis_blocked_workspace_size(const cis_model *model, const cis_shape *shape,
+                                      int32_t blocks, size_t *bytes);
+
+/*
+ * Same outputs as cis_discretize (dtype CIS_F64 only), computed with substep
+ * blocking: the K substeps of each interval are split into `blocks` blocks
+ * of K/blocks substeps.  A checkpointed nominal pass gives the block start
+ * states (and the defect and F~); the variational equations of every
+ * (block, interval) pair are then integrated in parallel, each from its block
+ * start, with the interval's FOH and dilation; finally the block
+ * sensitivities X_b = [Phi_b | B-_b | B+_b | S_b] are chained,
+ *   A = Phi_{B-1}..Phi_0,  [B- | B+ | S] = sum_b Phi_{B-1}..Phi_{b+1} [B-_b | B+_b | S_b],
+ * with dense products on the vector ALUs (CIS_COMPOSE_VALU) or on FP64
+ * matrix cores (CIS_COMPOSE_MFMA).  Mathematically equal to cis_discretize
+ * (chain rule over the block boundaries); the sums are ordered differently.
+ * ws must hold cis_blocked_workspace_size bytes (checkpoints and per-block
+ * sensitivities).  Trades (blocks - 1) dense products per interval for a
+ * blocks-times shorter sensitivity recursion.
+ */
+cis_status cis_discretize_blocked(const cis_model *model, const cis_shape *shape, const void *X,
+                                  const void *U, const void *s, const void *params,
+                                  int32_t blocks, int32_t compose, void *A, void *Bm, void *Bp,
+                                  void *S, void *defect, void *xprop, void *ws, size_t ws_bytes,
+                                  void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches of trajectories (multiple shooting over many trajectories at once,
  * Sec. VI): the per-interval work of every trajectory is put on one device

@@ -30,6 +30,8 @@ CIS_BATCH_ADJOINT = 2
 CIS_SCHED_GRID = 1
 CIS_SCHED_PERSISTENT = 2
 CIS_SCHED_TUNE = 3
+CIS_COMPOSE_VALU = 0
+CIS_COMPOSE_MFMA = 1
 
 # every symbol include/cis.h declares
 EXPORTS = [
@@ -37,6 +39,7 @@ EXPORTS = [
     "cis_model_destroy", "cis_model_dims", "cis_discretize", "cis_defects",
     "cis_adjoint_workspace_size", "cis_discretize_adjoint", "cis_batch_plan_create",
     "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
+    "cis_blocked_workspace_size", "cis_discretize_blocked",
 ]
 
 
@@ -106,6 +109,12 @@ def load(build_if_missing: bool = True):
     lib.cis_discretize_adjoint.restype = St
     lib.cis_discretize_adjoint.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, P, I32]
                                            + [P] * 6 + [ctypes.c_size_t, P])
+    lib.cis_blocked_workspace_size.restype = St
+    lib.cis_blocked_workspace_size.argtypes = [P, ctypes.POINTER(Shape), I32,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+    lib.cis_discretize_blocked.restype = St
+    lib.cis_discretize_blocked.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, I32, I32]
+                                           + [P] * 7 + [ctypes.c_size_t, P])
     lib.cis_batch_plan_create.restype = St
     lib.cis_batch_plan_create.argtypes = [ctypes.POINTER(Traj), I32, I32, I32, I32, I32, I32, P,
                                           ctypes.POINTER(P)]

@@ -142,6 +142,41 @@ def discretize_into(cm, X, U, s, params, K, out, stream=None):
     return out
 
 
+def blocked_workspace_bytes(cm: CisModel, N, K, blocks, ld_int=None):
+    sh = _lib.Shape(N, int(K), _lib.CIS_F64, 0, N + 1, N if ld_int is None else int(ld_int))
+    nbytes = ctypes.c_size_t()
+    _lib.check(_lib.load().cis_blocked_workspace_size(cm.handle, ctypes.byref(sh), int(blocks),
+                                                      ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def discretize_blocked(cm: CisModel, X, U, s, params, K, blocks, compose="valu", *,
+                       with_xprop=True, ws=None, stream=None):
+    """Same outputs as :func:`discretize` (FP64) with the substeps split into
+    `blocks` blocks integrated in parallel and chained by dense products
+    (compose = "valu" or "mfma").  ws: optional preallocated uint8 workspace."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    kw = dict(device=X.device, dtype=X.dtype)
+    out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+               Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+               d=torch.empty((nx, N), **kw))
+    out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+    nbytes = blocked_workspace_bytes(cm, N, K, blocks)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty((nbytes,), device=X.device, dtype=torch.uint8)
+    sh = _shape(X, s, K)
+    mode = {"valu": _lib.CIS_COMPOSE_VALU, "mfma": _lib.CIS_COMPOSE_MFMA}[compose]
+    lib = _lib.load()
+    _lib.check(lib.cis_discretize_blocked(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                          _ptr(params), int(blocks), mode, _ptr(out["A"]),
+                                          _ptr(out["Bm"] if m else None),
+                                          _ptr(out["Bp"] if m else None), _ptr(out["S"]),
+                                          _ptr(out["d"]), _ptr(out["xprop"]), _ptr(ws),
+                                          ws.numel(), _stream(stream)))
+    return out
+
+
 def defects(cm: CisModel, X, U, s, params, K, *, ckpt_every=None, stream=None):
     """F~ and defects only; optional substep checkpoints [K/C, n, N] for the adjoint."""
     _check_inputs(cm, X, U, s, params)

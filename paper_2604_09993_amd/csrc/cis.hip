@@ -228,12 +228,23 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
     static_assert(D > 0 || L <= 1, "several contacts on the torso are not laid out");
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int nth = TP::NTHREADS;
-    load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
+    // substep block of this item (whole interval when a.B <= 1)
+    const bool blocked = a.B > 1;
+    const int kin = blocked ? k % a.N : k;            // interval of the inputs
+    const int Kb = blocked ? a.K / a.B : a.K;         // substeps of this item
+    const int j0 = blocked ? (k / a.N) * Kb : 0;      // first substep
+    load_interval<T, TP>(sh.iv, a, mc, kin, tid, nth);
+    if (blocked) {
+        // block start: x from the checkpoint slot, integral states from zero
+        // (they feed back into nothing; only their sensitivities are kept)
+        const T* xi = a.xinit + (int64_t)(k / a.N) * NX * a.ld_blk + kin;
+        for (int e = tid; e < NXT; e += nth) sh.iv.x0[e] = e < NX ? xi[e * a.ld_blk] : T(0);
+    }
     for (int e = tid; e < NCOEF * C::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NCOEF; ++q) coef_constants<T, TP>(sh.iv, sh.coef[q], tid, nth);
-    const int nst = 4 * a.K;
+    const int nst = 4 * Kb;
     const int nsteps = nst + LAG;
     const int64_t ldi = a.ldi;
     __syncthreads();
@@ -257,14 +268,14 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
         for (int t = 0; t < nsteps; ++t) {
             if (t < nst) {
                 const int st = t & 3;
-                const T tau = (T(t >> 2) + T(stage_c(st))) / T(a.K);
+                const T tau = (T(j0 + (t >> 2)) + T(stage_c(st))) / T(a.K);
                 state_stage<T, TP>(sh.iv, mc, c, bs, st, tau, sh.xring[(t + 1) & 3],
                                    sh.csring[t & 3], sh.fring[t & 3], lane);
             }
             __syncthreads();
         }
         if constexpr (NCW > 1) __syncthreads();   // the integral-row hand-over step
-        if (grp == 0 && lane < NB) {
+        if (grp == 0 && lane < NB && !blocked) {
 #pragma unroll
             for (int kk = 0; kk < 6; ++kk) {
                 const int r = kk < 3 ? 3 * c.b + kk : NQ + 3 * c.b + kk - 3;
@@ -286,7 +297,7 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
         for (int t = 0; t < 1 + w; ++t) __syncthreads();
         for (int tc = w; tc < nst; tc += NCW) {
             const int st = tc & 3;
-            const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
+            const T tau = (T(j0 + (tc >> 2)) + T(stage_c(st))) / T(a.K);
             T ycc = T(0), yct = T(0);
             coef_stage<T, TP, (NCW > 1)>(sh.iv, mc, c, tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
                                          sh.csring[tc & 3], sh.fring[tc & 3], tau,
@@ -319,11 +330,11 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             }
         }
         if (grp == 0 && w == 0) {
-            if (c.contact) {
+            if (c.contact && !blocked) {
                 if (a.xprop) a.xprop[ycc_row * ldi + k] = ycb;
                 a.defect[ycc_row * ldi + k] = ycb - sh.iv.xk1[ycc_row];
             }
-            if (lane == 0) {
+            if (lane == 0 && !blocked) {
                 if (a.xprop) a.xprop[(NX + NC) * ldi + k] = ytb;
                 a.defect[(NX + NC) * ldi + k] = ytb - sh.iv.xk1[NX + NC];
             }
@@ -365,8 +376,8 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
         for (int t = 0; t < LAG; ++t) __syncthreads();
         // steps LAG .. nst+LAG-1 apply stages 0 .. nst-1, unrolled by the 4 RK stages
         const T Kt = T(a.K);
-        for (int j = 0; j < a.K; ++j) {
-            const T jt = T(j);
+        for (int j = 0; j < Kb; ++j) {
+            const T jt = T(j0 + j);
             const T tau0 = jt / Kt, tauh = (jt + T(0.5)) / Kt, tau1 = (jt + T(1)) / Kt;
             tangent_stage<T, TP, 0>(sh.iv, z, sh.coef[0], tau0, leg, wbm, wbp, fsel, fct, ctrl);
             __syncthreads();
@@ -592,6 +603,59 @@ static cis_status launch_defects(const cis_model* m, const cis_shape* sh, const 
                                    0, stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_defects launch: %s", hipGetErrorString(e));
     return CIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// substep blocks: pass 1 (defects with checkpoints at the block starts) and
+// pass 2 (one discretize work item per (block, interval))
+// ---------------------------------------------------------------------------
+template <int L, int D>
+static cis_status blocked_passes_t(const cis_model* m, const cis_shape* sh, const void* X,
+                                   const void* U, const void* s, const void* prm, int B,
+                                   double* ckpt, double* Ab, double* Bmb, double* Bpb,
+                                   double* Sb, void* defect, void* xprop, hipStream_t stream) {
+    using T = double;
+    cis_status st = launch_defects<T, L, D>(m, sh, X, U, s, prm, defect, xprop, ckpt,
+                                            sh->substeps / B, stream);
+    if (st != CIS_OK) return st;
+    FwdArgs<T> a = make_args<T>(sh, X, U, s, prm);
+    a.A = Ab;
+    a.Bm = Bmb;
+    a.Bp = Bpb;
+    a.S = Sb;
+    a.ldi = (int64_t)B * sh->N;   // block outputs: column b N + k
+    a.xinit = ckpt;
+    a.ld_blk = sh->ld_int;        // checkpoints as written by pass 1
+    a.B = B;
+    using TL = LatencyTopo<T, L, D>;
+    using TT = ThroughputTopo<T, L, D>;
+    const int64_t items = (int64_t)B * sh->N;
+    auto launch = [&](auto tp) -> cis_status {
+        using TP = decltype(tp);
+        auto mc = make_const<TP::NB, TP::NJ, TP::NC>(m);
+        void* args[] = {&a, &mc};
+        hipError_t e = hipLaunchKernel((const void*)&k_discretize<T, TP>,
+                                       dim3((unsigned)items, TP::NGRP), dim3(TP::NTHREADS), args,
+                                       0, stream);
+        if (e != hipSuccess)
+            return fail(CIS_ERR_HIP, "k_discretize (blocks) launch: %s", hipGetErrorString(e));
+        return CIS_OK;
+    };
+    if (items * TL::NGRP <= device_cus()) return launch(TL{});
+    return launch(TT{});
+}
+
+cis_status blocked_passes(const cis_model* m, const cis_shape* sh, const void* X, const void* U,
+                          const void* s, const void* prm, int B, double* ckpt, double* Ab,
+                          double* Bmb, double* Bpb, double* Sb, void* defect, void* xprop,
+                          hipStream_t stream) {
+#define CIS_BLK(LL, DD)                                                                     \
+    if (m->L == LL && m->D == DD)                                                           \
+        return blocked_passes_t<LL, DD>(m, sh, X, U, s, prm, B, ckpt, Ab, Bmb, Bpb, Sb,     \
+                                        defect, xprop, stream);
+    CIS_TOPOLOGIES(CIS_BLK)
+#undef CIS_BLK
+    return fail(CIS_ERR_UNSUPPORTED, "substep blocks: topology has no compiled kernel");
 }
 
 // ---------------------------------------------------------------------------

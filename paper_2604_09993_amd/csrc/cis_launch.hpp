@@ -82,6 +82,14 @@ cis_status prep_adjoint_reduce_batch(const void* rdesc, int n_traj, KLaunch* out
 // Column groups (work units per item) of the discretize kernel.
 int discretize_units_per_item(const cis_model* m, int32_t dtype);
 
+// Substep blocks, passes 1 and 2 (FP64): checkpoints [B][n][ld_int] at the
+// block starts, defect and F~ of the whole interval, and the block
+// sensitivities Ab [nx][nx][B N], Bmb / Bpb [nx][m][B N], Sb [nx][B N].
+cis_status blocked_passes(const cis_model* m, const cis_shape* sh, const void* X, const void* U,
+                          const void* s, const void* prm, int B, double* ckpt, double* Ab,
+                          double* Bmb, double* Bpb, double* Sb, void* defect, void* xprop,
+                          hipStream_t stream);
+
 // Per-trajectory inputs of the batched reduction.
 struct RedDesc {
     const double* ws_uk;

@@ -475,6 +475,13 @@ struct FwdArgs {
     T* ckpt;
     int64_t ldn, ldi;
     int N, K, C;
+    // substep blocks (discretize only): with B > 1 work item i is block
+    // b = i / N of interval i % N, substeps [b K/B, (b+1) K/B), started from
+    // the x part of xinit slot b ([B][n][ld_blk], interval index contiguous);
+    // outputs at column i, no defect or F~.
+    const T* xinit;
+    int64_t ld_blk;
+    int B;
 };
 
 // Arguments of the reverse sweep of one trajectory.
@@ -502,10 +509,17 @@ struct BatchArgs {
 
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  Map
 // dispatch slot w (of n) to a logical index such that, inside every full block
-// of 128 slots, 16 consecutive logical indices fall on one XCD: neighbouring
-// intervals then write their output lines through the same L2.
+// of 128 slots, 16 consecutive logical indices fall on one XCD, and the slots
+// of the last partial block are split into 8 runs of consecutive indices, one
+// per XCD: neighbouring intervals then write their output lines through the
+// same L2.
 __device__ __forceinline__ int xcd_slot(int w, int n) {
-    if (w >= (n & ~127)) return w;
+    const int full = n & ~127;
+    if (w >= full) {
+        const int r = n - full, j = w - full, x = j & 7;
+        const int q = r >> 3, rem = r & 7;
+        return full + x * q + (x < rem ? x : rem) + (j >> 3);
+    }
     const int r = w & 127;
     return (w & ~127) | ((r & 7) << 4) | (r >> 3);
 }

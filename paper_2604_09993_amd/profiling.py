@@ -1,0 +1,165 @@
+"""Profiling helpers: HBM counter calibration and rocprofv3 summaries.
+
+    python -m paper_2604_09993_amd.profiling copy
+        one plain device copy of 64 Mi doubles (512 MiB each way), three
+        dispatches: run under ``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc
+        WRITE_SIZE`` to get the bytes each counter reports per byte moved.
+
+    python -m paper_2604_09993_amd.profiling summarize --trace D --fetch D \
+        --write D --cfetch D --cwrite D --md OUT.md --traffic OUT.json [--cmd-* ...]
+        reads the rocprofv3 result databases under the given output folders
+        (kernel trace with --stats; FETCH_SIZE and WRITE_SIZE runs of the same
+        program; the two calibration runs) and writes the markdown summary and
+        the per-kernel traffic record (calibrated bytes per dispatch, tied to
+        the hash of the kernel sources).
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+COPY_ELEMS = 64 * 1024 * 1024   # doubles per calibration copy
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of the kernel sources and the ABI header (identifies measured kernels)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".cpp")))
+    for f in files + [os.path.join("..", "..", "include", "cis.h")]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def run_copy():
+    import torch
+    x = torch.ones(COPY_ELEMS, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copied 3 x {COPY_ELEMS * 8} bytes", flush=True)
+
+
+def _dbs(folder):
+    found = sorted(glob.glob(os.path.join(folder, "**", "*_results.db"), recursive=True))
+    if not found:
+        raise FileNotFoundError(f"no rocprofv3 results database under {folder}")
+    return found
+
+
+def _short(name: str) -> str:
+    """Kernel name without the namespace and argument list."""
+    n = name.replace("cis::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    depth, out = 0, []
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip().replace("> >", ">>")
+
+
+def kernel_stats(folder):
+    rows = defaultdict(lambda: [0, 0.0])
+    for db in _dbs(folder):
+        c = sqlite3.connect(db).cursor()
+        for name, calls, total, _avg, _pct in c.execute(
+                "select name, total_calls, total_duration, average, percentage from top_kernels"):
+            r = rows[_short(name)]
+            r[0] += int(calls)
+            r[1] += float(total)
+    # the top_kernels view reports microseconds
+    return {k: dict(calls=v[0], total_us=v[1], avg_us=v[1] / max(v[0], 1))
+            for k, v in rows.items()}
+
+
+def counter_means(folder, counter):
+    vals = defaultdict(list)
+    for db in _dbs(folder):
+        c = sqlite3.connect(db).cursor()
+        cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
+        ci = {n: i for i, n in enumerate(cols)}
+        kcol = ci.get("kernel_name", ci.get("name"))
+        for r in c.execute("select * from counters_collection"):
+            if r[ci["counter_name"]] == counter:
+                vals[_short(r[kcol])].append(float(r[ci["value"]]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}
+
+
+def summarize(a):
+    stats = kernel_stats(a.trace)
+    fetch = counter_means(a.fetch, "FETCH_SIZE")
+    write = counter_means(a.write, "WRITE_SIZE")
+    cf = counter_means(a.cfetch, "FETCH_SIZE")
+    cw = counter_means(a.cwrite, "WRITE_SIZE")
+    moved_kib = COPY_ELEMS * 8 / 1024.0
+    copy_f = max(cf.values()) if cf else None
+    copy_w = max(cw.values()) if cw else None
+    sf = moved_kib / copy_f if copy_f else 1.0
+    sw = moved_kib / copy_w if copy_w else 1.0
+    algo = json.loads(a.algorithmic) if a.algorithmic else {}
+    lines = [f"# {a.title}", "", "Box: one MI355X (gfx950). All commands run from the repository root.",
+             "", "## Kernel trace", "", f"    {a.cmd_trace}", "",
+             "| kernel | calls | total µs | average µs |", "|---|---|---|---|"]
+    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_us"]):
+        lines.append(f"| `{k}` | {v['calls']} | {v['total_us']:.1f} | {v['avg_us']:.2f} |")
+    lines += ["", "## HBM traffic (PMC), per dispatch", "", f"    {a.cmd_fetch}", f"    {a.cmd_write}",
+              "", "Calibration: a plain copy of 64 Mi doubles (512 MiB each way), 3 dispatches:", "",
+              f"    {a.cmd_cfetch}", f"    {a.cmd_cwrite}", "",
+              f"copy: FETCH_SIZE {copy_f:,.1f} KiB, WRITE_SIZE {copy_w:,.1f} KiB per dispatch for "
+              f"{moved_kib:,.0f} KiB moved each way -> scale factors {sf:.3f} (fetch) and "
+              f"{sw:.3f} (write).", "",
+              "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read bytes | write bytes | algorithmic bytes |",
+              "|---|---|---|---|---|---|"]
+    rec = {"sources_sha256": kernel_sources_sha256(), "scale_fetch": sf, "scale_write": sw,
+           "commands": [a.cmd_fetch, a.cmd_write, a.cmd_cfetch, a.cmd_cwrite], "kernels": {}}
+    for k in sorted(set(fetch) | set(write)):
+        f_kib, w_kib = fetch.get(k, 0.0), write.get(k, 0.0)
+        rb, wb = f_kib * 1024 * sf, w_kib * 1024 * sw
+        al = algo.get(k)
+        lines.append(f"| `{k}` | {f_kib:,.1f} | {w_kib:,.1f} | {rb:,.0f} | {wb:,.0f} | "
+                     f"{'' if al is None else f'{al:,.0f}'} |")
+        rec["kernels"][k] = {"fetch_bytes": rb, "write_bytes": wb, "algorithmic_bytes": al}
+    if a.note:
+        lines += ["", a.note]
+    with open(a.md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(a.traffic, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"wrote {a.md} and {a.traffic}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("copy")
+    s = sub.add_parser("summarize")
+    for k in ("trace", "fetch", "write", "cfetch", "cwrite", "md", "traffic"):
+        s.add_argument("--" + k, required=True)
+    for k in ("trace", "fetch", "write", "cfetch", "cwrite"):
+        s.add_argument("--cmd-" + k, default="")
+    s.add_argument("--title", default="Kernel profile")
+    s.add_argument("--algorithmic", default="", help="JSON {kernel: algorithmic bytes}")
+    s.add_argument("--note", default="")
+    a = ap.parse_args()
+    if a.cmd == "copy":
+        run_copy()
+    else:
+        summarize(a)
+
+
+if __name__ == "__main__":
+    main()
