@@ -2,10 +2,10 @@
 // every interval, for a cotangent seed lambda_k = dJ/dF~_k; the penalized
 // defect merit of the SCP subproblem (Sec. V) is one such J.
 //
-//   k_adjoint : one wave per interval.  Segments of C substeps are replayed
-//               from the checkpoints (x at substeps 0, C, 2C, ..), the stage
-//               inputs are kept in LDS, and the classical RK4 stages are then
-//               reversed:  kbar_i = h/6 w_i xbar + h a_{i+1} Xbar_{i+1},
+//   k_adjoint : two waves per interval.  Chunks of at most 8 substeps are
+//               replayed by one wave from the checkpoints (x at substeps 0, C,
+//               2C, ..), their stage inputs kept in LDS, while the other wave
+//               reverses the previously recorded chunk's classical RK4 stages:  kbar_i = h/6 w_i xbar + h a_{i+1} Xbar_{i+1},
 //               Xbar_i = s J_x(X_i)^T kbar_i, xbar <- xbar + sum_i Xbar_i,
 //               with the control, dilation and parameter adjoints gathered
 //               along the way.  The transposed Jacobian product is the
@@ -30,9 +30,10 @@ constexpr int CHUNK = 8;   // substeps whose stage inputs are kept in LDS at onc
 template <class T, class TP>
 struct AdjShared {
     Interval<T, TP> iv;
-    RhsScratch<T, TP> sc;
+    RhsScratch<T, TP> sc;               // reverse wave
+    RhsScratch<T, TP> scr;              // replay wave
     T coef[Coef<TP>::SIZE];
-    T hist[CHUNK * 4][TP::NX];          // stage inputs (x part) of the chunk
+    T hist[2][CHUNK * 4][TP::NX];       // stage inputs (x part) of two chunks
     T kb[TP::NXT];                      // kbar of the current stage
     T xbs[TP::NX];                      // Xbar of the current stage
     T jslot[cmax(TP::NJ, 1)][8];        // th_p, th_c, w_p, w_c, x_p, x_c, y_p, y_c
@@ -189,21 +190,69 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
     wave_lds_sync();
 }
 
+// One interval by two waves: the replay wave recomputes chunk u+1's stage
+// inputs from its checkpoint while the reverse wave sweeps chunk u backwards
+// (two history buffers, one workgroup barrier per chunk).
 template <class T, class TP>
 __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                              const int k) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NX = TP::NX, NXT = TP::NXT;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const FwdArgs<T>& f = a.f;
-    load_interval<T, TP>(ax.iv, f, mc, k, lane, 64);
+    load_interval<T, TP>(ax.iv, f, mc, k, tid, 128);
     // constant FOH forcing entries of the coefficient buffer (zero elsewhere)
-    for (int e = lane; e < Coef<TP>::SIZE; e += 64) ax.coef[e] = T(0);
-    wave_lds_sync();
-    coef_constants<T, TP>(ax.iv, ax.coef, lane, 64);
-    wave_lds_sync();
+    for (int e = tid; e < Coef<TP>::SIZE; e += 128) ax.coef[e] = T(0);
+    __syncthreads();
+    coef_constants<T, TP>(ax.iv, ax.coef, tid, 128);
+    __syncthreads();
 
     const int64_t ldi = f.ldi;
+    const int K = f.K, Cs = f.C;
+    const int nseg = K / Cs;
+    const int nch = (Cs + CHUNK - 1) / CHUNK;   // chunks per checkpoint segment
+    const int U = nseg * nch;                   // chunks, last first
+    if (wave == 1) {
+        // ------------- replay wave: chunk t at step t -------------
+        RowState<T> rs;
+        for (int t = 0; t <= U; ++t) {
+            if (t < U) {
+                const int g = nseg - 1 - t / nch;
+                const int c0 = (nch - 1 - t % nch) * CHUNK;
+                const int len = (Cs - c0) < CHUNK ? (Cs - c0) : CHUNK;
+                const int base = g * Cs;
+                T(*hist)[NX] = ax.hist[t & 1];
+                // replay from the checkpoint to the chunk start, then record the chunk
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int r = lane + 64 * q;
+                    rs.xb[q] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
+                    rs.xa[q] = T(0);
+                    if (r < NXT) ax.scr.ns[r] = rs.xb[q];
+                }
+                wave_lds_sync();
+                for (int jj = 0; jj < c0 + len; ++jj) {
+                    const int j = base + jj;
+                    for (int st = 0; st < 4; ++st) {
+                        if (jj >= c0) {
+#pragma unroll
+                            for (int q = 0; q < 2; ++q) {
+                                const int r = lane + 64 * q;
+                                if (r < NX) hist[(jj - c0) * 4 + st][r] = ax.scr.ns[r];
+                            }
+                        }
+                        const T tau = (T(j) + T(stage_c(st))) / T(K);
+                        rhs_eval<T, TP, LEAN>(ax.iv, ax.scr, mc, lane, tau, (T*)nullptr);
+                        rk_rows<T, TP, NX>(ax.iv, ax.scr, rs, lane, st, ax.scr.ns, (T*)nullptr);
+                    }
+                }
+                wave_lds_sync();
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // ------------- reverse wave: chunk t-1 at step t -------------
     T xbar[2], xprev[2], xsum[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -214,38 +263,14 @@ __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs
     }
     T sacc = T(0), muacc = T(0), macc = T(0);
     T uacc[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
-    const int K = f.K, Cs = f.C;
-    const int nseg = K / Cs;
-    RowState<T> rs;
-    for (int g = nseg - 1; g >= 0; --g) {
-        const int base = g * Cs;
-        for (int c0 = ((Cs - 1) / CHUNK) * CHUNK; c0 >= 0; c0 -= CHUNK) {
+    for (int t = 0; t <= U; ++t) {
+        if (t >= 1) {
+            const int u = t - 1;
+            const int g = nseg - 1 - u / nch;
+            const int c0 = (nch - 1 - u % nch) * CHUNK;
             const int len = (Cs - c0) < CHUNK ? (Cs - c0) : CHUNK;
-            // replay from the checkpoint to the chunk start, then record the chunk
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int r = lane + 64 * q;
-                rs.xb[q] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
-                rs.xa[q] = T(0);
-                if (r < NXT) ax.sc.ns[r] = rs.xb[q];
-            }
-            wave_lds_sync();
-            for (int jj = 0; jj < c0 + len; ++jj) {
-                const int j = base + jj;
-                for (int st = 0; st < 4; ++st) {
-                    if (jj >= c0) {
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int r = lane + 64 * q;
-                            if (r < NX) ax.hist[(jj - c0) * 4 + st][r] = ax.sc.ns[r];
-                        }
-                    }
-                    const T tau = (T(j) + T(stage_c(st))) / T(K);
-                    rhs_eval<T, TP, LEAN>(ax.iv, ax.sc, mc, lane, tau, (T*)nullptr);
-                    rk_rows<T, TP, NX>(ax.iv, ax.sc, rs, lane, st, ax.sc.ns, (T*)nullptr);
-                }
-            }
-            wave_lds_sync();
+            const int base = g * Cs;
+            const T(*hist)[NX] = ax.hist[u & 1];
             // reverse the recorded substeps
             for (int jj = len - 1; jj >= 0; --jj) {
                 const int j = base + c0 + jj;
@@ -253,7 +278,7 @@ __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         const int r = lane + 64 * q;
-                        if (r < NX) ax.sc.ns[r] = ax.hist[jj * 4 + st][r];
+                        if (r < NX) ax.sc.ns[r] = hist[jj * 4 + st][r];
                     }
                     wave_lds_sync();
                     const T tau = (T(j) + T(stage_c(st))) / T(K);
@@ -268,6 +293,7 @@ __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs
                 }
             }
         }
+        __syncthreads();
     }
     // gX_k = xbar
     const int64_t ldn = f.ldn;
@@ -314,14 +340,14 @@ __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs
 }
 
 template <class T, class TP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
     k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ AdjShared<T, TP> ax;
     adjoint_item<T, TP>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
 }
 
 template <class T, class TP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
     k_adjoint_batch(BatchArgs<AdjArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ AdjShared<T, TP> ax;
     const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
@@ -399,7 +425,7 @@ static cis_status launch_adjoint(const cis_model* m, const cis_shape* sh, const 
     a.ws_uk1 = w + (size_t)m->m * N;
     a.ws_p = w + (size_t)2 * m->m * N;
     void* args[] = {&a, &mc};
-    hipError_t e = hipLaunchKernel((const void*)&k_adjoint<T, TP>, dim3(N), dim3(64), args, 0,
+    hipError_t e = hipLaunchKernel((const void*)&k_adjoint<T, TP>, dim3(N), dim3(128), args, 0,
                                    stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_adjoint launch: %s", hipGetErrorString(e));
     const int64_t work = (int64_t)m->m * (N + 1) + m->nx + m->np;
@@ -432,7 +458,7 @@ static cis_status prep_adj_t(const cis_model* m, const BatchGroupDev& g, KLaunch
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
     out->func = (const void*)&k_adjoint_batch<double, TP>;
     out->grid = dim3(g.n_items);
-    out->block = dim3(64);
+    out->block = dim3(128);
     return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_adjoint_batch: launch record refused");
 }
 
