@@ -452,65 +452,117 @@ __global__ void __launch_bounds__(TP::NTHREADS)
 }
 
 // ---------------------------------------------------------------------------
-// K1: defects and checkpoints.  One wave per interval.
+// K1: defects and checkpoints.  Two waves per interval: the state wave of the
+// discretize kernel (body lanes, stage t at step t; x checkpoints every C
+// substeps) and one wave forming the integral-row integrands of stage t-1
+// from the same rings (no Jacobian).
 // ---------------------------------------------------------------------------
 template <class T, class TP>
 struct DefShared {
     Interval<T, TP> iv;
-    RhsScratch<T, TP> sc;
+    T xring[4][TP::NX];
+    T csring[4][TP::NB][2];
+    T fring[4][3 * TP::NB];
 };
 
 template <class T, class TP>
 __device__ __forceinline__ void defects_item(DefShared<T, TP>& sh, const FwdArgs<T>& a,
                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                              const int k) {
-    constexpr int NX = TP::NX, NXT = TP::NXT;
-    const int lane = threadIdx.x;
-    load_interval<T, TP>(sh.iv, a, mc, k, lane, 64);
-    RowState<T> rs;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int r = lane + 64 * q;
-        rs.xb[q] = r < NXT ? sh.iv.x0[r] : T(0);
-        rs.xa[q] = T(0);
-        if (r < NXT) sh.sc.ns[r] = rs.xb[q];
-    }
-    wave_lds_sync();
+    constexpr int NB = TP::NB, NX = TP::NX, NQ = TP::NQ, NC = TP::NC;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_interval<T, TP>(sh.iv, a, mc, k, tid, 128);
+    const int nst = 4 * a.K;
+    const int nsteps = nst + 1;
     const int64_t ldi = a.ldi;
-    for (int j = 0; j < a.K; ++j) {
-        if (a.ckpt && (j % a.C) == 0) {
-            const int slot = j / a.C;
+    const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+    if (wave == 0) {
+        BodyRK<T> bs;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int r = lane + 64 * q;
-                if (r < NX) a.ckpt[((int64_t)slot * NX + r) * ldi + k] = rs.xb[q];
+        for (int kk = 0; kk < 3; ++kk) {
+            bs.xb[kk] = sh.iv.x0[3 * c.b + kk];
+            bs.xb[3 + kk] = sh.iv.x0[NQ + 3 * c.b + kk];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) {
+            bs.xs[kk] = bs.xb[kk];
+            bs.xa[kk] = T(0);
+        }
+        for (int t = 0; t < nsteps; ++t) {
+            if (t < nst) {
+                const int st = t & 3, j = t >> 2;
+                if (st == 0 && a.ckpt && (j % a.C) == 0 && lane < NB) {
+                    T* ck = a.ckpt + (int64_t)(j / a.C) * NX * ldi + k;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) {
+                        ck[(3 * c.b + kk) * ldi] = bs.xb[kk];
+                        ck[(NQ + 3 * c.b + kk) * ldi] = bs.xb[3 + kk];
+                    }
+                }
+                const T tau = (T(j) + T(stage_c(st))) / T(a.K);
+                state_stage<T, TP>(sh.iv, mc, c, bs, st, tau, sh.xring[(t + 1) & 3],
+                                   sh.csring[t & 3], sh.fring[t & 3], lane);
+            }
+            __syncthreads();
+        }
+        if (lane < NB) {
+#pragma unroll
+            for (int kk = 0; kk < 6; ++kk) {
+                const int r = kk < 3 ? 3 * c.b + kk : NQ + 3 * c.b + kk - 3;
+                if (a.xprop) a.xprop[r * ldi + k] = bs.xb[kk];
+                a.defect[r * ldi + k] = bs.xb[kk] - sh.iv.xk1[r];
             }
         }
-        for (int st = 0; st < 4; ++st) {
-            const T tau = (T(j) + T(stage_c(st))) / T(a.K);
-            rhs_eval<T, TP, FULL>(sh.iv, sh.sc, mc, lane, tau, (T*)nullptr);
-            rk_rows<T, TP, NXT>(sh.iv, sh.sc, rs, lane, st, sh.sc.ns, (T*)nullptr);
+    } else {
+        const int ycc_row = NX + c.i;
+        T ycb = c.contact ? sh.iv.x0[ycc_row] : T(0), yca = T(0);
+        T ytb = lane == 0 ? sh.iv.x0[NX + NC] : T(0), yta = T(0);
+        const T s = sh.iv.s;
+        for (int t = 0; t < nsteps; ++t) {
+            const int tc = t - 1;
+            if (tc >= 0 && tc < nst) {
+                const int st = tc & 3;
+                const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
+                T ycc = T(0), yct = T(0);
+                coef_stage<T, TP, false, false>(sh.iv, mc, c,
+                                                tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
+                                                sh.csring[tc & 3], sh.fring[tc & 3], tau,
+                                                (T*)nullptr, ycc, yct, lane);
+                const T wk = (st == 0 || st == 3) ? T(1) : T(2);
+                if (st == 0) {
+                    yca = s * ycc;
+                    yta = s * yct;
+                } else {
+                    yca += wk * s * ycc;
+                    yta += wk * s * yct;
+                }
+                if (st == 3) {
+                    ycb += sh.iv.h6 * yca;
+                    ytb += sh.iv.h6 * yta;
+                }
+            }
+            __syncthreads();
         }
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int r = lane + 64 * q;
-        if (r < NXT) {
-            if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
-            a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
+        if (c.contact) {
+            if (a.xprop) a.xprop[ycc_row * ldi + k] = ycb;
+            a.defect[ycc_row * ldi + k] = ycb - sh.iv.xk1[ycc_row];
+        }
+        if (lane == 0) {
+            if (a.xprop) a.xprop[(NX + NC) * ldi + k] = ytb;
+            a.defect[(NX + NC) * ldi + k] = ytb - sh.iv.xk1[NX + NC];
         }
     }
 }
 
 template <class T, class TP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
     k_defects(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ DefShared<T, TP> sh;
     defects_item<T, TP>(sh, a, mc, xcd_slot(blockIdx.x, gridDim.x));
 }
 
 template <class T, class TP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
     k_defects_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ DefShared<T, TP> sh;
     const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
@@ -599,7 +651,7 @@ static cis_status launch_defects(const cis_model* m, const cis_shape* sh, const 
     a.ckpt = (T*)ckpt;
     a.C = C;
     void* args[] = {&a, &mc};
-    hipError_t e = hipLaunchKernel((const void*)&k_defects<T, TP>, dim3(sh->N), dim3(64), args,
+    hipError_t e = hipLaunchKernel((const void*)&k_defects<T, TP>, dim3(sh->N), dim3(128), args,
                                    0, stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_defects launch: %s", hipGetErrorString(e));
     return CIS_OK;
@@ -695,7 +747,7 @@ static cis_status prep_def_t(const cis_model* m, const BatchGroupDev& g, KLaunch
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
     out->func = (const void*)&k_defects_batch<T, TP>;
     out->grid = dim3(g.n_items);
-    out->block = dim3(64);
+    out->block = dim3(128);
     return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_defects_batch: launch record refused");
 }
 

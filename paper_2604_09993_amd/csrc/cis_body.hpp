@@ -284,9 +284,10 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
 // the state wave.  Writes cf (layout Coef<TP>) and returns, in the lanes that
 // own them, the integral-row right-hand sides (cc_i on contact lanes, the
 // violation row on lane 0) through ycc / yct.  With SPLIT the call contains
-// one workgroup barrier.
+// one workgroup barrier; without WRITE only the integral-row integrands are
+// formed (nothing is stored).
 // ---------------------------------------------------------------------------
-template <class T, class TP, bool SPLIT = false>
+template <class T, class TP, bool SPLIT = false, bool WRITE = true>
 __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                            const BodyConst<T, TP>& c, const T* xs,
@@ -343,17 +344,19 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     if (c.joint) {
         const int j = c.j;
         ctp += v0 + v1;   // |h_x|_s + |h_y|_s
-        cf[C::JH + 4 * j + 0] = s * d0;
-        cf[C::JH + 4 * j + 1] = s * d1;
-        cf[C::JH + 4 * j + 2] = s * (d1 * apx - d0 * apy);
-        cf[C::JH + 4 * j + 3] = s * (d0 * acy - d1 * acx);
-        const T ip = s * iv.iinv[p], ic = s * c.ii;
-        cf[C::GV + (3 * p + 2) * M + NJ + 2 * j] = -apy * ip;
-        cf[C::GV + (3 * p + 2) * M + NJ + 2 * j + 1] = apx * ip;
-        cf[C::GV + (3 * b + 2) * M + NJ + 2 * j] = acy * ic;
-        cf[C::GV + (3 * b + 2) * M + NJ + 2 * j + 1] = -acx * ic;
-        dTown += acx * lx + acy * ly;          // child side d(-a_c x lam)/dth
-        dTpar = -(apx * lx + apy * ly);        // parent side d(a_p x lam)/dth_p
+        if constexpr (WRITE) {
+            cf[C::JH + 4 * j + 0] = s * d0;
+            cf[C::JH + 4 * j + 1] = s * d1;
+            cf[C::JH + 4 * j + 2] = s * (d1 * apx - d0 * apy);
+            cf[C::JH + 4 * j + 3] = s * (d0 * acy - d1 * acx);
+            const T ip = s * iv.iinv[p], ic = s * c.ii;
+            cf[C::GV + (3 * p + 2) * M + NJ + 2 * j] = -apy * ip;
+            cf[C::GV + (3 * p + 2) * M + NJ + 2 * j + 1] = apx * ip;
+            cf[C::GV + (3 * b + 2) * M + NJ + 2 * j] = acy * ic;
+            cf[C::GV + (3 * b + 2) * M + NJ + 2 * j + 1] = -acx * ic;
+            dTown += acx * lx + acy * ly;          // child side d(-a_c x lam)/dth
+            dTpar = -(apx * lx + apy * ly);        // parent side d(a_p x lam)/dth_p
+        }
     }
     if (c.contact) {
         const int i = c.i;
@@ -367,49 +370,51 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         const T slack = mu * lnb - ltpb - ltmb;
         ycc = lnb * f.sd + ltpb * rp + ltmb * rm + slack * av;   // pairs of Sec. III
         ctp += -f.sd > T(0) ? v3 : T(0);                           // ramp_s(-sd)
-        const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) +
-                     slack * dav;
-        const T Dg = -(-f.sd > T(0) ? d3 : T(0));
-        const T dtx = f.dny, dty = -f.dnx;
-        const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
-        const T dvt_px = dtx * Pdx + dty * Pdy;
-        const T im = s * c.mi, ii = s * c.ii;
-        T* ct = cf + C::CT + C::NCT * i;
-        ct[C_AX] = ax;
-        ct[C_AY] = ay;
-        ct[C_FXP] = dfx * im;
-        ct[C_FYP] = dfy * im;
-        ct[C_TP] = (ax * dfy - ay * dfx) * ii;
-        ct[C_EPX] = s * (lnb * f.dsd_px + gv * dvt_px);
-        ct[C_EPY] = s * (lnb * f.dsd_py);
-        ct[C_EXD] = s * (gv * f.tx);
-        ct[C_EYD] = s * (gv * f.ty);
-        ct[C_EOM] = s * (gv * (f.ty * ax - f.tx * ay));
-        ct[C_ETH] = s * (-gv * om * (f.tx * ax + f.ty * ay));
-        ct[C_ZPX] = s * (Dg * f.dsd_px);
-        ct[C_ZPY] = s * (Dg * f.dsd_py);
-        ct[C_JMU] = s * (lnb * av);
-        const int u0 = 3 * NJ + 3 * i;
-        T* gvb = cf + C::GV;
-        gvb[(3 * b) * M + u0] = f.nx * im;
-        gvb[(3 * b + 1) * M + u0] = f.ny * im;
-        gvb[(3 * b + 2) * M + u0] = (ax * f.ny - ay * f.nx) * ii;
-        gvb[(3 * b) * M + u0 + 1] = f.tx * im;
-        gvb[(3 * b + 1) * M + u0 + 1] = f.ty * im;
-        gvb[(3 * b + 2) * M + u0 + 1] = (ax * f.ty - ay * f.tx) * ii;
-        gvb[(3 * b) * M + u0 + 2] = -f.tx * im;
-        gvb[(3 * b + 1) * M + u0 + 2] = -f.ty * im;
-        gvb[(3 * b + 2) * M + u0 + 2] = -(ax * f.ty - ay * f.tx) * ii;
-        T* gcb = cf + C::GC + i * M;
-        gcb[u0] = s * T(0.5) * (f.sd + mu * av);
-        gcb[u0 + 1] = s * T(0.5) * (rp - av);
-        gcb[u0 + 2] = s * T(0.5) * (rm - av);
-        const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
-        dTown += -(ax * fx + ay * fy);         // d(a x F)/dth at fixed F
-        cf[C::F + NX + i] = ycc;
+        if constexpr (WRITE) {
+            const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) +
+                         slack * dav;
+            const T Dg = -(-f.sd > T(0) ? d3 : T(0));
+            const T dtx = f.dny, dty = -f.dnx;
+            const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
+            const T dvt_px = dtx * Pdx + dty * Pdy;
+            const T im = s * c.mi, ii = s * c.ii;
+            T* ct = cf + C::CT + C::NCT * i;
+            ct[C_AX] = ax;
+            ct[C_AY] = ay;
+            ct[C_FXP] = dfx * im;
+            ct[C_FYP] = dfy * im;
+            ct[C_TP] = (ax * dfy - ay * dfx) * ii;
+            ct[C_EPX] = s * (lnb * f.dsd_px + gv * dvt_px);
+            ct[C_EPY] = s * (lnb * f.dsd_py);
+            ct[C_EXD] = s * (gv * f.tx);
+            ct[C_EYD] = s * (gv * f.ty);
+            ct[C_EOM] = s * (gv * (f.ty * ax - f.tx * ay));
+            ct[C_ETH] = s * (-gv * om * (f.tx * ax + f.ty * ay));
+            ct[C_ZPX] = s * (Dg * f.dsd_px);
+            ct[C_ZPY] = s * (Dg * f.dsd_py);
+            ct[C_JMU] = s * (lnb * av);
+            const int u0 = 3 * NJ + 3 * i;
+            T* gvb = cf + C::GV;
+            gvb[(3 * b) * M + u0] = f.nx * im;
+            gvb[(3 * b + 1) * M + u0] = f.ny * im;
+            gvb[(3 * b + 2) * M + u0] = (ax * f.ny - ay * f.nx) * ii;
+            gvb[(3 * b) * M + u0 + 1] = f.tx * im;
+            gvb[(3 * b + 1) * M + u0 + 1] = f.ty * im;
+            gvb[(3 * b + 2) * M + u0 + 1] = (ax * f.ty - ay * f.tx) * ii;
+            gvb[(3 * b) * M + u0 + 2] = -f.tx * im;
+            gvb[(3 * b + 1) * M + u0 + 2] = -f.ty * im;
+            gvb[(3 * b + 2) * M + u0 + 2] = -(ax * f.ty - ay * f.tx) * ii;
+            T* gcb = cf + C::GC + i * M;
+            gcb[u0] = s * T(0.5) * (f.sd + mu * av);
+            gcb[u0 + 1] = s * T(0.5) * (rp - av);
+            gcb[u0 + 2] = s * T(0.5) * (rm - av);
+            const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
+            dTown += -(ax * fx + ay * fy);         // d(a x F)/dth at fixed F
+            cf[C::F + NX + i] = ycc;
+        }
     }
     // F~: q rows are the stage velocities, v rows the state wave's accelerations
-    if (lane < NB) {
+    if (WRITE && lane < NB) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             cf[C::F + 3 * b + k] = xs[NQ + 3 * b + k];
@@ -417,15 +422,17 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         }
     }
     // dT_b/dth_b: own terms plus the parent-side terms of the children's joints
-    const T dT = dTown + from_children<TP>(dTpar, b);
-    if (lane < NB) cf[C::CTH + b] = s * dT * c.ii;
+    if constexpr (WRITE) {
+        const T dT = dTown + from_children<TP>(dTpar, b);
+        if (lane < NB) cf[C::CTH + b] = s * dT * c.ii;
+    }
     // violation row: sum over bodies (lane order) of their joint and contact parts
     T acc = T(0);
 #pragma unroll
     for (int e = 0; e < NB; ++e) acc += lane_value(ctp, e);
     if (lane == 0) {
         yct = acc;
-        cf[C::F + NX + NC] = acc;
+        if constexpr (WRITE) cf[C::F + NX + NC] = acc;
     }
 }
 
