@@ -259,6 +259,14 @@ enum { CIS_BATCH_DISCRETIZE = 1, CIS_BATCH_ADJOINT = 2 };
  *   CIS_SCHED_TUNE       time both at creation and keep the faster. */
 enum { CIS_SCHED_GRID = 1, CIS_SCHED_PERSISTENT = 2, CIS_SCHED_TUNE = 3 };
 
+/* Optional bits of `sched` fixing the form of the reverse sweep (waves per
+ * interval) instead of the default: timed at creation with CIS_SCHED_TUNE,
+ * else three waves.  3: stage evaluation one step ahead of the reverse sweep
+ * (checkpoints at most 8 substeps apart, else 2); 2: replay one chunk ahead;
+ * 1: one wave (fewest wave-cycles, for throughput).  The defects pass is
+ * likewise timed in its two forms with CIS_SCHED_TUNE. */
+enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30 };
+
 /*
  * Create a plan for n_traj trajectories (all of one dtype; CIS_BATCH_ADJOINT
  * needs CIS_F64).  ckpt_every: substeps between the checkpoints of the reverse
@@ -285,11 +293,12 @@ cis_status cis_batch_graph_run(cis_batch_plan *plan, int32_t op, void *stream);
 
 /* Description of a plan: number of model groups, and for group g (if
  * 0 <= g < groups) its trajectories, work items (intervals), units per item,
- * and the persistent grid size chosen for it (0 = one workgroup per unit).
+ * the persistent grid size chosen for it (0 = one workgroup per unit) and
+ * the waves per interval of its reverse sweep (0 without CIS_BATCH_ADJOINT).
  * Any output pointer may be NULL. */
 cis_status cis_batch_plan_info(const cis_batch_plan *plan, int32_t g, int32_t *groups,
                                int32_t *n_traj, int32_t *n_items, int32_t *units_per_item,
-                               int32_t *persist_blocks);
+                               int32_t *persist_blocks, int32_t *adjoint_waves);
 
 /* Release a plan (NULL accepted); synchronizes the device first. */
 void cis_batch_plan_destroy(cis_batch_plan *plan);

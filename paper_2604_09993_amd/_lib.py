@@ -30,6 +30,9 @@ CIS_BATCH_ADJOINT = 2
 CIS_SCHED_GRID = 1
 CIS_SCHED_PERSISTENT = 2
 CIS_SCHED_TUNE = 3
+CIS_SCHED_ADJ_1 = 0x10
+CIS_SCHED_ADJ_2 = 0x20
+CIS_SCHED_ADJ_3 = 0x30
 CIS_COMPOSE_VALU = 0
 CIS_COMPOSE_MFMA = 1
 
@@ -123,7 +126,7 @@ def load(build_if_missing: bool = True):
     lib.cis_batch_graph_run.restype = St
     lib.cis_batch_graph_run.argtypes = [P, I32, P]
     lib.cis_batch_plan_info.restype = St
-    lib.cis_batch_plan_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 5
+    lib.cis_batch_plan_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 6
     lib.cis_batch_plan_destroy.restype = None
     lib.cis_batch_plan_destroy.argtypes = [P]
     _lib = lib

@@ -300,7 +300,7 @@ class BatchPlan:
     """
 
     def __init__(self, trajs, ops=("discretize",), *, sched="tune", ckpt_every=0, graph=True,
-                 stream=None):
+                 adjoint_waves=None, stream=None):
         lib = _lib.load()
         if not trajs:
             raise ValueError("a batch needs at least one trajectory")
@@ -343,8 +343,12 @@ class BatchPlan:
                 setattr(tr, name, None if ten is None else ten.data_ptr())
         self._arr = arr
         h = ctypes.c_void_p()
+        sched_code = _SCHED[sched]
+        if adjoint_waves is not None:
+            sched_code |= {1: _lib.CIS_SCHED_ADJ_1, 2: _lib.CIS_SCHED_ADJ_2,
+                           3: _lib.CIS_SCHED_ADJ_3}[int(adjoint_waves)]
         _lib.check(lib.cis_batch_plan_create(arr, len(trajs), _dtype_code(dtype), self.ops,
-                                             _SCHED[sched], int(ckpt_every), int(bool(graph)),
+                                             sched_code, int(ckpt_every), int(bool(graph)),
                                              _stream(stream), ctypes.byref(h)))
         self._h = h
         self.graph = bool(graph)
@@ -359,13 +363,14 @@ class BatchPlan:
         """Per model group: trajectories, items, units per item, persistent grid (0 = grid)."""
         lib = _lib.load()
         ng = ctypes.c_int32()
-        _lib.check(lib.cis_batch_plan_info(self._h, -1, ctypes.byref(ng), None, None, None, None))
+        _lib.check(lib.cis_batch_plan_info(self._h, -1, ctypes.byref(ng), None, None, None, None,
+                                           None))
         res = []
         for g in range(ng.value):
-            v = [ctypes.c_int32() for _ in range(4)]
+            v = [ctypes.c_int32() for _ in range(5)]
             _lib.check(lib.cis_batch_plan_info(self._h, g, None, *[ctypes.byref(x) for x in v]))
             res.append(dict(n_traj=v[0].value, n_items=v[1].value, units_per_item=v[2].value,
-                            persist_blocks=v[3].value))
+                            persist_blocks=v[3].value, adjoint_waves=v[4].value))
         return res
 
     def close(self):

@@ -570,6 +570,66 @@ __global__ void __launch_bounds__(128)
     defects_item<T, TP>(sh, a, mc, it.y);
 }
 
+// Throughput form of K1 for batches: one wave per interval, element-parallel
+// right-hand side (one lane per body, joint, contact or row), fewer wave-cycles
+// per interval than the two body-lane waves above.
+template <class T, class TP>
+struct DefLaneShared {
+    Interval<T, TP> iv;
+    RhsScratch<T, TP> sc;
+};
+
+template <class T, class TP>
+__device__ __forceinline__ void defects_item_lane(DefLaneShared<T, TP>& sh, const FwdArgs<T>& a,
+                                                  const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                                  const int k) {
+    constexpr int NX = TP::NX, NXT = TP::NXT;
+    const int lane = threadIdx.x;
+    load_interval<T, TP>(sh.iv, a, mc, k, lane, 64);
+    RowState<T> rs;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        rs.xb[q] = r < NXT ? sh.iv.x0[r] : T(0);
+        rs.xa[q] = T(0);
+        if (r < NXT) sh.sc.ns[r] = rs.xb[q];
+    }
+    wave_lds_sync();
+    const int64_t ldi = a.ldi;
+    for (int j = 0; j < a.K; ++j) {
+        if (a.ckpt && (j % a.C) == 0) {
+            const int slot = j / a.C;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int r = lane + 64 * q;
+                if (r < NX) a.ckpt[((int64_t)slot * NX + r) * ldi + k] = rs.xb[q];
+            }
+        }
+        for (int st = 0; st < 4; ++st) {
+            const T tau = (T(j) + T(stage_c(st))) / T(a.K);
+            rhs_eval<T, TP, FULL>(sh.iv, sh.sc, mc, lane, tau, (T*)nullptr);
+            rk_rows<T, TP, NXT>(sh.iv, sh.sc, rs, lane, st, sh.sc.ns, (T*)nullptr);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        if (r < NXT) {
+            if (a.xprop) a.xprop[r * ldi + k] = rs.xb[q];
+            a.defect[r * ldi + k] = rs.xb[q] - sh.iv.xk1[r];
+        }
+    }
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(64)
+    k_defects_lane_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ DefLaneShared<T, TP> sh;
+    const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
+    const FwdArgs<T> a = b.descs[it.x];
+    defects_item_lane<T, TP>(sh, a, mc, it.y);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -741,13 +801,15 @@ static cis_status prep_disc_t(const cis_model* m, const BatchGroupDev& g, int pe
 }
 
 template <class T, int L, int D>
-static cis_status prep_def_t(const cis_model* m, const BatchGroupDev& g, KLaunch* out) {
+static cis_status prep_def_t(const cis_model* m, const BatchGroupDev& g, bool body_lanes,
+                             KLaunch* out) {
     using TP = Topo<L, D>;
     out->arg(batch_args<T>(g));
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
-    out->func = (const void*)&k_defects_batch<T, TP>;
+    out->func = body_lanes ? (const void*)&k_defects_batch<T, TP>
+                           : (const void*)&k_defects_lane_batch<T, TP>;
     out->grid = dim3(g.n_items);
-    out->block = dim3(128);
+    out->block = dim3(body_lanes ? 128 : 64);
     return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_defects_batch: launch record refused");
 }
 
@@ -768,11 +830,11 @@ cis_status prep_discretize_batch(const cis_model* m, int32_t dtype, const BatchG
 }
 
 cis_status prep_defects_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
-                              KLaunch* out) {
+                              bool body_lanes, KLaunch* out) {
 #define CIS_PREP_DEF(LL, DD)                                                                \
     if (m->L == LL && m->D == DD)                                                           \
-        return dtype == CIS_F64 ? prep_def_t<double, LL, DD>(m, g, out)                     \
-                                : prep_def_t<float, LL, DD>(m, g, out);
+        return dtype == CIS_F64 ? prep_def_t<double, LL, DD>(m, g, body_lanes, out)         \
+                                : prep_def_t<float, LL, DD>(m, g, body_lanes, out);
     CIS_TOPOLOGIES(CIS_PREP_DEF)
 #undef CIS_PREP_DEF
     return fail(CIS_ERR_UNSUPPORTED, "prep_defects_batch: topology has no compiled kernel");

@@ -30,9 +30,9 @@ constexpr int CHUNK = 8;   // substeps whose stage inputs are kept in LDS at onc
 template <class T, class TP>
 struct AdjShared {
     Interval<T, TP> iv;
-    RhsScratch<T, TP> sc;               // reverse wave
+    RhsScratch<T, TP> se[2];            // stage evaluations (state, F~, rotations) in flight
     RhsScratch<T, TP> scr;              // replay wave
-    T coef[Coef<TP>::SIZE];
+    T coef[2][Coef<TP>::SIZE];          // their Jacobian coefficients
     T hist[2][CHUNK * 4][TP::NX];       // stage inputs (x part) of two chunks
     T kb[TP::NXT];                      // kbar of the current stage
     T xbs[TP::NX];                      // Xbar of the current stage
@@ -41,18 +41,18 @@ struct AdjShared {
     T red[64];
 };
 
-// Reverse one RK4 stage at the stage input held in ax.sc.ns (coefficients are
-// recomputed there).  Lanes own rows r = lane, lane + 64.
-template <class T, class TP>
-__device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
-                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc, int lane,
-                                              int st, T tau, T (&xbar)[2], T (&xprev)[2],
-                                              T (&xsum)[2], T& sacc, T (&uacc)[3][2], T& muacc,
-                                              T& macc) {
+// Reverse one RK4 stage whose input is sc.ns.  EVAL: evaluate the stage
+// (right-hand side and Jacobian coefficients into sc and cf) here; otherwise
+// another wave has done it.  Lanes own rows r = lane, lane + 64.
+template <class T, class TP, bool EVAL>
+__device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax, RhsScratch<T, TP>& sc,
+                                              T* cf, const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                              int lane, int st, T tau, T (&xbar)[2],
+                                              T (&xprev)[2], T (&xsum)[2], T& sacc,
+                                              T (&uacc)[3][2], T& muacc, T& macc) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX;
     constexpr int NXT = TP::NXT, M = TP::M;
     using C = Coef<TP>;
-    T* cf = ax.coef;
     const Interval<T, TP>& iv = ax.iv;
     const T s = iv.s, h = iv.h;
     // kbar_st = h/6 w_st xbar + h a_{st+1} Xbar_{st+1}
@@ -63,7 +63,8 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
         const int r = lane + 64 * q;
         if (r < NXT) ax.kb[r] = iv.h6 * w * xbar[q] + (st < 3 ? anext * xprev[q] : T(0));
     }
-    rhs_eval<T, TP, EMIT>(iv, ax.sc, mc, lane, tau, cf);   // ends with a wave sync
+    if constexpr (EVAL) rhs_eval<T, TP, EMIT>(iv, sc, mc, lane, tau, cf);   // ends with a wave sync
+    else wave_lds_sync();
     const T omt = T(1) - tau;
     const T lc = ax.kb[NX + NC];
     // phase A: element lanes scatter into their slots; control adjoints
@@ -166,9 +167,9 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
         ax.xbs[NQ + 3 * b + 2] = s * ax.kb[3 * b + 2] + om;
         // d(s v')/d m_b = -(s/m_b) (v'_x, v'_y + g, w')
         macc -= s * iv.minv[b] *
-                (ax.sc.fn[NQ + 3 * b] * ax.kb[NQ + 3 * b] +
-                 (ax.sc.fn[NQ + 3 * b + 1] + T(mc.g)) * ax.kb[NQ + 3 * b + 1] +
-                 ax.sc.fn[NQ + 3 * b + 2] * ax.kb[NQ + 3 * b + 2]);
+                (sc.fn[NQ + 3 * b] * ax.kb[NQ + 3 * b] +
+                 (sc.fn[NQ + 3 * b + 1] + T(mc.g)) * ax.kb[NQ + 3 * b + 1] +
+                 sc.fn[NQ + 3 * b + 2] * ax.kb[NQ + 3 * b + 2]);
     }
     wave_lds_sync();
     // rows: collect Xbar_i, dilation adjoint F~ . kbar
@@ -183,118 +184,21 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax,
             xprev[q] = T(0);
         }
         if (r < NXT) {
-            const T F = r < NQ ? ax.sc.ns[NQ + r] : ax.sc.fn[r];
+            const T F = r < NQ ? sc.ns[NQ + r] : sc.fn[r];
             sacc += F * ax.kb[r];
         }
     }
     wave_lds_sync();
 }
 
-// One interval by two waves: the replay wave recomputes chunk u+1's stage
-// inputs from its checkpoint while the reverse wave sweeps chunk u backwards
-// (two history buffers, one workgroup barrier per chunk).
+// Outputs of the reverse wave: gX_k, the control partials of interval k
+// (left: U_k, right: U_k+1), the dilation and parameter adjoints.
 template <class T, class TP>
-__device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
-                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
-                                             const int k) {
-    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NX = TP::NX, NXT = TP::NXT;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+__device__ __forceinline__ void adjoint_outputs(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
+                                                const int k, const int lane, const T (&xbar)[2],
+                                                T sacc, const T (&uacc)[3][2], T muacc, T macc) {
+    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NXT = TP::NXT;
     const FwdArgs<T>& f = a.f;
-    load_interval<T, TP>(ax.iv, f, mc, k, tid, 128);
-    // constant FOH forcing entries of the coefficient buffer (zero elsewhere)
-    for (int e = tid; e < Coef<TP>::SIZE; e += 128) ax.coef[e] = T(0);
-    __syncthreads();
-    coef_constants<T, TP>(ax.iv, ax.coef, tid, 128);
-    __syncthreads();
-
-    const int64_t ldi = f.ldi;
-    const int K = f.K, Cs = f.C;
-    const int nseg = K / Cs;
-    const int nch = (Cs + CHUNK - 1) / CHUNK;   // chunks per checkpoint segment
-    const int U = nseg * nch;                   // chunks, last first
-    if (wave == 1) {
-        // ------------- replay wave: chunk t at step t -------------
-        RowState<T> rs;
-        for (int t = 0; t <= U; ++t) {
-            if (t < U) {
-                const int g = nseg - 1 - t / nch;
-                const int c0 = (nch - 1 - t % nch) * CHUNK;
-                const int len = (Cs - c0) < CHUNK ? (Cs - c0) : CHUNK;
-                const int base = g * Cs;
-                T(*hist)[NX] = ax.hist[t & 1];
-                // replay from the checkpoint to the chunk start, then record the chunk
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int r = lane + 64 * q;
-                    rs.xb[q] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
-                    rs.xa[q] = T(0);
-                    if (r < NXT) ax.scr.ns[r] = rs.xb[q];
-                }
-                wave_lds_sync();
-                for (int jj = 0; jj < c0 + len; ++jj) {
-                    const int j = base + jj;
-                    for (int st = 0; st < 4; ++st) {
-                        if (jj >= c0) {
-#pragma unroll
-                            for (int q = 0; q < 2; ++q) {
-                                const int r = lane + 64 * q;
-                                if (r < NX) hist[(jj - c0) * 4 + st][r] = ax.scr.ns[r];
-                            }
-                        }
-                        const T tau = (T(j) + T(stage_c(st))) / T(K);
-                        rhs_eval<T, TP, LEAN>(ax.iv, ax.scr, mc, lane, tau, (T*)nullptr);
-                        rk_rows<T, TP, NX>(ax.iv, ax.scr, rs, lane, st, ax.scr.ns, (T*)nullptr);
-                    }
-                }
-                wave_lds_sync();
-            }
-            __syncthreads();
-        }
-        return;
-    }
-    // ------------- reverse wave: chunk t-1 at step t -------------
-    T xbar[2], xprev[2], xsum[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int r = lane + 64 * q;
-        xbar[q] = r < NXT ? a.seed[r * ldi + k] : T(0);
-        xprev[q] = T(0);
-        xsum[q] = T(0);
-    }
-    T sacc = T(0), muacc = T(0), macc = T(0);
-    T uacc[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
-    for (int t = 0; t <= U; ++t) {
-        if (t >= 1) {
-            const int u = t - 1;
-            const int g = nseg - 1 - u / nch;
-            const int c0 = (nch - 1 - u % nch) * CHUNK;
-            const int len = (Cs - c0) < CHUNK ? (Cs - c0) : CHUNK;
-            const int base = g * Cs;
-            const T(*hist)[NX] = ax.hist[u & 1];
-            // reverse the recorded substeps
-            for (int jj = len - 1; jj >= 0; --jj) {
-                const int j = base + c0 + jj;
-                for (int st = 3; st >= 0; --st) {
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int r = lane + 64 * q;
-                        if (r < NX) ax.sc.ns[r] = hist[jj * 4 + st][r];
-                    }
-                    wave_lds_sync();
-                    const T tau = (T(j) + T(stage_c(st))) / T(K);
-                    reverse_stage<T, TP>(ax, mc, lane, st, tau, xbar, xprev, xsum, sacc, uacc,
-                                         muacc, macc);
-                }
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    xbar[q] += xsum[q];
-                    xsum[q] = T(0);
-                    xprev[q] = T(0);
-                }
-            }
-        }
-        __syncthreads();
-    }
     // gX_k = xbar
     const int64_t ldn = f.ldn;
 #pragma unroll
@@ -339,20 +243,306 @@ __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs
     if (lane < NB) a.ws_p[(int64_t)(2 + lane) * N + k] = macc;
 }
 
+// Chunk u of an interval's reverse order (segment g = nseg-1 - u / nch, chunk
+// offset c0 inside the segment, len substeps).
+struct ChunkPos {
+    int g, c0, len;
+};
+__device__ __forceinline__ ChunkPos chunk_pos(int u, int nseg, int nch, int Cs) {
+    ChunkPos c;
+    c.g = nseg - 1 - u / nch;
+    c.c0 = (nch - 1 - u % nch) * CHUNK;
+    c.len = (Cs - c.c0) < CHUNK ? (Cs - c.c0) : CHUNK;
+    return c;
+}
+
+// Replay from checkpoint g to the end of the chunk, recording the chunk's
+// stage inputs (x part) into hist.  One wave, scratch ax.scr.
 template <class T, class TP>
-__global__ void __launch_bounds__(128)
-    k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+__device__ __forceinline__ void replay_chunk(AdjShared<T, TP>& ax, const FwdArgs<T>& f,
+                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                             const int k, const int lane, const ChunkPos cp,
+                                             T (*hist)[TP::NX]) {
+    constexpr int NX = TP::NX, NXT = TP::NXT;
+    const int64_t ldi = f.ldi;
+    RowState<T> rs;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        rs.xb[q] = r < NX ? f.ckpt[((int64_t)cp.g * NX + r) * ldi + k] : T(0);
+        rs.xa[q] = T(0);
+        if (r < NXT) ax.scr.ns[r] = rs.xb[q];
+    }
+    wave_lds_sync();
+    const int base = cp.g * f.C;
+    for (int jj = 0; jj < cp.c0 + cp.len; ++jj) {
+        const int j = base + jj;
+        for (int st = 0; st < 4; ++st) {
+            if (jj >= cp.c0) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int r = lane + 64 * q;
+                    if (r < NX) hist[(jj - cp.c0) * 4 + st][r] = ax.scr.ns[r];
+                }
+            }
+            const T tau = (T(j) + T(stage_c(st))) / T(f.K);
+            rhs_eval<T, TP, LEAN>(ax.iv, ax.scr, mc, lane, tau, (T*)nullptr);
+            rk_rows<T, TP, NX>(ax.iv, ax.scr, rs, lane, st, ax.scr.ns, (T*)nullptr);
+        }
+    }
+    wave_lds_sync();
+}
+
+// Reverse sweep over a recorded chunk (stages evaluated here).
+template <class T, class TP>
+__device__ __forceinline__ void reverse_chunk(AdjShared<T, TP>& ax, const FwdArgs<T>& f,
+                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                              const int lane, const ChunkPos cp,
+                                              const T (*hist)[TP::NX], T (&xbar)[2],
+                                              T (&xprev)[2], T (&xsum)[2], T& sacc,
+                                              T (&uacc)[3][2], T& muacc, T& macc) {
+    constexpr int NX = TP::NX;
+    const int base = cp.g * f.C;
+    for (int jj = cp.len - 1; jj >= 0; --jj) {
+        const int j = base + cp.c0 + jj;
+        for (int st = 3; st >= 0; --st) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int r = lane + 64 * q;
+                if (r < NX) ax.se[0].ns[r] = hist[jj * 4 + st][r];
+            }
+            wave_lds_sync();
+            const T tau = (T(j) + T(stage_c(st))) / T(f.K);
+            reverse_stage<T, TP, true>(ax, ax.se[0], ax.coef[0], mc, lane, st, tau, xbar, xprev,
+                                       xsum, sacc, uacc, muacc, macc);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            xbar[q] += xsum[q];
+            xsum[q] = T(0);
+            xprev[q] = T(0);
+        }
+    }
+}
+
+// One interval by NW waves.  NW = 2: the replay wave records chunk u+1 while
+// the reverse wave sweeps chunk u (two history buffers, one workgroup barrier
+// per chunk).  NW = 1: one wave replays and reverses each chunk in turn (the
+// fewest wave-cycles per interval, for batches).
+template <class T, class TP, int NW>
+__device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
+                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                             const int k) {
+    constexpr int NXT = TP::NXT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int nth = 64 * NW;
+    const FwdArgs<T>& f = a.f;
+    load_interval<T, TP>(ax.iv, f, mc, k, tid, nth);
+    for (int e = tid; e < 2 * Coef<TP>::SIZE; e += nth) (&ax.coef[0][0])[e] = T(0);
+    __syncthreads();
+    coef_constants<T, TP>(ax.iv, ax.coef[0], tid, nth);
+    coef_constants<T, TP>(ax.iv, ax.coef[1], tid, nth);
+    __syncthreads();
+
+    const int64_t ldi = f.ldi;
+    const int Cs = f.C;
+    const int nseg = f.K / Cs;
+    const int nch = (Cs + CHUNK - 1) / CHUNK;   // chunks per checkpoint segment
+    const int U = nseg * nch;                   // chunks, last first
+    if (NW == 2 && wave == 1) {
+        for (int t = 0; t <= U; ++t) {
+            if (t < U) replay_chunk<T, TP>(ax, f, mc, k, lane, chunk_pos(t, nseg, nch, Cs),
+                                           ax.hist[t & 1]);
+            __syncthreads();
+        }
+        return;
+    }
+    T xbar[2], xprev[2], xsum[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        xbar[q] = r < NXT ? a.seed[r * ldi + k] : T(0);
+        xprev[q] = T(0);
+        xsum[q] = T(0);
+    }
+    T sacc = T(0), muacc = T(0), macc = T(0);
+    T uacc[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    if constexpr (NW == 2) {
+        for (int t = 0; t <= U; ++t) {
+            if (t >= 1)
+                reverse_chunk<T, TP>(ax, f, mc, lane, chunk_pos(t - 1, nseg, nch, Cs),
+                                     ax.hist[(t - 1) & 1], xbar, xprev, xsum, sacc, uacc, muacc,
+                                     macc);
+            __syncthreads();
+        }
+    } else {
+        for (int u = 0; u < U; ++u) {
+            const ChunkPos cp = chunk_pos(u, nseg, nch, Cs);
+            replay_chunk<T, TP>(ax, f, mc, k, lane, cp, ax.hist[0]);
+            reverse_chunk<T, TP>(ax, f, mc, lane, cp, ax.hist[0], xbar, xprev, xsum, sacc, uacc,
+                                 muacc, macc);
+        }
+    }
+    adjoint_outputs<T, TP>(ax, a, k, lane, xbar, sacc, uacc, muacc, macc);
+}
+
+// Checkpoints at most CHUNK substeps apart (one chunk per segment, 4C stages
+// each): three waves pipelined stage by stage, one workgroup barrier per step.
+// With r the stage index counted backwards from the end of the interval:
+//   step 0      : the replay wave records the last segment's stage inputs;
+//   step t >= 1 : the evaluation wave evaluates stage r = t-1 (right-hand side
+//                 and Jacobian coefficients into slot t & 1), the reverse wave
+//                 reverses stage r = t-2 (slot (t-1) & 1), and the replay wave
+//                 records one stage of the next segment;
+//   4K + 2 steps in all.
+template <class T, class TP>
+__device__ __forceinline__ void adjoint_item3(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
+                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                              const int k) {
+    constexpr int NX = TP::NX, NXT = TP::NXT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int nth = 192;
+    const FwdArgs<T>& f = a.f;
+    load_interval<T, TP>(ax.iv, f, mc, k, tid, nth);
+    for (int e = tid; e < 2 * Coef<TP>::SIZE; e += nth) (&ax.coef[0][0])[e] = T(0);
+    __syncthreads();
+    coef_constants<T, TP>(ax.iv, ax.coef[0], tid, nth);
+    coef_constants<T, TP>(ax.iv, ax.coef[1], tid, nth);
+    __syncthreads();
+
+    const int64_t ldi = f.ldi;
+    const int K = f.K, Cs = f.C;
+    const int nseg = K / Cs, S4 = 4 * Cs;
+    const int nst = 4 * K, nsteps = nst + 2;
+    if (wave == 1) {
+        // ---------------- replay wave ----------------
+        RowState<T> rs;
+        for (int t = 0; t < nsteps; ++t) {
+            int u = -1, q0 = 0, q1 = 0;   // record stages [q0, q1) of chunk u
+            if (t == 0) {
+                u = 0;
+                q1 = S4;
+            } else if (t <= nst) {
+                const int r = t - 1;
+                u = r / S4 + 1;
+                q0 = r % S4;
+                q1 = q0 + 1;
+                if (u >= nseg) u = -1;
+            }
+            if (u >= 0) {
+                const int g = nseg - 1 - u;
+                T(*hist)[NX] = ax.hist[u & 1];
+                for (int q = q0; q < q1; ++q) {
+                    if (q == 0) {
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) {
+                            const int r = lane + 64 * i;
+                            rs.xb[i] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
+                            rs.xa[i] = T(0);
+                            if (r < NXT) ax.scr.ns[r] = rs.xb[i];
+                        }
+                        wave_lds_sync();
+                    }
+                    const int jj = q >> 2, st = q & 3, j = g * Cs + jj;
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int r = lane + 64 * i;
+                        if (r < NX) hist[q][r] = ax.scr.ns[r];
+                    }
+                    const T tau = (T(j) + T(stage_c(st))) / T(K);
+                    rhs_eval<T, TP, LEAN>(ax.iv, ax.scr, mc, lane, tau, (T*)nullptr);
+                    rk_rows<T, TP, NX>(ax.iv, ax.scr, rs, lane, st, ax.scr.ns, (T*)nullptr);
+                }
+                wave_lds_sync();
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    if (wave == 2) {
+        // ---------------- evaluation wave ----------------
+        for (int t = 0; t < nsteps; ++t) {
+            if (t >= 1 && t <= nst) {
+                const int r = t - 1, u = r / S4, pp = r % S4;
+                const int g = nseg - 1 - u;
+                const int jj = Cs - 1 - (pp >> 2), st = 3 - (pp & 3), j = g * Cs + jj;
+                RhsScratch<T, TP>& sc = ax.se[t & 1];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int rr = lane + 64 * i;
+                    if (rr < NX) sc.ns[rr] = ax.hist[u & 1][jj * 4 + st][rr];
+                }
+                wave_lds_sync();
+                const T tau = (T(j) + T(stage_c(st))) / T(K);
+                rhs_eval<T, TP, EMIT>(ax.iv, sc, mc, lane, tau, ax.coef[t & 1]);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // ---------------- reverse wave ----------------
+    T xbar[2], xprev[2], xsum[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        xbar[q] = r < NXT ? a.seed[r * ldi + k] : T(0);
+        xprev[q] = T(0);
+        xsum[q] = T(0);
+    }
+    T sacc = T(0), muacc = T(0), macc = T(0);
+    T uacc[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    for (int t = 0; t < nsteps; ++t) {
+        if (t >= 2) {
+            const int r = t - 2, u = r / S4, pp = r % S4;
+            const int g = nseg - 1 - u;
+            const int jj = Cs - 1 - (pp >> 2), st = 3 - (pp & 3), j = g * Cs + jj;
+            const T tau = (T(j) + T(stage_c(st))) / T(K);
+            reverse_stage<T, TP, false>(ax, ax.se[(t - 1) & 1], ax.coef[(t - 1) & 1], mc, lane,
+                                        st, tau, xbar, xprev, xsum, sacc, uacc, muacc, macc);
+            if (st == 0) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    xbar[q] += xsum[q];
+                    xsum[q] = T(0);
+                    xprev[q] = T(0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    adjoint_outputs<T, TP>(ax, a, k, lane, xbar, sacc, uacc, muacc, macc);
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(192)
+    k_adjoint3(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ AdjShared<T, TP> ax;
-    adjoint_item<T, TP>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+    adjoint_item3<T, TP>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(192)
+    k_adjoint3_batch(BatchArgs<AdjArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ AdjShared<T, TP> ax;
+    const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
+    const AdjArgs<T> a = b.descs[it.x];
+    adjoint_item3<T, TP>(ax, a, mc, it.y);
 }
 
 template <class T, class TP>
 __global__ void __launch_bounds__(128)
+    k_adjoint(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ AdjShared<T, TP> ax;
+    adjoint_item<T, TP, 2>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+}
+
+template <class T, class TP, int NW>
+__global__ void __launch_bounds__(64 * NW)
     k_adjoint_batch(BatchArgs<AdjArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ AdjShared<T, TP> ax;
     const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
     const AdjArgs<T> a = b.descs[it.x];
-    adjoint_item<T, TP>(ax, a, mc, it.y);
+    adjoint_item<T, TP, NW>(ax, a, mc, it.y);
 }
 
 // gU, gX_N and gp from the per-interval partials, in a fixed order.
@@ -425,7 +615,10 @@ static cis_status launch_adjoint(const cis_model* m, const cis_shape* sh, const 
     a.ws_uk1 = w + (size_t)m->m * N;
     a.ws_p = w + (size_t)2 * m->m * N;
     void* args[] = {&a, &mc};
-    hipError_t e = hipLaunchKernel((const void*)&k_adjoint<T, TP>, dim3(N), dim3(128), args, 0,
+    const bool three = C <= CHUNK;   // one chunk per checkpoint segment
+    hipError_t e = hipLaunchKernel(three ? (const void*)&k_adjoint3<T, TP>
+                                         : (const void*)&k_adjoint<T, TP>,
+                                   dim3(N), dim3(three ? 192 : 128), args, 0,
                                    stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_adjoint launch: %s", hipGetErrorString(e));
     const int64_t work = (int64_t)m->m * (N + 1) + m->nx + m->np;
@@ -447,7 +640,8 @@ static cis_status launch_adjoint(const cis_model* m, const cis_shape* sh, const 
 }
 
 template <int L, int D>
-static cis_status prep_adj_t(const cis_model* m, const BatchGroupDev& g, KLaunch* out) {
+static cis_status prep_adj_t(const cis_model* m, const BatchGroupDev& g, int max_ckpt_every,
+                             int waves, KLaunch* out) {
     using TP = Topo<L, D>;
     BatchArgs<AdjArgs<double>> b;
     b.descs = (const AdjArgs<double>*)g.adesc;
@@ -456,15 +650,19 @@ static cis_status prep_adj_t(const cis_model* m, const BatchGroupDev& g, KLaunch
     b.cursor = g.cursor;
     out->arg(b);
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
-    out->func = (const void*)&k_adjoint_batch<double, TP>;
+    if (waves == 3 && max_ckpt_every > CHUNK) waves = 2;
+    out->func = waves == 3 ? (const void*)&k_adjoint3_batch<double, TP>
+                : waves == 2 ? (const void*)&k_adjoint_batch<double, TP, 2>
+                             : (const void*)&k_adjoint_batch<double, TP, 1>;
     out->grid = dim3(g.n_items);
-    out->block = dim3(128);
+    out->block = dim3(64 * waves);
     return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_adjoint_batch: launch record refused");
 }
 
-cis_status prep_adjoint_batch(const cis_model* m, const BatchGroupDev& g, KLaunch* out) {
+cis_status prep_adjoint_batch(const cis_model* m, const BatchGroupDev& g, int max_ckpt_every,
+                              int waves, KLaunch* out) {
 #define CIS_PREP_ADJ(LL, DD) \
-    if (m->L == LL && m->D == DD) return prep_adj_t<LL, DD>(m, g, out);
+    if (m->L == LL && m->D == DD) return prep_adj_t<LL, DD>(m, g, max_ckpt_every, waves, out);
     CIS_TOPOLOGIES(CIS_PREP_ADJ)
 #undef CIS_PREP_ADJ
     return fail(CIS_ERR_UNSUPPORTED, "prep_adjoint_batch: topology has no compiled kernel");

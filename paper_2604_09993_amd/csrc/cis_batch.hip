@@ -25,6 +25,7 @@ struct Group {
     std::vector<int2> items;   // {group-local trajectory, interval}
     int units_per_item = 0;
     int persist_blocks = 0;
+    int adj_waves = 0;         // waves per interval of the chosen reverse sweep
     size_t fdesc_off = 0, ddesc_off = 0, adesc_off = 0, items_off = 0, cursor_off = 0;
     BatchGroupDev dev{};
     KLaunch disc, def, adj;
@@ -164,10 +165,13 @@ static cis_status build_graph(cis_batch_plan* p, int op) {
     return CIS_OK;
 }
 
+static bool sched_bits_unknown(int32_t s) { return (s & ~0x3F) != 0; }
+
 extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_traj,
                                             cis_dtype dtype, int32_t ops, int32_t sched,
                                             int32_t ckpt_every, int32_t graph, void* stream,
                                             cis_batch_plan** out) {
+    const int32_t sched_all = sched;
     if (!out) return fail(CIS_ERR_NULL, "cis_batch_plan_create: plan output is required");
     *out = nullptr;
     if (!trajs) return fail(CIS_ERR_NULL, "cis_batch_plan_create: trajs is required");
@@ -177,8 +181,10 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
     if (ops < 1 || ops > 3) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ops=%d is not a mask of operations", ops);
     if ((ops & CIS_BATCH_ADJOINT) && dtype != CIS_F64)
         return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: the reverse sweep is offered in CIS_F64 only");
-    if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE)
-        return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched);
+    const int adj_force = (sched >> 4) & 3;   // 0: default, else waves of the reverse sweep
+    sched &= 0xF;
+    if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE || (sched_bits_unknown(sched_all)))
+        return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched_all);
     if (ckpt_every < 0) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ckpt_every=%d < 0", ckpt_every);
     for (int i = 0; i < n_traj; ++i) {
         cis_status st = check_traj(trajs[i], i, dtype, ops);
@@ -393,12 +399,52 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         if (ops & CIS_BATCH_ADJOINT) {
             BatchGroupDev dd = g.dev;
             dd.fdesc = d + g.ddesc_off;
-            st = prep_defects_batch(g.model, dtype, dd, &g.def);
-            if (st == CIS_OK) st = prep_adjoint_batch(g.model, g.dev, &g.adj);
+            KLaunch def_body, def_lane;
+            st = prep_defects_batch(g.model, dtype, dd, true, &def_body);
+            if (st == CIS_OK) st = prep_defects_batch(g.model, dtype, dd, false, &def_lane);
+            g.def = def_body;
+            if (st == CIS_OK && sched == CIS_SCHED_TUNE) {
+                const float tb = time_launch(def_body, hs, 3);
+                const float tl = time_launch(def_lane, hs, 3);
+                if (tb < 0.f || tl < 0.f) {
+                    plan_free(p);
+                    return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
+                }
+                if (tl < tb) g.def = def_lane;
+            }
+            int cmax_g = 1;
+            for (int i : g.trajs) cmax_g = std::max(cmax_g, p->ckpt_every[i]);
+            // reverse sweep with 3, 2 or 1 waves per interval (latency vs
+            // throughput): timed when tuning, else the three-wave form
+            KLaunch adjv[3];
+            for (int w = 0; w < 3 && st == CIS_OK; ++w)
+                st = prep_adjoint_batch(g.model, g.dev, cmax_g, 3 - w, &adjv[w]);
             if (st != CIS_OK) {
                 plan_free(p);
                 return st;
             }
+            int best = adj_force ? 3 - adj_force : 0;
+            if (sched == CIS_SCHED_TUNE && !adj_force) {
+                if (g.def.launch(hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess) {
+                    plan_free(p);
+                    return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
+                }
+                float tbest = -1.f;
+                for (int w = 0; w < 3; ++w) {
+                    if (w > 0 && adjv[w].func == adjv[w - 1].func) continue;
+                    const float tw = time_launch(adjv[w], hs, 3);
+                    if (tw < 0.f) {
+                        plan_free(p);
+                        return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
+                    }
+                    if (tbest < 0.f || tw < tbest) {
+                        tbest = tw;
+                        best = w;
+                    }
+                }
+            }
+            g.adj = adjv[best];
+            g.adj_waves = adjv[best].block.x / 64;
         }
     }
     if (ops & CIS_BATCH_ADJOINT) {
@@ -457,7 +503,8 @@ extern "C" cis_status cis_batch_graph_run(cis_batch_plan* p, int32_t op, void* s
 
 extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, int32_t* groups,
                                           int32_t* n_traj, int32_t* n_items,
-                                          int32_t* units_per_item, int32_t* persist_blocks) {
+                                          int32_t* units_per_item, int32_t* persist_blocks,
+                                          int32_t* adjoint_waves) {
     if (!p) return fail(CIS_ERR_NULL, "cis_batch_plan_info: plan is required");
     if (groups) *groups = (int32_t)p->groups.size();
     if (g < 0 || g >= (int32_t)p->groups.size()) return CIS_OK;
@@ -466,6 +513,7 @@ extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, in
     if (n_items) *n_items = (int32_t)gr.items.size();
     if (units_per_item) *units_per_item = gr.units_per_item;
     if (persist_blocks) *persist_blocks = gr.persist_blocks;
+    if (adjoint_waves) *adjoint_waves = gr.adj_waves;
     return CIS_OK;
 }
 

@@ -74,9 +74,14 @@ struct BatchGroupDev {
 // persistent workgroups draw units from the cursor.
 cis_status prep_discretize_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
                                  int persist_blocks, KLaunch* out);
+// (body_lanes: the two-wave body-lane kernel, else one element-lane wave per interval)
 cis_status prep_defects_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
-                              KLaunch* out);
-cis_status prep_adjoint_batch(const cis_model* m, const BatchGroupDev& g, KLaunch* out);
+                              bool body_lanes, KLaunch* out);
+// (max_ckpt_every: largest checkpoint spacing of the group's trajectories;
+// waves per interval: 3 = evaluation a stage ahead of the reverse sweep (when
+// the spacing is at most 8), 2 = replay a chunk ahead, 1 = one wave)
+cis_status prep_adjoint_batch(const cis_model* m, const BatchGroupDev& g, int max_ckpt_every,
+                              int waves, KLaunch* out);
 // gU, gX_N and gp of n_traj trajectories from their partials (RedDesc array).
 cis_status prep_adjoint_reduce_batch(const void* rdesc, int n_traj, KLaunch* out);
 // Column groups (work units per item) of the discretize kernel.

@@ -208,6 +208,7 @@ def test_batch_plan_validates_before_any_device_call():
     assert create([good], ops=0) == _lib.CIS_ERR_DIM
     assert create([good], ops=4) == _lib.CIS_ERR_DIM
     assert create([good], sched=0) == _lib.CIS_ERR_DIM
+    assert create([good], sched=_lib.CIS_SCHED_GRID | 0x40) == _lib.CIS_ERR_DIM   # unknown bit
     assert create([good], ops=_lib.CIS_BATCH_ADJOINT, dtype=_lib.CIS_F32) == _lib.CIS_ERR_DTYPE
     assert create([good, _traj(h, N=0)]) == _lib.CIS_ERR_DIM
     assert b"trajectory 1" in lib.cis_last_error()

@@ -180,14 +180,23 @@ def test_batch_fp32_matches_single_and_oracle():
     plan.close()
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_adjoint_matches_single(graph):
+@pytest.mark.parametrize("graph,sched,spacing,waves", [
+    (False, "grid", 0, None), (True, "grid", 0, 3), (True, "grid", 0, 2), (True, "grid", 0, 1),
+    (True, "tune", 0, None), (True, "grid", 10, None), (True, "grid", 10, 1)])
+def test_batch_adjoint_matches_single(graph, sched, spacing, waves):
+    """spacing 0: checkpoints at most 8 substeps apart; 10: every 10 substeps with
+    K in {10, 20} (chunked replay).  waves: forced form of the reverse sweep."""
     api = _api()
     batch = _small_batch(7, seed=15, K_range=(2, 8))
-    _say(f"batch adjoint graph={graph}")
+    if spacing:
+        batch = [(m, d, 10 * (1 + i % 2)) for i, (m, d, _) in enumerate(batch)]
+    _say(f"batch adjoint graph={graph} sched={sched} spacing={spacing} waves={waves}")
     trajs = _upload(batch, torch.float64)
-    plan = api.BatchPlan(trajs, ("discretize", "adjoint"), sched="grid", ckpt_every=0,
-                         graph=graph)
+    plan = api.BatchPlan(trajs, ("discretize", "adjoint"), sched=sched, ckpt_every=spacing,
+                         graph=graph, adjoint_waves=waves)
+    chosen = {g["adjoint_waves"] for g in plan.groups()}
+    if waves is not None:
+        assert chosen == {min(waves, 2) if spacing > 8 else waves}, chosen
     gen = torch.Generator(device="cpu").manual_seed(5)
     for o in plan.out:
         o["seed"].copy_(torch.randn(o["seed"].shape, generator=gen, dtype=torch.float64))
@@ -195,7 +204,7 @@ def test_batch_adjoint_matches_single(graph):
     torch.cuda.synchronize()
     for i, t in enumerate(trajs):
         K = t["K"]
-        C = max(c for c in range(1, 9) if K % c == 0)
+        C = spacing if spacing else max(c for c in range(1, 9) if K % c == 0)
         d = api.defects(t["cm"], t["X"], t["U"], t["s"], t["params"], K, ckpt_every=C)
         assert _rel(plan.out[i]["xprop"], d["xprop"]) <= SAME
         assert _rel(plan.out[i]["d"], d["d"]) <= SAME
