@@ -148,7 +148,11 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 #pragma unroll
             for (int k = 0; k < 3; ++k) kv[3 * lb + k] += cf[C::F + NQ + 3 * gb(lb) + k];
         if constexpr (L >= 1) kcc += cf[C::F + NX + leg];
-        kct += fct * cf[C::F + NX + NC];
+        // violation row: per-body parts of the own bodies (torso on leg 0 only)
+        T vp = fct * cf[C::CTP];
+#pragma unroll
+        for (int lb = 1; lb < LB; ++lb) vp += cf[C::CTP + gb(lb)];
+        kct += vp;
     }
     __builtin_amdgcn_sched_barrier(0);
     // classical RK4 combination (stage ST known at compile time)
@@ -265,15 +269,24 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             bs.xs[kk] = bs.xb[kk];
             bs.xa[kk] = T(0);
         }
-        for (int t = 0; t < nsteps; ++t) {
-            if (t < nst) {
-                const int st = t & 3;
-                const T tau = (T(j0 + (t >> 2)) + T(stage_c(st))) / T(a.K);
-                state_stage<T, TP>(sh.iv, mc, c, bs, st, tau, sh.xring[(t + 1) & 3],
-                                   sh.csring[t & 3], sh.fring[t & 3], lane);
-            }
+        // stage t = 4 j + ST at step t, the four RK stages unrolled
+        const T Kt = T(a.K);
+        for (int j = 0; j < Kb; ++j) {
+            const T jt = T(j0 + j);
+            state_stage<T, TP, 0>(sh.iv, mc, c, bs, jt / Kt, sh.xring[1], sh.csring[0],
+                                  sh.fring[0], lane);
+            __syncthreads();
+            state_stage<T, TP, 1>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[2], sh.csring[1],
+                                  sh.fring[1], lane);
+            __syncthreads();
+            state_stage<T, TP, 2>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[3], sh.csring[2],
+                                  sh.fring[2], lane);
+            __syncthreads();
+            state_stage<T, TP, 3>(sh.iv, mc, c, bs, (jt + T(1)) / Kt, sh.xring[0], sh.csring[3],
+                                  sh.fring[3], lane);
             __syncthreads();
         }
+        for (int t = nst; t < nsteps; ++t) __syncthreads();
         if constexpr (NCW > 1) __syncthreads();   // the integral-row hand-over step
         if (grp == 0 && lane < NB && !blocked) {
 #pragma unroll
@@ -318,6 +331,13 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
         }
         // trailing steps: the wave's last stage ends at step nst - NCW + w + NCW
         for (int t = nst + w + 1; t < nsteps; ++t) __syncthreads();
+        // violation row: the body lanes' parts, summed in lane order
+        {
+            T acc = T(0);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) acc += lane_value(ytb, e);
+            ytb = acc;
+        }
         if constexpr (NCW > 1) {
             if (w == 1) {
                 if (c.contact) sh.yshare[c.i] = ycb;
@@ -488,23 +508,31 @@ __device__ __forceinline__ void defects_item(DefShared<T, TP>& sh, const FwdArgs
             bs.xs[kk] = bs.xb[kk];
             bs.xa[kk] = T(0);
         }
-        for (int t = 0; t < nsteps; ++t) {
-            if (t < nst) {
-                const int st = t & 3, j = t >> 2;
-                if (st == 0 && a.ckpt && (j % a.C) == 0 && lane < NB) {
-                    T* ck = a.ckpt + (int64_t)(j / a.C) * NX * ldi + k;
+        const T Kt = T(a.K);
+        for (int j = 0; j < a.K; ++j) {
+            if (a.ckpt && (j % a.C) == 0 && lane < NB) {
+                T* ck = a.ckpt + (int64_t)(j / a.C) * NX * ldi + k;
 #pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) {
-                        ck[(3 * c.b + kk) * ldi] = bs.xb[kk];
-                        ck[(NQ + 3 * c.b + kk) * ldi] = bs.xb[3 + kk];
-                    }
+                for (int kk = 0; kk < 3; ++kk) {
+                    ck[(3 * c.b + kk) * ldi] = bs.xb[kk];
+                    ck[(NQ + 3 * c.b + kk) * ldi] = bs.xb[3 + kk];
                 }
-                const T tau = (T(j) + T(stage_c(st))) / T(a.K);
-                state_stage<T, TP>(sh.iv, mc, c, bs, st, tau, sh.xring[(t + 1) & 3],
-                                   sh.csring[t & 3], sh.fring[t & 3], lane);
             }
+            const T jt = T(j);
+            state_stage<T, TP, 0>(sh.iv, mc, c, bs, jt / Kt, sh.xring[1], sh.csring[0],
+                                  sh.fring[0], lane);
+            __syncthreads();
+            state_stage<T, TP, 1>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[2], sh.csring[1],
+                                  sh.fring[1], lane);
+            __syncthreads();
+            state_stage<T, TP, 2>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[3], sh.csring[2],
+                                  sh.fring[2], lane);
+            __syncthreads();
+            state_stage<T, TP, 3>(sh.iv, mc, c, bs, (jt + T(1)) / Kt, sh.xring[0], sh.csring[3],
+                                  sh.fring[3], lane);
             __syncthreads();
         }
+        for (int t = nst; t < nsteps; ++t) __syncthreads();
         if (lane < NB) {
 #pragma unroll
             for (int kk = 0; kk < 6; ++kk) {
@@ -542,6 +570,12 @@ __device__ __forceinline__ void defects_item(DefShared<T, TP>& sh, const FwdArgs
                 }
             }
             __syncthreads();
+        }
+        {   // violation row: the body lanes' parts, summed in lane order
+            T acc = T(0);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) acc += lane_value(ytb, e);
+            ytb = acc;
         }
         if (c.contact) {
             if (a.xprop) a.xprop[ycc_row * ldi + k] = ycb;

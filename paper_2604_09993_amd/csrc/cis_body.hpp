@@ -200,12 +200,12 @@ __device__ __forceinline__ Frame<T> terrain(const MC& mc, T Px, T Py) {
 // bs.xs and into ring[NX], the body rotation into cs_out[NB][2] and the
 // accelerations into fv_out[3 NB].
 // ---------------------------------------------------------------------------
-template <class T, class TP>
+template <class T, class TP, int ST>
 __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
-                                            const BodyConst<T, TP>& c, BodyRK<T>& bs, int st,
-                                            T tau, T* ring, T (*cs_out)[2], T* fv_out,
-                                            int lane) {
+                                            const BodyConst<T, TP>& c, BodyRK<T>& bs, T tau,
+                                            T* ring, T (*cs_out)[2], T* fv_out, int lane) {
+    constexpr int st = ST;   // RK stage, known at compile time
     constexpr int NB = TP::NB, NQ = TP::NQ;
     const T omt = T(1) - tau;
     T sb, cb;
@@ -249,8 +249,8 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const T kk = s * (k < 3 ? bs.xs[3 + k] : fv[k - 3]);
-        if (st == 0) bs.xa[k] = kk;
-        else if (st == 3) bs.xa[k] += kk;
+        if constexpr (st == 0) bs.xa[k] = kk;
+        else if constexpr (st == 3) bs.xa[k] += kk;
         else bs.xa[k] += T(2) * kk;
     }
     if (lane < NB) {
@@ -261,7 +261,7 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        if (st < 3) {
+        if constexpr (st < 3) {
             const T kk = s * (k < 3 ? bs.xs[3 + k] : fv[k - 3]);
             bs.xs[k] = bs.xb[k] + an * kk;
         } else {
@@ -426,13 +426,11 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         const T dT = dTown + from_children<TP>(dTpar, b);
         if (lane < NB) cf[C::CTH + b] = s * dT * c.ii;
     }
-    // violation row: sum over bodies (lane order) of their joint and contact parts
-    T acc = T(0);
-#pragma unroll
-    for (int e = 0; e < NB; ++e) acc += lane_value(ctp, e);
-    if (lane == 0) {
-        yct = acc;
-        if constexpr (WRITE) cf[C::F + NX + NC] = acc;
+    // violation row: each body lane keeps its own joint and contact part (the
+    // sum over bodies is taken by the consumers)
+    if (lane < NB) {
+        yct = ctp;
+        if constexpr (WRITE) cf[C::CTP + b] = ctp;
     }
 }
 

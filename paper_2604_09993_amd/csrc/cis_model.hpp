@@ -81,8 +81,9 @@ struct Coef {
     static constexpr int CT = JH + 4 * TP::NJ;         // [NC][NCT] contact terms
     static constexpr int GV = CT + NCT * TP::NC;       // [3NB][M] s dv'/du
     static constexpr int GC = GV + 3 * TP::NB * TP::M; // [NC][M] (s/2) dOmega_cc/dubar
-    static constexpr int F = GC + TP::NC * TP::M;      // [NXT] F~ (unscaled)
-    static constexpr int SIZE = even(F + TP::NXT);
+    static constexpr int F = GC + TP::NC * TP::M;      // [NXT] F~ (unscaled; the violation row unused)
+    static constexpr int CTP = F + TP::NXT;            // [NB] violation integrand, per body
+    static constexpr int SIZE = even(CTP + TP::NB);
 };
 // per-contact slots (C_JMU = s lbar_n |v_t|_s = d(s Omega_cc)/d mu)
 enum { C_AX = 0, C_AY, C_FXP, C_FYP, C_TP, C_EPX, C_EPY, C_EXD, C_EYD, C_EOM, C_ETH, C_ZPX, C_ZPY,
