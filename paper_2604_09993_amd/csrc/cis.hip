@@ -128,30 +128,28 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
         kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
     }
     __builtin_amdgcn_sched_barrier(0);
-    // FOH forcing of B-/B+ columns: s (J_u w(tau) + J_ubar / 2); only waves
-    // holding such columns take the branch
+    // FOH forcing of B-/B+ columns, s (J_u w(tau) + J_ubar / 2), and F~
+    // forcing of the dilation column, without branches (the weights are zero in
+    // the other columns) so that the loads issue with the stage's other loads
     if constexpr (M > 0) {
-        if (wbm + wbp != T(0)) {
-            const T wB = wbm * (T(1) - tau) + wbp * tau;
-#pragma unroll
-            for (int lb = 0; lb < LB; ++lb)
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    kv[3 * lb + k] += wB * cf[C::GV + (3 * gb(lb) + k) * M + ctrl];
-            if constexpr (L >= 1) kcc += cf[C::GC + leg * M + ctrl];
-        }
-    }
-    // dilation column forcing: F~ at the stage (q rows below)
-    if (fsel != T(0)) {
+        const T wB = wbm * (T(1) - tau) + wbp * tau;
+        const T wG = wbm + wbp;
 #pragma unroll
         for (int lb = 0; lb < LB; ++lb)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) kv[3 * lb + k] += cf[C::F + NQ + 3 * gb(lb) + k];
-        if constexpr (L >= 1) kcc += cf[C::F + NX + leg];
-        // violation row: per-body parts of the own bodies (torso on leg 0 only)
+            for (int k = 0; k < 3; ++k)
+                kv[3 * lb + k] += wB * cf[C::GV + (3 * gb(lb) + k) * M + ctrl];
+        if constexpr (L >= 1) kcc += wG * cf[C::GC + leg * M + ctrl];
+    }
+#pragma unroll
+    for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) kv[3 * lb + k] += fsel * cf[C::F + NQ + 3 * gb(lb) + k];
+    if constexpr (L >= 1) kcc += fsel * cf[C::F + NX + leg];
+    {   // violation row: per-body parts of the own bodies (torso on leg 0 only)
         T vp = fct * cf[C::CTP];
 #pragma unroll
-        for (int lb = 1; lb < LB; ++lb) vp += cf[C::CTP + gb(lb)];
+        for (int lb = 1; lb < LB; ++lb) vp += fsel * cf[C::CTP + gb(lb)];
         kct += vp;
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -163,8 +161,7 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int r = 3 * lb + k;
-            T kq = s * z.zs[3 * LB + r];
-            if (fsel != T(0)) kq += cf[C::F + 3 * gb(lb) + k];
+            const T kq = s * z.zs[3 * LB + r] + fsel * cf[C::F + 3 * gb(lb) + k];
             if (ST == 0) z.za[r] = kq;
             else z.za[r] += T(WK) * kq;
             if (ST < 3) z.zs[r] = z.zb[r] + an * kq;
