@@ -302,136 +302,128 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     const bool pt = p == 0;
     const T cp = from_parent<TP>(cb, pt), sp = from_parent<TP>(sb, pt);
     const T xp = from_parent<TP>(xb, pt), yp = from_parent<TP>(yb, pt);
-    // smooth-function arguments: joint h_x, h_y; contact v_t, -sd
-    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-    T apx = T(0), apy = T(0), acx = T(0), acy = T(0), lx = T(0), ly = T(0);
-    if (c.joint) {
-        apx = cp * c.rpx - sp * c.rpy;
-        apy = sp * c.rpx + cp * c.rpy;
-        acx = cb * c.rcx - sb * c.rcy;
-        acy = sb * c.rcx + cb * c.rcy;
-        lx = omt * c.uk[1] + tau * c.uk1[1];
-        ly = omt * c.uk[2] + tau * c.uk1[2];
-        a0 = xp + apx - xb - acx;
-        a1 = yp + apy - yb - acy;
-    }
-    T ax = T(0), ay = T(0), om = T(0), Pdx = T(0), Pdy = T(0), ln = T(0), ft = T(0);
-    Frame<T> f;
-    f.sd = T(0);
-    f.nx = f.dsd_px = f.dnx = f.dny = f.ty = T(0);
-    f.ny = f.tx = f.dsd_py = T(1);
-    if (c.contact) {
-        ax = cb * c.rx - sb * c.ry;
-        ay = sb * c.rx + cb * c.ry;
-        om = xs[NQ + 3 * b + 2];
-        Pdx = xs[NQ + 3 * b] - om * ay;
-        Pdy = xs[NQ + 3 * b + 1] + om * ax;
-        f = terrain<T>(mc, xb + ax, yb + ay);
-        ln = omt * c.ck[0] + tau * c.ck1[0];
-        ft = (omt * c.ck[1] + tau * c.ck1[1]) - (omt * c.ck[2] + tau * c.ck1[2]);
-        a2 = f.tx * Pdx + f.ty * Pdy;
-        a3 = -f.sd;
-    }
+    // Every lane evaluates both the joint and the contact terms (finite values
+    // from zero constants where it has none) and selects; stores of lanes
+    // without the datum go to the lane's TRASH slot, so the stage has no branches.
+    const bool jl = c.joint, cl = c.contact;
+    // joint: arms, h_x, h_y
+    const T apx = cp * c.rpx - sp * c.rpy, apy = sp * c.rpx + cp * c.rpy;
+    const T acx = cb * c.rcx - sb * c.rcy, acy = sb * c.rcx + cb * c.rcy;
+    const T lx = omt * c.uk[1] + tau * c.uk1[1];
+    const T ly = omt * c.uk[2] + tau * c.uk1[2];
+    const T a0 = xp + apx - xb - acx;
+    const T a1 = yp + apy - yb - acy;
+    // contact: point, velocity, terrain frame, v_t, -sd
+    const T ax = cb * c.rx - sb * c.ry, ay = sb * c.rx + cb * c.ry;
+    const T om = xs[NQ + 3 * b + 2];
+    const T Pdx = xs[NQ + 3 * b] - om * ay;
+    const T Pdy = xs[NQ + 3 * b + 1] + om * ax;
+    const Frame<T> f = terrain<T>(mc, xb + ax, yb + ay);
+    const T ln = omt * c.ck[0] + tau * c.ck1[0];
+    const T ft = (omt * c.ck[1] + tau * c.ck1[1]) - (omt * c.ck[2] + tau * c.ck1[2]);
+    const T a2 = f.tx * Pdx + f.ty * Pdy;
+    const T a3 = -f.sd;
     T v0, d0, v1, d1, v2, d2, v3, d3;
     sabs_d(a0, v0, d0);
     sabs_d(a1, v1, d1);
     sabs_d(a2, v2, d2);
     sabs_d(a3, v3, d3);
+    // integrands (Sec. III pairs; violation: |h|_s of joints, ramp_s(-sd))
+    const T lnb = T(0.5) * (c.ck[0] + c.ck1[0]);
+    const T ltpb = T(0.5) * (c.ck[1] + c.ck1[1]);
+    const T ltmb = T(0.5) * (c.ck[2] + c.ck1[2]);
+    const T vt = a2, av = v2, dav = d2;
+    const T rp = vt > T(0) ? av : T(0);
+    const T rm = vt < T(0) ? av : T(0);
+    const T mu = iv.prm[0];
+    const T slack = mu * lnb - ltpb - ltmb;
+    const bool pen = -f.sd > T(0);
+    ycc = cl ? lnb * f.sd + ltpb * rp + ltmb * rm + slack * av : T(0);
+    const T ctp = (jl ? v0 + v1 : T(0)) + (cl && pen ? v3 : T(0));
+    // dT_b/dth_b parts: child side of the own joint, contact, parent side
+    const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
+    const T dTown = (jl ? acx * lx + acy * ly : T(0)) + (cl ? -(ax * fx + ay * fy) : T(0));
+    const T dTpar = jl ? -(apx * lx + apy * ly) : T(0);
+    const T dT = dTown + from_children<TP>(dTpar, b);
+    // contact derivative terms
+    const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) + slack * dav;
+    const T Dg = -(pen ? d3 : T(0));
+    const T dtx = f.dny, dty = -f.dnx;
+    const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
+    const T dvt_px = dtx * Pdx + dty * Pdy;
+    const T im = s * c.mi, ii = s * c.ii;
+    // everything the stores need from LDS is read before the split
+    const T ip = s * iv.iinv[p];
+    T fq[3], fa[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fq[k] = xs[NQ + 3 * b + k];
+        fa[k] = fv[3 * b + k];
+    }
     // SPLIT: the stage spans two pipeline steps; the workgroup barrier between
     // them is taken here, after the evaluation and before the stores
     if constexpr (SPLIT) __syncthreads();
-    T dTown = T(0), ctp = T(0), dTpar = T(0);
-    if (c.joint) {
-        const int j = c.j;
-        ctp += v0 + v1;   // |h_x|_s + |h_y|_s
-        if constexpr (WRITE) {
-            cf[C::JH + 4 * j + 0] = s * d0;
-            cf[C::JH + 4 * j + 1] = s * d1;
-            cf[C::JH + 4 * j + 2] = s * (d1 * apx - d0 * apy);
-            cf[C::JH + 4 * j + 3] = s * (d0 * acy - d1 * acx);
-            const T ip = s * iv.iinv[p], ic = s * c.ii;
-            cf[C::GV + (3 * p + 2) * M + NJ + 2 * j] = -apy * ip;
-            cf[C::GV + (3 * p + 2) * M + NJ + 2 * j + 1] = apx * ip;
-            cf[C::GV + (3 * b + 2) * M + NJ + 2 * j] = acy * ic;
-            cf[C::GV + (3 * b + 2) * M + NJ + 2 * j + 1] = -acx * ic;
-            dTown += acx * lx + acy * ly;          // child side d(-a_c x lam)/dth
-            dTpar = -(apx * lx + apy * ly);        // parent side d(a_p x lam)/dth_p
-        }
-    }
-    if (c.contact) {
-        const int i = c.i;
-        const T lnb = T(0.5) * (c.ck[0] + c.ck1[0]);
-        const T ltpb = T(0.5) * (c.ck[1] + c.ck1[1]);
-        const T ltmb = T(0.5) * (c.ck[2] + c.ck1[2]);
-        const T vt = a2, av = v2, dav = d2;
-        const T rp = vt > T(0) ? av : T(0);
-        const T rm = vt < T(0) ? av : T(0);
-        const T mu = iv.prm[0];
-        const T slack = mu * lnb - ltpb - ltmb;
-        ycc = lnb * f.sd + ltpb * rp + ltmb * rm + slack * av;   // pairs of Sec. III
-        ctp += -f.sd > T(0) ? v3 : T(0);                           // ramp_s(-sd)
-        if constexpr (WRITE) {
-            const T gv = ltpb * (vt > T(0) ? dav : T(0)) + ltmb * (vt < T(0) ? dav : T(0)) +
-                         slack * dav;
-            const T Dg = -(-f.sd > T(0) ? d3 : T(0));
-            const T dtx = f.dny, dty = -f.dnx;
-            const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
-            const T dvt_px = dtx * Pdx + dty * Pdy;
-            const T im = s * c.mi, ii = s * c.ii;
-            T* ct = cf + C::CT + C::NCT * i;
-            ct[C_AX] = ax;
-            ct[C_AY] = ay;
-            ct[C_FXP] = dfx * im;
-            ct[C_FYP] = dfy * im;
-            ct[C_TP] = (ax * dfy - ay * dfx) * ii;
-            ct[C_EPX] = s * (lnb * f.dsd_px + gv * dvt_px);
-            ct[C_EPY] = s * (lnb * f.dsd_py);
-            ct[C_EXD] = s * (gv * f.tx);
-            ct[C_EYD] = s * (gv * f.ty);
-            ct[C_EOM] = s * (gv * (f.ty * ax - f.tx * ay));
-            ct[C_ETH] = s * (-gv * om * (f.tx * ax + f.ty * ay));
-            ct[C_ZPX] = s * (Dg * f.dsd_px);
-            ct[C_ZPY] = s * (Dg * f.dsd_py);
-            ct[C_JMU] = s * (lnb * av);
-            const int u0 = 3 * NJ + 3 * i;
-            T* gvb = cf + C::GV;
-            gvb[(3 * b) * M + u0] = f.nx * im;
-            gvb[(3 * b + 1) * M + u0] = f.ny * im;
-            gvb[(3 * b + 2) * M + u0] = (ax * f.ny - ay * f.nx) * ii;
-            gvb[(3 * b) * M + u0 + 1] = f.tx * im;
-            gvb[(3 * b + 1) * M + u0 + 1] = f.ty * im;
-            gvb[(3 * b + 2) * M + u0 + 1] = (ax * f.ty - ay * f.tx) * ii;
-            gvb[(3 * b) * M + u0 + 2] = -f.tx * im;
-            gvb[(3 * b + 1) * M + u0 + 2] = -f.ty * im;
-            gvb[(3 * b + 2) * M + u0 + 2] = -(ax * f.ty - ay * f.tx) * ii;
-            T* gcb = cf + C::GC + i * M;
-            gcb[u0] = s * T(0.5) * (f.sd + mu * av);
-            gcb[u0 + 1] = s * T(0.5) * (rp - av);
-            gcb[u0 + 2] = s * T(0.5) * (rm - av);
-            const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
-            dTown += -(ax * fx + ay * fy);         // d(a x F)/dth at fixed F
-            cf[C::F + NX + i] = ycc;
-        }
-    }
-    // F~: q rows are the stage velocities, v rows the state wave's accelerations
-    if (WRITE && lane < NB) {
+    if constexpr (WRITE) {
+        const int j = c.j, i = c.i;
+        // one sink slot per lane: stores of many lanes to one LDS address serialize
+        T* tr = cf + C::TRASH + lane;
+        // joint rows of the violation integrand and the joint-force torques
+        T* jh = jl ? cf + C::JH + 4 * j : tr;
+        jh[0] = s * d0;
+        jh[1] = s * d1;
+        jh[2] = s * (d1 * apx - d0 * apy);
+        jh[3] = s * (d0 * acy - d1 * acx);
+        T* gvj = cf + C::GV + NJ + 2 * j;
+        *(jl ? gvj + (3 * p + 2) * M : tr) = -apy * ip;
+        *(jl ? gvj + (3 * p + 2) * M + 1 : tr) = apx * ip;
+        *(jl ? gvj + (3 * b + 2) * M : tr) = acy * ii;
+        *(jl ? gvj + (3 * b + 2) * M + 1 : tr) = -acx * ii;
+        // contact terms
+        T* ct = cl ? cf + C::CT + C::NCT * i : tr;
+        ct[C_AX] = ax;
+        ct[C_AY] = ay;
+        ct[C_FXP] = dfx * im;
+        ct[C_FYP] = dfy * im;
+        ct[C_TP] = (ax * dfy - ay * dfx) * ii;
+        ct[C_EPX] = s * (lnb * f.dsd_px + gv * dvt_px);
+        ct[C_EPY] = s * (lnb * f.dsd_py);
+        ct[C_EXD] = s * (gv * f.tx);
+        ct[C_EYD] = s * (gv * f.ty);
+        ct[C_EOM] = s * (gv * (f.ty * ax - f.tx * ay));
+        ct[C_ETH] = s * (-gv * om * (f.tx * ax + f.ty * ay));
+        ct[C_ZPX] = s * (Dg * f.dsd_px);
+        ct[C_ZPY] = s * (Dg * f.dsd_py);
+        ct[C_JMU] = s * (lnb * av);
+        const int u0 = 3 * NJ + 3 * i;
+        const int gvc = C::GV + u0;
+        auto cslot = [&](int off) { return cl ? cf + off : tr; };
+        *cslot(gvc + (3 * b) * M) = f.nx * im;
+        *cslot(gvc + (3 * b + 1) * M) = f.ny * im;
+        *cslot(gvc + (3 * b + 2) * M) = (ax * f.ny - ay * f.nx) * ii;
+        *cslot(gvc + (3 * b) * M + 1) = f.tx * im;
+        *cslot(gvc + (3 * b + 1) * M + 1) = f.ty * im;
+        *cslot(gvc + (3 * b + 2) * M + 1) = (ax * f.ty - ay * f.tx) * ii;
+        *cslot(gvc + (3 * b) * M + 2) = -f.tx * im;
+        *cslot(gvc + (3 * b + 1) * M + 2) = -f.ty * im;
+        *cslot(gvc + (3 * b + 2) * M + 2) = -(ax * f.ty - ay * f.tx) * ii;
+        const int gcc = C::GC + i * M + u0;
+        *cslot(gcc) = s * T(0.5) * (f.sd + mu * av);
+        *cslot(gcc + 1) = s * T(0.5) * (rp - av);
+        *cslot(gcc + 2) = s * T(0.5) * (rm - av);
+        *cslot(C::F + NX + i) = ycc;
+        // F~ (q rows: stage velocities; v rows: the state wave's accelerations),
+        // dT/dth and the violation part of the lane's body
+        const bool bl = lane < NB;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            cf[C::F + 3 * b + k] = xs[NQ + 3 * b + k];
-            cf[C::F + NQ + 3 * b + k] = fv[3 * b + k];
+            *(bl ? cf + C::F + 3 * b + k : tr + k) = fq[k];
+            *(bl ? cf + C::F + NQ + 3 * b + k : tr + k) = fa[k];
         }
+        *(bl ? cf + C::CTH + b : tr) = s * dT * c.ii;
+        *(bl ? cf + C::CTP + b : tr) = ctp;
     }
-    // dT_b/dth_b: own terms plus the parent-side terms of the children's joints
-    if constexpr (WRITE) {
-        const T dT = dTown + from_children<TP>(dTpar, b);
-        if (lane < NB) cf[C::CTH + b] = s * dT * c.ii;
-    }
-    // violation row: each body lane keeps its own joint and contact part (the
-    // sum over bodies is taken by the consumers)
-    if (lane < NB) {
-        yct = ctp;
-        if constexpr (WRITE) cf[C::CTP + b] = ctp;
-    }
+    // the lane's body's part of the violation row (summed by the consumers)
+    yct = lane < NB ? ctp : T(0);
 }
 
 }  // namespace cis

@@ -83,7 +83,10 @@ struct Coef {
     static constexpr int GC = GV + 3 * TP::NB * TP::M; // [NC][M] (s/2) dOmega_cc/dubar
     static constexpr int F = GC + TP::NC * TP::M;      // [NXT] F~ (unscaled; the violation row unused)
     static constexpr int CTP = F + TP::NXT;            // [NB] violation integrand, per body
-    static constexpr int SIZE = even(CTP + TP::NB);
+    // per-lane sink for stores of lanes without the datum: lane l stores at
+    // TRASH + l + o with o < 16 (offsets within the contact block)
+    static constexpr int TRASH = even(CTP + TP::NB);
+    static constexpr int SIZE = TRASH + 64 + 16;
 };
 // per-contact slots (C_JMU = s lbar_n |v_t|_s = d(s Omega_cc)/d mu)
 enum { C_AX = 0, C_AY, C_FXP, C_FYP, C_TP, C_EPX, C_EPY, C_EXD, C_EYD, C_EOM, C_ETH, C_ZPX, C_ZPY,
