@@ -364,63 +364,77 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     // them is taken here, after the evaluation and before the stores
     if constexpr (SPLIT) __syncthreads();
     if constexpr (WRITE) {
+        // FP64: all values and addresses are formed first and stored in one
+        // burst, since a register overwritten right after an LDS store waits
+        // until the LDS unit has read it (measured faster); FP32 keeps the
+        // compiler's interleaved order (measured faster there).
+        constexpr int NV = 43;
+        T val[NV];
+        T* ptr[NV];
+        int e = 0;
         const int j = c.j, i = c.i;
         // one sink slot per lane: stores of many lanes to one LDS address serialize
         T* tr = cf + C::TRASH + lane;
+        auto put = [&](bool ok, int off, T v, int t = 0) {
+            ptr[e] = ok ? cf + off : tr + t;
+            val[e] = v;
+            ++e;
+        };
         // joint rows of the violation integrand and the joint-force torques
-        T* jh = jl ? cf + C::JH + 4 * j : tr;
-        jh[0] = s * d0;
-        jh[1] = s * d1;
-        jh[2] = s * (d1 * apx - d0 * apy);
-        jh[3] = s * (d0 * acy - d1 * acx);
-        T* gvj = cf + C::GV + NJ + 2 * j;
-        *(jl ? gvj + (3 * p + 2) * M : tr) = -apy * ip;
-        *(jl ? gvj + (3 * p + 2) * M + 1 : tr) = apx * ip;
-        *(jl ? gvj + (3 * b + 2) * M : tr) = acy * ii;
-        *(jl ? gvj + (3 * b + 2) * M + 1 : tr) = -acx * ii;
+        put(jl, C::JH + 4 * j + 0, s * d0);
+        put(jl, C::JH + 4 * j + 1, s * d1);
+        put(jl, C::JH + 4 * j + 2, s * (d1 * apx - d0 * apy));
+        put(jl, C::JH + 4 * j + 3, s * (d0 * acy - d1 * acx));
+        const int gvj = C::GV + NJ + 2 * j;
+        put(jl, gvj + (3 * p + 2) * M, -apy * ip);
+        put(jl, gvj + (3 * p + 2) * M + 1, apx * ip);
+        put(jl, gvj + (3 * b + 2) * M, acy * ii);
+        put(jl, gvj + (3 * b + 2) * M + 1, -acx * ii);
         // contact terms
-        T* ct = cl ? cf + C::CT + C::NCT * i : tr;
-        ct[C_AX] = ax;
-        ct[C_AY] = ay;
-        ct[C_FXP] = dfx * im;
-        ct[C_FYP] = dfy * im;
-        ct[C_TP] = (ax * dfy - ay * dfx) * ii;
-        ct[C_EPX] = s * (lnb * f.dsd_px + gv * dvt_px);
-        ct[C_EPY] = s * (lnb * f.dsd_py);
-        ct[C_EXD] = s * (gv * f.tx);
-        ct[C_EYD] = s * (gv * f.ty);
-        ct[C_EOM] = s * (gv * (f.ty * ax - f.tx * ay));
-        ct[C_ETH] = s * (-gv * om * (f.tx * ax + f.ty * ay));
-        ct[C_ZPX] = s * (Dg * f.dsd_px);
-        ct[C_ZPY] = s * (Dg * f.dsd_py);
-        ct[C_JMU] = s * (lnb * av);
+        const int ct = C::CT + C::NCT * i;
+        put(cl, ct + C_AX, ax, C_AX);
+        put(cl, ct + C_AY, ay, C_AY);
+        put(cl, ct + C_FXP, dfx * im, C_FXP);
+        put(cl, ct + C_FYP, dfy * im, C_FYP);
+        put(cl, ct + C_TP, (ax * dfy - ay * dfx) * ii, C_TP);
+        put(cl, ct + C_EPX, s * (lnb * f.dsd_px + gv * dvt_px), C_EPX);
+        put(cl, ct + C_EPY, s * (lnb * f.dsd_py), C_EPY);
+        put(cl, ct + C_EXD, s * (gv * f.tx), C_EXD);
+        put(cl, ct + C_EYD, s * (gv * f.ty), C_EYD);
+        put(cl, ct + C_EOM, s * (gv * (f.ty * ax - f.tx * ay)), C_EOM);
+        put(cl, ct + C_ETH, s * (-gv * om * (f.tx * ax + f.ty * ay)), C_ETH);
+        put(cl, ct + C_ZPX, s * (Dg * f.dsd_px), C_ZPX);
+        put(cl, ct + C_ZPY, s * (Dg * f.dsd_py), C_ZPY);
+        put(cl, ct + C_JMU, s * (lnb * av), C_JMU);
         const int u0 = 3 * NJ + 3 * i;
         const int gvc = C::GV + u0;
-        auto cslot = [&](int off) { return cl ? cf + off : tr; };
-        *cslot(gvc + (3 * b) * M) = f.nx * im;
-        *cslot(gvc + (3 * b + 1) * M) = f.ny * im;
-        *cslot(gvc + (3 * b + 2) * M) = (ax * f.ny - ay * f.nx) * ii;
-        *cslot(gvc + (3 * b) * M + 1) = f.tx * im;
-        *cslot(gvc + (3 * b + 1) * M + 1) = f.ty * im;
-        *cslot(gvc + (3 * b + 2) * M + 1) = (ax * f.ty - ay * f.tx) * ii;
-        *cslot(gvc + (3 * b) * M + 2) = -f.tx * im;
-        *cslot(gvc + (3 * b + 1) * M + 2) = -f.ty * im;
-        *cslot(gvc + (3 * b + 2) * M + 2) = -(ax * f.ty - ay * f.tx) * ii;
+        put(cl, gvc + (3 * b) * M, f.nx * im);
+        put(cl, gvc + (3 * b + 1) * M, f.ny * im);
+        put(cl, gvc + (3 * b + 2) * M, (ax * f.ny - ay * f.nx) * ii);
+        put(cl, gvc + (3 * b) * M + 1, f.tx * im);
+        put(cl, gvc + (3 * b + 1) * M + 1, f.ty * im);
+        put(cl, gvc + (3 * b + 2) * M + 1, (ax * f.ty - ay * f.tx) * ii);
+        put(cl, gvc + (3 * b) * M + 2, -f.tx * im);
+        put(cl, gvc + (3 * b + 1) * M + 2, -f.ty * im);
+        put(cl, gvc + (3 * b + 2) * M + 2, -(ax * f.ty - ay * f.tx) * ii);
         const int gcc = C::GC + i * M + u0;
-        *cslot(gcc) = s * T(0.5) * (f.sd + mu * av);
-        *cslot(gcc + 1) = s * T(0.5) * (rp - av);
-        *cslot(gcc + 2) = s * T(0.5) * (rm - av);
-        *cslot(C::F + NX + i) = ycc;
+        put(cl, gcc, s * T(0.5) * (f.sd + mu * av));
+        put(cl, gcc + 1, s * T(0.5) * (rp - av));
+        put(cl, gcc + 2, s * T(0.5) * (rm - av));
+        put(cl, C::F + NX + i, ycc);
         // F~ (q rows: stage velocities; v rows: the state wave's accelerations),
         // dT/dth and the violation part of the lane's body
         const bool bl = lane < NB;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            *(bl ? cf + C::F + 3 * b + k : tr + k) = fq[k];
-            *(bl ? cf + C::F + NQ + 3 * b + k : tr + k) = fa[k];
+            put(bl, C::F + 3 * b + k, fq[k], k);
+            put(bl, C::F + NQ + 3 * b + k, fa[k], k);
         }
-        *(bl ? cf + C::CTH + b : tr) = s * dT * c.ii;
-        *(bl ? cf + C::CTP + b : tr) = ctp;
+        put(bl, C::CTH + b, s * dT * c.ii);
+        put(bl, C::CTP + b, ctp);
+        if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) *ptr[q] = val[q];
     }
     // the lane's body's part of the violation row (summed by the consumers)
     yct = lane < NB ? ctp : T(0);
