@@ -267,6 +267,15 @@ enum { CIS_SCHED_GRID = 1, CIS_SCHED_PERSISTENT = 2, CIS_SCHED_TUNE = 3 };
  * likewise timed in its two forms with CIS_SCHED_TUNE. */
 enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30 };
 
+/* Optional bits of `sched` fixing the register budget of the discretize
+ * kernel: CIS_SCHED_WAVES_1 lets it take all registers it wants (one wave per
+ * SIMD); CIS_SCHED_WAVES_2 holds it to 256 registers per lane so that two
+ * workgroups share a compute unit (latency hiding, at the price of spills to
+ * scratch; CIS_F64 only, else CIS_ERR_DTYPE).  Without either bit both FP64
+ * forms are timed with CIS_SCHED_TUNE, and the first is used otherwise.
+ * Setting both bits is an error (CIS_ERR_DIM). */
+enum { CIS_SCHED_WAVES_1 = 0x40, CIS_SCHED_WAVES_2 = 0x80 };
+
 /*
  * Create a plan for n_traj trajectories (all of one dtype; CIS_BATCH_ADJOINT
  * needs CIS_F64).  ckpt_every: substeps between the checkpoints of the reverse
@@ -293,12 +302,14 @@ cis_status cis_batch_graph_run(cis_batch_plan *plan, int32_t op, void *stream);
 
 /* Description of a plan: number of model groups, and for group g (if
  * 0 <= g < groups) its trajectories, work items (intervals), units per item,
- * the persistent grid size chosen for it (0 = one workgroup per unit) and
- * the waves per interval of its reverse sweep (0 without CIS_BATCH_ADJOINT).
- * Any output pointer may be NULL. */
+ * the persistent grid size chosen for it (0 = one workgroup per unit), the
+ * waves per interval of its reverse sweep (0 without CIS_BATCH_ADJOINT) and
+ * the register budget of its discretize kernel in waves per SIMD (1 or 2; 0
+ * without CIS_BATCH_DISCRETIZE).  Any output pointer may be NULL. */
 cis_status cis_batch_plan_info(const cis_batch_plan *plan, int32_t g, int32_t *groups,
                                int32_t *n_traj, int32_t *n_items, int32_t *units_per_item,
-                               int32_t *persist_blocks, int32_t *adjoint_waves);
+                               int32_t *persist_blocks, int32_t *adjoint_waves,
+                               int32_t *waves_per_simd);
 
 /* Release a plan (NULL accepted); synchronizes the device first. */
 void cis_batch_plan_destroy(cis_batch_plan *plan);

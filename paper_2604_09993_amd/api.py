@@ -300,7 +300,7 @@ class BatchPlan:
     """
 
     def __init__(self, trajs, ops=("discretize",), *, sched="tune", ckpt_every=0, graph=True,
-                 adjoint_waves=None, stream=None):
+                 adjoint_waves=None, waves_per_simd=None, stream=None):
         lib = _lib.load()
         if not trajs:
             raise ValueError("a batch needs at least one trajectory")
@@ -347,6 +347,9 @@ class BatchPlan:
         if adjoint_waves is not None:
             sched_code |= {1: _lib.CIS_SCHED_ADJ_1, 2: _lib.CIS_SCHED_ADJ_2,
                            3: _lib.CIS_SCHED_ADJ_3}[int(adjoint_waves)]
+        if waves_per_simd is not None:
+            sched_code |= {1: _lib.CIS_SCHED_WAVES_1,
+                           2: _lib.CIS_SCHED_WAVES_2}[int(waves_per_simd)]
         _lib.check(lib.cis_batch_plan_create(arr, len(trajs), _dtype_code(dtype), self.ops,
                                              sched_code, int(ckpt_every), int(bool(graph)),
                                              _stream(stream), ctypes.byref(h)))
@@ -360,17 +363,19 @@ class BatchPlan:
         _lib.check(fn(self._h, _OPS[op], _stream(stream)))
 
     def groups(self):
-        """Per model group: trajectories, items, units per item, persistent grid (0 = grid)."""
+        """Per model group: trajectories, items, units per item, persistent grid (0 = grid),
+        waves of the reverse sweep, register budget of the discretize kernel."""
         lib = _lib.load()
         ng = ctypes.c_int32()
         _lib.check(lib.cis_batch_plan_info(self._h, -1, ctypes.byref(ng), None, None, None, None,
-                                           None))
+                                           None, None))
         res = []
         for g in range(ng.value):
-            v = [ctypes.c_int32() for _ in range(5)]
+            v = [ctypes.c_int32() for _ in range(6)]
             _lib.check(lib.cis_batch_plan_info(self._h, g, None, *[ctypes.byref(x) for x in v]))
             res.append(dict(n_traj=v[0].value, n_items=v[1].value, units_per_item=v[2].value,
-                            persist_blocks=v[3].value, adjoint_waves=v[4].value))
+                            persist_blocks=v[3].value, adjoint_waves=v[4].value,
+                            waves_per_simd=v[5].value))
         return res
 
     def close(self):

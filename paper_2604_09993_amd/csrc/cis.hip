@@ -112,7 +112,9 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
             const T* jh = cf + C::JH + 4 * j;
             kct += jh[0] * (ZQ(lb - 1, 0) - ZQ(lb, 0)) + jh[1] * (ZQ(lb - 1, 1) - ZQ(lb, 1)) +
                    jh[2] * ZQ(lb - 1, 2) + jh[3] * ZQ(lb, 2);
-            __builtin_amdgcn_sched_barrier(0);
+            // FP32 keeps the joints apart in the schedule (measured faster);
+            // FP64 lets the next joint's loads overlap this one (measured faster)
+            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         }
     }
     if constexpr (L >= 1) {
@@ -442,8 +444,11 @@ __global__ void __launch_bounds__(TP::NTHREADS)
 // K5: a batch of trajectories of one model.  PERSIST = false: one workgroup per
 // work unit (dispatch order follows the cost-sorted list); PERSIST = true: a
 // resident grid draws units from an atomic cursor until the list is empty.
-template <class T, class TP, bool PERSIST>
-__global__ void __launch_bounds__(TP::NTHREADS)
+// WAVES: the waves per SIMD the register allocation is held to (1: no cap;
+// 2: at most 256 registers per lane, which lets a second workgroup share the
+// compute unit and hide the other's latency, at the price of spills).
+template <class T, class TP, bool PERSIST, int WAVES>
+__global__ void __launch_bounds__(TP::NTHREADS) __attribute__((amdgpu_waves_per_eu(WAVES)))
     k_discretize_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     __shared__ DiscShared<T, TP> sh;
     const int total = b.n_items * TP::NGRP;
@@ -816,17 +821,25 @@ static BatchArgs<FwdArgs<T>> batch_args(const BatchGroupDev& g) {
 
 template <class T, int L, int D>
 static cis_status prep_disc_t(const cis_model* m, const BatchGroupDev& g, int persist_blocks,
-                              KLaunch* out) {
+                              int waves, KLaunch* out) {
     using TP = ThroughputTopo<T, L, D>;
     out->arg(batch_args<T>(g));
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
     out->block = dim3(TP::NTHREADS);
-    if (persist_blocks > 0) {
-        out->func = (const void*)&k_discretize_batch<T, TP, true>;
-        out->grid = dim3(persist_blocks);
+    const bool pers = persist_blocks > 0;
+    out->grid = dim3(pers ? persist_blocks : g.n_items * TP::NGRP);
+    if (waves == 1) {
+        out->func = pers ? (const void*)&k_discretize_batch<T, TP, true, 1>
+                         : (const void*)&k_discretize_batch<T, TP, false, 1>;
+    } else if (waves == 2) {
+        if constexpr (sizeof(T) == 8) {
+            out->func = pers ? (const void*)&k_discretize_batch<T, TP, true, 2>
+                             : (const void*)&k_discretize_batch<T, TP, false, 2>;
+        } else {
+            return fail(CIS_ERR_DTYPE, "prep_discretize_batch: the two-wave form is FP64 only");
+        }
     } else {
-        out->func = (const void*)&k_discretize_batch<T, TP, false>;
-        out->grid = dim3(g.n_items * TP::NGRP);
+        return fail(CIS_ERR_DIM, "prep_discretize_batch: waves=%d", waves);
     }
     return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_discretize_batch: launch record refused");
 }
@@ -850,11 +863,11 @@ static int units_t() {
 }
 
 cis_status prep_discretize_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
-                                 int persist_blocks, KLaunch* out) {
-#define CIS_PREP_DISC(LL, DD)                                                               \
-    if (m->L == LL && m->D == DD)                                                           \
-        return dtype == CIS_F64 ? prep_disc_t<double, LL, DD>(m, g, persist_blocks, out)    \
-                                : prep_disc_t<float, LL, DD>(m, g, persist_blocks, out);
+                                 int persist_blocks, int waves, KLaunch* out) {
+#define CIS_PREP_DISC(LL, DD)                                                                \
+    if (m->L == LL && m->D == DD)                                                            \
+        return dtype == CIS_F64 ? prep_disc_t<double, LL, DD>(m, g, persist_blocks, waves, out) \
+                                : prep_disc_t<float, LL, DD>(m, g, persist_blocks, waves, out);
     CIS_TOPOLOGIES(CIS_PREP_DISC)
 #undef CIS_PREP_DISC
     return fail(CIS_ERR_UNSUPPORTED, "prep_discretize_batch: topology has no compiled kernel");

@@ -25,6 +25,7 @@ struct Group {
     std::vector<int2> items;   // {group-local trajectory, interval}
     int units_per_item = 0;
     int persist_blocks = 0;
+    int disc_waves = 0;        // register budget of the discretize kernel (waves per SIMD)
     int adj_waves = 0;         // waves per interval of the chosen reverse sweep
     size_t fdesc_off = 0, ddesc_off = 0, adesc_off = 0, items_off = 0, cursor_off = 0;
     BatchGroupDev dev{};
@@ -165,7 +166,7 @@ static cis_status build_graph(cis_batch_plan* p, int op) {
     return CIS_OK;
 }
 
-static bool sched_bits_unknown(int32_t s) { return (s & ~0x3F) != 0; }
+static bool sched_bits_unknown(int32_t s) { return (s & ~0xFF) != 0; }
 
 extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_traj,
                                             cis_dtype dtype, int32_t ops, int32_t sched,
@@ -182,9 +183,13 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
     if ((ops & CIS_BATCH_ADJOINT) && dtype != CIS_F64)
         return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: the reverse sweep is offered in CIS_F64 only");
     const int adj_force = (sched >> 4) & 3;   // 0: default, else waves of the reverse sweep
+    const int waves_force = (sched >> 6) & 3;   // 0: default, 1 or 2: register budget
     sched &= 0xF;
-    if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE || (sched_bits_unknown(sched_all)))
+    if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE || sched_bits_unknown(sched_all) ||
+        waves_force == 3)
         return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched_all);
+    if (waves_force == 2 && dtype != CIS_F64)
+        return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: CIS_SCHED_WAVES_2 is offered in CIS_F64 only");
     if (ckpt_every < 0) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ckpt_every=%d < 0", ckpt_every);
     for (int i = 0; i < n_traj; ++i) {
         cis_status st = check_traj(trajs[i], i, dtype, ops);
@@ -364,37 +369,56 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         g.dev.cursor = (int*)(d + g.cursor_off);
         cis_status st;
         if (ops & CIS_BATCH_DISCRETIZE) {
+            // candidates: (grid | persistent) x register budget (1 or 2 waves
+            // per SIMD; FP64 only has the second); the schedule bits fix some
             const int units = g.dev.n_items * g.units_per_item;
-            KLaunch probe;
-            st = prep_discretize_batch(g.model, dtype, g.dev, 1, &probe);
-            if (st != CIS_OK) {
-                plan_free(p);
-                return st;
-            }
-            int occ = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, probe.func, probe.block.x, 0) !=
-                    hipSuccess || occ < 1)
-                occ = 1;
-            const int pblocks = std::min(units, occ * ncu);
-            KLaunch grid_l, pers_l;
-            st = prep_discretize_batch(g.model, dtype, g.dev, 0, &grid_l);
-            if (st == CIS_OK) st = prep_discretize_batch(g.model, dtype, g.dev, pblocks, &pers_l);
-            if (st != CIS_OK) {
-                plan_free(p);
-                return st;
-            }
-            int choice = sched == CIS_SCHED_PERSISTENT ? pblocks : 0;
-            if (sched == CIS_SCHED_TUNE) {
-                const float tg = time_launch(grid_l, hs, 3);
-                const float tp = time_launch(pers_l, hs, 3);
-                if (tg < 0.f || tp < 0.f) {
+            struct Cand { KLaunch l; int pblocks, waves; };
+            std::vector<Cand> cands;
+            for (int w = 1; w <= (dtype == CIS_F64 ? 2 : 1); ++w) {
+                if (waves_force ? w != waves_force : (sched != CIS_SCHED_TUNE && w != 1)) continue;
+                KLaunch probe;
+                st = prep_discretize_batch(g.model, dtype, g.dev, 1, w, &probe);
+                if (st != CIS_OK) {
                     plan_free(p);
-                    return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
+                    return st;
                 }
-                choice = tp < tg ? pblocks : 0;
+                int occ = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, probe.func, probe.block.x,
+                                                                 0) != hipSuccess || occ < 1)
+                    occ = 1;
+                const int pblocks = std::min(units, occ * ncu);
+                for (int pers = 0; pers < 2; ++pers) {
+                    if (sched == CIS_SCHED_GRID && pers) continue;
+                    if (sched == CIS_SCHED_PERSISTENT && !pers) continue;
+                    Cand c;
+                    c.pblocks = pers ? pblocks : 0;
+                    c.waves = w;
+                    st = prep_discretize_batch(g.model, dtype, g.dev, c.pblocks, w, &c.l);
+                    if (st != CIS_OK) {
+                        plan_free(p);
+                        return st;
+                    }
+                    cands.push_back(c);
+                }
             }
-            g.persist_blocks = choice;
-            g.disc = choice ? pers_l : grid_l;
+            size_t best = 0;
+            if (cands.size() > 1) {
+                float tbest = -1.f;
+                for (size_t c = 0; c < cands.size(); ++c) {
+                    const float t = time_launch(cands[c].l, hs, 3);
+                    if (t < 0.f) {
+                        plan_free(p);
+                        return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
+                    }
+                    if (tbest < 0.f || t < tbest) {
+                        tbest = t;
+                        best = c;
+                    }
+                }
+            }
+            g.persist_blocks = cands[best].pblocks;
+            g.disc_waves = cands[best].waves;
+            g.disc = cands[best].l;
         }
         if (ops & CIS_BATCH_ADJOINT) {
             BatchGroupDev dd = g.dev;
@@ -504,7 +528,7 @@ extern "C" cis_status cis_batch_graph_run(cis_batch_plan* p, int32_t op, void* s
 extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, int32_t* groups,
                                           int32_t* n_traj, int32_t* n_items,
                                           int32_t* units_per_item, int32_t* persist_blocks,
-                                          int32_t* adjoint_waves) {
+                                          int32_t* adjoint_waves, int32_t* waves_per_simd) {
     if (!p) return fail(CIS_ERR_NULL, "cis_batch_plan_info: plan is required");
     if (groups) *groups = (int32_t)p->groups.size();
     if (g < 0 || g >= (int32_t)p->groups.size()) return CIS_OK;
@@ -514,6 +538,7 @@ extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, in
     if (units_per_item) *units_per_item = gr.units_per_item;
     if (persist_blocks) *persist_blocks = gr.persist_blocks;
     if (adjoint_waves) *adjoint_waves = gr.adj_waves;
+    if (waves_per_simd) *waves_per_simd = gr.disc_waves;
     return CIS_OK;
 }
 

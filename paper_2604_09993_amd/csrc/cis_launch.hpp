@@ -71,9 +71,10 @@ struct BatchGroupDev {
 
 // Launch preparation for one model group (implemented next to the kernels).
 // `persist_blocks` = 0 selects one workgroup per work unit, otherwise that many
-// persistent workgroups draw units from the cursor.
+// persistent workgroups draw units from the cursor.  `waves` (1 or 2; 2 in
+// FP64 only): waves per SIMD the kernel's registers are budgeted for.
 cis_status prep_discretize_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
-                                 int persist_blocks, KLaunch* out);
+                                 int persist_blocks, int waves, KLaunch* out);
 // (body_lanes: the two-wave body-lane kernel, else one element-lane wave per interval)
 cis_status prep_defects_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
                               bool body_lanes, KLaunch* out);

@@ -87,19 +87,24 @@ def _compare_to_single(plan, trajs, keys=("A", "Bm", "Bp", "S", "d", "xprop"), t
     return worst
 
 
-@pytest.mark.parametrize("sched", ["grid", "persistent", "tune"])
-def test_batch_discretize_matches_single_and_oracle(sched):
+@pytest.mark.parametrize("sched,waves", [("grid", None), ("persistent", None), ("tune", None),
+                                         ("grid", 2), ("persistent", 2), ("tune", 1)])
+def test_batch_discretize_matches_single_and_oracle(sched, waves):
+    """waves: register budget of the discretize kernel (None: default or tuned)."""
     api = _api()
     batch = _small_batch(9, seed=11)
-    _say(f"batch discretize fp64 sched={sched} trajs={len(batch)}")
+    _say(f"batch discretize fp64 sched={sched} waves={waves} trajs={len(batch)}")
     trajs = _upload(batch, torch.float64)
-    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=False)
+    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=False, waves_per_simd=waves)
     groups = plan.groups()
     assert len(groups) == 3 and sum(g["n_traj"] for g in groups) == 9
     if sched == "persistent":
         assert all(g["persist_blocks"] > 0 for g in groups)
     if sched == "grid":
         assert all(g["persist_blocks"] == 0 for g in groups)
+    want = waves if waves is not None else (None if sched == "tune" else 1)
+    assert all(g["waves_per_simd"] == want if want else g["waves_per_simd"] in (1, 2)
+               for g in groups), groups
     plan.run("discretize")
     torch.cuda.synchronize()
     _compare_to_single(plan, trajs)
@@ -166,6 +171,7 @@ def test_batch_fp32_matches_single_and_oracle():
     _say("batch discretize fp32")
     trajs = _upload(batch, torch.float32)
     plan = api.BatchPlan(trajs, ("discretize",), sched="tune", graph=True)
+    assert all(g["waves_per_simd"] == 1 for g in plan.groups())   # one FP32 form
     plan.run("discretize", graph=True)
     torch.cuda.synchronize()
     _compare_to_single(plan, trajs, tol=1e-6)
