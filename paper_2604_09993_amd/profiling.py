@@ -99,6 +99,76 @@ def counter_means(folder, counter):
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
 
+def interval_bytes(model, K, op, C=1, dsize=8):
+    """Algorithmic HBM bytes of one interval (each datum moved once).
+
+    Every operation reads X_k, X_k+1, U_k, U_k+1, s_k and the P parameters.
+    discretize writes A (nx x nx), B- and B+ (nx x m), S, defect and x_prop;
+    defects writes defect, x_prop and the K/C body-state checkpoints; the
+    reverse sweep also reads the checkpoints and the seed, and writes gX_k,
+    the two control-gradient halves, gs_k and the P parameter partials.
+    """
+    nx, m, n, P = model.nx, model.m, model.n, model.n_params
+    read = 2 * nx + 2 * m + 1 + P
+    if op == "discretize":
+        return dsize * (read + nx * nx + 2 * nx * m + 3 * nx)
+    if op == "defects":
+        return dsize * (read + 2 * nx + (K // C) * n)
+    if op == "adjoint":
+        return dsize * (read + (K // C) * n + nx + nx + 2 * m + 1 + P)
+    raise ValueError(op)
+
+
+def _topo(model):
+    return f"Topo<{model.legs}, {model.depth}"
+
+
+def bench_algorithmic_bytes():
+    """Algorithmic bytes per launch of the kernels bench.py runs, keyed by
+    kernel-name prefix (the batch kernels by dtype and topology: every form
+    the tuner tries processes the same group)."""
+    from . import synth
+
+    def auto_ckpt(K):   # a plan's default spacing: the largest divisor of K not above 8
+        return max(c for c in range(1, 9) if K % c == 0)
+    out = {}
+    model, data, K = synth.make_config(2)
+    N = data["s"].shape[0]
+    t = _topo(model)
+    out[f"k_discretize<double, {t}"] = N * interval_bytes(model, K, "discretize")
+    out[f"k_discretize<float, {t}"] = N * interval_bytes(model, K, "discretize", dsize=4)
+    out[f"k_defects<double, {t}"] = N * interval_bytes(model, K, "defects", C=5)
+    out[f"k_adjoint3<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
+    out[f"k_adjoint<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
+    groups = {}
+    for m_, d, k in synth.mixed_batch():
+        groups.setdefault(_topo(m_), []).append((m_, d["s"].shape[0], k))
+    for t, items in groups.items():
+        def tot(op, cf=lambda k: 1, items=items):
+            return sum(n * interval_bytes(m_, k, op, C=cf(k)) for m_, n, k in items)
+        out[f"k_discretize_batch<double, {t}"] = tot("discretize")
+        out[f"k_defects_batch<double, {t}"] = tot("defects", auto_ckpt)
+        out[f"k_defects_lane_batch<double, {t}"] = tot("defects", auto_ckpt)
+        out[f"k_adjoint3_batch<double, {t}"] = tot("adjoint", auto_ckpt)
+        out[f"k_adjoint_batch<double, {t}"] = tot("adjoint", auto_ckpt)
+    qb = synth.config_batch(5)
+    t = _topo(qb[0][0])
+    out[f"k_discretize_batch<double, {t}"] = sum(d["s"].shape[0] * interval_bytes(m_, k, "discretize")
+                                                 for m_, d, k in qb)
+    out[f"k_discretize_batch<float, {t}"] = sum(d["s"].shape[0] *
+                                                interval_bytes(m_, k, "discretize", dsize=4)
+                                                for m_, d, k in qb)
+    return out
+
+
+def _match(table, kernel):
+    best = None
+    for pre, v in table.items():
+        if kernel.startswith(pre) and kernel[len(pre)] in ",>" and (best is None or len(pre) > len(best[0])):
+            best = (pre, v)
+    return None if best is None else best[1]
+
+
 def summarize(a):
     stats = kernel_stats(a.trace)
     fetch = counter_means(a.fetch, "FETCH_SIZE")
@@ -110,7 +180,7 @@ def summarize(a):
     copy_w = max(cw.values()) if cw else None
     sf = moved_kib / copy_f if copy_f else 1.0
     sw = moved_kib / copy_w if copy_w else 1.0
-    algo = json.loads(a.algorithmic) if a.algorithmic else {}
+    algo = json.loads(a.algorithmic) if a.algorithmic else bench_algorithmic_bytes()
     lines = [f"# {a.title}", "", "Box: one MI355X (gfx950). All commands run from the repository root.",
              "", "## Kernel trace", "", f"    {a.cmd_trace}", "",
              "| kernel | calls | total µs | average µs |", "|---|---|---|---|"]
@@ -129,7 +199,7 @@ def summarize(a):
     for k in sorted(set(fetch) | set(write)):
         f_kib, w_kib = fetch.get(k, 0.0), write.get(k, 0.0)
         rb, wb = f_kib * 1024 * sf, w_kib * 1024 * sw
-        al = algo.get(k)
+        al = _match(algo, k)
         lines.append(f"| `{k}` | {f_kib:,.1f} | {w_kib:,.1f} | {rb:,.0f} | {wb:,.0f} | "
                      f"{'' if al is None else f'{al:,.0f}'} |")
         rec["kernels"][k] = {"fetch_bytes": rb, "write_bytes": wb, "algorithmic_bytes": al}
@@ -152,7 +222,9 @@ def main():
     for k in ("trace", "fetch", "write", "cfetch", "cwrite"):
         s.add_argument("--cmd-" + k, default="")
     s.add_argument("--title", default="Kernel profile")
-    s.add_argument("--algorithmic", default="", help="JSON {kernel: algorithmic bytes}")
+    s.add_argument("--algorithmic", default="",
+                   help="JSON {kernel-name prefix: algorithmic bytes per launch}; default: "
+                        "the workloads of bench.py")
     s.add_argument("--note", default="")
     a = ap.parse_args()
     if a.cmd == "copy":
