@@ -92,7 +92,11 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
         kv[3 * lb + 2] = cf[C::CTH + gb(lb)] * ZQ(lb, 2);
     }
     T kct = T(0), kcc = T(0);
-    __builtin_amdgcn_sched_barrier(0);
+    // Scheduling fences: the stage is limited by LDS latency under register
+    // pressure, and where the compiler may move loads across sections was
+    // chosen by measurement per type (FP64: only before the RK combination;
+    // FP32: also here and between the joints).
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
     if constexpr (D >= 1) {
         // hip joints: torso-side stiffness and damping of every leg
         const T th1 = ZQ(1, 2), w1 = ZV(1, 2);
@@ -112,8 +116,6 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
             const T* jh = cf + C::JH + 4 * j;
             kct += jh[0] * (ZQ(lb - 1, 0) - ZQ(lb, 0)) + jh[1] * (ZQ(lb - 1, 1) - ZQ(lb, 1)) +
                    jh[2] * ZQ(lb - 1, 2) + jh[3] * ZQ(lb, 2);
-            // FP32 keeps the joints apart in the schedule (measured faster);
-            // FP64 lets the next joint's loads overlap this one (measured faster)
             if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -129,7 +131,6 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
               ct[C_EOM] * ZV(lb, 2) + ct[C_ETH] * ZQ(lb, 2);
         kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
     }
-    __builtin_amdgcn_sched_barrier(0);
     // FOH forcing of B-/B+ columns, s (J_u w(tau) + J_ubar / 2), and F~
     // forcing of the dilation column, without branches (the weights are zero in
     // the other columns) so that the loads issue with the stage's other loads
