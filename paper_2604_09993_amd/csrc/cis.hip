@@ -201,14 +201,20 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 //                       stages and each stage spans steps t-1 and t-2;
 //   tangent waves     : apply stage t-LAG to their columns.
 // ---------------------------------------------------------------------------
-// Workgroup layouts of the discretize kernel.  Latency (one trajectory): two
+// Workgroup layouts of the discretize kernel.  Latency (few intervals): two
 // coefficient waves; FP64 one tangent wave per workgroup (512 registers per
-// lane, one wave per SIMD), FP32 up to five (two waves per SIMD).  Throughput
-// (batches): one coefficient wave and more tangent waves per workgroup.
+// lane, one wave per SIMD), FP32 up to five (two waves per SIMD).  Narrow
+// (FP64, as many workgroups as CUs): one coefficient wave and two tangent
+// waves, still one wave per SIMD.  Throughput (large trajectories and
+// batches): up to six tangent waves per workgroup, so the state and
+// coefficient work is repeated over fewer column groups; a workgroup of more
+// than four waves holds every wave to 256 registers.
 template <class T, int L, int D>
 using LatencyTopo = Topo<L, D, sizeof(T) == 8 ? 1 : 5, 2>;
 template <class T, int L, int D>
-using ThroughputTopo = Topo<L, D, sizeof(T) == 8 ? 2 : 6, 1>;
+using NarrowTopo = Topo<L, D, sizeof(T) == 8 ? 2 : 6, 1>;
+template <class T, int L, int D>
+using ThroughputTopo = Topo<L, D, 6, 1>;
 
 template <class T, class TP>
 struct DiscShared {
@@ -723,16 +729,21 @@ static cis_status launch_discretize_as(const cis_model* m, const cis_shape* sh, 
 }
 
 // One trajectory: the latency layout while every (interval, column group)
-// workgroup can be resident at once, the throughput layout beyond.
+// workgroup can be resident at once on its own CU, else the narrow layout
+// while that holds for it, the throughput layout beyond.
 template <class T, int L, int D>
 static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, const void* X,
                                     const void* U, const void* s, const void* prm, void* A,
                                     void* Bm, void* Bp, void* S, void* d, void* xp,
                                     hipStream_t stream) {
     using TL = LatencyTopo<T, L, D>;
+    using TN = NarrowTopo<T, L, D>;
     using TT = ThroughputTopo<T, L, D>;
-    if ((int64_t)sh->N * TL::NGRP <= device_cus())
+    const int cus = device_cus();
+    if ((int64_t)sh->N * TL::NGRP <= cus)
         return launch_discretize_as<T, TL>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    if ((int64_t)sh->N * TN::NGRP <= cus)
+        return launch_discretize_as<T, TN>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
     return launch_discretize_as<T, TT>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
 }
 
@@ -777,6 +788,7 @@ static cis_status blocked_passes_t(const cis_model* m, const cis_shape* sh, cons
     a.ld_blk = sh->ld_int;        // checkpoints as written by pass 1
     a.B = B;
     using TL = LatencyTopo<T, L, D>;
+    using TN = NarrowTopo<T, L, D>;
     using TT = ThroughputTopo<T, L, D>;
     const int64_t items = (int64_t)B * sh->N;
     auto launch = [&](auto tp) -> cis_status {
@@ -791,6 +803,7 @@ static cis_status blocked_passes_t(const cis_model* m, const cis_shape* sh, cons
         return CIS_OK;
     };
     if (items * TL::NGRP <= device_cus()) return launch(TL{});
+    if (items * TN::NGRP <= device_cus()) return launch(TN{});
     return launch(TT{});
 }
 

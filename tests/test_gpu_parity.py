@@ -123,19 +123,22 @@ def test_discretize_small_fp32(name, N, K):
     check_against_oracle(model, data, K, res, dtype=torch.float32)
 
 
+@pytest.mark.parametrize("N", [300, 110, 30])
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", [n for n, _, _ in SMALL])
-def test_discretize_many_intervals_sampled(name, dtype):
-    """N = 300 intervals: more (interval, column group) workgroups than compute
-    units, so the single-trajectory call takes the throughput layout (the small
-    cases above take the latency layout); 4 sampled intervals vs the oracle."""
-    N, K = 300, 2
+def test_discretize_many_intervals_sampled(name, dtype, N):
+    """More intervals than the small cases above, which take the latency
+    layout: with 256 CUs, N = 300 takes the throughput layout for every model;
+    N = 110 the narrow FP64 layout for biped5 / cheetah7 (3 column groups in
+    the latency layout, 2 in the narrow one) and N = 30 for quad13 (11 and 6);
+    4 sampled intervals vs the oracle."""
+    K = 2
     _say(f"[gpu] discretize {dtype} {name} N={N} K={K} seed=102 (sampled)")
     dt = torch.float64 if dtype == "fp64" else torch.float32
     model, rng = _model(name, 102)
     data = synth.gen_nodes(model, N, rng, T=0.02 * N)
     res, _ = run_gpu(model, data, K, dtype=dt)
-    for k in (0, 1, 150, N - 1):
+    for k in (0, 1, N // 2, N - 1):
         sub = dict(X=data["X"][k:k + 2], U=data["U"][k:k + 2], s=data["s"][k:k + 1], p=data["p"])
         one = {key: (None if v is None else v[k:k + 1]) for key, v in res.items()}
         check_against_oracle(model, sub, K, one, dtype=dt)
