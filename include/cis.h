@@ -261,11 +261,15 @@ enum { CIS_SCHED_GRID = 1, CIS_SCHED_PERSISTENT = 2, CIS_SCHED_TUNE = 3 };
 
 /* Optional bits of `sched` fixing the form of the reverse sweep (waves per
  * interval) instead of the default: timed at creation with CIS_SCHED_TUNE,
- * else three waves.  3: stage evaluation one step ahead of the reverse sweep
- * (checkpoints at most 8 substeps apart, else 2); 2: replay one chunk ahead;
- * 1: one wave (fewest wave-cycles, for throughput).  The defects pass is
- * likewise timed in its two forms with CIS_SCHED_TUNE. */
-enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30 };
+ * else four waves.  4: two waves evaluate alternate stages ahead of the
+ * reverse sweep, each evaluation spread over two pipeline steps; 3: one wave
+ * evaluates each stage one step ahead (4 and 3 need checkpoints at most 8
+ * substeps apart, else 2 is used); 2: replay one chunk ahead; 1: one wave
+ * (fewest wave-cycles, for throughput).  At most one of these bits may be
+ * set.  The defects pass is likewise timed in its two forms with
+ * CIS_SCHED_TUNE. */
+enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30,
+       CIS_SCHED_ADJ_4 = 0x100 };
 
 /* Optional bits of `sched` fixing the register budget of the discretize
  * kernel: CIS_SCHED_WAVES_1 lets it take all registers it wants (one wave per

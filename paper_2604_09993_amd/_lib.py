@@ -33,6 +33,7 @@ CIS_SCHED_TUNE = 3
 CIS_SCHED_ADJ_1 = 0x10
 CIS_SCHED_ADJ_2 = 0x20
 CIS_SCHED_ADJ_3 = 0x30
+CIS_SCHED_ADJ_4 = 0x100
 CIS_SCHED_WAVES_1 = 0x40
 CIS_SCHED_WAVES_2 = 0x80
 CIS_COMPOSE_VALU = 0

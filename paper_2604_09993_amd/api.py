@@ -346,7 +346,7 @@ class BatchPlan:
         sched_code = _SCHED[sched]
         if adjoint_waves is not None:
             sched_code |= {1: _lib.CIS_SCHED_ADJ_1, 2: _lib.CIS_SCHED_ADJ_2,
-                           3: _lib.CIS_SCHED_ADJ_3}[int(adjoint_waves)]
+                           3: _lib.CIS_SCHED_ADJ_3, 4: _lib.CIS_SCHED_ADJ_4}[int(adjoint_waves)]
         if waves_per_simd is not None:
             sched_code |= {1: _lib.CIS_SCHED_WAVES_1,
                            2: _lib.CIS_SCHED_WAVES_2}[int(waves_per_simd)]

@@ -27,12 +27,12 @@ namespace cis {
 
 constexpr int CHUNK = 8;   // substeps whose stage inputs are kept in LDS at once
 
-template <class T, class TP>
+template <class T, class TP, int NSLOT = 2>
 struct AdjShared {
     Interval<T, TP> iv;
-    RhsScratch<T, TP> se[2];            // stage evaluations (state, F~, rotations) in flight
+    RhsScratch<T, TP> se[NSLOT];        // stage evaluations (state, F~, rotations) in flight
     RhsScratch<T, TP> scr;              // replay wave
-    T coef[2][Coef<TP>::SIZE];          // their Jacobian coefficients
+    T coef[NSLOT][Coef<TP>::SIZE];      // their Jacobian coefficients
     T hist[2][CHUNK * 4][TP::NX];       // stage inputs (x part) of two chunks
     T kb[TP::NXT];                      // kbar of the current stage
     T xbs[TP::NX];                      // Xbar of the current stage
@@ -44,8 +44,8 @@ struct AdjShared {
 // Reverse one RK4 stage whose input is sc.ns.  EVAL: evaluate the stage
 // (right-hand side and Jacobian coefficients into sc and cf) here; otherwise
 // another wave has done it.  Lanes own rows r = lane, lane + 64.
-template <class T, class TP, bool EVAL>
-__device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax, RhsScratch<T, TP>& sc,
+template <class T, class TP, bool EVAL, int NS>
+__device__ __forceinline__ void reverse_stage(AdjShared<T, TP, NS>& ax, RhsScratch<T, TP>& sc,
                                               T* cf, const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                               int lane, int st, T tau, T (&xbar)[2],
                                               T (&xprev)[2], T (&xsum)[2], T& sacc,
@@ -193,8 +193,8 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP>& ax, RhsScratch<T
 
 // Outputs of the reverse wave: gX_k, the control partials of interval k
 // (left: U_k, right: U_k+1), the dilation and parameter adjoints.
-template <class T, class TP>
-__device__ __forceinline__ void adjoint_outputs(AdjShared<T, TP>& ax, const AdjArgs<T>& a,
+template <class T, class TP, int NS>
+__device__ __forceinline__ void adjoint_outputs(AdjShared<T, TP, NS>& ax, const AdjArgs<T>& a,
                                                 const int k, const int lane, const T (&xbar)[2],
                                                 T sacc, const T (&uacc)[3][2], T muacc, T macc) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NXT = TP::NXT;
@@ -513,11 +513,147 @@ __device__ __forceinline__ void adjoint_item3(AdjShared<T, TP>& ax, const AdjArg
     adjoint_outputs<T, TP>(ax, a, k, lane, xbar, sacc, uacc, muacc, macc);
 }
 
+// Checkpoints at most CHUNK substeps apart, four waves: the replay wave as in
+// the three-wave form; two evaluation waves take alternate reverse stages,
+// each evaluation spanning two pipeline steps (a workgroup barrier between its
+// element wrenches and its smooth functions); the reverse wave applies stage
+// r at step r + 3.  Four evaluation slots: at step t the reverse reads r = t-3
+// while the evaluations of t-2 (second half) and t-1 (first half) write theirs.
 template <class T, class TP>
-__global__ void __launch_bounds__(192)
-    k_adjoint3(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
-    __shared__ AdjShared<T, TP> ax;
-    adjoint_item3<T, TP>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+__device__ __forceinline__ void adjoint_item4(AdjShared<T, TP, 4>& ax, const AdjArgs<T>& a,
+                                              const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                              const int k) {
+    constexpr int NX = TP::NX, NXT = TP::NXT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int nth = 256;
+    const FwdArgs<T>& f = a.f;
+    load_interval<T, TP>(ax.iv, f, mc, k, tid, nth);
+    for (int e = tid; e < 4 * Coef<TP>::SIZE; e += nth) (&ax.coef[0][0])[e] = T(0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) coef_constants<T, TP>(ax.iv, ax.coef[q], tid, nth);
+    __syncthreads();
+
+    const int64_t ldi = f.ldi;
+    const int K = f.K, Cs = f.C;
+    const int nseg = K / Cs, S4 = 4 * Cs;
+    const int nst = 4 * K, nsteps = nst + 3;
+    if (wave == 1) {
+        // ---------------- replay wave (as in the three-wave form) ----------------
+        RowState<T> rs;
+        for (int t = 0; t < nsteps; ++t) {
+            int u = -1, q0 = 0, q1 = 0;   // record stages [q0, q1) of chunk u
+            if (t == 0) {
+                u = 0;
+                q1 = S4;
+            } else if (t <= nst) {
+                const int r = t - 1;
+                u = r / S4 + 1;
+                q0 = r % S4;
+                q1 = q0 + 1;
+                if (u >= nseg) u = -1;
+            }
+            if (u >= 0) {
+                const int g = nseg - 1 - u;
+                T(*hist)[NX] = ax.hist[u & 1];
+                for (int q = q0; q < q1; ++q) {
+                    if (q == 0) {
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) {
+                            const int r = lane + 64 * i;
+                            rs.xb[i] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
+                            rs.xa[i] = T(0);
+                            if (r < NXT) ax.scr.ns[r] = rs.xb[i];
+                        }
+                        wave_lds_sync();
+                    }
+                    const int jj = q >> 2, st = q & 3, j = g * Cs + jj;
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int r = lane + 64 * i;
+                        if (r < NX) hist[q][r] = ax.scr.ns[r];
+                    }
+                    const T tau = (T(j) + T(stage_c(st))) / T(K);
+                    rhs_eval<T, TP, LEAN>(ax.iv, ax.scr, mc, lane, tau, (T*)nullptr);
+                    rk_rows<T, TP, NX>(ax.iv, ax.scr, rs, lane, st, ax.scr.ns, (T*)nullptr);
+                }
+                wave_lds_sync();
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    if (wave >= 2) {
+        // ------- evaluation waves: reverse stages r = e, e+2, ... at steps r+1, r+2 -------
+        const int e = wave - 2;
+        int done = 0;   // workgroup barriers passed
+        for (; done < e + 1; ++done) __syncthreads();
+        for (int r = e; r < nst; r += 2) {
+            const int u = r / S4, pp = r % S4;
+            const int g = nseg - 1 - u;
+            const int jj = Cs - 1 - (pp >> 2), st = 3 - (pp & 3), j = g * Cs + jj;
+            RhsScratch<T, TP>& sc = ax.se[r & 3];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int rr = lane + 64 * i;
+                if (rr < NX) sc.ns[rr] = ax.hist[u & 1][jj * 4 + st][rr];
+            }
+            wave_lds_sync();
+            const T tau = (T(j) + T(stage_c(st))) / T(K);
+            rhs_eval<T, TP, EMIT, false, true>(ax.iv, sc, mc, lane, tau, ax.coef[r & 3]);
+            __syncthreads();
+            done += 2;
+        }
+        for (; done < nsteps; ++done) __syncthreads();
+        return;
+    }
+    // ---------------- reverse wave ----------------
+    T xbar[2], xprev[2], xsum[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int r = lane + 64 * q;
+        xbar[q] = r < NXT ? a.seed[r * ldi + k] : T(0);
+        xprev[q] = T(0);
+        xsum[q] = T(0);
+    }
+    T sacc = T(0), muacc = T(0), macc = T(0);
+    T uacc[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    for (int t = 0; t < nsteps; ++t) {
+        if (t >= 3) {
+            const int r = t - 3, u = r / S4, pp = r % S4;
+            const int g = nseg - 1 - u;
+            const int jj = Cs - 1 - (pp >> 2), st = 3 - (pp & 3), j = g * Cs + jj;
+            const T tau = (T(j) + T(stage_c(st))) / T(K);
+            reverse_stage<T, TP, false>(ax, ax.se[r & 3], ax.coef[r & 3], mc, lane, st, tau,
+                                        xbar, xprev, xsum, sacc, uacc, muacc, macc);
+            if (st == 0) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    xbar[q] += xsum[q];
+                    xsum[q] = T(0);
+                    xprev[q] = T(0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    adjoint_outputs<T, TP>(ax, a, k, lane, xbar, sacc, uacc, muacc, macc);
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(256)
+    k_adjoint4(AdjArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ AdjShared<T, TP, 4> ax;
+    adjoint_item4<T, TP>(ax, a, mc, xcd_slot(blockIdx.x, gridDim.x));
+}
+
+template <class T, class TP>
+__global__ void __launch_bounds__(256)
+    k_adjoint4_batch(BatchArgs<AdjArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+    __shared__ AdjShared<T, TP, 4> ax;
+    const int2 it = b.items[xcd_slot(blockIdx.x, gridDim.x)];
+    const AdjArgs<T> a = b.descs[it.x];
+    adjoint_item4<T, TP>(ax, a, mc, it.y);
 }
 
 template <class T, class TP>
@@ -615,10 +751,10 @@ static cis_status launch_adjoint(const cis_model* m, const cis_shape* sh, const 
     a.ws_uk1 = w + (size_t)m->m * N;
     a.ws_p = w + (size_t)2 * m->m * N;
     void* args[] = {&a, &mc};
-    const bool three = C <= CHUNK;   // one chunk per checkpoint segment
-    hipError_t e = hipLaunchKernel(three ? (const void*)&k_adjoint3<T, TP>
-                                         : (const void*)&k_adjoint<T, TP>,
-                                   dim3(N), dim3(three ? 192 : 128), args, 0,
+    const bool four = C <= CHUNK;   // one chunk per checkpoint segment
+    hipError_t e = hipLaunchKernel(four ? (const void*)&k_adjoint4<T, TP>
+                                        : (const void*)&k_adjoint<T, TP>,
+                                   dim3(N), dim3(four ? 256 : 128), args, 0,
                                    stream);
     if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_adjoint launch: %s", hipGetErrorString(e));
     const int64_t work = (int64_t)m->m * (N + 1) + m->nx + m->np;
@@ -650,8 +786,9 @@ static cis_status prep_adj_t(const cis_model* m, const BatchGroupDev& g, int max
     b.cursor = g.cursor;
     out->arg(b);
     out->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
-    if (waves == 3 && max_ckpt_every > CHUNK) waves = 2;
-    out->func = waves == 3 ? (const void*)&k_adjoint3_batch<double, TP>
+    if (waves >= 3 && max_ckpt_every > CHUNK) waves = 2;
+    out->func = waves == 4   ? (const void*)&k_adjoint4_batch<double, TP>
+                : waves == 3 ? (const void*)&k_adjoint3_batch<double, TP>
                 : waves == 2 ? (const void*)&k_adjoint_batch<double, TP, 2>
                              : (const void*)&k_adjoint_batch<double, TP, 1>;
     out->grid = dim3(g.n_items);

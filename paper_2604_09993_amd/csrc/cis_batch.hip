@@ -166,7 +166,7 @@ static cis_status build_graph(cis_batch_plan* p, int op) {
     return CIS_OK;
 }
 
-static bool sched_bits_unknown(int32_t s) { return (s & ~0xFF) != 0; }
+static bool sched_bits_unknown(int32_t s) { return (s & ~0x1FF) != 0; }
 
 extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_traj,
                                             cis_dtype dtype, int32_t ops, int32_t sched,
@@ -182,12 +182,14 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
     if (ops < 1 || ops > 3) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ops=%d is not a mask of operations", ops);
     if ((ops & CIS_BATCH_ADJOINT) && dtype != CIS_F64)
         return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: the reverse sweep is offered in CIS_F64 only");
-    const int adj_force = (sched >> 4) & 3;   // 0: default, else waves of the reverse sweep
+    int adj_force = (sched >> 4) & 3;   // 0: default, else waves of the reverse sweep
+    const bool adj4 = (sched & CIS_SCHED_ADJ_4) != 0;
     const int waves_force = (sched >> 6) & 3;   // 0: default, 1 or 2: register budget
     sched &= 0xF;
     if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE || sched_bits_unknown(sched_all) ||
-        waves_force == 3)
+        waves_force == 3 || (adj4 && adj_force))
         return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched_all);
+    if (adj4) adj_force = 4;
     if (waves_force == 2 && dtype != CIS_F64)
         return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: CIS_SCHED_WAVES_2 is offered in CIS_F64 only");
     if (ckpt_every < 0) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ckpt_every=%d < 0", ckpt_every);
@@ -438,23 +440,23 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             }
             int cmax_g = 1;
             for (int i : g.trajs) cmax_g = std::max(cmax_g, p->ckpt_every[i]);
-            // reverse sweep with 3, 2 or 1 waves per interval (latency vs
-            // throughput): timed when tuning, else the three-wave form
-            KLaunch adjv[3];
-            for (int w = 0; w < 3 && st == CIS_OK; ++w)
-                st = prep_adjoint_batch(g.model, g.dev, cmax_g, 3 - w, &adjv[w]);
+            // reverse sweep with 4, 3, 2 or 1 waves per interval (latency vs
+            // throughput): timed when tuning, else the four-wave form
+            KLaunch adjv[4];
+            for (int w = 0; w < 4 && st == CIS_OK; ++w)
+                st = prep_adjoint_batch(g.model, g.dev, cmax_g, 4 - w, &adjv[w]);
             if (st != CIS_OK) {
                 plan_free(p);
                 return st;
             }
-            int best = adj_force ? 3 - adj_force : 0;
+            int best = adj_force ? 4 - adj_force : 0;
             if (sched == CIS_SCHED_TUNE && !adj_force) {
                 if (g.def.launch(hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess) {
                     plan_free(p);
                     return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
                 }
                 float tbest = -1.f;
-                for (int w = 0; w < 3; ++w) {
+                for (int w = 0; w < 4; ++w) {
                     if (w > 0 && adjv[w].func == adjv[w - 1].func) continue;
                     const float tw = time_launch(adjv[w], hs, 3);
                     if (tw < 0.f) {

@@ -201,8 +201,10 @@ enum RhsMode { LEAN = 0, FULL = 1, EMIT = 2 };
 // One right-hand-side evaluation at sc.ns by the 64 lanes of one wave.
 // If HAVE_CS the rotations sc.cs are already filled in.  Writes sc.fn (v rows
 // always, y rows from FULL on) and, in EMIT mode, the coefficients into cf.
+// SPLIT: one workgroup barrier between the element wrenches and the smooth
+// functions, so that the evaluation spans two steps of a barrier pipeline.
 // ---------------------------------------------------------------------------
-template <class T, class TP, int MODE, bool HAVE_CS = false>
+template <class T, class TP, int MODE, bool HAVE_CS = false, bool SPLIT = false>
 __device__ __forceinline__ void rhs_eval(const Interval<T, TP>& iv, RhsScratch<T, TP>& sc,
                                          const MConst<TP::NB, TP::NJ, TP::NC>& mc, int lane,
                                          T tau, T* cf) {
@@ -308,6 +310,7 @@ __device__ __forceinline__ void rhs_eval(const Interval<T, TP>& iv, RhsScratch<T
             sa1 = -sd;
         }
     }
+    if constexpr (SPLIT) __syncthreads();
     if (MODE >= FULL && NJ + NC > 0) {
         // step 2b: smooth functions, one code path for joints and contacts
         T v0, d0, v1, d1;

@@ -187,8 +187,9 @@ def test_batch_fp32_matches_single_and_oracle():
 
 
 @pytest.mark.parametrize("graph,sched,spacing,waves", [
-    (False, "grid", 0, None), (True, "grid", 0, 3), (True, "grid", 0, 2), (True, "grid", 0, 1),
-    (True, "tune", 0, None), (True, "grid", 10, None), (True, "grid", 10, 1)])
+    (False, "grid", 0, None), (True, "grid", 0, 4), (True, "grid", 0, 3), (True, "grid", 0, 2),
+    (True, "grid", 0, 1), (True, "tune", 0, None), (True, "grid", 10, None),
+    (True, "grid", 10, 1), (True, "grid", 10, 4)])
 def test_batch_adjoint_matches_single(graph, sched, spacing, waves):
     """spacing 0: checkpoints at most 8 substeps apart; 10: every 10 substeps with
     K in {10, 20} (chunked replay).  waves: forced form of the reverse sweep."""
