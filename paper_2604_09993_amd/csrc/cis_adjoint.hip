@@ -21,6 +21,7 @@
 #include "../../include/cis.h"
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
+#include "cis_body.hpp"
 #include "cis_model.hpp"
 
 namespace cis {
@@ -539,8 +540,15 @@ __device__ __forceinline__ void adjoint_item4(AdjShared<T, TP, 4>& ax, const Adj
     const int nseg = K / Cs, S4 = 4 * Cs;
     const int nst = 4 * K, nsteps = nst + 3;
     if (wave == 1) {
-        // ---------------- replay wave (as in the three-wave form) ----------------
-        RowState<T> rs;
+        // ---------------- replay wave: body lanes ----------------
+        // Same schedule as the three-wave form; one lane per body runs the
+        // nominal RK4 stages (the state wave of the forward kernel) and writes
+        // each next stage input straight into the chunk's history.
+        constexpr int NB = TP::NB, NQ = TP::NQ;
+        const BodyConst<T, TP> c = body_const<T, TP>(ax.iv, mc, lane);
+        BodyRK<T> bs;
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) bs.xb[kk] = bs.xs[kk] = bs.xa[kk] = T(0);
         for (int t = 0; t < nsteps; ++t) {
             int u = -1, q0 = 0, q1 = 0;   // record stages [q0, q1) of chunk u
             if (t == 0) {
@@ -557,25 +565,46 @@ __device__ __forceinline__ void adjoint_item4(AdjShared<T, TP, 4>& ax, const Adj
                 const int g = nseg - 1 - u;
                 T(*hist)[NX] = ax.hist[u & 1];
                 for (int q = q0; q < q1; ++q) {
-                    if (q == 0) {
+                    if (q == 0 && lane < NB) {
+                        const T* ck = f.ckpt + (int64_t)g * NX * ldi + k;
 #pragma unroll
-                        for (int i = 0; i < 2; ++i) {
-                            const int r = lane + 64 * i;
-                            rs.xb[i] = r < NX ? f.ckpt[((int64_t)g * NX + r) * ldi + k] : T(0);
-                            rs.xa[i] = T(0);
-                            if (r < NXT) ax.scr.ns[r] = rs.xb[i];
+                        for (int kk = 0; kk < 3; ++kk) {
+                            bs.xb[kk] = ck[(3 * c.b + kk) * ldi];
+                            bs.xb[3 + kk] = ck[(NQ + 3 * c.b + kk) * ldi];
                         }
-                        wave_lds_sync();
+#pragma unroll
+                        for (int kk = 0; kk < 6; ++kk) {
+                            bs.xs[kk] = bs.xb[kk];
+                            bs.xa[kk] = T(0);
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk) {
+                            hist[0][3 * c.b + kk] = bs.xs[kk];
+                            hist[0][NQ + 3 * c.b + kk] = bs.xs[3 + kk];
+                        }
                     }
                     const int jj = q >> 2, st = q & 3, j = g * Cs + jj;
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        const int r = lane + 64 * i;
-                        if (r < NX) hist[q][r] = ax.scr.ns[r];
-                    }
                     const T tau = (T(j) + T(stage_c(st))) / T(K);
-                    rhs_eval<T, TP, LEAN>(ax.iv, ax.scr, mc, lane, tau, (T*)nullptr);
-                    rk_rows<T, TP, NX>(ax.iv, ax.scr, rs, lane, st, ax.scr.ns, (T*)nullptr);
+                    // the state after the segment's last stage is not needed
+                    T* nxt = q + 1 < S4 ? hist[q + 1] : ax.scr.ns;
+                    switch (st) {
+                        case 0:
+                            state_stage<T, TP, 0>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                                  ax.scr.fn, lane);
+                            break;
+                        case 1:
+                            state_stage<T, TP, 1>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                                  ax.scr.fn, lane);
+                            break;
+                        case 2:
+                            state_stage<T, TP, 2>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                                  ax.scr.fn, lane);
+                            break;
+                        default:
+                            state_stage<T, TP, 3>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                                  ax.scr.fn, lane);
+                            break;
+                    }
                 }
                 wave_lds_sync();
             }
