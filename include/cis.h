@@ -261,7 +261,7 @@ enum { CIS_SCHED_GRID = 1, CIS_SCHED_PERSISTENT = 2, CIS_SCHED_TUNE = 3 };
 
 /* Optional bits of `sched` fixing the form of the reverse sweep (waves per
  * interval) instead of the default: timed at creation with CIS_SCHED_TUNE,
- * else four waves.  4: two waves evaluate alternate stages ahead of the
+ * else three waves.  4: two waves evaluate alternate stages ahead of the
  * reverse sweep, each evaluation spread over two pipeline steps; 3: one wave
  * evaluates each stage one step ahead (4 and 3 need checkpoints at most 8
  * substeps apart, else 2 is used); 2: replay one chunk ahead; 1: one wave

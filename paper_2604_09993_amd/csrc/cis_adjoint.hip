@@ -387,6 +387,91 @@ __device__ __forceinline__ void adjoint_item(AdjShared<T, TP>& ax, const AdjArgs
     adjoint_outputs<T, TP>(ax, a, k, lane, xbar, sacc, uacc, muacc, macc);
 }
 
+// Body-lane replay wave of the four-wave reverse sweep (checkpoints at most
+// CHUNK substeps apart): at step 0 it records the stage inputs of the last
+// checkpoint segment, then one stage per step those of the segment before,
+// into the other history buffer.  (The three-wave form keeps the
+// element-lane replay: fewer registers, which batches need for occupancy.)
+template <class T, class TP, int NS>
+__device__ __forceinline__ void replay_wave(AdjShared<T, TP, NS>& ax, const FwdArgs<T>& f,
+                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                            const int k, const int lane, const int nsteps) {
+    constexpr int NX = TP::NX;
+    const int64_t ldi = f.ldi;
+    const int K = f.K, Cs = f.C;
+    const int nseg = K / Cs, S4 = 4 * Cs;
+    const int nst = 4 * K;
+    // One lane per body runs the nominal RK4 stages (the state wave of the
+    // forward kernel) and writes each next stage input straight into the
+    // chunk's history; one workgroup barrier per step.
+    constexpr int NB = TP::NB, NQ = TP::NQ;
+    const BodyConst<T, TP> c = body_const<T, TP>(ax.iv, mc, lane);
+    BodyRK<T> bs;
+#pragma unroll
+    for (int kk = 0; kk < 6; ++kk) bs.xb[kk] = bs.xs[kk] = bs.xa[kk] = T(0);
+    for (int t = 0; t < nsteps; ++t) {
+        int u = -1, q0 = 0, q1 = 0;   // record stages [q0, q1) of chunk u
+        if (t == 0) {
+            u = 0;
+            q1 = S4;
+        } else if (t <= nst) {
+            const int r = t - 1;
+            u = r / S4 + 1;
+            q0 = r % S4;
+            q1 = q0 + 1;
+            if (u >= nseg) u = -1;
+        }
+        if (u >= 0) {
+            const int g = nseg - 1 - u;
+            T(*hist)[NX] = ax.hist[u & 1];
+            for (int q = q0; q < q1; ++q) {
+                if (q == 0 && lane < NB) {
+                    const T* ck = f.ckpt + (int64_t)g * NX * ldi + k;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) {
+                        bs.xb[kk] = ck[(3 * c.b + kk) * ldi];
+                        bs.xb[3 + kk] = ck[(NQ + 3 * c.b + kk) * ldi];
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 6; ++kk) {
+                        bs.xs[kk] = bs.xb[kk];
+                        bs.xa[kk] = T(0);
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) {
+                        hist[0][3 * c.b + kk] = bs.xs[kk];
+                        hist[0][NQ + 3 * c.b + kk] = bs.xs[3 + kk];
+                    }
+                }
+                const int jj = q >> 2, st = q & 3, j = g * Cs + jj;
+                const T tau = (T(j) + T(stage_c(st))) / T(K);
+                // the state after the segment's last stage is not needed
+                T* nxt = q + 1 < S4 ? hist[q + 1] : ax.scr.ns;
+                switch (st) {
+                    case 0:
+                        state_stage<T, TP, 0>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                              ax.scr.fn, lane);
+                        break;
+                    case 1:
+                        state_stage<T, TP, 1>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                              ax.scr.fn, lane);
+                        break;
+                    case 2:
+                        state_stage<T, TP, 2>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                              ax.scr.fn, lane);
+                        break;
+                    default:
+                        state_stage<T, TP, 3>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
+                                              ax.scr.fn, lane);
+                        break;
+                }
+            }
+            wave_lds_sync();
+        }
+        __syncthreads();
+    }
+}
+
 // Checkpoints at most CHUNK substeps apart (one chunk per segment, 4C stages
 // each): three waves pipelined stage by stage, one workgroup barrier per step.
 // With r the stage index counted backwards from the end of the interval:
@@ -514,8 +599,8 @@ __device__ __forceinline__ void adjoint_item3(AdjShared<T, TP>& ax, const AdjArg
     adjoint_outputs<T, TP>(ax, a, k, lane, xbar, sacc, uacc, muacc, macc);
 }
 
-// Checkpoints at most CHUNK substeps apart, four waves: the replay wave as in
-// the three-wave form; two evaluation waves take alternate reverse stages,
+// Checkpoints at most CHUNK substeps apart, four waves: the replay wave; two
+// evaluation waves take alternate reverse stages,
 // each evaluation spanning two pipeline steps (a workgroup barrier between its
 // element wrenches and its smooth functions); the reverse wave applies stage
 // r at step r + 3.  Four evaluation slots: at step t the reverse reads r = t-3
@@ -540,76 +625,7 @@ __device__ __forceinline__ void adjoint_item4(AdjShared<T, TP, 4>& ax, const Adj
     const int nseg = K / Cs, S4 = 4 * Cs;
     const int nst = 4 * K, nsteps = nst + 3;
     if (wave == 1) {
-        // ---------------- replay wave: body lanes ----------------
-        // Same schedule as the three-wave form; one lane per body runs the
-        // nominal RK4 stages (the state wave of the forward kernel) and writes
-        // each next stage input straight into the chunk's history.
-        constexpr int NB = TP::NB, NQ = TP::NQ;
-        const BodyConst<T, TP> c = body_const<T, TP>(ax.iv, mc, lane);
-        BodyRK<T> bs;
-#pragma unroll
-        for (int kk = 0; kk < 6; ++kk) bs.xb[kk] = bs.xs[kk] = bs.xa[kk] = T(0);
-        for (int t = 0; t < nsteps; ++t) {
-            int u = -1, q0 = 0, q1 = 0;   // record stages [q0, q1) of chunk u
-            if (t == 0) {
-                u = 0;
-                q1 = S4;
-            } else if (t <= nst) {
-                const int r = t - 1;
-                u = r / S4 + 1;
-                q0 = r % S4;
-                q1 = q0 + 1;
-                if (u >= nseg) u = -1;
-            }
-            if (u >= 0) {
-                const int g = nseg - 1 - u;
-                T(*hist)[NX] = ax.hist[u & 1];
-                for (int q = q0; q < q1; ++q) {
-                    if (q == 0 && lane < NB) {
-                        const T* ck = f.ckpt + (int64_t)g * NX * ldi + k;
-#pragma unroll
-                        for (int kk = 0; kk < 3; ++kk) {
-                            bs.xb[kk] = ck[(3 * c.b + kk) * ldi];
-                            bs.xb[3 + kk] = ck[(NQ + 3 * c.b + kk) * ldi];
-                        }
-#pragma unroll
-                        for (int kk = 0; kk < 6; ++kk) {
-                            bs.xs[kk] = bs.xb[kk];
-                            bs.xa[kk] = T(0);
-                        }
-#pragma unroll
-                        for (int kk = 0; kk < 3; ++kk) {
-                            hist[0][3 * c.b + kk] = bs.xs[kk];
-                            hist[0][NQ + 3 * c.b + kk] = bs.xs[3 + kk];
-                        }
-                    }
-                    const int jj = q >> 2, st = q & 3, j = g * Cs + jj;
-                    const T tau = (T(j) + T(stage_c(st))) / T(K);
-                    // the state after the segment's last stage is not needed
-                    T* nxt = q + 1 < S4 ? hist[q + 1] : ax.scr.ns;
-                    switch (st) {
-                        case 0:
-                            state_stage<T, TP, 0>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
-                                                  ax.scr.fn, lane);
-                            break;
-                        case 1:
-                            state_stage<T, TP, 1>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
-                                                  ax.scr.fn, lane);
-                            break;
-                        case 2:
-                            state_stage<T, TP, 2>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
-                                                  ax.scr.fn, lane);
-                            break;
-                        default:
-                            state_stage<T, TP, 3>(ax.iv, mc, c, bs, tau, nxt, ax.scr.cs,
-                                                  ax.scr.fn, lane);
-                            break;
-                    }
-                }
-                wave_lds_sync();
-            }
-            __syncthreads();
-        }
+        replay_wave<T, TP>(ax, f, mc, k, lane, nsteps);
         return;
     }
     if (wave >= 2) {

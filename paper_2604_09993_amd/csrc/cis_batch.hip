@@ -441,7 +441,7 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             int cmax_g = 1;
             for (int i : g.trajs) cmax_g = std::max(cmax_g, p->ckpt_every[i]);
             // reverse sweep with 4, 3, 2 or 1 waves per interval (latency vs
-            // throughput): timed when tuning, else the four-wave form
+            // throughput): timed when tuning, else the three-wave form
             KLaunch adjv[4];
             for (int w = 0; w < 4 && st == CIS_OK; ++w)
                 st = prep_adjoint_batch(g.model, g.dev, cmax_g, 4 - w, &adjv[w]);
@@ -449,7 +449,7 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
                 plan_free(p);
                 return st;
             }
-            int best = adj_force ? 4 - adj_force : 0;
+            int best = adj_force ? 4 - adj_force : 1;
             if (sched == CIS_SCHED_TUNE && !adj_force) {
                 if (g.def.launch(hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess) {
                     plan_free(p);
