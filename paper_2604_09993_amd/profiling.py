@@ -138,6 +138,7 @@ def bench_algorithmic_bytes():
     out[f"k_discretize<double, {t}"] = N * interval_bytes(model, K, "discretize")
     out[f"k_discretize<float, {t}"] = N * interval_bytes(model, K, "discretize", dsize=4)
     out[f"k_defects<double, {t}"] = N * interval_bytes(model, K, "defects", C=5)
+    out[f"k_adjoint4<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
     out[f"k_adjoint3<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
     out[f"k_adjoint<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
     groups = {}
@@ -149,6 +150,7 @@ def bench_algorithmic_bytes():
         out[f"k_discretize_batch<double, {t}"] = tot("discretize")
         out[f"k_defects_batch<double, {t}"] = tot("defects", auto_ckpt)
         out[f"k_defects_lane_batch<double, {t}"] = tot("defects", auto_ckpt)
+        out[f"k_adjoint4_batch<double, {t}"] = tot("adjoint", auto_ckpt)
         out[f"k_adjoint3_batch<double, {t}"] = tot("adjoint", auto_ckpt)
         out[f"k_adjoint_batch<double, {t}"] = tot("adjoint", auto_ckpt)
     qb = synth.config_batch(5)
