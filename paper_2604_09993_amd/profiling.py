@@ -139,7 +139,6 @@ def bench_algorithmic_bytes():
     out[f"k_discretize<float, {t}"] = N * interval_bytes(model, K, "discretize", dsize=4)
     out[f"k_defects<double, {t}"] = N * interval_bytes(model, K, "defects", C=5)
     out[f"k_adjoint4<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
-    out[f"k_adjoint3<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
     out[f"k_adjoint<double, {t}"] = N * interval_bytes(model, K, "adjoint", C=5)
     groups = {}
     for m_, d, k in synth.mixed_batch():
