@@ -68,21 +68,18 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP, NS>& ax, RhsScrat
     else wave_lds_sync();
     const T omt = T(1) - tau;
     const T lc = ax.kb[NX + NC];
-    // phase A: element lanes scatter into their slots; control adjoints
-    if (lane < NJ) {
-        const int j = lane, p = TP::parent(j), c = j + 1;
+    // phase A: element lanes scatter into their slots; control adjoints.  The
+    // joint and the contact terms are formed on every lane (element index
+    // clamped to a valid one) so that their loads issue together; only the
+    // owning lanes store and accumulate.
+    const bool jl = lane < NJ, cl = lane >= NJ && lane < NJ + NC;
+    if constexpr (NJ > 0) {
+        const int j = jl ? lane : 0, p = TP::parent(j), c = j + 1;
         const T gp = ax.kb[NQ + 3 * p + 2], gc = ax.kb[NQ + 3 * c + 2];
         const T t1 = iv.kc[j][0] * gp - iv.kc[j][2] * gc;
         const T t2 = iv.kc[j][1] * gp - iv.kc[j][3] * gc;
         const T* jh = cf + C::JH + 4 * j;
-        ax.jslot[j][0] = -t1 + jh[2] * lc;
-        ax.jslot[j][1] = t1 + jh[3] * lc;
-        ax.jslot[j][2] = -t2;
-        ax.jslot[j][3] = t2;
-        ax.jslot[j][4] = jh[0] * lc;
-        ax.jslot[j][5] = -jh[0] * lc;
-        ax.jslot[j][6] = jh[1] * lc;
-        ax.jslot[j][7] = -jh[1] * lc;
+        const T jh0 = jh[0], jh1 = jh[1], jh2 = jh[2], jh3 = jh[3];
         const T* gv = cf + C::GV;
         const T kxp = ax.kb[NQ + 3 * p], kyp = ax.kb[NQ + 3 * p + 1];
         const T kxc = ax.kb[NQ + 3 * c], kyc = ax.kb[NQ + 3 * c + 1];
@@ -92,36 +89,56 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP, NS>& ax, RhsScrat
                       gv[(3 * p + 2) * M + ux] * gp + gv[(3 * c + 2) * M + ux] * gc;
         const T ayy = gv[(3 * p + 1) * M + uy] * kyp + gv[(3 * c + 1) * M + uy] * kyc +
                       gv[(3 * p + 2) * M + uy] * gp + gv[(3 * c + 2) * M + uy] * gc;
-        uacc[0][0] += omt * at;  uacc[0][1] += tau * at;
-        uacc[1][0] += omt * axx; uacc[1][1] += tau * axx;
-        uacc[2][0] += omt * ayy; uacc[2][1] += tau * ayy;
-    } else if (lane < NJ + NC) {
-        const int i = lane - NJ, b = TP::cbody(i);
+        if (jl) {
+            ax.jslot[j][0] = -t1 + jh2 * lc;
+            ax.jslot[j][1] = t1 + jh3 * lc;
+            ax.jslot[j][2] = -t2;
+            ax.jslot[j][3] = t2;
+            ax.jslot[j][4] = jh0 * lc;
+            ax.jslot[j][5] = -jh0 * lc;
+            ax.jslot[j][6] = jh1 * lc;
+            ax.jslot[j][7] = -jh1 * lc;
+            uacc[0][0] += omt * at;  uacc[0][1] += tau * at;
+            uacc[1][0] += omt * axx; uacc[1][1] += tau * axx;
+            uacc[2][0] += omt * ayy; uacc[2][1] += tau * ayy;
+        }
+    }
+    if constexpr (NC > 0) {
+        const int i = cl ? lane - NJ : 0, b = TP::cbody(i);
         const T* ct = cf + C::CT + C::NCT * i;
         const T kx = ax.kb[NQ + 3 * b], ky = ax.kb[NQ + 3 * b + 1], kw = ax.kb[NQ + 3 * b + 2];
         const T kcc = ax.kb[NX + i];
         const T pbx = ct[C_FXP] * kx + ct[C_FYP] * ky + ct[C_TP] * kw + ct[C_EPX] * kcc +
                       ct[C_ZPX] * lc;
         const T pby = ct[C_EPY] * kcc + ct[C_ZPY] * lc;
-        ax.cslot[i][0] = pbx;
-        ax.cslot[i][1] = pby;
-        ax.cslot[i][2] = -ct[C_AY] * pbx + ct[C_AX] * pby + ct[C_ETH] * kcc;
-        ax.cslot[i][3] = ct[C_EXD] * kcc;
-        ax.cslot[i][4] = ct[C_EYD] * kcc;
-        ax.cslot[i][5] = ct[C_EOM] * kcc;
+        const T c2 = -ct[C_AY] * pbx + ct[C_AX] * pby + ct[C_ETH] * kcc;
+        const T c3 = ct[C_EXD] * kcc, c4 = ct[C_EYD] * kcc, c5 = ct[C_EOM] * kcc;
+        const T jmu = ct[C_JMU] * kcc;
         const T* gv = cf + C::GV;
         const T* gc = cf + C::GC + i * M;
         const int u0 = 3 * NJ + 3 * i;
+        T inst[3], bar[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int u = u0 + q;
-            const T inst = gv[(3 * b) * M + u] * kx + gv[(3 * b + 1) * M + u] * ky +
-                           gv[(3 * b + 2) * M + u] * kw;
-            const T bar = gc[u] * kcc;
-            uacc[q][0] += omt * inst + bar;
-            uacc[q][1] += tau * inst + bar;
+            inst[q] = gv[(3 * b) * M + u] * kx + gv[(3 * b + 1) * M + u] * ky +
+                      gv[(3 * b + 2) * M + u] * kw;
+            bar[q] = gc[u] * kcc;
         }
-        muacc += ct[C_JMU] * kcc;
+        if (cl) {
+            ax.cslot[i][0] = pbx;
+            ax.cslot[i][1] = pby;
+            ax.cslot[i][2] = c2;
+            ax.cslot[i][3] = c3;
+            ax.cslot[i][4] = c4;
+            ax.cslot[i][5] = c5;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                uacc[q][0] += omt * inst[q] + bar[q];
+                uacc[q][1] += tau * inst[q] + bar[q];
+            }
+            muacc += jmu;
+        }
     }
     wave_lds_sync();
     // phase B: body lanes gather their slots into Xbar of the stage
@@ -189,7 +206,11 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP, NS>& ax, RhsScrat
             sacc += F * ax.kb[r];
         }
     }
-    wave_lds_sync();
+    // With EVAL the next stage's evaluation rewrites sc, read above by other
+    // lanes.  Without it the callers pass a workgroup barrier before the next
+    // stage, and the only LDS the next stage writes before its first wave sync
+    // is each lane's own kb rows, read above by the same lane.
+    if constexpr (EVAL) wave_lds_sync();
 }
 
 // Outputs of the reverse wave: gX_k, the control partials of interval k
