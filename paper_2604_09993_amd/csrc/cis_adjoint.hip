@@ -145,18 +145,6 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP, NS>& ax, RhsScrat
     if (lane < NB) {
         const int b = lane;
         T xq = T(0), yq = T(0), th = T(0), xd = T(0), yd = T(0), om = T(0);
-        auto as_parent = [&](int j) {
-            th += ax.jslot[j][0];
-            om += ax.jslot[j][2];
-            xq += ax.jslot[j][4];
-            yq += ax.jslot[j][6];
-        };
-        auto as_child = [&](int j) {
-            th += ax.jslot[j][1];
-            om += ax.jslot[j][3];
-            xq += ax.jslot[j][5];
-            yq += ax.jslot[j][7];
-        };
         auto contact = [&](int i) {
             xq += ax.cslot[i][0];
             yq += ax.cslot[i][1];
@@ -165,16 +153,41 @@ __device__ __forceinline__ void reverse_stage(AdjShared<T, TP, NS>& ax, RhsScrat
             yd += ax.cslot[i][4];
             om += ax.cslot[i][5];
         };
-        if (b == 0) {
+        if constexpr (TP::D > 0) {
+            // every lane reads the slots of all its possible elements (torso:
+            // the L first joints; link: its own joint, the next joint or its
+            // contact) so that the loads issue together; weights keep the
+            // owning ones (x + 0 == x, so the sums are those of the owners)
+            constexpr int D = TP::D;
+            const bool link = b >= 1;
+            const bool has_next = link && b % D != 0, foot = link && b % D == 0;
+            auto take = [&](bool on, const T* e, int i0, int i1, int i2, int i3) {
+                const T w = on ? T(1) : T(0);
+                th += w * e[i0];
+                om += w * e[i1];
+                xq += w * e[i2];
+                yq += w * e[i3];
+            };
+            take(link, ax.jslot[link ? b - 1 : 0], 1, 3, 5, 7);   // own joint, as child
 #pragma unroll
-            for (int l = 0; l < TP::L; ++l) {
-                if (TP::D > 0) as_parent(l * TP::D);
-                else contact(l);
+            for (int l = 0; l < TP::L; ++l) {                       // as parent
+                const bool on = link ? (l == 0 && has_next) : true;
+                const int j = link ? (has_next ? b : 0) : l * D;
+                take(on, ax.jslot[j], 0, 2, 4, 6);
             }
-        } else if constexpr (TP::D > 0) {
-            as_child(b - 1);
-            if (b % TP::D != 0) as_parent(b);
-            else contact(b / TP::D - 1);
+            {
+                const int i = foot ? b / D - 1 : 0;
+                const T w = foot ? T(1) : T(0);
+                xq += w * ax.cslot[i][0];
+                yq += w * ax.cslot[i][1];
+                th += w * ax.cslot[i][2];
+                xd += w * ax.cslot[i][3];
+                yd += w * ax.cslot[i][4];
+                om += w * ax.cslot[i][5];
+            }
+        } else if (b == 0) {
+#pragma unroll
+            for (int l = 0; l < TP::L; ++l) contact(l);
         }
         const T gw = ax.kb[NQ + 3 * b + 2];
         ax.xbs[3 * b] = xq;
