@@ -328,6 +328,10 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     sabs_d(a1, v1, d1);
     sabs_d(a2, v2, d2);
     sabs_d(a3, v3, d3);
+    // SPLIT: the stage spans two pipeline steps.  FP32 takes the workgroup
+    // barrier here, between the smooth functions and the integrands (the two
+    // steps balance better, measured faster); FP64 after the evaluation.
+    if constexpr (SPLIT && sizeof(T) == 4) __syncthreads();
     // integrands (Sec. III pairs; violation: |h|_s of joints, ramp_s(-sd))
     const T lnb = T(0.5) * (c.ck[0] + c.ck1[0]);
     const T ltpb = T(0.5) * (c.ck[1] + c.ck1[1]);
@@ -352,7 +356,9 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
     const T dvt_px = dtx * Pdx + dty * Pdy;
     const T im = s * c.mi, ii = s * c.ii;
-    // everything the stores need from LDS is read before the split
+    // what the stores need from LDS (FP64: read before the split barrier; the
+    // rings hold this stage's entries until the state wave's step t+3, after
+    // both steps of the stage)
     const T ip = s * iv.iinv[p];
     T fq[3], fa[3];
 #pragma unroll
@@ -360,9 +366,7 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         fq[k] = xs[NQ + 3 * b + k];
         fa[k] = fv[3 * b + k];
     }
-    // SPLIT: the stage spans two pipeline steps; the workgroup barrier between
-    // them is taken here, after the evaluation and before the stores
-    if constexpr (SPLIT) __syncthreads();
+    if constexpr (SPLIT && sizeof(T) == 8) __syncthreads();
     if constexpr (WRITE) {
         // FP64: all values and addresses are formed first and stored in one
         // burst, since a register overwritten right after an LDS store waits
