@@ -72,7 +72,7 @@ __device__ __forceinline__ T column_sum(T v) {
     }
 }
 
-template <class T, class TP, int ST>
+template <class T, class TP, int ST, bool HF>
 __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T, TP>& z,
                                               const T* __restrict__ cf, T tau, int leg, T wbm,
                                               T wbp, T fsel, T fct, int ctrl) {
@@ -144,12 +144,13 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
                 kv[3 * lb + k] += wB * cf[C::GV + (3 * gb(lb) + k) * M + ctrl];
         if constexpr (L >= 1) kcc += wG * cf[C::GC + leg * M + ctrl];
     }
+    if constexpr (HF) {
 #pragma unroll
-    for (int lb = 0; lb < LB; ++lb)
+        for (int lb = 0; lb < LB; ++lb)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) kv[3 * lb + k] += fsel * cf[C::F + NQ + 3 * gb(lb) + k];
-    if constexpr (L >= 1) kcc += fsel * cf[C::F + NX + leg];
-    {   // violation row: per-body parts of the own bodies (torso on leg 0 only)
+            for (int k = 0; k < 3; ++k) kv[3 * lb + k] += fsel * cf[C::F + NQ + 3 * gb(lb) + k];
+        if constexpr (L >= 1) kcc += fsel * cf[C::F + NX + leg];
+        // violation row: per-body parts of the own bodies (torso on leg 0 only)
         T vp = fct * cf[C::CTP];
 #pragma unroll
         for (int lb = 1; lb < LB; ++lb) vp += fsel * cf[C::CTP + gb(lb)];
@@ -164,7 +165,8 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int r = 3 * lb + k;
-            const T kq = s * z.zs[3 * LB + r] + fsel * cf[C::F + 3 * gb(lb) + k];
+            T kq = s * z.zs[3 * LB + r];
+            if constexpr (HF) kq += fsel * cf[C::F + 3 * gb(lb) + k];
             if (ST == 0) z.za[r] = kq;
             else z.za[r] += T(WK) * kq;
             if (ST < 3) z.zs[r] = z.zb[r] + an * kq;
@@ -190,6 +192,100 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 #undef ZV
 }
 
+// The dilation column S on body lanes (its own column group in the latency
+// layout): lane b < NB holds the six rows of body b; a foot lane holds the
+// cross-complementarity row of its contact (the torso lane all of them when
+// the legs have no links); every body lane integrates its part of the
+// violation row.  The Jacobian product is that of the tangent lanes with the
+// joint terms exchanged between parent and child lanes, plus the F~ forcing.
+template <class T, class TP>
+struct SLane {
+    static constexpr int NCL = TP::D == 0 ? (TP::L > 0 ? TP::L : 1) : 1;   // cc rows per lane
+    T zs[6], zb[6], za[6];
+    T ycc[NCL], yct;
+};
+
+template <class T, class TP, int ST>
+__device__ __forceinline__ void s_stage(const Interval<T, TP>& iv, const BodyConst<T, TP>& c,
+                                        SLane<T, TP>& z, const T* __restrict__ cf, int lane) {
+    constexpr int NB = TP::NB, NQ = TP::NQ, NX = TP::NX, D = TP::D, L = TP::L;
+    constexpr int NCL = SLane<T, TP>::NCL;
+    using C = Coef<TP>;
+    const T s = iv.s, h = iv.h;
+    const int b = c.b;
+    const T x = z.zs[0], y = z.zs[1], th = z.zs[2];
+    const T vx = z.zs[3], vy = z.zs[4], om = z.zs[5];
+    T kv[3] = {cf[C::F + NQ + 3 * b], cf[C::F + NQ + 3 * b + 1],
+               cf[C::F + NQ + 3 * b + 2] + cf[C::CTH + b] * th};
+    T kct = lane < NB ? cf[C::CTP + b] : T(0);
+    T kcc[NCL];
+#pragma unroll
+    for (int l = 0; l < NCL; ++l) kcc[l] = T(0);
+    if constexpr (D >= 1) {
+        // own joint (this body is its child): stiffness and damping, and the
+        // joint rows of the violation integrand; the parent's share of the
+        // stiffness and damping torque goes back to the parent lane
+        const bool pt = c.p == 0;
+        const T thp = from_parent<TP>(th, pt), omp = from_parent<TP>(om, pt);
+        const T xp = from_parent<TP>(x, pt), yp = from_parent<TP>(y, pt);
+        T tp = T(0);
+        if (c.joint) {
+            const int j = c.j;
+            const T dth = th - thp, dom = om - omp;
+            kv[2] -= iv.kc[j][2] * dth + iv.kc[j][3] * dom;
+            tp = iv.kc[j][0] * dth + iv.kc[j][1] * dom;
+            const T* jh = cf + C::JH + 4 * j;
+            kct += jh[0] * (xp - x) + jh[1] * (yp - y) + jh[2] * thp + jh[3] * th;
+        }
+        kv[2] += from_children<TP>(tp, b);
+    }
+    if constexpr (L >= 1) {
+#pragma unroll
+        for (int l = 0; l < NCL; ++l) {
+            const bool on = D >= 1 ? c.contact : (lane == 0);
+            const int i = D >= 1 ? c.i : l;
+            if (on) {
+                const T* ct = cf + C::CT + C::NCT * i;
+                const T dPx = x - ct[C_AY] * th;
+                const T dPy = y + ct[C_AX] * th;
+                kv[0] += ct[C_FXP] * dPx;
+                kv[1] += ct[C_FYP] * dPx;
+                kv[2] += ct[C_TP] * dPx;
+                kcc[l] = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * vx + ct[C_EYD] * vy +
+                         ct[C_EOM] * om + ct[C_ETH] * th + cf[C::F + NX + i];
+                kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
+            }
+        }
+    }
+    // classical RK4 combination (stage ST known at compile time)
+    constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
+    const T an = (ST == 2) ? h : T(0.5) * h;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T kq = s * z.zs[3 + k] + cf[C::F + 3 * b + k];
+        if (ST == 0) z.za[k] = kq;
+        else z.za[k] += T(WK) * kq;
+        if (ST < 3) z.zs[k] = z.zb[k] + an * kq;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (ST == 0) z.za[3 + k] = kv[k];
+        else z.za[3 + k] += T(WK) * kv[k];
+        if (ST < 3) z.zs[3 + k] = z.zb[3 + k] + an * kv[k];
+    }
+    const T h6 = iv.h6;
+#pragma unroll
+    for (int l = 0; l < NCL; ++l) z.ycc[l] += (h6 * T(WK)) * kcc[l];
+    z.yct += (h6 * T(WK)) * kct;
+    if (ST == 3) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            z.zb[r] += h6 * z.za[r];
+            z.zs[r] = z.zb[r];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K2: discretize.  One workgroup per (interval, column group), three wave roles
 // separated by one workgroup barrier per pipeline step:
@@ -211,6 +307,9 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 // than four waves holds every wave to 256 registers.
 template <class T, int L, int D>
 using LatencyTopo = Topo<L, D, sizeof(T) == 8 ? 1 : 5, 2>;
+// the latency layout with the S column on leg lanes (one column group fewer)
+template <class T, int L, int D>
+using LatencyTopoS = Topo<L, D, sizeof(T) == 8 ? 1 : 5, 2, false>;
 template <class T, int L, int D>
 using NarrowTopo = Topo<L, D, sizeof(T) == 8 ? 2 : 6, 1>;
 template <class T, int L, int D>
@@ -371,6 +470,55 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
             }
         }
     } else {
+        if constexpr (TP::SEP_S) {
+            if (grp == TP::NGRPT) {
+                // ---------- the S column on body lanes (first wave of the group) ----------
+                if (wave != 0) {
+                    for (int t = 0; t < LAG + 4 * Kb + (NCW > 1 ? 1 : 0); ++t) __syncthreads();
+                    return;
+                }
+                const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+                SLane<T, TP> z;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) z.zs[r] = z.zb[r] = z.za[r] = T(0);
+#pragma unroll
+                for (int l = 0; l < SLane<T, TP>::NCL; ++l) z.ycc[l] = T(0);
+                z.yct = T(0);
+#pragma unroll
+                for (int t = 0; t < LAG; ++t) __syncthreads();
+                for (int j = 0; j < Kb; ++j) {
+                    s_stage<T, TP, 0>(sh.iv, c, z, sh.coef[0], lane);
+                    __syncthreads();
+                    s_stage<T, TP, 1>(sh.iv, c, z, sh.coef[1], lane);
+                    __syncthreads();
+                    s_stage<T, TP, 2>(sh.iv, c, z, sh.coef[2 % NCOEF], lane);
+                    __syncthreads();
+                    s_stage<T, TP, 3>(sh.iv, c, z, sh.coef[3 % NCOEF], lane);
+                    __syncthreads();
+                }
+                if constexpr (NCW > 1) __syncthreads();   // the integral-row hand-over step
+                T yct = T(0);
+#pragma unroll
+                for (int e = 0; e < NB; ++e) yct += lane_value(z.yct, e);
+                if (lane < NB) {
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) {
+                        a.S[(int64_t)(3 * c.b + kk) * ldi + k] = z.zb[kk];
+                        a.S[(int64_t)(NQ + 3 * c.b + kk) * ldi + k] = z.zb[3 + kk];
+                    }
+                    if constexpr (L >= 1) {
+#pragma unroll
+                        for (int l = 0; l < SLane<T, TP>::NCL; ++l) {
+                            const bool on = D >= 1 ? c.contact : (lane == 0);
+                            const int i = D >= 1 ? c.i : l;
+                            if (on) a.S[(int64_t)(NX + i) * ldi + k] = z.ycc[l];
+                        }
+                    }
+                    if (lane == 0) a.S[(int64_t)(NX + NC) * ldi + k] = yct;
+                }
+                return;
+            }
+        }
         // ---------------- tangent waves: stage t-LAG at step t ----------------
         const int col = grp * TP::CPG + (wave * 64 + lane) / G;
         const int leg = G == 1 ? 0 : (lane & (G - 1));
@@ -405,20 +553,20 @@ __device__ __forceinline__ void discretize_item(DiscShared<T, TP>& sh, const Fwd
         for (int j = 0; j < Kb; ++j) {
             const T jt = T(j0 + j);
             const T tau0 = jt / Kt, tauh = (jt + T(0.5)) / Kt, tau1 = (jt + T(1)) / Kt;
-            tangent_stage<T, TP, 0>(sh.iv, z, sh.coef[0], tau0, leg, wbm, wbp, fsel, fct, ctrl);
+            tangent_stage<T, TP, 0, !TP::SEP_S>(sh.iv, z, sh.coef[0], tau0, leg, wbm, wbp, fsel, fct, ctrl);
             __syncthreads();
-            tangent_stage<T, TP, 1>(sh.iv, z, sh.coef[1], tauh, leg, wbm, wbp, fsel, fct, ctrl);
+            tangent_stage<T, TP, 1, !TP::SEP_S>(sh.iv, z, sh.coef[1], tauh, leg, wbm, wbp, fsel, fct, ctrl);
             __syncthreads();
-            tangent_stage<T, TP, 2>(sh.iv, z, sh.coef[2 % NCOEF], tauh, leg, wbm, wbp, fsel, fct,
+            tangent_stage<T, TP, 2, !TP::SEP_S>(sh.iv, z, sh.coef[2 % NCOEF], tauh, leg, wbm, wbp, fsel, fct,
                                     ctrl);
             __syncthreads();
-            tangent_stage<T, TP, 3>(sh.iv, z, sh.coef[3 % NCOEF], tau1, leg, wbm, wbp, fsel, fct,
+            tangent_stage<T, TP, 3, !TP::SEP_S>(sh.iv, z, sh.coef[3 % NCOEF], tau1, leg, wbm, wbp, fsel, fct,
                                     ctrl);
             __syncthreads();
         }
         if constexpr (NCW > 1) __syncthreads();   // the integral-row hand-over step
         const T yct = column_sum<G>(z.yct);
-        if (col < TP::NCOL) {
+        if (col < TP::NCOLT) {
             T* out;
             int64_t cstride, c0;   // element (row, column) at out[(row * cstride + c0) * ldi + k]
             if (col < NX) { out = a.A; cstride = NXT; c0 = col; }
@@ -728,20 +876,23 @@ static cis_status launch_discretize_as(const cis_model* m, const cis_shape* sh, 
     return CIS_OK;
 }
 
-// One trajectory: the latency layout while every (interval, column group)
-// workgroup can be resident at once on its own CU, else the narrow layout
-// while that holds for it, the throughput layout beyond.
+// One trajectory: the first layout whose (interval, column group) workgroups
+// can all be resident at once, one per CU: latency (S group of its own), the
+// latency layout with S on leg lanes, narrow; the throughput layout beyond.
 template <class T, int L, int D>
 static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, const void* X,
                                     const void* U, const void* s, const void* prm, void* A,
                                     void* Bm, void* Bp, void* S, void* d, void* xp,
                                     hipStream_t stream) {
     using TL = LatencyTopo<T, L, D>;
+    using TLS = LatencyTopoS<T, L, D>;
     using TN = NarrowTopo<T, L, D>;
     using TT = ThroughputTopo<T, L, D>;
     const int cus = device_cus();
     if ((int64_t)sh->N * TL::NGRP <= cus)
         return launch_discretize_as<T, TL>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    if ((int64_t)sh->N * TLS::NGRP <= cus)
+        return launch_discretize_as<T, TLS>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
     if ((int64_t)sh->N * TN::NGRP <= cus)
         return launch_discretize_as<T, TN>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
     return launch_discretize_as<T, TT>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
@@ -788,6 +939,7 @@ static cis_status blocked_passes_t(const cis_model* m, const cis_shape* sh, cons
     a.ld_blk = sh->ld_int;        // checkpoints as written by pass 1
     a.B = B;
     using TL = LatencyTopo<T, L, D>;
+    using TLS = LatencyTopoS<T, L, D>;
     using TN = NarrowTopo<T, L, D>;
     using TT = ThroughputTopo<T, L, D>;
     const int64_t items = (int64_t)B * sh->N;
@@ -803,6 +955,7 @@ static cis_status blocked_passes_t(const cis_model* m, const cis_shape* sh, cons
         return CIS_OK;
     };
     if (items * TL::NGRP <= device_cus()) return launch(TL{});
+    if (items * TLS::NGRP <= device_cus()) return launch(TLS{});
     if (items * TN::NGRP <= device_cus()) return launch(TN{});
     return launch(TT{});
 }

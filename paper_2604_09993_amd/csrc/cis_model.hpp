@@ -27,7 +27,7 @@ namespace cis {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int even(int a) { return (a + 1) & ~1; }
 
-template <int L_, int D_, int TW_MAX_ = 6, int NCW_ = 1>
+template <int L_, int D_, int TW_MAX_ = 6, int NCW_ = 1, bool SEPS_ = (NCW_ == 2)>
 struct Topo {
     static constexpr int L = L_, D = D_;
     static constexpr int NB = 1 + L * D, NJ = L * D, NC = L;
@@ -36,12 +36,19 @@ struct Topo {
     static constexpr int NCOL = NX + 2 * M + 1;   // tangent columns [Phi_x | B- | B+ | S]
     static constexpr int G = L > 1 ? L : 1;       // lanes per tangent column (one per leg)
     static constexpr int LB = D + 1;              // bodies held by one tangent lane
-    static constexpr int NTW_ALL = (NCOL * G + 63) / 64;   // tangent waves per interval
-    // columns are split over NGRP workgroups of at most TW_MAX_ tangent waves
+    // SEP_S (by default with two coefficient waves, the latency layout): the
+    // dilation column S has a column group of its own, integrated on body
+    // lanes by one wave, so the leg-lane tangent waves carry no F~ forcing.
+    static constexpr bool SEP_S = SEPS_;
+    static_assert(!SEPS_ || NCW_ == 2, "the S group is laid out with two coefficient waves");
+    static constexpr int NCOLT = NCOL - (SEP_S ? 1 : 0);   // columns on leg lanes
+    static constexpr int NTW_ALL = (NCOLT * G + 63) / 64;  // leg-lane tangent waves per interval
+    // columns are split over NGRPT workgroups of at most TW_MAX_ tangent waves
     // (TW_MAX_ = 6: two waves per SIMD, 256 VGPRs each; TW_MAX_ = 2: one wave
     // per SIMD and 512 registers, for the FP64 columns)
-    static constexpr int NGRP = (NTW_ALL + TW_MAX_ - 1) / TW_MAX_;
-    static constexpr int NTW = (NTW_ALL + NGRP - 1) / NGRP;  // tangent waves per workgroup
+    static constexpr int NGRPT = (NTW_ALL + TW_MAX_ - 1) / TW_MAX_;
+    static constexpr int NGRP = NGRPT + (SEP_S ? 1 : 0);    // + the S group
+    static constexpr int NTW = (NTW_ALL + NGRPT - 1) / NGRPT;  // tangent waves per workgroup
     static constexpr int CPG = NTW * 64 / G;                  // columns per workgroup
     // coefficient waves: with NCW_ = 2 two waves take alternate stages, each
     // stage spread over two pipeline steps

@@ -123,15 +123,19 @@ def test_discretize_small_fp32(name, N, K):
     check_against_oracle(model, data, K, res, dtype=torch.float32)
 
 
-@pytest.mark.parametrize("N", [300, 110, 30])
+@pytest.mark.parametrize("N", [300, 200, 110, 70, 30, 22])
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", [n for n, _, _ in SMALL])
 def test_discretize_many_intervals_sampled(name, dtype, N):
     """More intervals than the small cases above, which take the latency
-    layout: with 256 CUs, N = 300 takes the throughput layout for every model;
-    N = 110 the narrow FP64 layout for biped5 / cheetah7 (3 column groups in
-    the latency layout, 2 in the narrow one) and N = 30 for quad13 (11 and 6);
-    4 sampled intervals vs the oracle."""
+    layout with the S column in a group of its own.  With 256 CUs (FP64 column
+    groups: latency / latency with S on leg lanes / narrow = 4 / 3 / 2 for
+    biped5 and cheetah7, 12 / 11 / 6 for quad13, 2 / 1 / 1 for hopper):
+    N = 300 takes the throughput layout for every model; N = 200 the latency
+    layout with S on leg lanes for hopper (and FP32 models); N = 110 the
+    narrow layout for biped5 / cheetah7; N = 70 the latency layout with S on
+    leg lanes for them; N = 30 the narrow layout and N = 22 the latency layout
+    with S on leg lanes for quad13.  4 sampled intervals vs the oracle."""
     K = 2
     _say(f"[gpu] discretize {dtype} {name} N={N} K={K} seed=102 (sampled)")
     dt = torch.float64 if dtype == "fp64" else torch.float32
