@@ -178,7 +178,7 @@ def main():
 
     flops = algorithmic_flops_per_interval(model, K) * N
     achieved = flops / (ms64 * 1e-3)
-    kname = "k_discretize<double, Topo<2, 3, 1, 2>>"
+    kname = "k_discretize<double, Topo<2, 3, 1, 2, true>>"
 
     batch = {}
     if not args.no_batch:
