@@ -92,7 +92,7 @@ def main():
     import torch
     from paper_2604_09993_amd import _lib, api, synth
 
-    model, data, K = synth.make_config(2)
+    model, data, K = synth.make_workload("cheetah7_N50_K20")
     N = data["s"].shape[0]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -187,7 +187,7 @@ def main():
         for name, make, ops, dtypes in (
                 ("mixed256", lambda: synth.mixed_batch(), ("discretize", "adjoint"),
                  (torch.float64,)),
-                ("quad13x64", lambda: synth.config_batch(5), ("discretize",),
+                ("quad13x64", lambda: synth.workload_batch("quad13_N200_K20_x64"), ("discretize",),
                  (torch.float64, torch.float32))):
             bl = make()
             nint = sum(d["s"].shape[0] for _, d, _ in bl)

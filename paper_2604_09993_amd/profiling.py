@@ -132,7 +132,7 @@ def bench_algorithmic_bytes():
     def auto_ckpt(K):   # a plan's default spacing: the largest divisor of K not above 8
         return max(c for c in range(1, 9) if K % c == 0)
     out = {}
-    model, data, K = synth.make_config(2)
+    model, data, K = synth.make_workload("cheetah7_N50_K20")
     N = data["s"].shape[0]
     t = _topo(model)
     out[f"k_discretize<double, {t}"] = N * interval_bytes(model, K, "discretize")
@@ -152,7 +152,7 @@ def bench_algorithmic_bytes():
         out[f"k_adjoint4_batch<double, {t}"] = tot("adjoint", auto_ckpt)
         out[f"k_adjoint3_batch<double, {t}"] = tot("adjoint", auto_ckpt)
         out[f"k_adjoint_batch<double, {t}"] = tot("adjoint", auto_ckpt)
-    qb = synth.config_batch(5)
+    qb = synth.workload_batch("quad13_N200_K20_x64")
     t = _topo(qb[0][0])
     out[f"k_discretize_batch<double, {t}"] = sum(d["s"].shape[0] * interval_bytes(m_, k, "discretize")
                                                  for m_, d, k in qb)

@@ -272,18 +272,21 @@ def gen_nodes(model: Model, N: int, rng: np.random.Generator,
 
 
 # Workload recipes (model, N, substeps) of the benchmark configurations.
-CONFIGS = {
-    1: dict(model="hopper", N=20, K=10),
-    2: dict(model="cheetah7", N=50, K=20),
-    3: dict(model="cheetah7", N=50, K=20, ckpt=5),
-    5: dict(model="quad13", N=200, K=20, batch=64),
+# The benchmark workloads by name: model, intervals N, substeps K, and the
+# seed of their node data (batch: trajectories; ckpt: substeps between the
+# checkpoints of the reverse sweep).
+WORKLOADS = {
+    "hopper_N20_K10": dict(model="hopper", N=20, K=10, seed=1),
+    "cheetah7_N50_K20": dict(model="cheetah7", N=50, K=20, seed=2),
+    "cheetah7_N50_K20_ckpt5": dict(model="cheetah7", N=50, K=20, ckpt=5, seed=3),
+    "quad13_N200_K20_x64": dict(model="quad13", N=200, K=20, batch=64, seed=5),
 }
 
 
-def make_config(config_id: int, traj_id: int = 0):
-    """Model and node data for a configuration, seeded by (config_id, traj_id)."""
-    cfg = CONFIGS[config_id]
-    rng = np.random.default_rng([config_id, traj_id])
+def make_workload(name: str, traj_id: int = 0):
+    """Model and node data of a named workload, seeded by (its seed, traj_id)."""
+    cfg = WORKLOADS[name]
+    rng = np.random.default_rng([cfg["seed"], traj_id])
     model = MODEL_MAKERS[cfg["model"]](rng)
     data = gen_nodes(model, cfg["N"], rng)
     return model, data, cfg["K"]
@@ -318,18 +321,18 @@ def mixed_batch(n_traj: int = 256, seed: int = 4, N_range=(20, 100), K_range=(10
     return out
 
 
-def config_batch(config_id: int, n_traj=None):
-    """The trajectories of a batched configuration, all of one model.
+def workload_batch(name: str, n_traj=None):
+    """The trajectories of a batched workload, all of one model.
 
-    Trajectory 0 is make_config(config_id, 0); trajectory t > 0 takes the
-    same model and draws its nodes from (config_id, t).
+    Trajectory 0 is make_workload(name, 0); trajectory t > 0 takes the same
+    model and draws its nodes from (the workload's seed, t).
     """
-    cfg = CONFIGS[config_id]
+    cfg = WORKLOADS[name]
     n_traj = cfg.get("batch", 1) if n_traj is None else n_traj
-    model, data, K = make_config(config_id, 0)
+    model, data, K = make_workload(name, 0)
     out = [(model, data, K)]
     for t in range(1, n_traj):
-        r = np.random.default_rng([config_id, t])
-        MODEL_MAKERS[cfg["model"]](r)   # same stream position as make_config
+        r = np.random.default_rng([cfg["seed"], t])
+        MODEL_MAKERS[cfg["model"]](r)   # same stream position as make_workload
         out.append((model, gen_nodes(model, cfg["N"], r), K))
     return out

@@ -97,12 +97,12 @@ def _merit_seed(model, d):
     return lam
 
 
-def test_config3_merit_gradients_via_autograd():
+def test_workload_cheetah7_ckpt5_merit_gradients_via_autograd():
     """Cheetah N=50, K=20, checkpoints every 5 substeps, merit through torch.autograd."""
     from paper_2604_09993_amd import api
-    _say("[gpu] config 3: cheetah7 N=50 K=20 C=5 adjoint via autograd")
-    model, data, K = synth.make_config(3)
-    C = synth.CONFIGS[3]["ckpt"]
+    _say("[gpu] workload cheetah7 N=50 K=20 C=5: adjoint via autograd")
+    model, data, K = synth.make_workload("cheetah7_N50_K20_ckpt5")
+    C = synth.WORKLOADS["cheetah7_N50_K20_ckpt5"]["ckpt"]
     dev = torch.device("cuda:0")
     cm = api.CisModel(model)
     X, U, s, p = _dev_inputs(api, data, dev)

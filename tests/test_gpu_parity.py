@@ -167,29 +167,29 @@ def test_edge_padded_leading_dimensions_and_no_xprop():
     check_against_oracle(model, data, 2, res)
 
 
-def test_config1_hopper_full():
-    _say("[gpu] config 1: hopper N=20 K=10 fp64")
-    model, data, K = synth.make_config(1)
+def test_workload_hopper_N20_K10_full():
+    _say("[gpu] workload hopper N=20 K=10 fp64")
+    model, data, K = synth.make_workload("hopper_N20_K10")
     res, _ = run_gpu(model, data, K)
     check_against_oracle(model, data, K, res)
 
 
-def test_config2_cheetah_full_fp64_fp32():
-    _say("[gpu] config 2: cheetah7 N=50 K=20 fp64")
-    model, data, K = synth.make_config(2)
+def test_workload_cheetah7_N50_K20_full_fp64_fp32():
+    _say("[gpu] workload cheetah7 N=50 K=20 fp64")
+    model, data, K = synth.make_workload("cheetah7_N50_K20")
     res, _ = run_gpu(model, data, K)
     check_against_oracle(model, data, K, res)
-    _say("[gpu] config 2: cheetah7 N=50 K=20 fp32")
+    _say("[gpu] workload cheetah7 N=50 K=20 fp32")
     res, _ = run_gpu(model, data, K, dtype=torch.float32)
     check_against_oracle(model, data, K, res, dtype=torch.float32)
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-def test_config5_quad13_sampled(dtype):
+def test_workload_quad13_N200_K20_sampled(dtype):
     """Full N=200, K=20 trajectory on the GPU; 6 sampled intervals recomputed by the oracle."""
-    _say(f"[gpu] config 5: quad13 N=200 K=20 {dtype} (sampled)")
+    _say(f"[gpu] workload quad13 N=200 K=20 {dtype} (sampled)")
     dt = torch.float64 if dtype == "fp64" else torch.float32
-    model, data, K = synth.make_config(5)
+    model, data, K = synth.make_workload("quad13_N200_K20_x64")
     res, _ = run_gpu(model, data, K, dtype=dt)
     for k in (0, 1, 77, 128, 198, 199):
         sub = dict(X=data["X"][k:k + 2], U=data["U"][k:k + 2], s=data["s"][k:k + 1], p=data["p"])
