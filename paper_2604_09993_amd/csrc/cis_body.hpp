@@ -328,9 +328,10 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     sabs_d(a1, v1, d1);
     sabs_d(a2, v2, d2);
     sabs_d(a3, v3, d3);
-    // SPLIT: the stage spans two pipeline steps.  FP32 takes the workgroup
-    // barrier here, between the smooth functions and the integrands (the two
-    // steps balance better, measured faster); FP64 after the evaluation.
+    // SPLIT: the stage spans two pipeline steps, split by one workgroup
+    // barrier where the two halves balance best as measured: FP32 here,
+    // between the smooth functions and the integrands; FP64 after the
+    // integrands, before the Jacobian terms.
     if constexpr (SPLIT && sizeof(T) == 4) __syncthreads();
     // integrands (Sec. III pairs; violation: |h|_s of joints, ramp_s(-sd))
     const T lnb = T(0.5) * (c.ck[0] + c.ck1[0]);
@@ -344,6 +345,7 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     const bool pen = -f.sd > T(0);
     ycc = cl ? lnb * f.sd + ltpb * rp + ltmb * rm + slack * av : T(0);
     const T ctp = (jl ? v0 + v1 : T(0)) + (cl && pen ? v3 : T(0));
+    if constexpr (SPLIT && sizeof(T) == 8) __syncthreads();
     // dT_b/dth_b parts: child side of the own joint, contact, parent side
     const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
     const T dTown = (jl ? acx * lx + acy * ly : T(0)) + (cl ? -(ax * fx + ay * fy) : T(0));
@@ -356,9 +358,9 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
     const T dfx = dtx * ft + f.dnx * ln, dfy = dty * ft + f.dny * ln;
     const T dvt_px = dtx * Pdx + dty * Pdy;
     const T im = s * c.mi, ii = s * c.ii;
-    // what the stores need from LDS (FP64: read before the split barrier; the
-    // rings hold this stage's entries until the state wave's step t+3, after
-    // both steps of the stage)
+    // what the stores need from LDS (read after the split barrier; the rings
+    // hold this stage's entries until the state wave's step t+3, after both
+    // steps of the stage)
     const T ip = s * iv.iinv[p];
     T fq[3], fa[3];
 #pragma unroll
@@ -366,7 +368,6 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         fq[k] = xs[NQ + 3 * b + k];
         fa[k] = fv[3 * b + k];
     }
-    if constexpr (SPLIT && sizeof(T) == 8) __syncthreads();
     if constexpr (WRITE) {
         // FP64: all values and addresses are formed first and stored in one
         // burst, since a register overwritten right after an LDS store waits
