@@ -272,12 +272,14 @@ enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30,
        CIS_SCHED_ADJ_4 = 0x100 };
 
 /* Optional bits of `sched` fixing the register budget of the discretize
- * kernel: CIS_SCHED_WAVES_1 lets it take all registers it wants (one wave per
- * SIMD); CIS_SCHED_WAVES_2 holds it to 256 registers per lane so that two
- * workgroups share a compute unit (latency hiding, at the price of spills to
- * scratch; CIS_F64 only, else CIS_ERR_DTYPE).  Without either bit both FP64
- * forms are timed with CIS_SCHED_TUNE, and the first is used otherwise.
- * Setting both bits is an error (CIS_ERR_DIM). */
+ * kernel: CIS_SCHED_WAVES_1 lets it take all the registers its workgroup
+ * size allows; CIS_SCHED_WAVES_2 holds it to 256 registers per lane so that
+ * two workgroups can share a compute unit (latency hiding, at the price of
+ * spills to scratch; CIS_F64 only, else CIS_ERR_DTYPE).  Workgroups of more
+ * than four waves (models with many tangent columns) are held to 256
+ * registers in both forms.  Without either bit both FP64 forms are timed
+ * with CIS_SCHED_TUNE, and the first is used otherwise.  Setting both bits
+ * is an error (CIS_ERR_DIM). */
 enum { CIS_SCHED_WAVES_1 = 0x40, CIS_SCHED_WAVES_2 = 0x80 };
 
 /*
