@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus must be 1 (no multi-GPU path in this build)",
+        print("bench.py measures one GPU only; --gpus must be 1 (the kernels run on a single GPU)",
               file=sys.stderr)
         sys.exit(2)
 
