@@ -490,3 +490,35 @@ def test_parallel_matches_serial():
     b = oracle.discretize(mdl, data["X"], data["U"], data["s"], mdl.params(), 4, nthreads=4)
     for key in a:
         assert np.array_equal(a[key], b[key])
+
+
+def test_defects_closed_form_and_consistency():
+    """oracle.defects: F~ of a free body is the exact parabola (RK4 is exact for
+    constant acceleration) and d_k = F~_k - X_{k+1} (eq. cito-augdyn); on a
+    legged model F~ and d equal, bit for bit, what oracle.discretize returns
+    for the same intervals, and d = xprop - X[1:] exactly."""
+    rng = np.random.default_rng(31)
+    mdl = synth.make_free_body(rng)
+    N, K = 4, 3
+    X = np.zeros((N + 1, mdl.nx))
+    X[:, :6] = rng.normal(size=(N + 1, 6))
+    X[:, 6] = rng.normal(size=N + 1)
+    s = rng.uniform(0.1, 0.6, size=N)
+    U = np.zeros((N + 1, 0))
+    out = oracle.defects(mdl, X, U, s, mdl.params(), K)
+    a = np.array([0.0, -G, 0.0])
+    for k in range(N):
+        q1 = X[k, :3] + s[k] * X[k, 3:6] + 0.5 * s[k] ** 2 * a
+        v1 = X[k, 3:6] + s[k] * a
+        want = np.concatenate([q1, v1, X[k, 6:7]])
+        np.testing.assert_allclose(out["xprop"][k], want, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(out["d"][k], want - X[k + 1], rtol=0, atol=1e-14)
+    for name in ("hopper", "biped5", "cheetah7"):
+        r = np.random.default_rng([32, len(name)])
+        mdl = synth.MODEL_MAKERS[name](r)
+        data = synth.gen_nodes(mdl, 3, r, T=0.06)
+        dd = oracle.defects(mdl, data["X"], data["U"], data["s"], data["p"], 4)
+        full = oracle.discretize(mdl, data["X"], data["U"], data["s"], data["p"], 4)
+        assert np.array_equal(dd["xprop"], full["xprop"]), name
+        assert np.array_equal(dd["d"], full["d"]), name
+        assert np.array_equal(dd["d"], dd["xprop"] - data["X"][1:]), name
