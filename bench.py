@@ -1,21 +1,26 @@
 #!/usr/bin/env python3
 """Discretized intervals/s of the CI-SCvx linearize-and-discretize step on one MI355X.
 
-Workload: HalfCheetah-shaped planar chain (7 bodies, 6 joints, 2 contacts;
-nx = 45, m = 24), N = 50 intervals, K = 20 RK4 substeps, FP64, synthetic
-seeded node data (inputs resident in HBM before timing).  One step = one call
-of cis_discretize over all 50 intervals (A, B-, B+, S, defects, F~).
+Headline workload: 64 trajectories of a planar 13-body quadruped-shaped chain
+(torso + four 3-link legs, 12 revolute joints, 4 foot contacts; nx = 83,
+m = 48), N = 200 intervals each (12,800 intervals), K = 20 RK4 substeps,
+FP64, synthetic seeded node data resident in HBM before timing.  One step =
+one replay of the batch plan's HIP graph: every interval's A, B-, B+, S,
+defect and F~.
 
-Prints one JSON line.  Extra fields: the FP32 form of the same step, the
-adjoint gradient step, batched multiple shooting (256 mixed trajectories;
-64 quad13 trajectories of N = 200), the parity error of the timed output
-against the CPU oracle, the roofline of the dominant kernel (k_discretize)
-and the CPU oracle baseline.
+Prints one JSON line.  Extra fields: the FP32 form and the gradient step
+(defects with checkpoints + reverse sweep + reduction) of the same batch;
+the uneven 256-trajectory batch (hopper / cheetah7 / biped5); the
+single-trajectory cheetah7 (N = 50, K = 20) and hopper (N = 20, K = 10)
+calls; substep blocking with VALU and MFMA composition on one quad13
+trajectory; the parity of every timed output against the CPU oracle
+(sampled); the roofline of the dominant kernels; the CPU oracle baseline.
 """
 import argparse
 import ctypes
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,10 +29,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s (AMD published)
 PEAK_FP32_VALU = 157.3e12
+PHI_FJ = {2: 300, 5: 700, 7: 1000, 13: 2000}   # per-stage RHS + Jacobian FLOP by body count
 
 
 def algorithmic_flops_per_interval(model, K):
-    """Per-interval FLOPs of the sparse method: K [8 nnz(J) c + 14 nx c + 4 phi_fJ].
+    """Per-interval FLOPs of the sparse forward method: K [8 nnz(J) c + 14 nx c + 4 phi_fJ].
 
     nnz(J) = 2 n_q + 2 n_b + 4 n_j + 4 n_c (flat ground), c = n + 2m + 1 tangent
     columns, phi_fJ = per-stage right-hand side + Jacobian cost (0.3k hopper,
@@ -36,8 +42,27 @@ def algorithmic_flops_per_interval(model, K):
     nb, nj, nc = model.nb, model.nj, model.nc
     nnz = 2 * 3 * nb + 2 * nb + 4 * nj + 4 * nc
     c = model.n + 2 * model.m + 1
-    phi = {2: 300, 5: 700, 7: 1000, 13: 2000}.get(nb, 1000)
+    phi = PHI_FJ.get(nb, 1000)
     return K * (8 * nnz * c + 14 * model.nx * c + 4 * phi)
+
+
+def adjoint_flops_per_interval(model, K):
+    """Per-interval FLOPs of one gradient step (defects pass + reverse sweep):
+    K [6 phi_fJ + 8 (nnz(J) + nnz(J_u, J_ubar) + nnz(J_p)) + 14 nx] + 2 K phi_fJ.
+
+    The reverse sweep re-evaluates the right-hand side and Jacobian at every
+    stage (4 phi_fJ per substep), recomputes the stage states from the
+    checkpoints (4 phi_f ~ 2 phi_fJ), applies the transposed products (four
+    stages, one FMA per nonzero of J, of the control Jacobians J_u (10 n_j +
+    9 n_c) and J_ubar (3 n_c), and of J_p (3 n_b + n_c)) and the RK4 adjoint
+    combination (14 nx); the defects pass is the nominal RK4 (2 K phi_fJ).
+    """
+    nb, nj, nc = model.nb, model.nj, model.nc
+    nnz = 2 * 3 * nb + 2 * nb + 4 * nj + 4 * nc
+    nnz_u = 10 * nj + 12 * nc
+    nnz_p = 3 * nb + nc
+    phi = PHI_FJ.get(nb, 1000)
+    return K * (6 * phi + 8 * (nnz + nnz_u + nnz_p) + 14 * model.nx) + 2 * K * phi
 
 
 def committed_traffic(kernel):
@@ -73,58 +98,69 @@ def upload_batch(api, batch, dev, dtype):
     return trajs
 
 
+def batch_kernel_name(model, group, dtype):
+    """rocprofv3 short name of a batch group's discretize kernel."""
+    t = "double" if dtype == "f64" else "float"
+    pers = "true" if group["persist_blocks"] > 0 else "false"
+    return (f"k_discretize_batch<{t}, Topo<{model.legs}, {model.depth}, 6, 1, false>, {pers}, "
+            f"{group['waves_per_simd']}>")
+
+
+def host_cpu():
+    """CPU model, logical CPUs, CPUs this process may run on, and the cgroup quota."""
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, per = fh.read().split()[:2]
+            if q != "max":
+                quota = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    usable = affinity if quota is None else max(1, min(affinity, int(quota)))
+    return {"model": model, "logical_cpus": os.cpu_count(), "affinity_cpus": affinity,
+            "cgroup_cpu_quota": quota, "usable_cpus": usable}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the headline workload only (profiling runs)")
+    ap.add_argument("--extra-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus must be 1 (the kernels run on a single GPU)",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: this build runs every kernel on a single GPU "
+              "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     from paper_2604_09993_amd import _lib, api, synth
 
-    model, data, K = synth.make_workload("cheetah7_N50_K20")
-    N = data["s"].shape[0]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cm = api.CisModel(model)
     lib = _lib.load(build_if_missing=False)
+    stream = torch.cuda.current_stream()
 
-    def prepare(dtype):
-        X = api.to_device_soa(data["X"], dev, dtype)
-        U = api.to_device_soa(data["U"], dev, dtype)
-        s = torch.tensor(data["s"], device=dev, dtype=dtype)
-        p = torch.tensor(data["p"], device=dev, dtype=dtype)
-        kw = dict(device=dev, dtype=dtype)
-        nx, m = cm.nx, cm.m
-        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
-                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
-                   d=torch.empty((nx, N), **kw), xprop=torch.empty((nx, N), **kw))
-        api.discretize_into(cm, X, U, s, p, K, out)   # validates shapes once
-        stream = torch.cuda.current_stream()
-        sh = _lib.Shape(N, K, api._dtype_code(dtype), 0, X.stride(0), N)
-        argv = [cm.handle, ctypes.byref(sh)] + [ctypes.c_void_p(t.data_ptr()) for t in
-                (X, U, s, p, out["A"], out["Bm"], out["Bp"], out["S"], out["d"], out["xprop"])]
-        argv.append(ctypes.c_void_p(stream.cuda_stream))
-        fn = lib.cis_discretize
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-        def launch():
-            st = fn(*argv)
-            if st != 0:
-                _lib.check(st)
-        keep = (X, U, s, p, sh)
-        return launch, out, stream, keep
-
-    def timed(launch, stream, steps, warmup):
+    def timed(launch, steps, warmup):
+        """Average ms per step over `steps` launches on `stream`, bracketed by HIP
+        events recorded on that stream (after `warmup` untimed launches)."""
         for _ in range(warmup):
             launch()
         torch.cuda.synchronize()
@@ -139,141 +175,340 @@ def main():
         wall = time.perf_counter() - t0
         return e0.elapsed_time(e1) / steps, wall
 
-    def progress(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    # Parity of the timed outputs: sampled GPU outputs are copied to the host
+    # here and compared with the oracle in the CPU-baseline leg at the end
+    # (the only part of this script that runs the oracle).
+    parity, pending = {}, []
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
 
-    launch64, out64, stream, keep64 = prepare(torch.float64)
-    ms64, wall64 = timed(launch64, stream, args.steps, args.warmup)
-    progress(f"fp64 discretize {ms64:.4f} ms/step")
-    launch32, out32, _, keep32 = prepare(torch.float32)
-    ms32, _ = timed(launch32, stream, args.steps, args.warmup)
-    progress(f"fp32 discretize {ms32:.4f} ms/step")
+    def check_intervals(key, batch, plan, windows, fp32):
+        """Queue an oracle check of contiguous windows of intervals."""
+        if args.no_cpu_baseline:
+            return
+        got_all = []
+        for t, k0, n in windows:
+            sl = slice(k0, k0 + n)
+            got = api.as_interval_major({k: v[..., sl] for k, v in plan.out[t].items()
+                                         if k in ("A", "Bm", "Bp", "S", "d", "xprop")})
+            got_all.append({k: v.double().cpu().numpy() for k, v in got.items()})
 
-    # adjoint form on the same workload (checkpoints every 5 substeps): one
-    # gradient step = forward defects with checkpoints + reverse sweep + reduce
-    C = 5
-    X64, U64, s64, p64 = keep64[:4]
-    fw = api.defects(cm, X64, U64, s64, p64, K, ckpt_every=C)
-    seed = fw["d"].clone()
-    seed[cm.n:] += 1.0          # d(1/2 ||d||^2 + sum of integral increments)/dF~
-    nbytes = api.adjoint_workspace_bytes(cm, N, K)
-    ws = torch.empty((nbytes,), device=dev, dtype=torch.uint8)
-    gX = torch.empty((cm.nx, N + 1), device=dev, dtype=torch.float64)
-    gU = torch.empty((cm.m, N + 1), device=dev, dtype=torch.float64)
-    gs = torch.empty((N,), device=dev, dtype=torch.float64)
-    gp = torch.empty((cm.np,), device=dev, dtype=torch.float64)
-    sh_adj = _lib.Shape(N, K, _lib.CIS_F64, 0, X64.stride(0), N)
-    vp = lambda t: ctypes.c_void_p(t.data_ptr())
-    d_fw, xp_fw, ck = fw["d"], fw["xprop"], fw["ckpt"]
-    st_ptr = ctypes.c_void_p(stream.cuda_stream)
+        def run():
+            import oracle
+            from parity import PHI32, PHI64, block_err
+            r = (lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)) if fp32 else \
+                (lambda a: np.asarray(a, dtype=np.float64))
+            worst = 0.0
+            for (t, k0, n), got in zip(windows, got_all):
+                model, data, K = batch[t]
+                ref = oracle.discretize(model, r(data["X"][k0:k0 + n + 1]),
+                                        r(data["U"][k0:k0 + n + 1]), r(data["s"][k0:k0 + n]),
+                                        r(data["p"]), K)
+                for k in ("A", "Bm", "Bp", "S", "d", "xprop"):
+                    if model.m == 0 and k in ("Bm", "Bp"):
+                        continue
+                    worst = max(worst, block_err(got[k], ref[k], PHI32 if fp32 else PHI64))
+            parity[key] = {"max_rel_err_vs_oracle": worst,
+                           "metric": "normwise" if fp32 else "per-entry (phi = 1e-3)",
+                           "bar": 1e-4 if fp32 else 1e-10,
+                           "sample": "; ".join(f"trajectory {t} intervals {k0}..{k0 + n - 1}"
+                                               for t, k0, n in windows)}
+        pending.append(run)
 
-    def launch_grad():
-        _lib.check(lib.cis_defects(cm.handle, ctypes.byref(sh_adj), vp(X64), vp(U64), vp(s64), vp(p64),
-                                   vp(d_fw), vp(xp_fw), vp(ck), C, st_ptr))
-        _lib.check(lib.cis_discretize_adjoint(cm.handle, ctypes.byref(sh_adj), vp(X64), vp(U64),
-                                              vp(s64), vp(p64), vp(ck), C, vp(seed), vp(gX),
-                                              vp(gU), vp(gs), vp(gp), vp(ws), nbytes, st_ptr))
-    ms_grad, _ = timed(launch_grad, stream, max(args.steps // 2, 10), args.warmup)
-    progress(f"gradient step {ms_grad:.4f} ms")
+    def check_adjoint(key, batch, plan, lams, picks):
+        """Queue an oracle check of the gradients of whole trajectories."""
+        if args.no_cpu_baseline:
+            return
+        got_all = []
+        for t in picks:
+            model, data, K = batch[t]
+            N = data["s"].shape[0]
+            o = plan.out[t]
+            got_all.append((o["gX"][:, :N + 1].cpu().numpy().T, o["gs"].cpu().numpy(),
+                            o["gp"].cpu().numpy(), o["gU"][:model.m, :N + 1].cpu().numpy().T))
 
-    flops = algorithmic_flops_per_interval(model, K) * N
-    achieved = flops / (ms64 * 1e-3)
-    kname = "k_discretize<double, Topo<2, 3, 1, 2, true>>"
+        def run():
+            import oracle
+            from parity import PHI64, block_err
+            worst = 0.0
+            for t, (gX, gs, gp, gU) in zip(picks, got_all):
+                model, data, K = batch[t]
+                ref = oracle.adjoint(model, data["X"], data["U"], data["s"], data["p"], K,
+                                     lams[t])
+                pairs = [(gX, ref["gX"]), (gs.reshape(1, -1), ref["gs"].reshape(1, -1)),
+                         (gp.reshape(1, -1), ref["gp"].reshape(1, -1))]
+                if model.m:
+                    pairs.append((gU, ref["gU"]))
+                for g, r in pairs:
+                    worst = max(worst, block_err(g, r, PHI64))
+            parity[key] = {"max_rel_err_vs_oracle": worst, "metric": "per-entry (phi = 1e-3)",
+                           "bar": 1e-10,
+                           "sample": f"whole trajectories {picks} (gX, gU, gs, gp)"}
+        pending.append(run)
 
-    batch = {}
-    if not args.no_batch:
-        # multiple shooting over many trajectories: one plan per workload,
-        # replayed as a HIP graph (one kernel per model, run concurrently)
-        for name, make, ops, dtypes in (
-                ("mixed256", lambda: synth.mixed_batch(), ("discretize", "adjoint"),
-                 (torch.float64,)),
-                ("quad13x64", lambda: synth.workload_batch("quad13_N200_K20_x64"), ("discretize",),
-                 (torch.float64, torch.float32))):
-            bl = make()
-            nint = sum(d["s"].shape[0] for _, d, _ in bl)
-            bflops = sum(algorithmic_flops_per_interval(m, k) * d["s"].shape[0] for m, d, k in bl)
-            for dt in dtypes:
-                trajs = upload_batch(api, bl, dev, dt)
-                plan = api.BatchPlan(trajs, ops if dt == torch.float64 else ("discretize",),
-                                     sched="tune", graph=True, stream=stream)
-                res = {}
-                for op in (ops if dt == torch.float64 else ("discretize",)):
-                    ms_b, _ = timed(lambda: plan.run(op, graph=True, stream=stream), stream,
-                                    args.batch_steps, 2)
-                    res[op] = {"value": nint / (ms_b * 1e-3),
-                               "unit": "intervals/s" if op == "discretize" else "interval grads/s",
-                               "ms_per_step": ms_b}
-                    if op == "discretize":
-                        peak = PEAK_FP64_VALU if dt == torch.float64 else PEAK_FP32_VALU
-                        res[op]["roofline_frac"] = bflops / (ms_b * 1e-3) / peak
-                key = f"{name}_{'f64' if dt == torch.float64 else 'f32'}"
-                progress(f"batch {key}: " + ", ".join(f"{o} {r['ms_per_step']:.3f} ms"
-                                                      for o, r in res.items()))
-                batch[key] = dict(trajectories=len(bl), intervals=nint, **res,
-                                  groups=plan.groups())
-                plan.close()
-                del trajs
+    def merit_seeds(plan, cms):
+        """Seeds of the merit 1/2 sum ||d_k||^2 + sum of integral increments:
+        dJ/dF~_k = d_k + [0; 1] (from the plan's own defects pass)."""
+        lams = []
+        for o, cm in zip(plan.out, cms):
+            sd = o["d"].clone()
+            sd[cm.n:] += 1.0
+            o["seed"].copy_(sd)
+            lams.append(sd.cpu().numpy().T.copy())
+        return lams
 
+    # ---------------- headline: quad13 x 64, FP64 forward ----------------
+    qb = synth.workload_batch("quad13_N200_K20_x64")
+    qmodel = qb[0][0]
+    q_int = sum(d["s"].shape[0] for _, d, _ in qb)
+    q_flops = sum(algorithmic_flops_per_interval(m, k) * d["s"].shape[0] for m, d, k in qb)
+    q_adj_flops = sum(adjoint_flops_per_interval(m, k) * d["s"].shape[0] for m, d, k in qb)
+    trajs = upload_batch(api, qb, dev, torch.float64)
+    plan64 = api.BatchPlan(trajs, ("discretize", "adjoint"), sched="tune", graph=True,
+                           stream=stream)
+    g64 = plan64.groups()[0]
+    ms_q64, wall_q64 = timed(lambda: plan64.run("discretize", graph=True, stream=stream),
+                             args.steps, args.warmup)
+    progress(f"quad13 x64 fp64 discretize {ms_q64:.3f} ms/step ({g64})")
+    check_intervals("quad13x64_f64_discretize", qb, plan64, [(0, 0, 8), (37, 192, 8)], False)
+    # gradient step of the same batch (merit seeds from its own defects pass)
+    plan64.run("adjoint", graph=True, stream=stream)
+    torch.cuda.synchronize()
+    lams = merit_seeds(plan64, [t["cm"] for t in trajs])
+    ms_qadj, _ = timed(lambda: plan64.run("adjoint", graph=True, stream=stream),
+                       max(args.steps // 2, 5), args.warmup)
+    progress(f"quad13 x64 fp64 gradient step {ms_qadj:.3f} ms/step")
+    check_adjoint("quad13x64_f64_adjoint", qb, plan64, lams, [0, 21, 42, 63])
+    plan64.close()
+    del plan64, trajs
+    torch.cuda.empty_cache()
+
+    kname = batch_kernel_name(qmodel, g64, "f64")
+    achieved = q_flops / (ms_q64 * 1e-3)
     line = {
         "metric": "discretized intervals/s (x+STM+B±) at 1e-10 rel vs oracle",
-        "value": N / (ms64 * 1e-3),
+        "value": q_int / (ms_q64 * 1e-3),
         "unit": "intervals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms64,
+        "ms_per_step": ms_q64,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cheetah7 planar chain (7 bodies, 6 joints, 2 contacts), "
-                               "N=50 intervals, K=20 RK4 substeps, FP64 forward",
-                   "N": N, "substeps": K, "nx": cm.nx, "m": cm.m},
-        "fp32": {"value": N / (ms32 * 1e-3), "unit": "intervals/s", "ms_per_step": ms32},
-        "adjoint": {"value": N / (ms_grad * 1e-3), "unit": "interval grads/s",
-                    "ms_per_step": ms_grad,
-                    "step": "cis_defects with checkpoints every 5 substeps + cis_discretize_adjoint"},
+        "config": {"workload": "quad13 x 64: 64 trajectories of a planar 13-body chain "
+                               "(torso + four 3-link legs, 12 joints, 4 contacts), N=200 "
+                               "intervals each, K=20 RK4 substeps, FP64 forward, one batch "
+                               "plan replayed as a HIP graph",
+                   "trajectories": len(qb), "intervals": q_int, "N": 200, "substeps": 20,
+                   "nx": qmodel.nx, "m": qmodel.m, "launch": g64},
         "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                      "traffic": committed_traffic(kname),
-                     "algorithmic_flop_per_launch": flops},
-        "batch": batch,
-        "wall_s_timed_region": wall64,
+                     "algorithmic_flop_per_launch": q_flops,
+                     "timing": "HIP events on the launch stream around the graph replays "
+                               "(one kernel node per replay)"},
+        "gradient_step": {"value": q_int / (ms_qadj * 1e-3), "unit": "interval grads/s",
+                          "ms_per_step": ms_qadj,
+                          "roofline_frac": q_adj_flops / (ms_qadj * 1e-3) / PEAK_FP64_VALU,
+                          "algorithmic_flop_per_step": q_adj_flops,
+                          "step": "defects with checkpoints + reverse sweep + reduction, "
+                                  "graph replay; merit 1/2 sum ||d||^2 + integral increments"},
+        "wall_s_timed_region": wall_q64,
     }
+
+    extras = {}
+    if not args.no_extras:
+        # FP32 forward of the same batch
+        trajs = upload_batch(api, qb, dev, torch.float32)
+        plan32 = api.BatchPlan(trajs, ("discretize",), sched="tune", graph=True, stream=stream)
+        g32 = plan32.groups()[0]
+        ms_q32, _ = timed(lambda: plan32.run("discretize", graph=True, stream=stream),
+                          args.extra_steps, 2)
+        progress(f"quad13 x64 fp32 discretize {ms_q32:.3f} ms/step")
+        check_intervals("quad13x64_f32_discretize", qb, plan32, [(0, 0, 8), (37, 192, 8)], True)
+        extras["quad13x64_f32"] = {"value": q_int / (ms_q32 * 1e-3), "unit": "intervals/s",
+                                   "ms_per_step": ms_q32, "launch": g32,
+                                   "kernel": batch_kernel_name(qmodel, g32, "f32"),
+                                   "roofline_frac": q_flops / (ms_q32 * 1e-3) / PEAK_FP32_VALU}
+        plan32.close()
+        del plan32, trajs
+        torch.cuda.empty_cache()
+
+        # uneven batch of 256 trajectories over three models
+        mb = synth.mixed_batch()
+        m_int = sum(d["s"].shape[0] for _, d, _ in mb)
+        m_flops = sum(algorithmic_flops_per_interval(m, k) * d["s"].shape[0] for m, d, k in mb)
+        m_adj = sum(adjoint_flops_per_interval(m, k) * d["s"].shape[0] for m, d, k in mb)
+        trajs = upload_batch(api, mb, dev, torch.float64)
+        planm = api.BatchPlan(trajs, ("discretize", "adjoint"), sched="tune", graph=True,
+                              stream=stream)
+        ms_m, _ = timed(lambda: planm.run("discretize", graph=True, stream=stream),
+                        args.extra_steps, 2)
+        first = {}
+        for i, (m_, _, _) in enumerate(mb):
+            first.setdefault(id(m_), i)
+        check_intervals("mixed256_f64_discretize", mb, planm,
+                        [(i, 0, 6) for i in sorted(first.values())], False)
+        planm.run("adjoint", graph=True, stream=stream)
+        torch.cuda.synchronize()
+        lams_m = merit_seeds(planm, [t["cm"] for t in trajs])
+        ms_madj, _ = timed(lambda: planm.run("adjoint", graph=True, stream=stream),
+                           args.extra_steps, 2)
+        check_adjoint("mixed256_f64_adjoint", mb, planm, lams_m,
+                      sorted(set(first.values()) | {5, 100, 200}))
+        progress(f"mixed256 fp64 discretize {ms_m:.3f} ms, gradient step {ms_madj:.3f} ms")
+        extras["mixed256_f64"] = {
+            "trajectories": len(mb), "intervals": m_int,
+            "discretize": {"value": m_int / (ms_m * 1e-3), "unit": "intervals/s",
+                           "ms_per_step": ms_m,
+                           "roofline_frac": m_flops / (ms_m * 1e-3) / PEAK_FP64_VALU},
+            "gradient_step": {"value": m_int / (ms_madj * 1e-3), "unit": "interval grads/s",
+                              "ms_per_step": ms_madj,
+                              "roofline_frac": m_adj / (ms_madj * 1e-3) / PEAK_FP64_VALU},
+            "groups": planm.groups()}
+        planm.close()
+        del planm, trajs
+        torch.cuda.empty_cache()
+
+        # single trajectories: cheetah7 N=50 K=20 (FP64, FP32, gradient), hopper N=20 K=10
+        def single(name, dtype):
+            model, data, K = synth.make_workload(name)
+            N = data["s"].shape[0]
+            cm = api.CisModel(model)
+            X = api.to_device_soa(data["X"], dev, dtype)
+            U = api.to_device_soa(data["U"], dev, dtype)
+            s = torch.tensor(data["s"], device=dev, dtype=dtype)
+            p = torch.tensor(data["p"], device=dev, dtype=dtype)
+            kw = dict(device=dev, dtype=dtype)
+            out = dict(A=torch.empty((cm.nx, cm.nx, N), **kw), Bm=torch.empty((cm.nx, cm.m, N), **kw),
+                       Bp=torch.empty((cm.nx, cm.m, N), **kw), S=torch.empty((cm.nx, N), **kw),
+                       d=torch.empty((cm.nx, N), **kw), xprop=torch.empty((cm.nx, N), **kw))
+            api.discretize_into(cm, X, U, s, p, K, out)
+            sh = _lib.Shape(N, K, api._dtype_code(dtype), 0, X.stride(0), N)
+            argv = [cm.handle, ctypes.byref(sh)] + [ctypes.c_void_p(t.data_ptr()) for t in
+                    (X, U, s, p, out["A"], out["Bm"], out["Bp"], out["S"], out["d"], out["xprop"])]
+            argv.append(ctypes.c_void_p(stream.cuda_stream))
+
+            def launch():
+                st = lib.cis_discretize(*argv)
+                if st != 0:
+                    _lib.check(st)
+            ms, _ = timed(launch, 200, 20)
+            wrap = [(model, data, K)]
+            fake = type("P", (), {"out": [out]})()
+            check_intervals(f"{name}_{'f64' if dtype == torch.float64 else 'f32'}", wrap, fake,
+                            [(0, 0, N)], dtype == torch.float32)
+            return dict(value=N / (ms * 1e-3), unit="intervals/s", ms_per_step=ms,
+                        roofline_frac=algorithmic_flops_per_interval(model, K) * N / (ms * 1e-3) /
+                        (PEAK_FP64_VALU if dtype == torch.float64 else PEAK_FP32_VALU)), \
+                (cm, X, U, s, p, N, K)
+
+        extras["cheetah7_N50_K20_f64"], keep = single("cheetah7_N50_K20", torch.float64)
+        extras["cheetah7_N50_K20_f32"], _ = single("cheetah7_N50_K20", torch.float32)
+        extras["hopper_N20_K10_f64"], _ = single("hopper_N20_K10", torch.float64)
+        cm, X, U, s, p, N, K = keep
+        C = 5
+        fw = api.defects(cm, X, U, s, p, K, ckpt_every=C)
+        seed = fw["d"].clone()
+        seed[cm.n:] += 1.0
+        nbytes = api.adjoint_workspace_bytes(cm, N, K)
+        ws = torch.empty((nbytes,), device=dev, dtype=torch.uint8)
+        gX = torch.empty((cm.nx, N + 1), device=dev, dtype=torch.float64)
+        gU = torch.empty((cm.m, N + 1), device=dev, dtype=torch.float64)
+        gs = torch.empty((N,), device=dev, dtype=torch.float64)
+        gp = torch.empty((cm.np,), device=dev, dtype=torch.float64)
+        sh_adj = _lib.Shape(N, K, _lib.CIS_F64, 0, X.stride(0), N)
+        vp = lambda t: ctypes.c_void_p(t.data_ptr())
+        st_ptr = ctypes.c_void_p(stream.cuda_stream)
+
+        def launch_grad():
+            _lib.check(lib.cis_defects(cm.handle, ctypes.byref(sh_adj), vp(X), vp(U), vp(s), vp(p),
+                                       vp(fw["d"]), vp(fw["xprop"]), vp(fw["ckpt"]), C, st_ptr))
+            _lib.check(lib.cis_discretize_adjoint(cm.handle, ctypes.byref(sh_adj), vp(X), vp(U),
+                                                  vp(s), vp(p), vp(fw["ckpt"]), C, vp(seed),
+                                                  vp(gX), vp(gU), vp(gs), vp(gp), vp(ws), nbytes,
+                                                  st_ptr))
+        ms_g, _ = timed(launch_grad, 100, 20)
+        cmodel = cm.model
+        extras["cheetah7_N50_K20_gradient_step"] = {
+            "value": N / (ms_g * 1e-3), "unit": "interval grads/s", "ms_per_step": ms_g,
+            "roofline_frac": adjoint_flops_per_interval(cmodel, K) * N / (ms_g * 1e-3) /
+            PEAK_FP64_VALU,
+            "step": "cis_defects (checkpoints every 5 substeps) + cis_discretize_adjoint"}
+        progress("single trajectories: " + ", ".join(
+            f"{k} {v['ms_per_step']:.4f} ms" for k, v in extras.items() if k.startswith(("cheetah", "hopper"))))
+
+        # substep blocking on one quad13 trajectory (N = 200): fused kernel
+        # against B blocks chained by dense VALU or MFMA products
+        model, data, K = qb[0]
+        cmq = api.CisModel(model)
+        Xq = api.to_device_soa(data["X"], dev)
+        Uq = api.to_device_soa(data["U"], dev)
+        sq = torch.tensor(data["s"], device=dev)
+        pq = torch.tensor(data["p"], device=dev)
+        blk = {}
+        ms_f, _ = timed(lambda: api.discretize(cmq, Xq, Uq, sq, pq, K, stream=stream), 10, 2)
+        blk["fused_ms"] = ms_f
+        for B in (2, 4, 5):
+            nb_ = api.blocked_workspace_bytes(cmq, data["s"].shape[0], K, B)
+            wsb = torch.empty((nb_,), device=dev, dtype=torch.uint8)
+            for mode in ("valu", "mfma"):
+                ms_b, _ = timed(lambda: api.discretize_blocked(cmq, Xq, Uq, sq, pq, K, B, mode,
+                                                               ws=wsb, stream=stream), 10, 2)
+                blk[f"B{B}_{mode}_ms"] = ms_b
+        extras["quad13_N200_K20_single_blocking"] = blk
+        progress("blocking: " + ", ".join(f"{k} {v:.3f}" for k, v in blk.items()))
+
+    line["extras"] = extras
+
+    bad = []
     if not args.no_cpu_baseline:
-        # CPU-baseline leg: the plain FP64 oracle on the host cores, on the same
-        # seeded inputs; its result also gives the parity of the timed outputs.
+        for run in pending:
+            run()
+        line["parity"] = parity
+        bad = [k for k, v in parity.items() if not v["max_rel_err_vs_oracle"] <= v["bar"]]
+        line["parity_ok"] = not bad
+        line["max_rel_err_vs_oracle"] = parity["quad13x64_f64_discretize"]["max_rel_err_vs_oracle"]
+        progress(f"parity checked on {len(parity)} outputs; above the bar: {bad}")
+        # CPU-baseline leg: the plain FP64 oracle on the host cores, on a bounded
+        # sample of the headline workload (consecutive quad13 intervals, K = 20).
         import oracle
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from parity import PHI32, PHI64, block_err
-        ref = oracle.discretize(model, data["X"], data["U"], data["s"], data["p"], K)
-        v64 = api.as_interval_major(out64)
-        line["max_rel_err_vs_oracle"] = max(
-            block_err(v64[k].double().cpu().numpy(), ref[k], PHI64)
-            for k in ("A", "Bm", "Bp", "S", "d", "xprop"))
-        r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
-        ref32 = oracle.discretize(model, r32(data["X"]), r32(data["U"]), r32(data["s"]),
-                                  r32(data["p"]), K)
-        v32 = api.as_interval_major(out32)
-        line["fp32"]["max_rel_err_vs_oracle_normwise"] = max(
-            block_err(v32[k].double().cpu().numpy(), ref32[k], PHI32)
-            for k in ("A", "Bm", "Bp", "S", "d", "xprop"))
-        ncores = os.cpu_count() or 1
-        ncores = min(ncores, 16)
-        reps = 0
+        cpu = host_cpu()
+        nthr = cpu["usable_cpus"]
+        # all usable threads: whole trajectories 1.. of the batch (1000 intervals
+        # with 8 or more threads); one thread: the first 12 intervals of one
+        n_tr = max(1, min(5, nthr // 3))
+        n_all = 0
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < args.cpu_seconds:
-            oracle.discretize(model, data["X"], data["U"], data["s"], data["p"], K, nthreads=ncores)
-            reps += 1
-        dt = time.perf_counter() - t0
-        progress(f"cpu baseline {reps} repetitions in {dt:.1f} s")
-        line["cpu_baseline"] = {"value": reps * N / dt, "unit": "intervals/s", "cores": ncores,
-                                "kind": "oracle",
-                                "sample": f"{reps} repetitions of the same 50-interval workload "
-                                          f"({reps * N} intervals, {dt:.1f} s, OpenMP over intervals)"}
+        for t in range(1, 1 + n_tr):
+            model, data, K = qb[t]
+            oracle.discretize(model, data["X"], data["U"], data["s"], data["p"], K,
+                              nthreads=nthr)
+            n_all += data["s"].shape[0]
+        dt_all = time.perf_counter() - t0
+        model, data, K = qb[1]
+        n_one = 12
+        t0 = time.perf_counter()
+        oracle.discretize(model, data["X"][:n_one + 1], data["U"][:n_one + 1], data["s"][:n_one],
+                          data["p"], K, nthreads=1)
+        dt_one = time.perf_counter() - t0
+        progress(f"cpu baseline: {n_all} intervals on {nthr} threads in {dt_all:.1f} s, "
+                 f"{n_one} on 1 thread in {dt_one:.1f} s")
+        line["cpu_baseline"] = {
+            "value": n_all / dt_all, "unit": "intervals/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{n_all} intervals ({n_tr} whole quad13 trajectories of the headline "
+                      f"batch, K=20, FP64), OpenMP over intervals on {nthr} threads, "
+                      f"{dt_all:.1f} s",
+            "one_thread": {"value": n_one / dt_one, "unit": "intervals/s", "cores": 1,
+                           "sample": f"{n_one} intervals on 1 thread, {dt_one:.1f} s"},
+            "host": cpu}
     print(json.dumps(line), flush=True)
+    if bad:
+        print(f"bench.py: parity above the bar for {bad}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -282,6 +282,15 @@ enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30,
  * is an error (CIS_ERR_DIM). */
 enum { CIS_SCHED_WAVES_1 = 0x40, CIS_SCHED_WAVES_2 = 0x80 };
 
+/* Optional bits of `sched` fixing the form of the defects pass that the
+ * reverse sweep starts from (CIS_BATCH_ADJOINT): CIS_SCHED_DEF_BODY takes
+ * two waves per interval (body-lane state recursion and a wave forming the
+ * integral rows, as cis_defects), CIS_SCHED_DEF_LANE one wave per interval
+ * (element-parallel right-hand side).  Without either bit both are timed
+ * with CIS_SCHED_TUNE, and the first is used otherwise.  Setting both bits
+ * is an error (CIS_ERR_DIM). */
+enum { CIS_SCHED_DEF_BODY = 0x200, CIS_SCHED_DEF_LANE = 0x400 };
+
 /*
  * Create a plan for n_traj trajectories (all of one dtype; CIS_BATCH_ADJOINT
  * needs CIS_F64).  ckpt_every: substeps between the checkpoints of the reverse
@@ -309,13 +318,15 @@ cis_status cis_batch_graph_run(cis_batch_plan *plan, int32_t op, void *stream);
 /* Description of a plan: number of model groups, and for group g (if
  * 0 <= g < groups) its trajectories, work items (intervals), units per item,
  * the persistent grid size chosen for it (0 = one workgroup per unit), the
- * waves per interval of its reverse sweep (0 without CIS_BATCH_ADJOINT) and
- * the register budget of its discretize kernel in waves per SIMD (1 or 2; 0
- * without CIS_BATCH_DISCRETIZE).  Any output pointer may be NULL. */
+ * waves per interval of its reverse sweep (0 without CIS_BATCH_ADJOINT), the
+ * register budget of its discretize kernel in waves per SIMD (1 or 2; 0
+ * without CIS_BATCH_DISCRETIZE) and the waves per interval of its defects
+ * pass (2: body lanes, 1: element lanes; 0 without CIS_BATCH_ADJOINT).  Any
+ * output pointer may be NULL. */
 cis_status cis_batch_plan_info(const cis_batch_plan *plan, int32_t g, int32_t *groups,
                                int32_t *n_traj, int32_t *n_items, int32_t *units_per_item,
                                int32_t *persist_blocks, int32_t *adjoint_waves,
-                               int32_t *waves_per_simd);
+                               int32_t *waves_per_simd, int32_t *defects_waves);
 
 /* Release a plan (NULL accepted); synchronizes the device first. */
 void cis_batch_plan_destroy(cis_batch_plan *plan);

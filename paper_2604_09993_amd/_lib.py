@@ -36,6 +36,8 @@ CIS_SCHED_ADJ_3 = 0x30
 CIS_SCHED_ADJ_4 = 0x100
 CIS_SCHED_WAVES_1 = 0x40
 CIS_SCHED_WAVES_2 = 0x80
+CIS_SCHED_DEF_BODY = 0x200
+CIS_SCHED_DEF_LANE = 0x400
 CIS_COMPOSE_VALU = 0
 CIS_COMPOSE_MFMA = 1
 
@@ -129,7 +131,7 @@ def load(build_if_missing: bool = True):
     lib.cis_batch_graph_run.restype = St
     lib.cis_batch_graph_run.argtypes = [P, I32, P]
     lib.cis_batch_plan_info.restype = St
-    lib.cis_batch_plan_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 7
+    lib.cis_batch_plan_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 8
     lib.cis_batch_plan_destroy.restype = None
     lib.cis_batch_plan_destroy.argtypes = [P]
     _lib = lib

@@ -8,6 +8,7 @@ memory and the current stream; every arithmetic step runs in the kernels.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -24,6 +25,13 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _alloc_on(stream):
+    """Allocate outputs and workspaces on the stream the kernels run on, so the
+    caching allocator does not hand their memory to other work before the
+    kernels have finished with it."""
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
 
 
 class CisModel:
@@ -103,10 +111,11 @@ def discretize(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None
     _check_inputs(cm, X, U, s, params)
     N, nx, m = s.shape[0], cm.nx, cm.m
     kw = dict(device=X.device, dtype=X.dtype)
-    out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
-               Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
-               d=torch.empty((nx, N), **kw))
-    out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+    with _alloc_on(stream):
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw))
+        out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
     sh = _shape(X, s, K)
     lib = _lib.load()
     _lib.check(lib.cis_discretize(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
@@ -158,13 +167,14 @@ def discretize_blocked(cm: CisModel, X, U, s, params, K, blocks, compose="valu",
     _check_inputs(cm, X, U, s, params)
     N, nx, m = s.shape[0], cm.nx, cm.m
     kw = dict(device=X.device, dtype=X.dtype)
-    out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
-               Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
-               d=torch.empty((nx, N), **kw))
-    out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
     nbytes = blocked_workspace_bytes(cm, N, K, blocks)
-    if ws is None or ws.numel() < nbytes:
-        ws = torch.empty((nbytes,), device=X.device, dtype=torch.uint8)
+    with _alloc_on(stream):
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw))
+        out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty((nbytes,), device=X.device, dtype=torch.uint8)
     sh = _shape(X, s, K)
     mode = {"valu": _lib.CIS_COMPOSE_VALU, "mfma": _lib.CIS_COMPOSE_MFMA}[compose]
     lib = _lib.load()
@@ -182,13 +192,15 @@ def defects(cm: CisModel, X, U, s, params, K, *, ckpt_every=None, stream=None):
     _check_inputs(cm, X, U, s, params)
     N, nx = s.shape[0], cm.nx
     kw = dict(device=X.device, dtype=X.dtype)
-    out = dict(d=torch.empty((nx, N), **kw), xprop=torch.empty((nx, N), **kw), ckpt=None)
     C = 0
     if ckpt_every is not None:
         C = int(ckpt_every)
         if C < 1 or K % C:
             raise ValueError("ckpt_every must divide K")
-        out["ckpt"] = torch.empty((K // C, cm.n, N), **kw)
+    with _alloc_on(stream):
+        out = dict(d=torch.empty((nx, N), **kw), xprop=torch.empty((nx, N), **kw), ckpt=None)
+        if C:
+            out["ckpt"] = torch.empty((K // C, cm.n, N), **kw)
     sh = _shape(X, s, K)
     lib = _lib.load()
     _lib.check(lib.cis_defects(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
@@ -215,12 +227,13 @@ def adjoint(cm: CisModel, X, U, s, params, K, ckpt, ckpt_every, seed, *, stream=
     if ckpt is None or ckpt.shape != (K // ckpt_every, cm.n, N) or not ckpt.is_contiguous():
         raise ValueError("ckpt must come from defects(..., ckpt_every=C) with the same K, C")
     ld = X.stride(0)
-    gX = torch.empty((nx, ld), **kw)
-    gU = torch.empty((max(m, 1), ld), **kw)
-    gs = torch.empty((N,), **kw)
-    gp = torch.empty((cm.np,), **kw)
     nbytes = adjoint_workspace_bytes(cm, N, K, X.dtype)
-    ws = torch.empty((max(nbytes, 1),), device=X.device, dtype=torch.uint8)
+    with _alloc_on(stream):
+        gX = torch.empty((nx, ld), **kw)
+        gU = torch.empty((max(m, 1), ld), **kw)
+        gs = torch.empty((N,), **kw)
+        gp = torch.empty((cm.np,), **kw)
+        ws = torch.empty((max(nbytes, 1),), device=X.device, dtype=torch.uint8)
     sh = _shape(X, s, K)
     lib = _lib.load()
     _lib.check(lib.cis_discretize_adjoint(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
@@ -300,7 +313,7 @@ class BatchPlan:
     """
 
     def __init__(self, trajs, ops=("discretize",), *, sched="tune", ckpt_every=0, graph=True,
-                 adjoint_waves=None, waves_per_simd=None, stream=None):
+                 adjoint_waves=None, waves_per_simd=None, defects_waves=None, stream=None):
         lib = _lib.load()
         if not trajs:
             raise ValueError("a batch needs at least one trajectory")
@@ -350,6 +363,9 @@ class BatchPlan:
         if waves_per_simd is not None:
             sched_code |= {1: _lib.CIS_SCHED_WAVES_1,
                            2: _lib.CIS_SCHED_WAVES_2}[int(waves_per_simd)]
+        if defects_waves is not None:
+            sched_code |= {2: _lib.CIS_SCHED_DEF_BODY,
+                           1: _lib.CIS_SCHED_DEF_LANE}[int(defects_waves)]
         _lib.check(lib.cis_batch_plan_create(arr, len(trajs), _dtype_code(dtype), self.ops,
                                              sched_code, int(ckpt_every), int(bool(graph)),
                                              _stream(stream), ctypes.byref(h)))
@@ -364,18 +380,19 @@ class BatchPlan:
 
     def groups(self):
         """Per model group: trajectories, items, units per item, persistent grid (0 = grid),
-        waves of the reverse sweep, register budget of the discretize kernel."""
+        waves of the reverse sweep, register budget of the discretize kernel, waves of the
+        defects pass."""
         lib = _lib.load()
         ng = ctypes.c_int32()
         _lib.check(lib.cis_batch_plan_info(self._h, -1, ctypes.byref(ng), None, None, None, None,
-                                           None, None))
+                                           None, None, None))
         res = []
         for g in range(ng.value):
-            v = [ctypes.c_int32() for _ in range(6)]
+            v = [ctypes.c_int32() for _ in range(7)]
             _lib.check(lib.cis_batch_plan_info(self._h, g, None, *[ctypes.byref(x) for x in v]))
             res.append(dict(n_traj=v[0].value, n_items=v[1].value, units_per_item=v[2].value,
                             persist_blocks=v[3].value, adjoint_waves=v[4].value,
-                            waves_per_simd=v[5].value))
+                            waves_per_simd=v[5].value, defects_waves=v[6].value))
         return res
 
     def close(self):

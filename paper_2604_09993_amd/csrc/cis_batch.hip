@@ -27,6 +27,7 @@ struct Group {
     int persist_blocks = 0;
     int disc_waves = 0;        // register budget of the discretize kernel (waves per SIMD)
     int adj_waves = 0;         // waves per interval of the chosen reverse sweep
+    int def_waves = 0;         // waves per interval of the chosen defects pass
     size_t fdesc_off = 0, ddesc_off = 0, adesc_off = 0, items_off = 0, cursor_off = 0;
     BatchGroupDev dev{};
     KLaunch disc, def, adj;
@@ -166,7 +167,7 @@ static cis_status build_graph(cis_batch_plan* p, int op) {
     return CIS_OK;
 }
 
-static bool sched_bits_unknown(int32_t s) { return (s & ~0x1FF) != 0; }
+static bool sched_bits_unknown(int32_t s) { return (s & ~0x7FF) != 0; }
 
 extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_traj,
                                             cis_dtype dtype, int32_t ops, int32_t sched,
@@ -185,9 +186,10 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
     int adj_force = (sched >> 4) & 3;   // 0: default, else waves of the reverse sweep
     const bool adj4 = (sched & CIS_SCHED_ADJ_4) != 0;
     const int waves_force = (sched >> 6) & 3;   // 0: default, 1 or 2: register budget
+    const int def_force = (sched >> 9) & 3;     // 0: default, 1: body lanes, 2: element lanes
     sched &= 0xF;
     if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE || sched_bits_unknown(sched_all) ||
-        waves_force == 3 || (adj4 && adj_force))
+        waves_force == 3 || def_force == 3 || (adj4 && adj_force))
         return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched_all);
     if (adj4) adj_force = 4;
     if (waves_force == 2 && dtype != CIS_F64)
@@ -428,8 +430,8 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             KLaunch def_body, def_lane;
             st = prep_defects_batch(g.model, dtype, dd, true, &def_body);
             if (st == CIS_OK) st = prep_defects_batch(g.model, dtype, dd, false, &def_lane);
-            g.def = def_body;
-            if (st == CIS_OK && sched == CIS_SCHED_TUNE) {
+            g.def = def_force == 2 ? def_lane : def_body;
+            if (st == CIS_OK && sched == CIS_SCHED_TUNE && !def_force) {
                 const float tb = time_launch(def_body, hs, 3);
                 const float tl = time_launch(def_lane, hs, 3);
                 if (tb < 0.f || tl < 0.f) {
@@ -471,6 +473,7 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             }
             g.adj = adjv[best];
             g.adj_waves = adjv[best].block.x / 64;
+            g.def_waves = g.def.block.x / 64;
         }
     }
     if (ops & CIS_BATCH_ADJOINT) {
@@ -530,7 +533,8 @@ extern "C" cis_status cis_batch_graph_run(cis_batch_plan* p, int32_t op, void* s
 extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, int32_t* groups,
                                           int32_t* n_traj, int32_t* n_items,
                                           int32_t* units_per_item, int32_t* persist_blocks,
-                                          int32_t* adjoint_waves, int32_t* waves_per_simd) {
+                                          int32_t* adjoint_waves, int32_t* waves_per_simd,
+                                          int32_t* defects_waves) {
     if (!p) return fail(CIS_ERR_NULL, "cis_batch_plan_info: plan is required");
     if (groups) *groups = (int32_t)p->groups.size();
     if (g < 0 || g >= (int32_t)p->groups.size()) return CIS_OK;
@@ -541,6 +545,7 @@ extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, in
     if (persist_blocks) *persist_blocks = gr.persist_blocks;
     if (adjoint_waves) *adjoint_waves = gr.adj_waves;
     if (waves_per_simd) *waves_per_simd = gr.disc_waves;
+    if (defects_waves) *defects_waves = gr.def_waves;
     return CIS_OK;
 }
 
