@@ -183,6 +183,26 @@ cis_status cis_discretize_adjoint(const cis_model *model, const cis_shape *shape
                                   const void *seed, void *gX, void *gU, void *gs,
                                   void *gparams, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reverse sweep as cis_discretize_adjoint, same arguments and outputs, with
+ * no workspace argument.  Its workspace is a device array inside the library,
+ * 8 MiB per GPU (held from the first call on that GPU until the process
+ * ends), enough for (2 m + P) N <= 1,048,576 doubles (quad13: N <= 9446);
+ * larger shapes return CIS_ERR_WORKSPACE.  Nothing is allocated on any call.
+ * Every call on one GPU uses that GPU's single array: calls that overlap on
+ * one GPU (concurrent streams, or threads without ordering) race and give
+ * undefined results; calls ordered on one stream are safe.  The array keeps
+ * the last call's partial sums; every entry a call reads it writes first.
+ * Other errors as for cis_discretize_adjoint.
+ */
+cis_status cis_discretize_adjoint_noalloc(const cis_model *model, const cis_shape *shape,
+                                          const void *X, const void *U, const void *s,
+                                          const void *params, const void *ckpt,
+                                          int32_t ckpt_every, const void *seed, void *gX,
+                                          void *gU, void *gs, void *gparams, void *stream);
+
 /* Composition of the substep blocks of cis_discretize_blocked. */
 enum { CIS_COMPOSE_VALU = 0, CIS_COMPOSE_MFMA = 1 };
 

@@ -47,7 +47,7 @@ EXPORTS = [
     "cis_model_destroy", "cis_model_dims", "cis_discretize", "cis_defects",
     "cis_adjoint_workspace_size", "cis_discretize_adjoint", "cis_batch_plan_create",
     "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
-    "cis_blocked_workspace_size", "cis_discretize_blocked",
+    "cis_blocked_workspace_size", "cis_discretize_blocked", "cis_discretize_adjoint_noalloc",
 ]
 
 
@@ -117,6 +117,9 @@ def load(build_if_missing: bool = True):
     lib.cis_discretize_adjoint.restype = St
     lib.cis_discretize_adjoint.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, P, I32]
                                            + [P] * 6 + [ctypes.c_size_t, P])
+    lib.cis_discretize_adjoint_noalloc.restype = St
+    lib.cis_discretize_adjoint_noalloc.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, P, I32]
+                                                   + [P] * 6)
     lib.cis_blocked_workspace_size.restype = St
     lib.cis_blocked_workspace_size.argtypes = [P, ctypes.POINTER(Shape), I32,
                                                ctypes.POINTER(ctypes.c_size_t)]

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 
 #include "../../include/cis.h"
 #include "cis_host.hpp"
@@ -896,6 +897,40 @@ cis_status prep_adjoint_reduce_batch(const void* rdesc, int n_traj, KLaunch* out
     return out->ok() ? CIS_OK : fail(CIS_ERR_DIM, "prep_adjoint_reduce_batch: launch record refused");
 }
 
+// Workspace of the allocation-free reverse sweep: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// Host code never passes the array's name to a kernel: its device address is
+// looked up once per device, with that device current, and kept here.
+constexpr size_t NOALLOC_DOUBLES = (size_t)1 << 20;   // 8 MiB per GPU
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static double* scratch_dev[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+static cis_status scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(CIS_ERR_HIP, "cis_discretize_adjoint_noalloc: hipGetDevice: %s",
+                    hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_adjoint_noalloc: device %d beyond %d",
+                    dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(CIS_ERR_HIP, "cis_discretize_adjoint_noalloc: hipGetSymbolAddress: %s",
+                        hipGetErrorString(e));
+        scratch_dev[dev] = (double*)ptr;
+    }
+    *out = scratch_dev[dev];
+    return CIS_OK;
+}
+
 }  // namespace cis
 
 using namespace cis;
@@ -939,4 +974,28 @@ extern "C" cis_status cis_discretize_adjoint(const cis_model* model, const cis_s
     CIS_TOPOLOGIES(CIS_DISPATCH_ADJ)
 #undef CIS_DISPATCH_ADJ
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_adjoint: topology has no compiled kernel");
+}
+
+extern "C" cis_status cis_discretize_adjoint_noalloc(const cis_model* model,
+                                                     const cis_shape* shape, const void* X,
+                                                     const void* U, const void* s,
+                                                     const void* params, const void* ckpt,
+                                                     int32_t ckpt_every, const void* seed,
+                                                     void* gX, void* gU, void* gs,
+                                                     void* gparams, void* stream) {
+    cis_status st = check_common(model, shape, X, U, s, params);
+    if (st != CIS_OK) return st;
+    const size_t need = ws_elems(model, shape->N);
+    if (need > NOALLOC_DOUBLES)
+        return fail(CIS_ERR_WORKSPACE,
+                    "cis_discretize_adjoint_noalloc: needs %zu bytes of workspace, more than "
+                    "the %zu bytes it holds ((2 m + P) N doubles; use cis_discretize_adjoint)",
+                    need * sizeof(double), NOALLOC_DOUBLES * sizeof(double));
+    double* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != CIS_OK) return st;
+    // same validation and kernels as cis_discretize_adjoint, with the device
+    // array as the workspace
+    return cis_discretize_adjoint(model, shape, X, U, s, params, ckpt, ckpt_every, seed, gX, gU,
+                                  gs, gparams, ws, NOALLOC_DOUBLES * sizeof(double), stream);
 }

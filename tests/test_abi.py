@@ -133,6 +133,31 @@ def test_entry_points_validate_before_launch():
     assert lib.cis_defects(h, ctypes.byref(good), P(8), P(8), P(8), P(8), None, None, None, 0,
                            None) == _lib.CIS_ERR_NULL
     assert lib.cis_status_string(_lib.CIS_ERR_DIM) == b"dimension out of range"
+    # workspaces: missing or short workspaces are refused before any launch
+    need = ctypes.c_size_t(0)
+    assert lib.cis_adjoint_workspace_size(h, ctypes.byref(good), ctypes.byref(need)) == 0
+    assert need.value == (2 * model.m + model.n_params) * 5 * 8
+    adj = lambda ws, nb: lib.cis_discretize_adjoint(h, ctypes.byref(good), P(8), P(8), P(8), P(8),
+                                                     P(8), 2, P(8), P(8), P(8), P(8), P(8), ws,
+                                                     nb, None)
+    assert adj(None, need.value) == _lib.CIS_ERR_WORKSPACE
+    assert adj(P(8), need.value - 8) == _lib.CIS_ERR_WORKSPACE
+    sh4 = _lib.Shape(5, 4, _lib.CIS_F64, 0, 6, 5)
+    assert lib.cis_blocked_workspace_size(h, ctypes.byref(sh4), 2, ctypes.byref(need)) == 0
+    blk = lambda ws, nb: lib.cis_discretize_blocked(h, ctypes.byref(sh4), P(8), P(8), P(8), P(8),
+                                                    2, _lib.CIS_COMPOSE_VALU, P(8), P(8), P(8),
+                                                    P(8), P(8), None, ws, nb, None)
+    assert blk(None, need.value) == _lib.CIS_ERR_WORKSPACE
+    assert blk(P(8), need.value - 8) == _lib.CIS_ERR_WORKSPACE
+    # the allocation-free reverse sweep holds (2 m + P) N <= 2^20 doubles
+    big = (1 << 20) // (2 * model.m + model.n_params) + 1
+    shb = _lib.Shape(big, 4, _lib.CIS_F64, 0, big + 1, big)
+    assert lib.cis_discretize_adjoint_noalloc(h, ctypes.byref(shb), P(8), P(8), P(8), P(8), P(8),
+                                              2, P(8), P(8), P(8), P(8), P(8),
+                                              None) == _lib.CIS_ERR_WORKSPACE
+    assert b"cis_discretize_adjoint_noalloc" in lib.cis_last_error()
+    assert lib.cis_discretize_adjoint_noalloc(h, None, P(8), P(8), P(8), P(8), P(8), 2, P(8),
+                                              P(8), P(8), P(8), P(8), None) == _lib.CIS_ERR_NULL
     lib.cis_model_destroy(h)
 
 
