@@ -203,6 +203,30 @@ cis_status cis_discretize_adjoint_noalloc(const cis_model *model, const cis_shap
                                           int32_t ckpt_every, const void *seed, void *gX,
                                           void *gU, void *gs, void *gparams, void *stream);
 
+/* Bytes of device workspace cis_discretize_split needs for this shape (the
+ * model must have legs with links, else CIS_ERR_UNSUPPORTED). */
+cis_status cis_split_workspace_size(const cis_model *model, const cis_shape *shape,
+                                    size_t *bytes);
+
+/*
+ * Same outputs as cis_discretize (same discrete map, Sec. IV-B and Sec. VI;
+ * dtype CIS_F64 or CIS_F32), computed in two launches for throughput on many
+ * intervals.  The first integrates the nominal state, the integral rows and
+ * S, and stores every RK stage's Jacobian coefficients in `ws` (a compact
+ * record per stage); the second integrates the columns of Phi_x, B- and B+
+ * from those records, one wave per leg and one column per lane, reading the
+ * coefficients with scalar loads.  Results equal those of cis_discretize up
+ * to the order of floating-point sums.  waves (1 or 2): register budget of
+ * the second launch in waves per SIMD (2: two workgroups share a compute
+ * unit).  ws must hold cis_split_workspace_size bytes, 8-byte aligned; its
+ * contents are scratch.  Models without legs with links: CIS_ERR_UNSUPPORTED.
+ */
+cis_status cis_discretize_split(const cis_model *model, const cis_shape *shape, const void *X,
+                                const void *U, const void *s, const void *params,
+                                int32_t waves, void *A, void *Bm, void *Bp, void *S,
+                                void *defect, void *xprop, void *ws, size_t ws_bytes,
+                                void *stream);
+
 /* Composition of the substep blocks of cis_discretize_blocked. */
 enum { CIS_COMPOSE_VALU = 0, CIS_COMPOSE_MFMA = 1 };
 
@@ -311,6 +335,18 @@ enum { CIS_SCHED_WAVES_1 = 0x40, CIS_SCHED_WAVES_2 = 0x80 };
  * is an error (CIS_ERR_DIM). */
 enum { CIS_SCHED_DEF_BODY = 0x200, CIS_SCHED_DEF_LANE = 0x400 };
 
+/* Optional bits of `sched` fixing the form of the discretize step per model:
+ * CIS_SCHED_SPLIT takes the two-launch form of cis_discretize_split for every
+ * model with legs with links (others keep the one-launch form);
+ * CIS_SCHED_FUSED takes the one-launch form.  Without either bit both forms
+ * (and, for the split form, both register budgets of its tangent launch, which
+ * CIS_SCHED_WAVES_1/2 otherwise fix) are timed with CIS_SCHED_TUNE, and the
+ * one-launch form is used otherwise.  The split form keeps its stage records
+ * in plan memory (about 8 (8 + 4 n_j + 4 K R) bytes per interval in FP64, R
+ * the record length: 280 for quad13, 120 for cheetah7).  Setting both bits is
+ * an error (CIS_ERR_DIM). */
+enum { CIS_SCHED_SPLIT = 0x800, CIS_SCHED_FUSED = 0x1000 };
+
 /*
  * Create a plan for n_traj trajectories (all of one dtype; CIS_BATCH_ADJOINT
  * needs CIS_F64).  ckpt_every: substeps between the checkpoints of the reverse
@@ -347,6 +383,12 @@ cis_status cis_batch_plan_info(const cis_batch_plan *plan, int32_t g, int32_t *g
                                int32_t *n_traj, int32_t *n_items, int32_t *units_per_item,
                                int32_t *persist_blocks, int32_t *adjoint_waves,
                                int32_t *waves_per_simd, int32_t *defects_waves);
+
+/* Discretize form of group g (0 <= g < groups): *split = 1 when it runs in
+ * the split form, with *tangent_waves its register budget (waves per SIMD),
+ * else 0 and 0.  Any output pointer may be NULL; g out of range: CIS_ERR_DIM. */
+cis_status cis_batch_plan_discretize_form(const cis_batch_plan *plan, int32_t g, int32_t *split,
+                                          int32_t *tangent_waves);
 
 /* Release a plan (NULL accepted); synchronizes the device first. */
 void cis_batch_plan_destroy(cis_batch_plan *plan);

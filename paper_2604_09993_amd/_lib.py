@@ -38,6 +38,8 @@ CIS_SCHED_WAVES_1 = 0x40
 CIS_SCHED_WAVES_2 = 0x80
 CIS_SCHED_DEF_BODY = 0x200
 CIS_SCHED_DEF_LANE = 0x400
+CIS_SCHED_SPLIT = 0x800
+CIS_SCHED_FUSED = 0x1000
 CIS_COMPOSE_VALU = 0
 CIS_COMPOSE_MFMA = 1
 
@@ -48,6 +50,7 @@ EXPORTS = [
     "cis_adjoint_workspace_size", "cis_discretize_adjoint", "cis_batch_plan_create",
     "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
     "cis_blocked_workspace_size", "cis_discretize_blocked", "cis_discretize_adjoint_noalloc",
+    "cis_split_workspace_size", "cis_discretize_split", "cis_batch_plan_discretize_form",
 ]
 
 
@@ -120,6 +123,12 @@ def load(build_if_missing: bool = True):
     lib.cis_discretize_adjoint_noalloc.restype = St
     lib.cis_discretize_adjoint_noalloc.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, P, I32]
                                                    + [P] * 6)
+    lib.cis_split_workspace_size.restype = St
+    lib.cis_split_workspace_size.argtypes = [P, ctypes.POINTER(Shape),
+                                             ctypes.POINTER(ctypes.c_size_t)]
+    lib.cis_discretize_split.restype = St
+    lib.cis_discretize_split.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, I32]
+                                         + [P] * 7 + [ctypes.c_size_t, P])
     lib.cis_blocked_workspace_size.restype = St
     lib.cis_blocked_workspace_size.argtypes = [P, ctypes.POINTER(Shape), I32,
                                                ctypes.POINTER(ctypes.c_size_t)]
@@ -135,6 +144,8 @@ def load(build_if_missing: bool = True):
     lib.cis_batch_graph_run.argtypes = [P, I32, P]
     lib.cis_batch_plan_info.restype = St
     lib.cis_batch_plan_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 8
+    lib.cis_batch_plan_discretize_form.restype = St
+    lib.cis_batch_plan_discretize_form.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.cis_batch_plan_destroy.restype = None
     lib.cis_batch_plan_destroy.argtypes = [P]
     _lib = lib

@@ -187,6 +187,41 @@ def discretize_blocked(cm: CisModel, X, U, s, params, K, blocks, compose="valu",
     return out
 
 
+def split_workspace_bytes(cm: CisModel, N, K, dtype=torch.float64):
+    sh = _lib.Shape(N, int(K), _dtype_code(dtype), 0, N + 1, N)
+    nbytes = ctypes.c_size_t()
+    _lib.check(_lib.load().cis_split_workspace_size(cm.handle, ctypes.byref(sh),
+                                                    ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def discretize_split(cm: CisModel, X, U, s, params, K, *, waves=1, with_xprop=True, ws=None,
+                     stream=None):
+    """Same outputs as :func:`discretize`, computed by the two-launch split
+    form (stage coefficient records, then one wave per leg over 64 tangent
+    columns).  ws: optional preallocated uint8 workspace."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    kw = dict(device=X.device, dtype=X.dtype)
+    nbytes = split_workspace_bytes(cm, N, K, X.dtype)
+    with _alloc_on(stream):
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw))
+        out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty((nbytes,), device=X.device, dtype=torch.uint8)
+    sh = _shape(X, s, K)
+    lib = _lib.load()
+    _lib.check(lib.cis_discretize_split(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                        _ptr(params), int(waves), _ptr(out["A"]),
+                                        _ptr(out["Bm"] if m else None),
+                                        _ptr(out["Bp"] if m else None), _ptr(out["S"]),
+                                        _ptr(out["d"]), _ptr(out["xprop"]), _ptr(ws),
+                                        ws.numel(), _stream(stream)))
+    return out
+
+
 def defects(cm: CisModel, X, U, s, params, K, *, ckpt_every=None, stream=None):
     """F~ and defects only; optional substep checkpoints [K/C, n, N] for the adjoint."""
     _check_inputs(cm, X, U, s, params)
@@ -313,7 +348,8 @@ class BatchPlan:
     """
 
     def __init__(self, trajs, ops=("discretize",), *, sched="tune", ckpt_every=0, graph=True,
-                 adjoint_waves=None, waves_per_simd=None, defects_waves=None, stream=None):
+                 adjoint_waves=None, waves_per_simd=None, defects_waves=None, form=None,
+                 stream=None):
         lib = _lib.load()
         if not trajs:
             raise ValueError("a batch needs at least one trajectory")
@@ -366,6 +402,8 @@ class BatchPlan:
         if defects_waves is not None:
             sched_code |= {2: _lib.CIS_SCHED_DEF_BODY,
                            1: _lib.CIS_SCHED_DEF_LANE}[int(defects_waves)]
+        if form is not None:
+            sched_code |= {"split": _lib.CIS_SCHED_SPLIT, "fused": _lib.CIS_SCHED_FUSED}[form]
         _lib.check(lib.cis_batch_plan_create(arr, len(trajs), _dtype_code(dtype), self.ops,
                                              sched_code, int(ckpt_every), int(bool(graph)),
                                              _stream(stream), ctypes.byref(h)))
@@ -381,7 +419,7 @@ class BatchPlan:
     def groups(self):
         """Per model group: trajectories, items, units per item, persistent grid (0 = grid),
         waves of the reverse sweep, register budget of the discretize kernel, waves of the
-        defects pass."""
+        defects pass, and the discretize form (split: 1 for the two-launch form)."""
         lib = _lib.load()
         ng = ctypes.c_int32()
         _lib.check(lib.cis_batch_plan_info(self._h, -1, ctypes.byref(ng), None, None, None, None,
@@ -390,9 +428,13 @@ class BatchPlan:
         for g in range(ng.value):
             v = [ctypes.c_int32() for _ in range(7)]
             _lib.check(lib.cis_batch_plan_info(self._h, g, None, *[ctypes.byref(x) for x in v]))
+            sp, tw = ctypes.c_int32(), ctypes.c_int32()
+            _lib.check(lib.cis_batch_plan_discretize_form(self._h, g, ctypes.byref(sp),
+                                                          ctypes.byref(tw)))
             res.append(dict(n_traj=v[0].value, n_items=v[1].value, units_per_item=v[2].value,
                             persist_blocks=v[3].value, adjoint_waves=v[4].value,
-                            waves_per_simd=v[5].value, defects_waves=v[6].value))
+                            waves_per_simd=v[5].value, defects_waves=v[6].value,
+                            split=sp.value))
         return res
 
     def close(self):

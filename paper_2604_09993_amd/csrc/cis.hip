@@ -192,100 +192,6 @@ __device__ __forceinline__ void tangent_stage(const Interval<T, TP>& iv, TLane<T
 #undef ZV
 }
 
-// The dilation column S on body lanes (its own column group in the latency
-// layout): lane b < NB holds the six rows of body b; a foot lane holds the
-// cross-complementarity row of its contact (the torso lane all of them when
-// the legs have no links); every body lane integrates its part of the
-// violation row.  The Jacobian product is that of the tangent lanes with the
-// joint terms exchanged between parent and child lanes, plus the F~ forcing.
-template <class T, class TP>
-struct SLane {
-    static constexpr int NCL = TP::D == 0 ? (TP::L > 0 ? TP::L : 1) : 1;   // cc rows per lane
-    T zs[6], zb[6], za[6];
-    T ycc[NCL], yct;
-};
-
-template <class T, class TP, int ST>
-__device__ __forceinline__ void s_stage(const Interval<T, TP>& iv, const BodyConst<T, TP>& c,
-                                        SLane<T, TP>& z, const T* __restrict__ cf, int lane) {
-    constexpr int NB = TP::NB, NQ = TP::NQ, NX = TP::NX, D = TP::D, L = TP::L;
-    constexpr int NCL = SLane<T, TP>::NCL;
-    using C = Coef<TP>;
-    const T s = iv.s, h = iv.h;
-    const int b = c.b;
-    const T x = z.zs[0], y = z.zs[1], th = z.zs[2];
-    const T vx = z.zs[3], vy = z.zs[4], om = z.zs[5];
-    T kv[3] = {cf[C::F + NQ + 3 * b], cf[C::F + NQ + 3 * b + 1],
-               cf[C::F + NQ + 3 * b + 2] + cf[C::CTH + b] * th};
-    T kct = lane < NB ? cf[C::CTP + b] : T(0);
-    T kcc[NCL];
-#pragma unroll
-    for (int l = 0; l < NCL; ++l) kcc[l] = T(0);
-    if constexpr (D >= 1) {
-        // own joint (this body is its child): stiffness and damping, and the
-        // joint rows of the violation integrand; the parent's share of the
-        // stiffness and damping torque goes back to the parent lane
-        const bool pt = c.p == 0;
-        const T thp = from_parent<TP>(th, pt), omp = from_parent<TP>(om, pt);
-        const T xp = from_parent<TP>(x, pt), yp = from_parent<TP>(y, pt);
-        T tp = T(0);
-        if (c.joint) {
-            const int j = c.j;
-            const T dth = th - thp, dom = om - omp;
-            kv[2] -= iv.kc[j][2] * dth + iv.kc[j][3] * dom;
-            tp = iv.kc[j][0] * dth + iv.kc[j][1] * dom;
-            const T* jh = cf + C::JH + 4 * j;
-            kct += jh[0] * (xp - x) + jh[1] * (yp - y) + jh[2] * thp + jh[3] * th;
-        }
-        kv[2] += from_children<TP>(tp, b);
-    }
-    if constexpr (L >= 1) {
-#pragma unroll
-        for (int l = 0; l < NCL; ++l) {
-            const bool on = D >= 1 ? c.contact : (lane == 0);
-            const int i = D >= 1 ? c.i : l;
-            if (on) {
-                const T* ct = cf + C::CT + C::NCT * i;
-                const T dPx = x - ct[C_AY] * th;
-                const T dPy = y + ct[C_AX] * th;
-                kv[0] += ct[C_FXP] * dPx;
-                kv[1] += ct[C_FYP] * dPx;
-                kv[2] += ct[C_TP] * dPx;
-                kcc[l] = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * vx + ct[C_EYD] * vy +
-                         ct[C_EOM] * om + ct[C_ETH] * th + cf[C::F + NX + i];
-                kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
-            }
-        }
-    }
-    // classical RK4 combination (stage ST known at compile time)
-    constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
-    const T an = (ST == 2) ? h : T(0.5) * h;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const T kq = s * z.zs[3 + k] + cf[C::F + 3 * b + k];
-        if (ST == 0) z.za[k] = kq;
-        else z.za[k] += T(WK) * kq;
-        if (ST < 3) z.zs[k] = z.zb[k] + an * kq;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (ST == 0) z.za[3 + k] = kv[k];
-        else z.za[3 + k] += T(WK) * kv[k];
-        if (ST < 3) z.zs[3 + k] = z.zb[3 + k] + an * kv[k];
-    }
-    const T h6 = iv.h6;
-#pragma unroll
-    for (int l = 0; l < NCL; ++l) z.ycc[l] += (h6 * T(WK)) * kcc[l];
-    z.yct += (h6 * T(WK)) * kct;
-    if (ST == 3) {
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            z.zb[r] += h6 * z.za[r];
-            z.zs[r] = z.zb[r];
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // K2: discretize.  One workgroup per (interval, column group), three wave roles
 // separated by one workgroup barrier per pipeline step:

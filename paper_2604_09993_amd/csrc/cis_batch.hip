@@ -29,8 +29,13 @@ struct Group {
     int adj_waves = 0;         // waves per interval of the chosen reverse sweep
     int def_waves = 0;         // waves per interval of the chosen defects pass
     size_t fdesc_off = 0, ddesc_off = 0, adesc_off = 0, items_off = 0, cursor_off = 0;
+    // split form: record offsets per item (device), the group's part of the
+    // record memory (elements), and whether the chosen discretize form is it
+    bool split_ok = false, split = false;
+    size_t recoff_off = 0, rec_base = 0;
+    std::vector<int64_t> rec_off;
     BatchGroupDev dev{};
-    KLaunch disc, def, adj;
+    KLaunch disc, disc_b, def, adj;   // disc_b: tangent launch of the split form
 };
 
 int auto_ckpt(int K) {
@@ -50,6 +55,7 @@ struct cis_batch_plan {
     std::vector<Group> groups;
     size_t rdesc_off = 0;
     unsigned char* dmem = nullptr;
+    unsigned char* recmem = nullptr;   // stage records of the split form
     KLaunch red;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -62,6 +68,7 @@ static void plan_free(cis_batch_plan* p) {
         if (p->graph[i]) (void)hipGraphDestroy(p->graph[i]);
     }
     if (p->dmem) (void)hipFree(p->dmem);
+    if (p->recmem) (void)hipFree(p->recmem);
     delete p;
 }
 
@@ -139,6 +146,31 @@ static float time_launch(KLaunch& l, hipStream_t s, int reps) {
     return ts[ts.size() / 2];
 }
 
+// Median time in microseconds of `reps` launches of a pair (the split form).
+static float time_pair(KLaunch& a, KLaunch& b, hipStream_t s, int reps) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    std::vector<float> ts;
+    bool ok = a.launch(s) == hipSuccess && b.launch(s) == hipSuccess;   // warm-up
+    for (int r = 0; ok && r < reps; ++r) {
+        ok = hipEventRecord(e0, s) == hipSuccess && a.launch(s) == hipSuccess &&
+             b.launch(s) == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        ts.push_back(ms * 1e3f);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok || ts.empty()) return -1.f;
+    std::sort(ts.begin(), ts.end());
+    return ts[ts.size() / 2];
+}
+
 static cis_status build_graph(cis_batch_plan* p, int op) {
     const int gi = op == CIS_BATCH_DISCRETIZE ? 0 : 1;
     hipGraph_t g = nullptr;
@@ -150,6 +182,8 @@ static cis_status build_graph(cis_batch_plan* p, int op) {
         if (op == CIS_BATCH_DISCRETIZE) {
             if (gr.disc.node(g, nullptr, 0, &n0) != hipSuccess)
                 return fail(CIS_ERR_HIP, "graph: discretize node refused");
+            if (gr.split && gr.disc_b.node(g, &n0, 1, &n1) != hipSuccess)
+                return fail(CIS_ERR_HIP, "graph: tangent node refused");
         } else {
             if (gr.def.node(g, nullptr, 0, &n0) != hipSuccess ||
                 gr.adj.node(g, &n0, 1, &n1) != hipSuccess)
@@ -167,7 +201,7 @@ static cis_status build_graph(cis_batch_plan* p, int op) {
     return CIS_OK;
 }
 
-static bool sched_bits_unknown(int32_t s) { return (s & ~0x7FF) != 0; }
+static bool sched_bits_unknown(int32_t s) { return (s & ~0x1FFF) != 0; }
 
 extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_traj,
                                             cis_dtype dtype, int32_t ops, int32_t sched,
@@ -187,9 +221,10 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
     const bool adj4 = (sched & CIS_SCHED_ADJ_4) != 0;
     const int waves_force = (sched >> 6) & 3;   // 0: default, 1 or 2: register budget
     const int def_force = (sched >> 9) & 3;     // 0: default, 1: body lanes, 2: element lanes
+    const int split_force = (sched >> 11) & 3;  // 0: default, 1: split form, 2: fused form
     sched &= 0xF;
     if (sched < CIS_SCHED_GRID || sched > CIS_SCHED_TUNE || sched_bits_unknown(sched_all) ||
-        waves_force == 3 || def_force == 3 || (adj4 && adj_force))
+        waves_force == 3 || def_force == 3 || split_force == 3 || (adj4 && adj_force))
         return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched_all);
     if (adj4) adj_force = 4;
     if (waves_force == 2 && dtype != CIS_F64)
@@ -255,6 +290,26 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         off = align_up(off + g.items.size() * sizeof(int2));
         g.cursor_off = off;
         off = align_up(off + 2 * sizeof(int));
+        // split form: candidate when forced, or timed with CIS_SCHED_TUNE
+        g.split_ok = (ops & CIS_BATCH_DISCRETIZE) && split_form_supported(g.model) &&
+                     split_force != 2 && (split_force == 1 || sched == CIS_SCHED_TUNE);
+        if (g.split_ok) {
+            g.recoff_off = off;
+            off = align_up(off + g.items.size() * sizeof(int64_t));
+        }
+    }
+    size_t rec_total = 0;   // elements
+    for (Group& g : p->groups) {
+        if (!g.split_ok) continue;
+        g.rec_base = rec_total;
+        int64_t cum = 0;
+        g.rec_off.resize(g.items.size());
+        for (size_t it = 0; it < g.items.size(); ++it) {
+            g.rec_off[it] = cum;
+            cum += split_elems_per_interval(g.model, trajs[g.trajs[g.items[it].x]].substeps);
+        }
+        rec_total += (size_t)cum;
+        rec_total = (rec_total + 31) / 32 * 32;
     }
     p->rdesc_off = off;
     off = align_up(off + (ops & CIS_BATCH_ADJOINT ? n_traj * sizeof(RedDesc) : 0));
@@ -279,6 +334,14 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         return fail(CIS_ERR_HIP, "cis_batch_plan_create: hipMalloc(%zu): %s", off, hipGetErrorString(e));
     }
     unsigned char* d = p->dmem;
+    if (rec_total > 0) {
+        e = hipMalloc((void**)&p->recmem, rec_total * es);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return fail(CIS_ERR_HIP, "cis_batch_plan_create: hipMalloc(%zu) of the stage records: %s",
+                        rec_total * es, hipGetErrorString(e));
+        }
+    }
 
     // host image of the descriptor part
     std::vector<unsigned char> img(host_part, 0);
@@ -333,6 +396,8 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         }
         if (!g.items.empty())
             std::memcpy(&img[g.items_off], g.items.data(), g.items.size() * sizeof(int2));
+        if (g.split_ok && !g.items.empty())
+            std::memcpy(&img[g.recoff_off], g.rec_off.data(), g.items.size() * sizeof(int64_t));
     }
     if (ops & CIS_BATCH_ADJOINT) {
         for (int i = 0; i < n_traj; ++i) {
@@ -371,14 +436,33 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         g.dev.items = (const int2*)(d + g.items_off);
         g.dev.n_items = (int)g.items.size();
         g.dev.cursor = (int*)(d + g.cursor_off);
+        g.dev.rec = g.split_ok ? (void*)(p->recmem + g.rec_base * es) : nullptr;
+        g.dev.rec_off = g.split_ok ? (const int64_t*)(d + g.recoff_off) : nullptr;
         cis_status st;
         if (ops & CIS_BATCH_DISCRETIZE) {
             // candidates: (grid | persistent) x register budget (1 or 2 waves
             // per SIMD; FP64 only has the second); the schedule bits fix some
             const int units = g.dev.n_items * g.units_per_item;
-            struct Cand { KLaunch l; int pblocks, waves; };
+            struct Cand { KLaunch l, lb; int pblocks, waves; bool split; };
             std::vector<Cand> cands;
+            if (g.split_ok) {
+                for (int w = 1; w <= 2; ++w) {
+                    if (waves_force ? w != waves_force : (sched != CIS_SCHED_TUNE && w != 1))
+                        continue;
+                    Cand c;
+                    c.pblocks = 0;
+                    c.waves = w;
+                    c.split = true;
+                    st = prep_split_batch(g.model, dtype, g.dev, w, &c.l, &c.lb);
+                    if (st != CIS_OK) {
+                        plan_free(p);
+                        return st;
+                    }
+                    cands.push_back(c);
+                }
+            }
             for (int w = 1; w <= (dtype == CIS_F64 ? 2 : 1); ++w) {
+                if (split_force == 1 && g.split_ok) break;
                 if (waves_force ? w != waves_force : (sched != CIS_SCHED_TUNE && w != 1)) continue;
                 KLaunch probe;
                 st = prep_discretize_batch(g.model, dtype, g.dev, 1, w, &probe);
@@ -397,6 +481,7 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
                     Cand c;
                     c.pblocks = pers ? pblocks : 0;
                     c.waves = w;
+                    c.split = false;
                     st = prep_discretize_batch(g.model, dtype, g.dev, c.pblocks, w, &c.l);
                     if (st != CIS_OK) {
                         plan_free(p);
@@ -409,7 +494,8 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             if (cands.size() > 1) {
                 float tbest = -1.f;
                 for (size_t c = 0; c < cands.size(); ++c) {
-                    const float t = time_launch(cands[c].l, hs, 3);
+                    const float t = cands[c].split ? time_pair(cands[c].l, cands[c].lb, hs, 3)
+                                                   : time_launch(cands[c].l, hs, 3);
                     if (t < 0.f) {
                         plan_free(p);
                         return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
@@ -423,6 +509,8 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             g.persist_blocks = cands[best].pblocks;
             g.disc_waves = cands[best].waves;
             g.disc = cands[best].l;
+            g.split = cands[best].split;
+            if (g.split) g.disc_b = cands[best].lb;
         }
         if (ops & CIS_BATCH_ADJOINT) {
             BatchGroupDev dd = g.dev;
@@ -476,6 +564,18 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             g.def_waves = g.def.block.x / 64;
         }
     }
+    if (p->recmem) {
+        bool used = false;
+        for (const Group& g : p->groups) used = used || g.split;
+        if (!used) {
+            if (hipStreamSynchronize(hs) != hipSuccess) {
+                plan_free(p);
+                return fail(CIS_ERR_HIP, "cis_batch_plan_create: synchronization failed");
+            }
+            (void)hipFree(p->recmem);
+            p->recmem = nullptr;
+        }
+    }
     if (ops & CIS_BATCH_ADJOINT) {
         cis_status st = prep_adjoint_reduce_batch(d + p->rdesc_off, n_traj, &p->red);
         if (st != CIS_OK) {
@@ -506,6 +606,7 @@ extern "C" cis_status cis_batch_run(cis_batch_plan* p, int32_t op, void* stream)
         hipError_t e;
         if (op == CIS_BATCH_DISCRETIZE) {
             e = g.disc.launch(hs);
+            if (e == hipSuccess && g.split) e = g.disc_b.launch(hs);
         } else {
             e = g.def.launch(hs);
             if (e == hipSuccess) e = g.adj.launch(hs);
@@ -546,6 +647,17 @@ extern "C" cis_status cis_batch_plan_info(const cis_batch_plan* p, int32_t g, in
     if (adjoint_waves) *adjoint_waves = gr.adj_waves;
     if (waves_per_simd) *waves_per_simd = gr.disc_waves;
     if (defects_waves) *defects_waves = gr.def_waves;
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_plan_discretize_form(const cis_batch_plan* p, int32_t g,
+                                                     int32_t* split, int32_t* tangent_waves) {
+    if (!p) return fail(CIS_ERR_NULL, "cis_batch_plan_discretize_form: plan is required");
+    if (g < 0 || g >= (int32_t)p->groups.size())
+        return fail(CIS_ERR_DIM, "cis_batch_plan_discretize_form: group %d out of range", g);
+    const Group& gr = p->groups[g];
+    if (split) *split = gr.split ? 1 : 0;
+    if (tangent_waves) *tangent_waves = gr.split ? gr.disc_waves : 0;
     return CIS_OK;
 }
 

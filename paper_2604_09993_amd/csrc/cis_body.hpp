@@ -287,14 +287,14 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
 // one workgroup barrier; without WRITE only the integral-row integrands are
 // formed (nothing is stored).
 // ---------------------------------------------------------------------------
-template <class T, class TP, bool SPLIT = false, bool WRITE = true>
+template <class T, class TP, bool SPLIT = false, bool WRITE = true, class LY = CoefDense<TP>,
+          bool BURST = (sizeof(T) == 8)>
 __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                            const BodyConst<T, TP>& c, const T* xs,
                                            const T (*cs)[2], const T* fv, T tau, T* cf, T& ycc,
                                            T& yct, int lane) {
-    constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, NX = TP::NX, M = TP::M;
-    using C = Coef<TP>;
+    constexpr int NB = TP::NB, NQ = TP::NQ, NX = TP::NX;
     const T s = iv.s, omt = T(1) - tau;
     const int b = c.b, p = c.p;
     const T cb = cs[b][0], sb = cs[b][1];
@@ -369,80 +369,180 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         fa[k] = fv[3 * b + k];
     }
     if constexpr (WRITE) {
-        // FP64: all values and addresses are formed first and stored in one
-        // burst, since a register overwritten right after an LDS store waits
-        // until the LDS unit has read it (measured faster); FP32 keeps the
-        // compiler's interleaved order (measured faster there).
-        constexpr int NV = 43;
+        // BURST (FP64 by default): all values and addresses are formed first
+        // and stored in one burst, since a register overwritten right after an
+        // LDS store waits until the LDS unit has read it (measured faster);
+        // FP32 keeps the compiler's interleaved order (measured faster there).
+        constexpr int NV = BURST ? 42 + LY::TORSO_COPIES : 1;
         T val[NV];
         T* ptr[NV];
         int e = 0;
         const int j = c.j, i = c.i;
         // one sink slot per lane: stores of many lanes to one LDS address serialize
-        T* tr = cf + C::TRASH + lane;
+        T* tr = cf + LY::TRASH + lane;
         auto put = [&](bool ok, int off, T v, int t = 0) {
-            ptr[e] = ok ? cf + off : tr + t;
-            val[e] = v;
-            ++e;
+            T* const a = ok ? cf + off : tr + t;
+            if constexpr (BURST) {
+                ptr[e] = a;
+                val[e] = v;
+                ++e;
+            } else {
+                *a = v;
+            }
         };
         // joint rows of the violation integrand and the joint-force torques
-        put(jl, C::JH + 4 * j + 0, s * d0);
-        put(jl, C::JH + 4 * j + 1, s * d1);
-        put(jl, C::JH + 4 * j + 2, s * (d1 * apx - d0 * apy));
-        put(jl, C::JH + 4 * j + 3, s * (d0 * acy - d1 * acx));
-        const int gvj = C::GV + NJ + 2 * j;
-        put(jl, gvj + (3 * p + 2) * M, -apy * ip);
-        put(jl, gvj + (3 * p + 2) * M + 1, apx * ip);
-        put(jl, gvj + (3 * b + 2) * M, acy * ii);
-        put(jl, gvj + (3 * b + 2) * M + 1, -acx * ii);
+        put(jl, LY::jh(j, 0), s * d0);
+        put(jl, LY::jh(j, 1), s * d1);
+        put(jl, LY::jh(j, 2), s * (d1 * apx - d0 * apy));
+        put(jl, LY::jh(j, 3), s * (d0 * acy - d1 * acx));
+        put(jl, LY::gv_joint(j, 0, p, b, 0), -apy * ip);
+        put(jl, LY::gv_joint(j, 0, p, b, 1), apx * ip);
+        put(jl, LY::gv_joint(j, 1, p, b, 0), acy * ii);
+        put(jl, LY::gv_joint(j, 1, p, b, 1), -acx * ii);
         // contact terms
-        const int ct = C::CT + C::NCT * i;
-        put(cl, ct + C_AX, ax, C_AX);
-        put(cl, ct + C_AY, ay, C_AY);
-        put(cl, ct + C_FXP, dfx * im, C_FXP);
-        put(cl, ct + C_FYP, dfy * im, C_FYP);
-        put(cl, ct + C_TP, (ax * dfy - ay * dfx) * ii, C_TP);
-        put(cl, ct + C_EPX, s * (lnb * f.dsd_px + gv * dvt_px), C_EPX);
-        put(cl, ct + C_EPY, s * (lnb * f.dsd_py), C_EPY);
-        put(cl, ct + C_EXD, s * (gv * f.tx), C_EXD);
-        put(cl, ct + C_EYD, s * (gv * f.ty), C_EYD);
-        put(cl, ct + C_EOM, s * (gv * (f.ty * ax - f.tx * ay)), C_EOM);
-        put(cl, ct + C_ETH, s * (-gv * om * (f.tx * ax + f.ty * ay)), C_ETH);
-        put(cl, ct + C_ZPX, s * (Dg * f.dsd_px), C_ZPX);
-        put(cl, ct + C_ZPY, s * (Dg * f.dsd_py), C_ZPY);
-        put(cl, ct + C_JMU, s * (lnb * av), C_JMU);
-        const int u0 = 3 * NJ + 3 * i;
-        const int gvc = C::GV + u0;
-        put(cl, gvc + (3 * b) * M, f.nx * im);
-        put(cl, gvc + (3 * b + 1) * M, f.ny * im);
-        put(cl, gvc + (3 * b + 2) * M, (ax * f.ny - ay * f.nx) * ii);
-        put(cl, gvc + (3 * b) * M + 1, f.tx * im);
-        put(cl, gvc + (3 * b + 1) * M + 1, f.ty * im);
-        put(cl, gvc + (3 * b + 2) * M + 1, (ax * f.ty - ay * f.tx) * ii);
-        put(cl, gvc + (3 * b) * M + 2, -f.tx * im);
-        put(cl, gvc + (3 * b + 1) * M + 2, -f.ty * im);
-        put(cl, gvc + (3 * b + 2) * M + 2, -(ax * f.ty - ay * f.tx) * ii);
-        const int gcc = C::GC + i * M + u0;
-        put(cl, gcc, s * T(0.5) * (f.sd + mu * av));
-        put(cl, gcc + 1, s * T(0.5) * (rp - av));
-        put(cl, gcc + 2, s * T(0.5) * (rm - av));
-        put(cl, C::F + NX + i, ycc);
+        put(cl, LY::ct(i, C_AX), ax, C_AX);
+        put(cl, LY::ct(i, C_AY), ay, C_AY);
+        put(cl, LY::ct(i, C_FXP), dfx * im, C_FXP);
+        put(cl, LY::ct(i, C_FYP), dfy * im, C_FYP);
+        put(cl, LY::ct(i, C_TP), (ax * dfy - ay * dfx) * ii, C_TP);
+        put(cl, LY::ct(i, C_EPX), s * (lnb * f.dsd_px + gv * dvt_px), C_EPX);
+        put(cl, LY::ct(i, C_EPY), s * (lnb * f.dsd_py), C_EPY);
+        put(cl, LY::ct(i, C_EXD), s * (gv * f.tx), C_EXD);
+        put(cl, LY::ct(i, C_EYD), s * (gv * f.ty), C_EYD);
+        put(cl, LY::ct(i, C_EOM), s * (gv * (f.ty * ax - f.tx * ay)), C_EOM);
+        put(cl, LY::ct(i, C_ETH), s * (-gv * om * (f.tx * ax + f.ty * ay)), C_ETH);
+        put(cl, LY::ct(i, C_ZPX), s * (Dg * f.dsd_px), C_ZPX);
+        put(cl, LY::ct(i, C_ZPY), s * (Dg * f.dsd_py), C_ZPY);
+        put(cl, LY::ct(i, C_JMU), s * (lnb * av), C_JMU);
+        put(cl, LY::gv_contact(i, b, 0, 0), f.nx * im);
+        put(cl, LY::gv_contact(i, b, 1, 0), f.ny * im);
+        put(cl, LY::gv_contact(i, b, 2, 0), (ax * f.ny - ay * f.nx) * ii);
+        put(cl, LY::gv_contact(i, b, 0, 1), f.tx * im);
+        put(cl, LY::gv_contact(i, b, 1, 1), f.ty * im);
+        put(cl, LY::gv_contact(i, b, 2, 1), (ax * f.ty - ay * f.tx) * ii);
+        put(cl, LY::gv_contact(i, b, 0, 2), -f.tx * im);
+        put(cl, LY::gv_contact(i, b, 1, 2), -f.ty * im);
+        put(cl, LY::gv_contact(i, b, 2, 2), -(ax * f.ty - ay * f.tx) * ii);
+        put(cl, LY::gc(i, 0), s * T(0.5) * (f.sd + mu * av));
+        put(cl, LY::gc(i, 1), s * T(0.5) * (rp - av));
+        put(cl, LY::gc(i, 2), s * T(0.5) * (rm - av));
+        put(cl, LY::f(NX + i), ycc);
         // F~ (q rows: stage velocities; v rows: the state wave's accelerations),
         // dT/dth and the violation part of the lane's body
         const bool bl = lane < NB;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            put(bl, C::F + 3 * b + k, fq[k], k);
-            put(bl, C::F + NQ + 3 * b + k, fa[k], k);
+            put(bl, LY::f(3 * b + k), fq[k], k);
+            put(bl, LY::f(NQ + 3 * b + k), fa[k], k);
         }
-        put(bl, C::CTH + b, s * dT * c.ii);
-        put(bl, C::CTP + b, ctp);
-        if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+        const T cth = s * dT * c.ii;
+        put(bl, LY::cth(b, 0), cth);
+        // further copies of the torso entry (compact record: one per leg block)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) *ptr[q] = val[q];
+        for (int q = 1; q < LY::TORSO_COPIES; ++q) put(lane == 0, LY::cth(0, q), cth, q);
+        put(bl, LY::ctp(b), ctp);
+        if constexpr (BURST) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) *ptr[q] = val[q];
+        }
+        (void)e;
     }
     // the lane's body's part of the violation row (summed by the consumers)
     yct = lane < NB ? ctp : T(0);
+}
+
+// The dilation column S on body lanes (its own column group in the latency
+// layout): lane b < NB holds the six rows of body b; a foot lane holds the
+// cross-complementarity row of its contact (the torso lane all of them when
+// the legs have no links); every body lane integrates its part of the
+// violation row.  The Jacobian product is that of the tangent lanes with the
+// joint terms exchanged between parent and child lanes, plus the F~ forcing.
+template <class T, class TP>
+struct SLane {
+    static constexpr int NCL = TP::D == 0 ? (TP::L > 0 ? TP::L : 1) : 1;   // cc rows per lane
+    T zs[6], zb[6], za[6];
+    T ycc[NCL], yct;
+};
+
+template <class T, class TP, int ST, class LY = CoefDense<TP>>
+__device__ __forceinline__ void s_stage(const Interval<T, TP>& iv, const BodyConst<T, TP>& c,
+                                        SLane<T, TP>& z, const T* __restrict__ cf, int lane) {
+    constexpr int NB = TP::NB, NQ = TP::NQ, NX = TP::NX, D = TP::D, L = TP::L;
+    constexpr int NCL = SLane<T, TP>::NCL;
+    const T s = iv.s, h = iv.h;
+    const int b = c.b;
+    const T x = z.zs[0], y = z.zs[1], th = z.zs[2];
+    const T vx = z.zs[3], vy = z.zs[4], om = z.zs[5];
+    T kv[3] = {cf[LY::f(NQ + 3 * b)], cf[LY::f(NQ + 3 * b + 1)],
+               cf[LY::f(NQ + 3 * b + 2)] + cf[LY::cth(b)] * th};
+    T kct = lane < NB ? cf[LY::ctp(b)] : T(0);
+    T kcc[NCL];
+#pragma unroll
+    for (int l = 0; l < NCL; ++l) kcc[l] = T(0);
+    if constexpr (D >= 1) {
+        // own joint (this body is its child): stiffness and damping, and the
+        // joint rows of the violation integrand; the parent's share of the
+        // stiffness and damping torque goes back to the parent lane
+        const bool pt = c.p == 0;
+        const T thp = from_parent<TP>(th, pt), omp = from_parent<TP>(om, pt);
+        const T xp = from_parent<TP>(x, pt), yp = from_parent<TP>(y, pt);
+        T tp = T(0);
+        if (c.joint) {
+            const int j = c.j;
+            const T dth = th - thp, dom = om - omp;
+            kv[2] -= iv.kc[j][2] * dth + iv.kc[j][3] * dom;
+            tp = iv.kc[j][0] * dth + iv.kc[j][1] * dom;
+            kct += cf[LY::jh(j, 0)] * (xp - x) + cf[LY::jh(j, 1)] * (yp - y) +
+                   cf[LY::jh(j, 2)] * thp + cf[LY::jh(j, 3)] * th;
+        }
+        kv[2] += from_children<TP>(tp, b);
+    }
+    if constexpr (L >= 1) {
+#pragma unroll
+        for (int l = 0; l < NCL; ++l) {
+            const bool on = D >= 1 ? c.contact : (lane == 0);
+            const int i = D >= 1 ? c.i : l;
+            if (on) {
+                auto ct = [&](int q) { return cf[LY::ct(i, q)]; };
+                const T dPx = x - ct(C_AY) * th;
+                const T dPy = y + ct(C_AX) * th;
+                kv[0] += ct(C_FXP) * dPx;
+                kv[1] += ct(C_FYP) * dPx;
+                kv[2] += ct(C_TP) * dPx;
+                kcc[l] = ct(C_EPX) * dPx + ct(C_EPY) * dPy + ct(C_EXD) * vx + ct(C_EYD) * vy +
+                         ct(C_EOM) * om + ct(C_ETH) * th + cf[LY::f(NX + i)];
+                kct += ct(C_ZPX) * dPx + ct(C_ZPY) * dPy;
+            }
+        }
+    }
+    // classical RK4 combination (stage ST known at compile time)
+    constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
+    const T an = (ST == 2) ? h : T(0.5) * h;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T kq = s * z.zs[3 + k] + cf[LY::f(3 * b + k)];
+        if (ST == 0) z.za[k] = kq;
+        else z.za[k] += T(WK) * kq;
+        if (ST < 3) z.zs[k] = z.zb[k] + an * kq;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (ST == 0) z.za[3 + k] = kv[k];
+        else z.za[3 + k] += T(WK) * kv[k];
+        if (ST < 3) z.zs[3 + k] = z.zb[3 + k] + an * kv[k];
+    }
+    const T h6 = iv.h6;
+#pragma unroll
+    for (int l = 0; l < NCL; ++l) z.ycc[l] += (h6 * T(WK)) * kcc[l];
+    z.yct += (h6 * T(WK)) * kct;
+    if (ST == 3) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            z.zb[r] += h6 * z.za[r];
+            z.zs[r] = z.zb[r];
+        }
+    }
 }
 
 }  // namespace cis

@@ -67,6 +67,8 @@ struct BatchGroupDev {
     const int2* items;   // work list, sorted by decreasing substep count
     int n_items;
     int* cursor;         // [2], zero between launches
+    void* rec;           // split form: stage records of every item
+    const int64_t* rec_off;   // [n_items] element offset of an item's records
 };
 
 // Launch preparation for one model group (implemented next to the kernels).
@@ -85,6 +87,14 @@ cis_status prep_adjoint_batch(const cis_model* m, const BatchGroupDev& g, int ma
                               int waves, KLaunch* out);
 // gU, gX_N and gp of n_traj trajectories from their partials (RedDesc array).
 cis_status prep_adjoint_reduce_batch(const void* rdesc, int n_traj, KLaunch* out);
+// Split form of the discretize step (coefficient records, then tangent
+// columns): the two launches of one model group.
+// (waves: register budget of the tangent kernel in waves per SIMD, 1 or 2)
+cis_status prep_split_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g, int waves,
+                            KLaunch* coefrec, KLaunch* tangent);
+bool split_form_supported(const cis_model* m);
+// elements of one interval's part of the split workspace (-1: not offered)
+int64_t split_elems_per_interval(const cis_model* m, int K);
 // Column groups (work units per item) of the discretize kernel.
 int discretize_units_per_item(const cis_model* m, int32_t dtype);
 

@@ -99,6 +99,86 @@ struct Coef {
 enum { C_AX = 0, C_AY, C_FXP, C_FYP, C_TP, C_EPX, C_EPY, C_EXD, C_EYD, C_EOM, C_ETH, C_ZPX, C_ZPY,
        C_JMU };
 
+// Where a stage's coefficients sit in a coefficient buffer, as offsets
+// (element units).  Dense: the Coef<TP> layout above, read in place by the
+// leg-lane tangent waves and the reverse sweep.
+template <class TP>
+struct CoefDense {
+    using C = Coef<TP>;
+    static constexpr int SIZE = C::SIZE, TRASH = C::TRASH;
+    // dT_b/dth_b; `copy` < L selects one of the copies of the torso entry
+    // (the dense layout has one)
+    __device__ static constexpr int cth(int b, int copy = 0) { return C::CTH + b + 0 * copy; }
+    static constexpr int TORSO_COPIES = 1;
+    __device__ static constexpr int jh(int j, int q) { return C::JH + 4 * j + q; }
+    __device__ static constexpr int ct(int i, int q) { return C::CT + C::NCT * i + q; }
+    // theta row of the parent (side 0, body p) or child (side 1, body c) of
+    // joint j, column of its force component ax
+    __device__ static constexpr int gv_joint(int j, int side, int p, int c, int ax) {
+        return C::GV + (3 * (side ? c : p) + 2) * TP::M + TP::NJ + 2 * j + ax;
+    }
+    // row r (0: x, 1: y, 2: theta) of contact body b, column of control q of contact i
+    __device__ static constexpr int gv_contact(int i, int b, int r, int q) {
+        return C::GV + (3 * b + r) * TP::M + 3 * TP::NJ + 3 * i + q;
+    }
+    __device__ static constexpr int gc(int i, int q) {
+        return C::GC + i * TP::M + 3 * TP::NJ + 3 * i + q;
+    }
+    __device__ static constexpr int f(int r) { return C::F + r; }
+    __device__ static constexpr int ctp(int b) { return C::CTP + b; }
+};
+
+// Compact stage record of the split discretize form (legs with links only).
+// The first GLOBAL elements are what the tangent kernel reads, copied to
+// device memory once per stage; F~ and the violation parts (used by the
+// dilation column only) follow, then the per-lane sinks.
+//   leg block l (LEGB elements, a multiple of 8 so each block starts on a
+//   64-byte boundary): [0] dT/dth of the torso (one copy per leg),
+//   [1 + d] dT/dth of link d of the leg, [1 + D + 4 d + q] violation-row
+//   coefficients of joint l D + d, [1 + 5 D + q] the 13 contact terms C_AX..C_ZPY
+//   of contact l;
+//   joint block j (8): theta-row forcing of the parent and child for the
+//   force components x, y: [th_p x, th_p y, th_c x, th_c y], then the
+//   constant entries [s/m_p, -s/m_c, -s/I_p, s/I_c];
+//   contact block i (12): x, y, theta rows of the contact body for
+//   lambda_n, lambda_t+, lambda_t- ([3 r + q]), then the three
+//   cross-complementarity entries (s/2) dOmega_cc/dubar;
+//   one zero.
+template <class TP>
+struct CoefRec {
+    static_assert(TP::L >= 1 && TP::D >= 1, "the compact record needs legs with links");
+    static constexpr int L = TP::L, D = TP::D, NJ = TP::NJ, NC = TP::NC;
+    static constexpr int LEGB = (5 * D + 14 + 7) / 8 * 8;
+    static constexpr int JB = L * LEGB;                 // joint blocks
+    static constexpr int CB = JB + 8 * NJ;              // contact blocks
+    static constexpr int ZERO = CB + 12 * NC;
+    static constexpr int GLOBAL = (ZERO + 1 + 7) / 8 * 8;   // elements copied per stage
+    static constexpr int F = GLOBAL;                    // [NXT] F~
+    static constexpr int CTP = F + TP::NXT;             // [NB] violation parts
+    static constexpr int TRASH = (CTP + TP::NB + 1) / 2 * 2;
+    static constexpr int SIZE = TRASH + 64 + 16;
+    static constexpr int TORSO_COPIES = L;
+    __device__ static constexpr int cth(int b, int copy = 0) {
+        return b == 0 ? copy * LEGB : ((b - 1) / D) * LEGB + 1 + (b - 1) % D;
+    }
+    __device__ static constexpr int jh(int j, int q) {
+        return (j / D) * LEGB + 1 + D + 4 * (j % D) + q;
+    }
+    __device__ static constexpr int ct(int i, int q) {
+        // C_JMU (the friction-coefficient derivative) is not kept
+        return q < 13 ? i * LEGB + 1 + 5 * D + q : TRASH + 15;
+    }
+    __device__ static constexpr int gv_joint(int j, int side, int, int, int ax) {
+        return JB + 8 * j + 2 * side + ax;
+    }
+    __device__ static constexpr int gv_contact(int i, int, int r, int q) {
+        return CB + 12 * i + 3 * r + q;
+    }
+    __device__ static constexpr int gc(int i, int q) { return CB + 12 * i + 9 + q; }
+    __device__ static constexpr int f(int r) { return F + r; }
+    __device__ static constexpr int ctp(int b) { return CTP + b; }
+};
+
 // Per-interval data shared by every role.
 template <class T, class TP>
 struct Interval {

@@ -1,0 +1,698 @@
+// Split form of the discretize step for many intervals (arxiv 2604.09993,
+// Sec. IV-B eq. intg-aug-sys-param; sensitivities by internal numerical
+// differentiation, Sec. VI).  Two kernels per batch of intervals:
+//
+//   k_coefrec : per interval three waves, the nominal RK4 recursion on body
+//               lanes, the right-hand side and Jacobian coefficients of
+//               every stage, and the dilation column S on body lanes; writes
+//               F~, the defect, S, the integral-state columns of A, and a
+//               compact record of every stage's coefficients (CoefRec) to a
+//               workspace in device memory.
+//   k_tangent : per (interval, block of 64 tangent columns) one wave per leg.
+//               Lane c holds column c of Z = [Phi_x | B- | B+] on the rows of
+//               the torso and of the wave's leg; every coefficient a wave
+//               needs is the same for all its lanes, so it is read with
+//               scalar loads from the stage record and enters the FMAs as a
+//               scalar operand (no LDS traffic for coefficients, no wait on
+//               the nominal recursion).  The torso rows are integrated
+//               identically in every leg wave; the only exchange is the hip
+//               stiffness and damping torque of each leg on the torso (one
+//               value per column and stage, through LDS).
+//
+// The two kernels exchange per interval 8 + 4 n_j constants and 4 K records
+// of CoefRec<TP>::GLOBAL elements.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/cis.h"
+#include "cis_body.hpp"
+#include "cis_host.hpp"
+#include "cis_launch.hpp"
+#include "cis_model.hpp"
+
+namespace cis {
+
+// Layout of an interval's part of the split workspace (elements of T):
+//   [0, CRS)                        s, h, h/6, 0 x5, then k/I terms kc[j][4]
+//   CRS + t * GLOBAL, t < 4 K       stage record t (CoefRec<TP> prefix)
+template <class TP>
+struct SplitRec {
+    using R = CoefRec<TP>;
+    static constexpr int CRS = (8 + 4 * TP::NJ + 7) / 8 * 8;
+    static constexpr int GLOBAL = R::GLOBAL;
+    static constexpr int64_t per_interval(int K) { return CRS + (int64_t)4 * K * GLOBAL; }
+    static constexpr int NCOLT = TP::NX + 2 * TP::M;      // tangent columns of k_tangent
+    static constexpr int NBLK = (NCOLT + 63) / 64;        // column blocks of 64 lanes
+};
+
+// Constant entries of a compact record (joint blocks) and its zero.
+template <class T, class TP>
+__device__ __forceinline__ void coefrec_constants(const Interval<T, TP>& iv, T* cf, int tid,
+                                                  int nth) {
+    using R = CoefRec<TP>;
+    const T s = iv.s;
+    for (int j = tid; j < TP::NJ; j += nth) {
+        const int p = TP::parent(j), c = j + 1;
+        T* jb = cf + R::JB + 8 * j;
+        jb[4] = s * iv.minv[p];
+        jb[5] = -s * iv.minv[c];
+        jb[6] = -s * iv.iinv[p];
+        jb[7] = s * iv.iinv[c];
+    }
+    if (tid == 0) cf[R::ZERO] = T(0);
+}
+
+template <class T, class TP>
+struct RecShared {
+    Interval<T, TP> iv;
+    T xring[4][TP::NX];        // stage inputs from the state wave
+    T csring[4][TP::NB][2];    // their rotations
+    T fring[4][3 * TP::NB];    // their accelerations
+    T coef[2][CoefRec<TP>::SIZE];
+};
+
+// ---------------------------------------------------------------------------
+// k_coefrec: interval k by three waves, one workgroup barrier per step:
+//   wave 0 (state)       : stage t at step t;
+//   wave 1 (coefficients): stage t-1 at step t, into coef[(t-1) & 1];
+//   wave 2 (S column)    : stage t-2 at step t from coef[(t-2) & 1], and the
+//                          copy of that record to device memory.
+// ---------------------------------------------------------------------------
+template <class T, class TP>
+__device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs<T>& a,
+                                             const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                             const int k, T* __restrict__ rec) {
+    constexpr int NB = TP::NB, NX = TP::NX, NXT = TP::NXT, NY = TP::NY, NQ = TP::NQ;
+    constexpr int NC = TP::NC, NJ = TP::NJ, L = TP::L, D = TP::D;
+    using R = CoefRec<TP>;
+    using SR = SplitRec<TP>;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int nth = 192;
+    load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
+    for (int e = tid; e < 2 * R::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
+    __syncthreads();
+    coefrec_constants<T, TP>(sh.iv, sh.coef[0], tid, nth);
+    coefrec_constants<T, TP>(sh.iv, sh.coef[1], tid, nth);
+    // per-interval constants of the tangent kernel
+    for (int e = tid; e < SR::CRS; e += nth) {
+        T v = T(0);
+        if (e == 0) v = sh.iv.s;
+        else if (e == 1) v = sh.iv.h;
+        else if (e == 2) v = sh.iv.h6;
+        else if (e >= 8 && e < 8 + 4 * NJ) v = sh.iv.kc[(e - 8) >> 2][(e - 8) & 3];
+        rec[e] = v;
+    }
+    const int nst = 4 * a.K;
+    const int nsteps = nst + 2;
+    const int64_t ldi = a.ldi;
+    __syncthreads();
+
+    if (wave == 0) {
+        // ---------------- state wave: stage t at step t ----------------
+        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+        BodyRK<T> bs;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            bs.xb[kk] = sh.iv.x0[3 * c.b + kk];
+            bs.xb[3 + kk] = sh.iv.x0[NQ + 3 * c.b + kk];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) {
+            bs.xs[kk] = bs.xb[kk];
+            bs.xa[kk] = T(0);
+        }
+        const T Kt = T(a.K);
+        for (int j = 0; j < a.K; ++j) {
+            const T jt = T(j);
+            state_stage<T, TP, 0>(sh.iv, mc, c, bs, jt / Kt, sh.xring[1], sh.csring[0],
+                                  sh.fring[0], lane);
+            __syncthreads();
+            state_stage<T, TP, 1>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[2], sh.csring[1],
+                                  sh.fring[1], lane);
+            __syncthreads();
+            state_stage<T, TP, 2>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[3], sh.csring[2],
+                                  sh.fring[2], lane);
+            __syncthreads();
+            state_stage<T, TP, 3>(sh.iv, mc, c, bs, (jt + T(1)) / Kt, sh.xring[0], sh.csring[3],
+                                  sh.fring[3], lane);
+            __syncthreads();
+        }
+        for (int t = nst; t < nsteps; ++t) __syncthreads();
+        if (lane < NB) {
+#pragma unroll
+            for (int kk = 0; kk < 6; ++kk) {
+                const int r = kk < 3 ? 3 * c.b + kk : NQ + 3 * c.b + kk - 3;
+                if (a.xprop) a.xprop[r * ldi + k] = bs.xb[kk];
+                a.defect[r * ldi + k] = bs.xb[kk] - sh.iv.xk1[r];
+            }
+        }
+    } else if (wave == 1) {
+        // ------- coefficient wave: stage tc at step tc + 1; integral rows -------
+        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+        const int ycc_row = NX + c.i;
+        T ycb = c.contact ? sh.iv.x0[ycc_row] : T(0), yca = T(0);
+        T ytb = lane == 0 ? sh.iv.x0[NX + NC] : T(0), yta = T(0);
+        const T s = sh.iv.s;
+        __syncthreads();
+        for (int tc = 0; tc < nst; ++tc) {
+            const int st = tc & 3;
+            const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
+            T ycc = T(0), yct = T(0);
+            coef_stage<T, TP, false, true, R, false>(sh.iv, mc, c,
+                                                     tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
+                                                     sh.csring[tc & 3], sh.fring[tc & 3], tau,
+                                                     sh.coef[tc & 1], ycc, yct, lane);
+            const T wk = (st == 0 || st == 3) ? T(1) : T(2);
+            if (st == 0) {
+                yca = wk * s * ycc;
+                yta = wk * s * yct;
+            } else {
+                yca += wk * s * ycc;
+                yta += wk * s * yct;
+            }
+            if (st == 3) {
+                ycb += sh.iv.h6 * yca;
+                ytb += sh.iv.h6 * yta;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        {
+            T acc = T(0);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) acc += lane_value(ytb, e);
+            ytb = acc;
+        }
+        if (c.contact) {
+            if (a.xprop) a.xprop[ycc_row * ldi + k] = ycb;
+            a.defect[ycc_row * ldi + k] = ycb - sh.iv.xk1[ycc_row];
+        }
+        if (lane == 0) {
+            if (a.xprop) a.xprop[(NX + NC) * ldi + k] = ytb;
+            a.defect[(NX + NC) * ldi + k] = ytb - sh.iv.xk1[NX + NC];
+        }
+        // A[:, n:] = [0; I]: the integral states feed back into nothing
+        for (int e = lane; e < NXT * NY; e += 64) {
+            const int r = e / NY, cc = NX + e % NY;
+            a.A[((int64_t)r * NXT + cc) * ldi + k] = (r == cc) ? T(1) : T(0);
+        }
+    } else {
+        // ---- S wave: stage t-2 at step t on body lanes; record copy ----
+        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
+        SLane<T, TP> z;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) z.zs[r] = z.zb[r] = z.za[r] = T(0);
+#pragma unroll
+        for (int l = 0; l < SLane<T, TP>::NCL; ++l) z.ycc[l] = T(0);
+        z.yct = T(0);
+        __syncthreads();
+        __syncthreads();
+        T* out = rec + SR::CRS;
+        for (int j = 0; j < a.K; ++j) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const T* cf = sh.coef[st & 1];
+                if (st == 0) s_stage<T, TP, 0, R>(sh.iv, c, z, cf, lane);
+                else if (st == 1) s_stage<T, TP, 1, R>(sh.iv, c, z, cf, lane);
+                else if (st == 2) s_stage<T, TP, 2, R>(sh.iv, c, z, cf, lane);
+                else s_stage<T, TP, 3, R>(sh.iv, c, z, cf, lane);
+#pragma unroll
+                for (int e = lane; e < R::GLOBAL; e += 64) out[e] = cf[e];
+                out += R::GLOBAL;
+                __syncthreads();
+            }
+        }
+        T yct = T(0);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) yct += lane_value(z.yct, e);
+        if (lane < NB) {
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                a.S[(int64_t)(3 * c.b + kk) * ldi + k] = z.zb[kk];
+                a.S[(int64_t)(NQ + 3 * c.b + kk) * ldi + k] = z.zb[3 + kk];
+            }
+            if (c.contact) a.S[(int64_t)(NX + c.i) * ldi + k] = z.ycc[0];
+            if (lane == 0) a.S[(int64_t)(NX + NC) * ldi + k] = yct;
+        }
+        (void)L;
+        (void)D;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_tangent: one stage of a leg wave.  Local body lb = 0 is the torso, lb =
+// 1..D the links of leg `leg`; rows z[3 lb + k] (q) and z[3 LB + 3 lb + k] (v).
+// lr: the wave's leg block of the stage record; rs: the whole stage record
+// (forcing entries, read per lane at offsets off[], offcc).
+// ---------------------------------------------------------------------------
+template <class T, class TP>
+struct TanLane {
+    static constexpr int LB = TP::D + 1;
+    T zb[6 * LB], za[6 * LB], zs[6 * LB];
+    T ycc, yct;
+};
+
+template <class T, class TP, int ST, bool FORCE>
+__device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* __restrict__ cr,
+                                                    const T* __restrict__ lr,
+                                                    const T* __restrict__ rs, T* xch, int leg,
+                                                    int lane, T tau, T wbm, T wbp,
+                                                    const int (&off)[3 * (TP::D + 1)],
+                                                    int offcc) {
+    constexpr int LB = TP::D + 1, D = TP::D, L = TP::L;
+    const T s = cr[0], h = cr[1], h6 = cr[2];
+#define ZQ(lb, k) z.zs[3 * (lb) + (k)]
+#define ZV(lb, k) z.zs[3 * LB + 3 * (lb) + (k)]
+    // forcing of B-/B+ columns (zero offsets and weights elsewhere): issued
+    // first, used last
+    T g[3 * LB];
+    T gcc = T(0);
+    if constexpr (FORCE) {
+#pragma unroll
+        for (int r = 0; r < 3 * LB; ++r) g[r] = rs[off[r]];
+        gcc = rs[offcc];
+    }
+    // hip stiffness and damping of this leg on the torso, exchanged
+    const T* kcl = cr + 8 + 4 * leg * D;   // kc[j][4] of the leg's joints
+    T hip = kcl[0] * (ZQ(1, 2) - ZQ(0, 2)) + kcl[1] * (ZV(1, 2) - ZV(0, 2));
+    if constexpr (L > 1) {
+        xch[leg * 64 + lane] = hip;
+        __syncthreads();
+        hip = xch[lane];
+#pragma unroll
+        for (int l = 1; l < L; ++l) hip += xch[l * 64 + lane];
+    }
+    T kv[3 * LB];
+    kv[0] = T(0);
+    kv[1] = T(0);
+    kv[2] = lr[0] * ZQ(0, 2) + hip;
+#pragma unroll
+    for (int lb = 1; lb <= D; ++lb) {
+        kv[3 * lb] = T(0);
+        kv[3 * lb + 1] = T(0);
+        kv[3 * lb + 2] = lr[lb] * ZQ(lb, 2);
+    }
+    T kct = T(0), kcc;
+#pragma unroll
+    for (int lb = 1; lb <= D; ++lb) {
+        const T* kc = kcl + 4 * (lb - 1);
+        const T dth = ZQ(lb, 2) - ZQ(lb - 1, 2);
+        const T dom = ZV(lb, 2) - ZV(lb - 1, 2);
+        if (lb >= 2) kv[3 * (lb - 1) + 2] += kc[0] * dth + kc[1] * dom;
+        kv[3 * lb + 2] -= kc[2] * dth + kc[3] * dom;
+        const T* jh = lr + 1 + D + 4 * (lb - 1);
+        kct += jh[0] * (ZQ(lb - 1, 0) - ZQ(lb, 0)) + jh[1] * (ZQ(lb - 1, 1) - ZQ(lb, 1)) +
+               jh[2] * ZQ(lb - 1, 2) + jh[3] * ZQ(lb, 2);
+    }
+    {
+        const T* ct = lr + 1 + 5 * D;   // contact terms C_AX .. C_ZPY of the leg's contact
+        constexpr int lb = D;
+        const T dPx = ZQ(lb, 0) - ct[C_AY] * ZQ(lb, 2);
+        const T dPy = ZQ(lb, 1) + ct[C_AX] * ZQ(lb, 2);
+        kv[3 * lb] += ct[C_FXP] * dPx;
+        kv[3 * lb + 1] += ct[C_FYP] * dPx;
+        kv[3 * lb + 2] += ct[C_TP] * dPx;
+        kcc = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * ZV(lb, 0) + ct[C_EYD] * ZV(lb, 1) +
+              ct[C_EOM] * ZV(lb, 2) + ct[C_ETH] * ZQ(lb, 2);
+        kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
+    }
+    if constexpr (FORCE) {
+        const T wB = wbm * (T(1) - tau) + wbp * tau;
+#pragma unroll
+        for (int r = 0; r < 3 * LB; ++r) kv[r] += wB * g[r];
+        kcc += (wbm + wbp) * gcc;
+    }
+    // classical RK4 combination (stage ST known at compile time)
+    constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
+    const T an = (ST == 2) ? h : T(0.5) * h;
+#pragma unroll
+    for (int r = 0; r < 3 * LB; ++r) {
+        const T kq = s * z.zs[3 * LB + r];
+        if (ST == 0) z.za[r] = kq;
+        else z.za[r] += T(WK) * kq;
+        if (ST < 3) z.zs[r] = z.zb[r] + an * kq;
+    }
+#pragma unroll
+    for (int r = 0; r < 3 * LB; ++r) {
+        const T kk = kv[r];
+        if (ST == 0) z.za[3 * LB + r] = kk;
+        else z.za[3 * LB + r] += T(WK) * kk;
+        if (ST < 3) z.zs[3 * LB + r] = z.zb[3 * LB + r] + an * kk;
+    }
+    z.ycc += (h6 * T(WK)) * kcc;
+    z.yct += (h6 * T(WK)) * kct;
+    if (ST == 3) {
+#pragma unroll
+        for (int r = 0; r < 6 * LB; ++r) {
+            z.zb[r] += h6 * z.za[r];
+            z.zs[r] = z.zb[r];
+        }
+    }
+#undef ZQ
+#undef ZV
+}
+
+// Record offset of the forcing entry of control `ctrl` in row k (0: x, 1: y,
+// 2: theta) of body gb, or the zero entry (Sec. IV-B FOH: dF~/du of the
+// joint torques, joint forces and contact forces).
+template <class TP>
+__device__ __forceinline__ int forcing_offset(int ctrl, int gb, int k) {
+    using R = CoefRec<TP>;
+    constexpr int NJ = TP::NJ;
+    if (ctrl < NJ) {
+        const int j = ctrl, p = TP::parent(j), c = j + 1;
+        if (k == 2 && gb == p) return R::JB + 8 * j + 6;
+        if (k == 2 && gb == c) return R::JB + 8 * j + 7;
+        return R::ZERO;
+    }
+    if (ctrl < 3 * NJ) {
+        const int j = (ctrl - NJ) >> 1, ax = (ctrl - NJ) & 1, p = TP::parent(j), c = j + 1;
+        if (k == ax && gb == p) return R::JB + 8 * j + 4;
+        if (k == ax && gb == c) return R::JB + 8 * j + 5;
+        if (k == 2 && gb == p) return R::JB + 8 * j + ax;
+        if (k == 2 && gb == c) return R::JB + 8 * j + 2 + ax;
+        return R::ZERO;
+    }
+    const int i = (ctrl - 3 * NJ) / 3, q = (ctrl - 3 * NJ) % 3;
+    return gb == TP::cbody(i) ? R::CB + 12 * i + 3 * k + q : R::ZERO;
+}
+
+template <class T, class TP, bool FORCE>
+__device__ __forceinline__ void tangent_split_loop(TanLane<T, TP>& z, const T* __restrict__ cr,
+                                                   const T* __restrict__ rec0, T* xch, int leg,
+                                                   int lane, int K, T wbm, T wbp,
+                                                   const int (&off)[3 * (TP::D + 1)], int offcc) {
+    using R = CoefRec<TP>;
+    constexpr int LEGB = R::LEGB, GL = R::GLOBAL, L = TP::L;
+    const T Kt = T(K);
+    const T* rs = rec0;
+    for (int j = 0; j < K; ++j) {
+        const T jt = T(j);
+        const T tau0 = jt / Kt, tauh = (jt + T(0.5)) / Kt, tau1 = (jt + T(1)) / Kt;
+        T* x0 = xch;
+        T* x1 = xch + L * 64;
+        tangent_split_stage<T, TP, 0, FORCE>(z, cr, rs + leg * LEGB, rs, x0, leg, lane, tau0,
+                                             wbm, wbp, off, offcc);
+        rs += GL;
+        tangent_split_stage<T, TP, 1, FORCE>(z, cr, rs + leg * LEGB, rs, x1, leg, lane, tauh,
+                                             wbm, wbp, off, offcc);
+        rs += GL;
+        tangent_split_stage<T, TP, 2, FORCE>(z, cr, rs + leg * LEGB, rs, x0, leg, lane, tauh,
+                                             wbm, wbp, off, offcc);
+        rs += GL;
+        tangent_split_stage<T, TP, 3, FORCE>(z, cr, rs + leg * LEGB, rs, x1, leg, lane, tau1,
+                                             wbm, wbp, off, offcc);
+        rs += GL;
+    }
+}
+
+// Columns [64 cb, 64 cb + 64) of interval k, wave `leg` (all waves of the block).
+template <class T, class TP>
+__device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __restrict__ rec,
+                                             const int k, const int cb, T* xch) {
+    constexpr int NX = TP::NX, NXT = TP::NXT, NQ = TP::NQ, M = TP::M, NC = TP::NC;
+    constexpr int D = TP::D, L = TP::L, LB = D + 1;
+    using SR = SplitRec<TP>;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int leg = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = cb * 64 + lane;
+    const bool active = col < SR::NCOLT;
+    auto gbody = [&](int lb) { return lb == 0 ? 0 : 1 + leg * D + lb - 1; };
+    T wbm = T(0), wbp = T(0);
+    int ctrl = 0;
+    if (col >= NX && col < NX + M) { wbm = T(1); ctrl = col - NX; }
+    else if (col >= NX + M && col < NX + 2 * M) { wbp = T(1); ctrl = col - NX - M; }
+    const bool bcol = wbm != T(0) || wbp != T(0);
+    int off[3 * LB];
+#pragma unroll
+    for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+            off[3 * lb + kk] = bcol ? forcing_offset<TP>(ctrl, gbody(lb), kk) : CoefRec<TP>::ZERO;
+    int offcc = CoefRec<TP>::ZERO;
+    if (bcol && ctrl >= 3 * TP::NJ && (ctrl - 3 * TP::NJ) / 3 == leg)
+        offcc = CoefRec<TP>::gc(leg, (ctrl - 3 * TP::NJ) % 3);
+    TanLane<T, TP> z;
+#pragma unroll
+    for (int lb = 0; lb < LB; ++lb)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            const int gq = 3 * gbody(lb) + kk;
+            z.zb[3 * lb + kk] = (gq == col) ? T(1) : T(0);
+            z.zb[3 * LB + 3 * lb + kk] = (NQ + gq == col) ? T(1) : T(0);
+        }
+#pragma unroll
+    for (int r = 0; r < 6 * LB; ++r) {
+        z.zs[r] = z.zb[r];
+        z.za[r] = T(0);
+    }
+    z.ycc = T(0);
+    z.yct = T(0);
+    const T* cr = rec;
+    const T* rec0 = rec + SR::CRS;
+    // blocks holding no B-/B+ column skip the forcing code (uniform branch)
+    if ((cb + 1) * 64 <= NX) tangent_split_loop<T, TP, false>(z, cr, rec0, xch, leg, lane, a.K,
+                                                             wbm, wbp, off, offcc);
+    else tangent_split_loop<T, TP, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, off, offcc);
+    // violation row: sum of the legs' parts in leg order
+    T yct = z.yct;
+    if constexpr (L > 1) {
+        __syncthreads();
+        xch[leg * 64 + lane] = z.yct;
+        __syncthreads();
+        yct = xch[lane];
+#pragma unroll
+        for (int l = 1; l < L; ++l) yct += xch[l * 64 + lane];
+    }
+    if (!active) return;
+    const int64_t ldi = a.ldi;
+    T* out;
+    int64_t cstride, c0;   // element (row, column) at out[(row * cstride + c0) * ldi + k]
+    if (col < NX) { out = a.A; cstride = NXT; c0 = col; }
+    else if (col < NX + M) { out = a.Bm; cstride = M; c0 = col - NX; }
+    else { out = a.Bp; cstride = M; c0 = col - NX - M; }
+#pragma unroll
+    for (int lb = 0; lb < LB; ++lb) {
+        if (lb == 0 && leg != 0) continue;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            const int gq = 3 * gbody(lb) + kk;
+            out[((int64_t)gq * cstride + c0) * ldi + k] = z.zb[3 * lb + kk];
+            out[((int64_t)(NQ + gq) * cstride + c0) * ldi + k] = z.zb[3 * LB + 3 * lb + kk];
+        }
+    }
+    out[((int64_t)(NX + leg) * cstride + c0) * ldi + k] = z.ycc;
+    if (leg == 0) out[((int64_t)(NX + NC) * cstride + c0) * ldi + k] = yct;
+}
+
+// Single trajectory: rec holds N interval parts of per_interval(K) elements.
+template <class T, class TP>
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2)))
+    k_coefrec(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc,
+                                                 T* __restrict__ rec) {
+    __shared__ RecShared<T, TP> sh;
+    const int k = xcd_slot(blockIdx.x, gridDim.x);
+    coefrec_item<T, TP>(sh, a, mc, k, rec + (int64_t)k * SplitRec<TP>::per_interval(a.K));
+}
+
+template <class T, class TP, int WAVES>
+__global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu(WAVES)))
+    k_tangent(FwdArgs<T> a, const T* __restrict__ rec) {
+    __shared__ T xch[2 * TP::L * 64];
+    int item, cb;
+    unit_item(xcd_slot(blockIdx.x, gridDim.x), a.N, SplitRec<TP>::NBLK, item, cb);
+    tangent_item<T, TP>(a, rec + (int64_t)item * SplitRec<TP>::per_interval(a.K), item, cb, xch);
+}
+
+// Batches: one launch per model over the work list; rec_off[item] is the
+// element offset of the item's part of the workspace.
+template <class T, class TP>
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2)))
+    k_coefrec_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc,
+                    T* __restrict__ rec, const int64_t* __restrict__ rec_off) {
+    __shared__ RecShared<T, TP> sh;
+    const int item = xcd_slot(blockIdx.x, gridDim.x);
+    const int2 it = b.items[item];
+    const FwdArgs<T> a = b.descs[it.x];
+    coefrec_item<T, TP>(sh, a, mc, it.y, rec + rec_off[item]);
+}
+
+template <class T, class TP, int WAVES>
+__global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu(WAVES)))
+    k_tangent_batch(BatchArgs<FwdArgs<T>> b, const T* __restrict__ rec,
+                    const int64_t* __restrict__ rec_off) {
+    __shared__ T xch[2 * TP::L * 64];
+    int item, cb;
+    unit_item(xcd_slot(blockIdx.x, gridDim.x), b.n_items, SplitRec<TP>::NBLK, item, cb);
+    const int2 it = b.items[item];
+    const FwdArgs<T> a = b.descs[it.x];
+    tangent_item<T, TP>(a, rec + rec_off[item], it.y, cb, xch);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+template <int L, int D>
+struct SplitTopo {
+    static constexpr bool ok = L >= 1 && D >= 1;
+};
+
+static bool split_supported(const cis_model* m) { return m->L >= 1 && m->D >= 1; }
+
+template <int L, int D>
+static int64_t split_elems_t(int K) {
+    if constexpr (L >= 1 && D >= 1) return SplitRec<Topo<L, D>>::per_interval(K);
+    else return -1;
+}
+
+int64_t split_elems_per_interval(const cis_model* m, int K) {
+#define CIS_SPLIT_SZ(LL, DD) \
+    if (m->L == LL && m->D == DD) return split_elems_t<LL, DD>(K);
+    CIS_TOPOLOGIES(CIS_SPLIT_SZ)
+#undef CIS_SPLIT_SZ
+    return -1;
+}
+
+template <class T, int L, int D>
+static cis_status launch_split_t(const cis_model* m, const cis_shape* sh, const void* X,
+                                 const void* U, const void* s, const void* prm, void* A, void* Bm,
+                                 void* Bp, void* S, void* defect, void* xprop, void* ws,
+                                 int waves, hipStream_t stream) {
+    if constexpr (L >= 1 && D >= 1) {
+        using TP = Topo<L, D>;
+        auto mc = make_const<TP::NB, TP::NJ, TP::NC>(m);
+        FwdArgs<T> a;
+        std::memset(&a, 0, sizeof(a));
+        a.X = (const T*)X;
+        a.U = (const T*)U;
+        a.s = (const T*)s;
+        a.prm = (const T*)prm;
+        a.A = (T*)A;
+        a.Bm = (T*)Bm;
+        a.Bp = (T*)Bp;
+        a.S = (T*)S;
+        a.defect = (T*)defect;
+        a.xprop = (T*)xprop;
+        a.ldn = sh->ld_node;
+        a.ldi = sh->ld_int;
+        a.N = sh->N;
+        a.K = sh->substeps;
+        a.C = 1;
+        T* rec = (T*)ws;
+        void* args_a[] = {&a, &mc, &rec};
+        hipError_t e = hipLaunchKernel((const void*)&k_coefrec<T, TP>, dim3(sh->N), dim3(192),
+                                       args_a, 0, stream);
+        if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_coefrec launch: %s", hipGetErrorString(e));
+        const T* crec = rec;
+        void* args_b[] = {&a, &crec};
+        e = hipLaunchKernel(waves == 2 ? (const void*)&k_tangent<T, TP, 2>
+                                       : (const void*)&k_tangent<T, TP, 1>,
+                            dim3(sh->N * SplitRec<TP>::NBLK), dim3(64 * TP::L), args_b, 0, stream);
+        if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_tangent launch: %s", hipGetErrorString(e));
+        return CIS_OK;
+    } else {
+        return fail(CIS_ERR_UNSUPPORTED, "split form needs legs with links");
+    }
+}
+
+template <class T, int L, int D>
+static cis_status prep_split_t(const cis_model* m, const BatchGroupDev& g, int waves,
+                               KLaunch* ka, KLaunch* kb) {
+    if constexpr (L >= 1 && D >= 1) {
+        using TP = Topo<L, D>;
+        BatchArgs<FwdArgs<T>> b;
+        b.descs = (const FwdArgs<T>*)g.fdesc;
+        b.items = g.items;
+        b.n_items = g.n_items;
+        b.cursor = g.cursor;
+        ka->arg(b);
+        ka->arg(make_const<TP::NB, TP::NJ, TP::NC>(m));
+        ka->arg((T*)g.rec);
+        ka->arg(g.rec_off);
+        ka->func = (const void*)&k_coefrec_batch<T, TP>;
+        ka->grid = dim3(g.n_items);
+        ka->block = dim3(192);
+        kb->arg(b);
+        kb->arg((const T*)g.rec);
+        kb->arg(g.rec_off);
+        kb->func = waves == 2 ? (const void*)&k_tangent_batch<T, TP, 2>
+                              : (const void*)&k_tangent_batch<T, TP, 1>;
+        kb->grid = dim3(g.n_items * SplitRec<TP>::NBLK);
+        kb->block = dim3(64 * TP::L);
+        return ka->ok() && kb->ok() ? CIS_OK
+                                    : fail(CIS_ERR_DIM, "prep_split_batch: launch record refused");
+    } else {
+        return fail(CIS_ERR_UNSUPPORTED, "split form needs legs with links");
+    }
+}
+
+cis_status prep_split_batch(const cis_model* m, int32_t dtype, const BatchGroupDev& g,
+                            int waves, KLaunch* ka, KLaunch* kb) {
+#define CIS_PREP_SPLIT(LL, DD)                                                        \
+    if (m->L == LL && m->D == DD)                                                     \
+        return dtype == CIS_F64 ? prep_split_t<double, LL, DD>(m, g, waves, ka, kb)   \
+                                : prep_split_t<float, LL, DD>(m, g, waves, ka, kb);
+    CIS_TOPOLOGIES(CIS_PREP_SPLIT)
+#undef CIS_PREP_SPLIT
+    return fail(CIS_ERR_UNSUPPORTED, "prep_split_batch: topology has no compiled kernel");
+}
+
+bool split_form_supported(const cis_model* m) { return split_supported(m); }
+
+}  // namespace cis
+
+using namespace cis;
+
+static cis_status split_ws_bytes(const cis_model* m, const cis_shape* sh, size_t* bytes) {
+    const int64_t per = split_elems_per_interval(m, sh->substeps);
+    if (per < 0)
+        return fail(CIS_ERR_UNSUPPORTED, "split form: the model has no legs with links");
+    *bytes = (size_t)per * (size_t)sh->N * elem_size(sh->dtype);
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_split_workspace_size(const cis_model* m, const cis_shape* sh,
+                                               size_t* bytes) {
+    if (!m || !sh || !bytes) return fail(CIS_ERR_NULL, "cis_split_workspace_size: null argument");
+    if (sh->N < 1 || sh->substeps < 1 || sh->substeps > 4096)
+        return fail(CIS_ERR_DIM, "cis_split_workspace_size: N=%d, K=%d out of range", sh->N,
+                    sh->substeps);
+    if (sh->dtype != CIS_F64 && sh->dtype != CIS_F32)
+        return fail(CIS_ERR_DTYPE, "cis_split_workspace_size: unknown dtype %d", sh->dtype);
+    return split_ws_bytes(m, sh, bytes);
+}
+
+extern "C" cis_status cis_discretize_split(const cis_model* model, const cis_shape* shape,
+                                           const void* X, const void* U, const void* s,
+                                           const void* params, int32_t waves, void* A, void* Bm,
+                                           void* Bp, void* S, void* defect, void* xprop, void* ws,
+                                           size_t ws_bytes, void* stream) {
+    cis_status st = check_common(model, shape, X, U, s, params);
+    if (st != CIS_OK) return st;
+    if (waves != 1 && waves != 2)
+        return fail(CIS_ERR_DIM, "cis_discretize_split: waves=%d must be 1 or 2", waves);
+    const bool hasm = model->m > 0;
+    if (!A || !S || !defect || (hasm && (!Bm || !Bp)))
+        return fail(CIS_ERR_NULL, "cis_discretize_split: A, S, defect (and Bm, Bp when m > 0) are required");
+    const size_t es = elem_size(shape->dtype);
+    if (!aligned(A, es) || !aligned(S, es) || !aligned(defect, es) || !aligned(xprop, es) ||
+        !aligned(Bm, es) || !aligned(Bp, es) || !aligned(ws, 8))
+        return fail(CIS_ERR_LAYOUT, "cis_discretize_split: pointer not aligned to %zu bytes", es);
+    size_t need = 0;
+    st = split_ws_bytes(model, shape, &need);
+    if (st != CIS_OK) return st;
+    if (!ws || ws_bytes < need)
+        return fail(CIS_ERR_WORKSPACE, "cis_discretize_split: workspace of %zu bytes needed", need);
+    hipStream_t hs = (hipStream_t)stream;
+#define CIS_DISPATCH_SPLIT(LL, DD)                                                             \
+    if (model->L == LL && model->D == DD)                                                      \
+        return shape->dtype == CIS_F64                                                         \
+                   ? launch_split_t<double, LL, DD>(model, shape, X, U, s, params, A, Bm, Bp, \
+                                                    S, defect, xprop, ws, waves, hs)           \
+                   : launch_split_t<float, LL, DD>(model, shape, X, U, s, params, A, Bm, Bp,  \
+                                                   S, defect, xprop, ws, waves, hs);
+    CIS_TOPOLOGIES(CIS_DISPATCH_SPLIT)
+#undef CIS_DISPATCH_SPLIT
+    return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_split: topology has no compiled kernel");
+}

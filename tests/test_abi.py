@@ -233,7 +233,9 @@ def test_batch_plan_validates_before_any_device_call():
     assert create([good], ops=0) == _lib.CIS_ERR_DIM
     assert create([good], ops=4) == _lib.CIS_ERR_DIM
     assert create([good], sched=0) == _lib.CIS_ERR_DIM
-    assert create([good], sched=_lib.CIS_SCHED_GRID | 0x800) == _lib.CIS_ERR_DIM   # unknown bit
+    assert create([good], sched=_lib.CIS_SCHED_GRID | 0x2000) == _lib.CIS_ERR_DIM   # unknown bit
+    assert create([good], sched=_lib.CIS_SCHED_TUNE | _lib.CIS_SCHED_SPLIT
+                  | _lib.CIS_SCHED_FUSED) == _lib.CIS_ERR_DIM
     two_def = _lib.CIS_SCHED_DEF_BODY | _lib.CIS_SCHED_DEF_LANE
     assert create([good], sched=_lib.CIS_SCHED_GRID | two_def) == _lib.CIS_ERR_DIM
     assert create([good], sched=_lib.CIS_SCHED_GRID | _lib.CIS_SCHED_ADJ_4

@@ -105,3 +105,24 @@ def test_quad13_adjoint_configuration_intervals_well_conditioned():
     model, data, lam = _quad13_adjoint_case(T=0.04)
     spread = _adj_spread(model, data, 4, lam, 2.0 ** -53)
     assert spread < 0.1 * TOL64, spread
+
+
+def _quad13_split_case(T):
+    # the model and nodes of the quad13 FP64 case of the split-form tests
+    # (seed 300, N = 3, K = 2)
+    rng = np.random.default_rng(300)
+    model = synth.make_quad13(rng)
+    data = synth.gen_nodes(model, 3, rng) if T is None else synth.gen_nodes(model, 3, rng, T=T)
+    return model, data
+
+
+def test_quad13_split_case_conditioning():
+    """With the default 1 s over 3 intervals (0.26-0.37 s each, K = 2) a one-ulp
+    input perturbation moves the oracle by the order of the FP64 bar; at the
+    configurations' 0.02 s intervals by less than a thousandth of it."""
+    model, data = _quad13_split_case(None)
+    long_spread = _fwd_spread(model, data, 2, 2.0 ** -53, PHI64)
+    assert long_spread > 0.3 * TOL64, long_spread
+    model, data = _quad13_split_case(0.06)
+    short_spread = _fwd_spread(model, data, 2, 2.0 ** -53, PHI64)
+    assert short_spread < 1e-3 * TOL64, short_spread

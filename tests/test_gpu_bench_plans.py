@@ -125,18 +125,23 @@ def quad13():
     return batch, ref64, ref32
 
 
-@pytest.mark.parametrize("sched,waves", [("tune", None), ("grid", 1), ("grid", 2),
-                                         ("persistent", 1), ("persistent", 2)])
-def test_quad13x64_fp64_discretize_plans(quad13, sched, waves):
+@pytest.mark.parametrize("sched,waves,form", [("tune", None, None), ("grid", 1, "fused"),
+                                              ("grid", 2, "fused"), ("persistent", 1, "fused"),
+                                              ("persistent", 2, "fused"), ("grid", 1, "split"),
+                                              ("grid", 2, "split")])
+def test_quad13x64_fp64_discretize_plans(quad13, sched, waves, form):
     api = _api()
     batch, ref64, _ = quad13
-    _say(f"quad13 x64 fp64 discretize sched={sched} waves={waves}")
+    _say(f"quad13 x64 fp64 discretize sched={sched} waves={waves} form={form}")
     trajs = _upload(batch, torch.float64)
-    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=True, waves_per_simd=waves)
+    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=True, waves_per_simd=waves,
+                         form=form)
     g = plan.groups()
     assert len(g) == 1 and g[0]["n_items"] == 64 * 200
     if waves is not None:
         assert g[0]["waves_per_simd"] == waves
+    if form is not None:
+        assert g[0]["split"] == (form == "split")
     # NaN-filled outputs first, so a unit the plan skips cannot pass
     for o in plan.out:
         for key in KEYS:
@@ -151,13 +156,18 @@ def test_quad13x64_fp64_discretize_plans(quad13, sched, waves):
     plan.close()
 
 
-@pytest.mark.parametrize("sched", ["tune", "grid", "persistent"])
-def test_quad13x64_fp32_discretize_plans(quad13, sched):
+@pytest.mark.parametrize("sched,form,waves", [("tune", None, None), ("grid", "fused", None),
+                                              ("persistent", "fused", None),
+                                              ("grid", "split", 1), ("grid", "split", 2)])
+def test_quad13x64_fp32_discretize_plans(quad13, sched, form, waves):
     api = _api()
     batch, _, ref32 = quad13
-    _say(f"quad13 x64 fp32 discretize sched={sched}")
+    _say(f"quad13 x64 fp32 discretize sched={sched} form={form} waves={waves}")
     trajs = _upload(batch, torch.float32)
-    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=True)
+    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=True, form=form,
+                         waves_per_simd=waves)
+    if form is not None:
+        assert plan.groups()[0]["split"] == (form == "split")
     for o in plan.out:
         for key in KEYS:
             o[key].fill_(float("nan"))
@@ -247,16 +257,28 @@ def mixed():
     return batch, refs
 
 
-@pytest.mark.parametrize("sched,waves", [("tune", None), ("grid", 2), ("persistent", 1)])
-def test_mixed256_discretize_plans(mixed, sched, waves):
+@pytest.mark.parametrize("sched,waves,form", [("tune", None, None), ("grid", 2, "fused"),
+                                              ("persistent", 1, "fused"), ("grid", 1, "split"),
+                                              ("grid", 2, "split")])
+def test_mixed256_discretize_plans(mixed, sched, waves, form):
     api = _api()
     batch, refs = mixed
-    _say(f"mixed 256 fp64 discretize sched={sched} waves={waves}")
+    _say(f"mixed 256 fp64 discretize sched={sched} waves={waves} form={form}")
     trajs = _upload(batch, torch.float64)
-    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=True, waves_per_simd=waves)
-    assert len(plan.groups()) == 3
+    plan = api.BatchPlan(trajs, ("discretize",), sched=sched, graph=True, waves_per_simd=waves,
+                         form=form)
+    g = plan.groups()
+    assert len(g) == 3
+    if form is not None:
+        assert all(x["split"] == (form == "split") for x in g), g
+    for o in plan.out:
+        for key in KEYS:
+            o[key].fill_(float("nan"))
     plan.run("discretize", graph=True)
     torch.cuda.synchronize()
+    for o in plan.out:
+        for key in KEYS:
+            assert bool(torch.isfinite(o[key]).all()), key
     worst = _check_sampled(plan, batch, refs, fp32=False)
     _say(f"  worst block error {worst:.3e}")
     plan.close()
