@@ -46,6 +46,20 @@ def algorithmic_flops_per_interval(model, K):
     return K * (8 * nnz * c + 14 * model.nx * c + 4 * phi)
 
 
+def split_flops_per_interval(model, K):
+    """(coefficient-record launch, tangent launch) shares of the forward
+    FLOPs of one interval in the split form: the tangent launch integrates the
+    c - 1 columns of Phi_x, B-, B+ (K [8 nnz(J) + 14 nx] (c - 1)); the record
+    launch the right-hand side and Jacobian (4 K phi_fJ) and the dilation
+    column S (K [8 nnz(J) + 14 nx])."""
+    total = algorithmic_flops_per_interval(model, K)
+    nb, nj, nc = model.nb, model.nj, model.nc
+    nnz = 2 * 3 * nb + 2 * nb + 4 * nj + 4 * nc
+    c = model.n + 2 * model.m + 1
+    tangent = K * (8 * nnz + 14 * model.nx) * (c - 1)
+    return total - tangent, tangent
+
+
 def adjoint_flops_per_interval(model, K):
     """Per-interval FLOPs of one gradient step (defects pass + reverse sweep):
     K [6 phi_fJ + 8 (nnz(J) + nnz(J_u, J_ubar) + nnz(J_p)) + 14 nx] + 2 K phi_fJ.
@@ -99,11 +113,19 @@ def upload_batch(api, batch, dev, dtype):
 
 
 def batch_kernel_name(model, group, dtype):
-    """rocprofv3 short name of a batch group's discretize kernel."""
+    """rocprofv3 short name of a batch group's discretize kernel (the tangent
+    launch for the split form)."""
     t = "double" if dtype == "f64" else "float"
+    topo = f"Topo<{model.legs}, {model.depth}, 6, 1, false>"
+    if group.get("split"):
+        return f"k_tangent_batch<{t}, {topo}, {group['waves_per_simd']}>"
     pers = "true" if group["persist_blocks"] > 0 else "false"
-    return (f"k_discretize_batch<{t}, Topo<{model.legs}, {model.depth}, 6, 1, false>, {pers}, "
-            f"{group['waves_per_simd']}>")
+    return f"k_discretize_batch<{t}, {topo}, {pers}, {group['waves_per_simd']}>"
+
+
+def coefrec_kernel_name(model, dtype):
+    t = "double" if dtype == "f64" else "float"
+    return f"k_coefrec_batch<{t}, Topo<{model.legs}, {model.depth}, 6, 1, false>>"
 
 
 def host_cpu():
@@ -269,6 +291,14 @@ def main():
     ms_q64, wall_q64 = timed(lambda: plan64.run("discretize", graph=True, stream=stream),
                              args.steps, args.warmup)
     progress(f"quad13 x64 fp64 discretize {ms_q64:.3f} ms/step ({g64})")
+    # the launches of the step one by one (HIP events on the launch stream)
+    ms_part0, _ = timed(lambda: plan64.run_part("discretize", 0, stream=stream),
+                        max(args.steps // 5, 3), 1)
+    ms_part1 = None
+    if g64.get("split"):
+        ms_part1, _ = timed(lambda: plan64.run_part("discretize", 1, stream=stream),
+                            max(args.steps // 5, 3), 1)
+    progress(f"  launches: {ms_part0:.3f} ms" + (f" + {ms_part1:.3f} ms" if ms_part1 else ""))
     check_intervals("quad13x64_f64_discretize", qb, plan64, [(0, 0, 8), (37, 192, 8)], False)
     # gradient step of the same batch (merit seeds from its own defects pass)
     plan64.run("adjoint", graph=True, stream=stream)
@@ -283,7 +313,15 @@ def main():
     torch.cuda.empty_cache()
 
     kname = batch_kernel_name(qmodel, g64, "f64")
-    achieved = q_flops / (ms_q64 * 1e-3)
+    if g64.get("split"):
+        # dominant kernel: the tangent launch, timed alone
+        rec_fl = sum(split_flops_per_interval(m, k)[0] * d["s"].shape[0] for m, d, k in qb)
+        tan_fl = q_flops - rec_fl
+        achieved = tan_fl / (ms_part1 * 1e-3)
+        kflops, kms = tan_fl, ms_part1
+    else:
+        achieved = q_flops / (ms_part0 * 1e-3)
+        kflops, kms = q_flops, ms_part0
     line = {
         "metric": "discretized intervals/s (x+STM+B±) at 1e-10 rel vs oracle",
         "value": q_int / (ms_q64 * 1e-3),
@@ -307,9 +345,16 @@ def main():
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                      "traffic": committed_traffic(kname),
-                     "algorithmic_flop_per_launch": q_flops,
-                     "timing": "HIP events on the launch stream around the graph replays "
-                               "(one kernel node per replay)"},
+                     "algorithmic_flop_per_launch": kflops, "ms_per_launch": kms,
+                     "timing": "HIP events on the launch stream around launches of this "
+                               "kernel alone (cis_batch_run_part)",
+                     "step": {"achieved": q_flops / (ms_q64 * 1e-3) / 1e12,
+                              "frac": q_flops / (ms_q64 * 1e-3) / PEAK_FP64_VALU,
+                              "algorithmic_flop_per_step": q_flops,
+                              "kernels": ([coefrec_kernel_name(qmodel, "f64"), kname]
+                                          if g64.get("split") else [kname]),
+                              "ms_per_launch": ([ms_part0, ms_part1] if g64.get("split")
+                                                else [ms_part0])}},
         "gradient_step": {"value": q_int / (ms_qadj * 1e-3), "unit": "interval grads/s",
                           "ms_per_step": ms_qadj,
                           "roofline_frac": q_adj_flops / (ms_qadj * 1e-3) / PEAK_FP64_VALU,
@@ -452,6 +497,8 @@ def main():
         blk = {}
         ms_f, _ = timed(lambda: api.discretize(cmq, Xq, Uq, sq, pq, K, stream=stream), 10, 2)
         blk["fused_ms"] = ms_f
+        ms_s, _ = timed(lambda: api.discretize_split(cmq, Xq, Uq, sq, pq, K, stream=stream), 10, 2)
+        blk["split_ms"] = ms_s
         for B in (2, 4, 5):
             nb_ = api.blocked_workspace_bytes(cmq, data["s"].shape[0], K, B)
             wsb = torch.empty((nb_,), device=dev, dtype=torch.uint8)
@@ -478,9 +525,10 @@ def main():
         import oracle
         cpu = host_cpu()
         nthr = cpu["usable_cpus"]
-        # all usable threads: whole trajectories 1.. of the batch (1000 intervals
-        # with 8 or more threads); one thread: the first 12 intervals of one
-        n_tr = max(1, min(5, nthr // 3))
+        # all usable threads: whole trajectories 1.. of the batch (5000 intervals
+        # with 16 or more threads, about 10 s); one thread: one whole
+        # trajectory (200 intervals, about 7 s)
+        n_tr = max(1, min(25, (25 * nthr) // 16))
         n_all = 0
         t0 = time.perf_counter()
         for t in range(1, 1 + n_tr):
@@ -490,7 +538,7 @@ def main():
             n_all += data["s"].shape[0]
         dt_all = time.perf_counter() - t0
         model, data, K = qb[1]
-        n_one = 12
+        n_one = 200   # one whole trajectory
         t0 = time.perf_counter()
         oracle.discretize(model, data["X"][:n_one + 1], data["U"][:n_one + 1], data["s"][:n_one],
                           data["p"], K, nthreads=1)

@@ -319,7 +319,8 @@ enum { CIS_SCHED_ADJ_1 = 0x10, CIS_SCHED_ADJ_2 = 0x20, CIS_SCHED_ADJ_3 = 0x30,
  * kernel: CIS_SCHED_WAVES_1 lets it take all the registers its workgroup
  * size allows; CIS_SCHED_WAVES_2 holds it to 256 registers per lane so that
  * two workgroups can share a compute unit (latency hiding, at the price of
- * spills to scratch; CIS_F64 only, else CIS_ERR_DTYPE).  Workgroups of more
+ * spills to scratch; CIS_F64 only, else CIS_ERR_DTYPE, except together with
+ * CIS_SCHED_SPLIT, whose tangent launch has both budgets in both types).  Workgroups of more
  * than four waves (models with many tangent columns) are held to 256
  * registers in both forms.  Without either bit both FP64 forms are timed
  * with CIS_SCHED_TUNE, and the first is used otherwise.  Setting both bits
@@ -366,6 +367,15 @@ cis_status cis_batch_plan_create(const cis_traj *trajs, int32_t n_traj, cis_dtyp
  * must have been requested at creation) of every trajectory on `stream`:
  * the models' launches are issued one after another. */
 cis_status cis_batch_run(cis_batch_plan *plan, int32_t op, void *stream);
+
+/* One launch of cis_batch_run for every model group, so that each kernel of
+ * an operation can be timed on its own: for CIS_BATCH_DISCRETIZE part 0 is
+ * the one-launch kernel or the split form's coefficient-record launch, part 1
+ * the split form's tangent launch (nothing for groups in the one-launch form);
+ * for CIS_BATCH_ADJOINT part 0 is the defects pass, 1 the reverse sweep, 2
+ * the reduction.  Parts of one run must be enqueued in order on one stream
+ * (each reads what the previous part wrote).  part out of range: CIS_ERR_DIM. */
+cis_status cis_batch_run_part(cis_batch_plan *plan, int32_t op, int32_t part, void *stream);
 
 /* Same work as cis_batch_run, replayed from the plan's HIP graph, in which
  * the models' launches are independent nodes (they may run concurrently). */

@@ -51,6 +51,7 @@ EXPORTS = [
     "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
     "cis_blocked_workspace_size", "cis_discretize_blocked", "cis_discretize_adjoint_noalloc",
     "cis_split_workspace_size", "cis_discretize_split", "cis_batch_plan_discretize_form",
+    "cis_batch_run_part",
 ]
 
 
@@ -140,6 +141,8 @@ def load(build_if_missing: bool = True):
                                           ctypes.POINTER(P)]
     lib.cis_batch_run.restype = St
     lib.cis_batch_run.argtypes = [P, I32, P]
+    lib.cis_batch_run_part.restype = St
+    lib.cis_batch_run_part.argtypes = [P, I32, I32, P]
     lib.cis_batch_graph_run.restype = St
     lib.cis_batch_graph_run.argtypes = [P, I32, P]
     lib.cis_batch_plan_info.restype = St

@@ -416,6 +416,12 @@ class BatchPlan:
         fn = lib.cis_batch_graph_run if graph else lib.cis_batch_run
         _lib.check(fn(self._h, _OPS[op], _stream(stream)))
 
+    def run_part(self, op="discretize", part=0, *, stream=None):
+        """Enqueue one launch of the operation for every model group (for timing
+        the kernels one by one; parts of one run in order on one stream)."""
+        lib = _lib.load()
+        _lib.check(lib.cis_batch_run_part(self._h, _OPS[op], int(part), _stream(stream)))
+
     def groups(self):
         """Per model group: trajectories, items, units per item, persistent grid (0 = grid),
         waves of the reverse sweep, register budget of the discretize kernel, waves of the

@@ -227,8 +227,9 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         waves_force == 3 || def_force == 3 || split_force == 3 || (adj4 && adj_force))
         return fail(CIS_ERR_DIM, "cis_batch_plan_create: unknown schedule %d", sched_all);
     if (adj4) adj_force = 4;
-    if (waves_force == 2 && dtype != CIS_F64)
-        return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: CIS_SCHED_WAVES_2 is offered in CIS_F64 only");
+    if (waves_force == 2 && dtype != CIS_F64 && split_force != 1)
+        return fail(CIS_ERR_DTYPE, "cis_batch_plan_create: CIS_SCHED_WAVES_2 is offered in CIS_F64 "
+                                   "only (FP32: with CIS_SCHED_SPLIT)");
     if (ckpt_every < 0) return fail(CIS_ERR_DIM, "cis_batch_plan_create: ckpt_every=%d < 0", ckpt_every);
     for (int i = 0; i < n_traj; ++i) {
         cis_status st = check_traj(trajs[i], i, dtype, ops);
@@ -616,6 +617,35 @@ extern "C" cis_status cis_batch_run(cis_batch_plan* p, int32_t op, void* stream)
     if (op == CIS_BATCH_ADJOINT) {
         hipError_t e = p->red.launch(hs);
         if (e != hipSuccess) return fail(CIS_ERR_HIP, "cis_batch_run: reduction launch: %s", hipGetErrorString(e));
+    }
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_run_part(cis_batch_plan* p, int32_t op, int32_t part,
+                                         void* stream) {
+    if (!p) return fail(CIS_ERR_NULL, "cis_batch_run_part: plan is required");
+    if ((op != CIS_BATCH_DISCRETIZE && op != CIS_BATCH_ADJOINT) || !(p->ops & op))
+        return fail(CIS_ERR_DIM, "cis_batch_run_part: operation %d was not planned", op);
+    if (part != 0 && part != 1 && !(op == CIS_BATCH_ADJOINT && part == 2))
+        return fail(CIS_ERR_DIM, "cis_batch_run_part: part %d out of range", part);
+    hipStream_t hs = (hipStream_t)stream;
+    for (Group& g : p->groups) {
+        hipError_t e = hipSuccess;
+        if (op == CIS_BATCH_DISCRETIZE) {
+            if (part == 0) e = g.disc.launch(hs);
+            else if (g.split) e = g.disc_b.launch(hs);
+        } else if (part == 0) {
+            e = g.def.launch(hs);
+        } else if (part == 1) {
+            e = g.adj.launch(hs);
+        }
+        if (e != hipSuccess)
+            return fail(CIS_ERR_HIP, "cis_batch_run_part: launch: %s", hipGetErrorString(e));
+    }
+    if (op == CIS_BATCH_ADJOINT && part == 2) {
+        hipError_t e = p->red.launch(hs);
+        if (e != hipSuccess)
+            return fail(CIS_ERR_HIP, "cis_batch_run_part: reduction launch: %s", hipGetErrorString(e));
     }
     return CIS_OK;
 }

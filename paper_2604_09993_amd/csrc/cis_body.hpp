@@ -287,8 +287,12 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
 // one workgroup barrier; without WRITE only the integral-row integrands are
 // formed (nothing is stored).
 // ---------------------------------------------------------------------------
+// STORES: 0 = values gathered, stored at the end in the compiler's order
+// (FP32 default); 1 = the same with a scheduling fence before the stores
+// (FP64 default); 2 = each value stored as soon as it is formed (fewest
+// registers).
 template <class T, class TP, bool SPLIT = false, bool WRITE = true, class LY = CoefDense<TP>,
-          bool BURST = (sizeof(T) == 8)>
+          int STORES = (sizeof(T) == 8 ? 1 : 0)>
 __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
                                            const BodyConst<T, TP>& c, const T* xs,
@@ -369,11 +373,12 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         fa[k] = fv[3 * b + k];
     }
     if constexpr (WRITE) {
-        // BURST (FP64 by default): all values and addresses are formed first
-        // and stored in one burst, since a register overwritten right after an
-        // LDS store waits until the LDS unit has read it (measured faster);
-        // FP32 keeps the compiler's interleaved order (measured faster there).
-        constexpr int NV = BURST ? 42 + LY::TORSO_COPIES : 1;
+        // STORES = 1 (FP64 by default): all values and addresses are formed
+        // first and stored in one burst, since a register overwritten right
+        // after an LDS store waits until the LDS unit has read it (measured
+        // faster); FP32 keeps the compiler's interleaved order (measured faster
+        // there); STORES = 2 stores at once (throughput kernels).
+        constexpr int NV = STORES < 2 ? 42 + LY::TORSO_COPIES : 1;
         T val[NV];
         T* ptr[NV];
         int e = 0;
@@ -382,7 +387,7 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
         T* tr = cf + LY::TRASH + lane;
         auto put = [&](bool ok, int off, T v, int t = 0) {
             T* const a = ok ? cf + off : tr + t;
-            if constexpr (BURST) {
+            if constexpr (STORES < 2) {
                 ptr[e] = a;
                 val[e] = v;
                 ++e;
@@ -441,8 +446,8 @@ __device__ __forceinline__ void coef_stage(const Interval<T, TP>& iv,
 #pragma unroll
         for (int q = 1; q < LY::TORSO_COPIES; ++q) put(lane == 0, LY::cth(0, q), cth, q);
         put(bl, LY::ctp(b), ctp);
-        if constexpr (BURST) {
-            __builtin_amdgcn_sched_barrier(0);
+        if constexpr (STORES < 2) {
+            if constexpr (STORES == 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < NV; ++q) *ptr[q] = val[q];
         }

@@ -159,7 +159,7 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
             const int st = tc & 3;
             const T tau = (T(tc >> 2) + T(stage_c(st))) / T(a.K);
             T ycc = T(0), yct = T(0);
-            coef_stage<T, TP, false, true, R, false>(sh.iv, mc, c,
+            coef_stage<T, TP, false, true, R, 2>(sh.iv, mc, c,
                                                      tc == 0 ? sh.iv.x0 : sh.xring[tc & 3],
                                                      sh.csring[tc & 3], sh.fring[tc & 3], tau,
                                                      sh.coef[tc & 1], ycc, yct, lane);
@@ -253,25 +253,38 @@ struct TanLane {
     T ycc, yct;
 };
 
+// One element of a raw buffer at byte offset `off` (offsets within the
+// resource's byte range only).
+template <class T>
+__device__ __forceinline__ T buffer_elem(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
 template <class T, class TP, int ST, bool FORCE>
 __device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* __restrict__ cr,
                                                     const T* __restrict__ lr,
                                                     const T* __restrict__ rs, T* xch, int leg,
                                                     int lane, T tau, T wbm, T wbp,
-                                                    const int (&off)[3 * (TP::D + 1)],
-                                                    int offcc) {
+                                                    const unsigned (&off)[3 * (TP::D + 1)],
+                                                    unsigned offcc) {
     constexpr int LB = TP::D + 1, D = TP::D, L = TP::L;
     const T s = cr[0], h = cr[1], h6 = cr[2];
 #define ZQ(lb, k) z.zs[3 * (lb) + (k)]
 #define ZV(lb, k) z.zs[3 * LB + 3 * (lb) + (k)]
     // forcing of B-/B+ columns (zero offsets and weights elsewhere): issued
-    // first, used last
+    // first, used last; buffer loads at per-lane byte offsets from the stage
+    // record (a scalar resource, so no per-lane 64-bit addresses)
     T g[3 * LB];
     T gcc = T(0);
     if constexpr (FORCE) {
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<T*>(rs), (short)0, (int)(CoefRec<TP>::GLOBAL * sizeof(T)), 0x00020000);
 #pragma unroll
-        for (int r = 0; r < 3 * LB; ++r) g[r] = rs[off[r]];
-        gcc = rs[offcc];
+        for (int r = 0; r < 3 * LB; ++r) g[r] = buffer_elem<T>(rsrc, off[r]);
+        gcc = buffer_elem<T>(rsrc, offcc);
     }
     // hip stiffness and damping of this leg on the torso, exchanged
     const T* kcl = cr + 8 + 4 * leg * D;   // kc[j][4] of the leg's joints
@@ -382,7 +395,8 @@ template <class T, class TP, bool FORCE>
 __device__ __forceinline__ void tangent_split_loop(TanLane<T, TP>& z, const T* __restrict__ cr,
                                                    const T* __restrict__ rec0, T* xch, int leg,
                                                    int lane, int K, T wbm, T wbp,
-                                                   const int (&off)[3 * (TP::D + 1)], int offcc) {
+                                                   const unsigned (&off)[3 * (TP::D + 1)],
+                                                   unsigned offcc) {
     using R = CoefRec<TP>;
     constexpr int LEGB = R::LEGB, GL = R::GLOBAL, L = TP::L;
     const T Kt = T(K);
@@ -424,15 +438,17 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
     if (col >= NX && col < NX + M) { wbm = T(1); ctrl = col - NX; }
     else if (col >= NX + M && col < NX + 2 * M) { wbp = T(1); ctrl = col - NX - M; }
     const bool bcol = wbm != T(0) || wbp != T(0);
-    int off[3 * LB];
+    // byte offsets of the forcing entries of the lane's control in a stage record
+    unsigned off[3 * LB];
 #pragma unroll
     for (int lb = 0; lb < LB; ++lb)
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk)
-            off[3 * lb + kk] = bcol ? forcing_offset<TP>(ctrl, gbody(lb), kk) : CoefRec<TP>::ZERO;
-    int offcc = CoefRec<TP>::ZERO;
+            off[3 * lb + kk] = sizeof(T) * (unsigned)(bcol ? forcing_offset<TP>(ctrl, gbody(lb), kk)
+                                                           : CoefRec<TP>::ZERO);
+    unsigned offcc = sizeof(T) * (unsigned)CoefRec<TP>::ZERO;
     if (bcol && ctrl >= 3 * TP::NJ && (ctrl - 3 * TP::NJ) / 3 == leg)
-        offcc = CoefRec<TP>::gc(leg, (ctrl - 3 * TP::NJ) % 3);
+        offcc = sizeof(T) * (unsigned)CoefRec<TP>::gc(leg, (ctrl - 3 * TP::NJ) % 3);
     TanLane<T, TP> z;
 #pragma unroll
     for (int lb = 0; lb < LB; ++lb)
