@@ -152,6 +152,12 @@ def bench_algorithmic_bytes():
         out[f"k_adjoint4_batch<double, {t}"] = tot("adjoint", auto_ckpt)
         out[f"k_adjoint3_batch<double, {t}"] = tot("adjoint", auto_ckpt)
         out[f"k_adjoint_batch<double, {t}"] = tot("adjoint", auto_ckpt)
+    for t, items in groups.items():
+        for ds, tn in ((8, "double"), (4, "float")):
+            rec = sum(n * split_bytes(m_, ds)[0] for m_, n, k in items)
+            tan = sum(n * split_bytes(m_, ds)[1] for m_, n, k in items)
+            out[f"k_coefrec_batch<{tn}, {t}"] = rec
+            out[f"k_tangent_batch<{tn}, {t}"] = tan
     qb = synth.workload_batch("quad13_N200_K20_x64")
     t = _topo(qb[0][0])
     out[f"k_discretize_batch<double, {t}"] = sum(d["s"].shape[0] * interval_bytes(m_, k, "discretize")
@@ -159,7 +165,125 @@ def bench_algorithmic_bytes():
     out[f"k_discretize_batch<float, {t}"] = sum(d["s"].shape[0] *
                                                 interval_bytes(m_, k, "discretize", dsize=4)
                                                 for m_, d, k in qb)
+    for ds, tn in ((8, "double"), (4, "float")):
+        out[f"k_coefrec_batch<{tn}, {t}"] = sum(d["s"].shape[0] * split_bytes(m_, ds)[0]
+                                               for m_, d, k in qb)
+        out[f"k_tangent_batch<{tn}, {t}"] = sum(d["s"].shape[0] * split_bytes(m_, ds)[1]
+                                               for m_, d, k in qb)
     return out
+
+
+def split_bytes(model, dsize=8):
+    """Algorithmic bytes of one interval in the two launches of the split form:
+    the record launch reads the interval's inputs and writes S, the defect,
+    F~ and the integral-state columns of A; the tangent launch writes the
+    x-state columns of A and B-, B+ (the stage records between them are
+    intermediate, not algorithmic, traffic)."""
+    nx, m, n, P = model.nx, model.m, model.n, model.n_params
+    rec = dsize * ((2 * nx + 2 * m + 1 + P) + 3 * nx + nx * (nx - n))
+    tan = dsize * (nx * n + 2 * nx * m)
+    return rec, tan
+
+
+PHI_FJ = {2: 300, 5: 700, 7: 1000, 13: 2000}   # per-stage RHS + Jacobian FLOP by body count
+
+
+def interval_flops(model, K):
+    """Algorithmic forward FLOPs of one interval, K [8 nnz(J) c + 14 nx c + 4 phi_fJ],
+    and the tangent launch's share K [8 nnz(J) + 14 nx] (c - 1) in the split form."""
+    nnz = 2 * 3 * model.nb + 2 * model.nb + 4 * model.nj + 4 * model.nc
+    c = model.n + 2 * model.m + 1
+    phi = PHI_FJ.get(model.nb, 1000)
+    total = K * (8 * nnz * c + 14 * model.nx * c + 4 * phi)
+    tangent = K * (8 * nnz + 14 * model.nx) * (c - 1)
+    return total, tangent
+
+
+def bench_algorithmic_flops():
+    """Algorithmic FLOPs per launch of the forward kernels of bench.py's
+    batched workloads, keyed by kernel-name prefix."""
+    from . import synth
+    out = {}
+    groups = {}
+    for m_, d, k in synth.mixed_batch():
+        groups.setdefault(_topo(m_), []).append((m_, d["s"].shape[0], k))
+    qb = synth.workload_batch("quad13_N200_K20_x64")
+    groups[_topo(qb[0][0])] = [(m_, d["s"].shape[0], k) for m_, d, k in qb]
+    for t, items in groups.items():
+        tot = sum(n * interval_flops(m_, k)[0] for m_, n, k in items)
+        tan = sum(n * interval_flops(m_, k)[1] for m_, n, k in items)
+        for tn in ("double", "float"):
+            out[f"k_discretize_batch<{tn}, {t}"] = tot
+            out[f"k_coefrec_batch<{tn}, {t}"] = tot - tan
+            out[f"k_tangent_batch<{tn}, {t}"] = tan
+    return out
+
+
+def valu_summary(a):
+    """Markdown table of VALU/LDS counters per kernel: counter FLOPs against
+    algorithmic FLOPs, achieved counter FLOP/s, VALU issue estimate."""
+    import csv
+    per = defaultdict(lambda: defaultdict(list))   # kernel -> counter -> per-dispatch values
+    for path in a.csv:
+        vals = defaultdict(lambda: defaultdict(float))
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                vals[(_short(r["Kernel_Name"]), r["Dispatch_Id"])][r["Counter_Name"]] += \
+                    float(r["Counter_Value"])
+        for (k, _), cs in vals.items():
+            for c, v in cs.items():
+                per[k][c].append(v)
+    mean = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in per.items()}
+    stats = kernel_stats(a.trace) if a.trace else {}
+    algo = bench_algorithmic_flops()
+    clock = 2.4e9
+    simds = 1024
+    lines = [f"# {a.title}", "", "Box: one MI355X (gfx950). All commands run from the repository root.",
+             "", "Counter passes (one rocprofv3 run each, --pmc only):", ""]
+    lines += [f"    {c}" for c in a.commands]
+    lines += ["", f"Kernel durations: `{a.cmd_trace}`", "",
+              "Per dispatch: F64 FLOP = 64 (2 FMA + ADD + MUL) over the F64 VALU instruction counters "
+              "(64 lanes per wave instruction, inactive lanes included), likewise F32; "
+              "`VALU issue` = SQ_INSTS_VALU x 4 cycles (a 64-lane instruction at 16 lanes per "
+              "clock) / (kernel time x 2.4 GHz x 1024 SIMDs), an estimate of the fraction of "
+              "SIMD cycles spent issuing VALU instructions.", "",
+              "| kernel | avg µs | F64 FLOP (counter) | algorithmic FLOP | counter / algorithmic | "
+              "counter TFLOP/s | algorithmic TFLOP/s | VALU instr | VALU issue | LDS instr | "
+              "LDS bank-conflict cycles | waves |",
+              "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(mean, key=lambda k: -stats.get(k, {}).get("total_us", 0.0)):
+        if not k.startswith("k_"):
+            continue
+        c = mean[k]
+        f64 = 64 * (2 * c.get("SQ_INSTS_VALU_FMA_F64", 0) + c.get("SQ_INSTS_VALU_ADD_F64", 0) +
+                    c.get("SQ_INSTS_VALU_MUL_F64", 0))
+        f32 = 64 * (2 * c.get("SQ_INSTS_VALU_FMA_F32", 0) + c.get("SQ_INSTS_VALU_ADD_F32", 0) +
+                    c.get("SQ_INSTS_VALU_MUL_F32", 0))
+        fl = f64 if f64 >= f32 else f32
+        al = _match(algo, k)
+        us = stats.get(k, {}).get("avg_us")
+        t = us * 1e-6 if us else None
+        issue = c.get("SQ_INSTS_VALU", 0) * 4 / (t * clock * simds) if t else None
+        fmt = lambda v, f="{:.3g}": "" if v is None else f.format(v)
+        lines.append("| `{}` | {} | {} | {} | {} | {} | {} | {} | {} | {} | {} | {} |".format(
+            k, fmt(us, "{:.1f}"), fmt(fl), fmt(al), fmt(fl / al if al else None, "{:.2f}"),
+            fmt(fl / t / 1e12 if t else None, "{:.2f}"),
+            fmt(al / t / 1e12 if (t and al) else None, "{:.2f}"),
+            fmt(c.get("SQ_INSTS_VALU")), fmt(issue, "{:.2f}"), fmt(c.get("SQ_INSTS_LDS")),
+            fmt(c.get("SQ_LDS_BANK_CONFLICT")), fmt(c.get("SQ_WAVES"))))
+    lines += ["", "Raw counters per dispatch (means):", ""]
+    names = sorted({n for cs in mean.values() for n in cs})
+    lines.append("| kernel | " + " | ".join(names) + " |")
+    lines.append("|---|" + "---|" * len(names))
+    for k in sorted(mean):
+        if not k.startswith("k_"):
+            continue
+        lines.append(f"| `{k}` | " + " | ".join(f"{mean[k].get(n, 0):.4g}" for n in names) + " |")
+    if a.note:
+        lines += ["", a.note]
+    with open(a.md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {a.md}")
 
 
 def _match(table, kernel):
@@ -227,9 +351,19 @@ def main():
                    help="JSON {kernel-name prefix: algorithmic bytes per launch}; default: "
                         "the workloads of bench.py")
     s.add_argument("--note", default="")
+    v = sub.add_parser("valu")
+    v.add_argument("--csv", nargs="+", required=True, help="rocprofv3 CSV counter files")
+    v.add_argument("--trace", default="", help="kernel-trace output folder (durations)")
+    v.add_argument("--commands", nargs="*", default=[], help="the counter commands, for the record")
+    v.add_argument("--cmd-trace", default="")
+    v.add_argument("--md", required=True)
+    v.add_argument("--title", default="VALU and LDS counters")
+    v.add_argument("--note", default="")
     a = ap.parse_args()
     if a.cmd == "copy":
         run_copy()
+    elif a.cmd == "valu":
+        valu_summary(a)
     else:
         summarize(a)
 
