@@ -175,3 +175,106 @@ def test_adjoint_contraction_of_forward_sensitivities():
     assert block_err(g["gX"].T[:5], gX, PHI64) <= 1e-12 * 100
     assert block_err(g["gU"].T, gU, PHI64) <= 1e-12 * 100
     assert _vec_err(g["gs"], np.einsum("ki,ki->k", S, lam)) <= 1e-12 * 100
+
+
+def _merit_autograd(api, cm, model, data, K, C, dev):
+    """Gradients of the R15 merit through CisDefects (reverse-mode kernel)."""
+    X, U, s, p = _dev_inputs(api, data, dev)
+    for t in (X, U, s, p):
+        t.requires_grad_(True)
+    N = data["s"].shape[0]
+    F = api.CisDefects.apply(X, U, s, p, cm, K, C)
+    d = F - X[:, 1:N + 1]
+    J = 0.5 * (d ** 2).sum() + (F[model.n:] - X[model.n:, :N]).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    return X, U, s, p
+
+
+def test_merit_gradients_match_central_differences_of_nodes_controls_dilations():
+    """Central differences (h = 1e-6 relative, absolute 1e-6 for entries below
+    one) of the merit, evaluated with the GPU defects kernel, against the
+    reverse-mode gradients on 10 sampled entries each of X, U and s
+    (cheetah7 N = 50, K = 20, checkpoints every 5 substeps)."""
+    from paper_2604_09993_amd import api
+    _say("[gpu] merit FD on X, U, s: cheetah7 N=50 K=20 C=5, 10 entries each, seed 205")
+    model, data, K = synth.make_workload("cheetah7_N50_K20_ckpt5")
+    C = synth.WORKLOADS["cheetah7_N50_K20_ckpt5"]["ckpt"]
+    dev = torch.device("cuda:0")
+    cm = api.CisModel(model)
+    X, U, s, p = _merit_autograd(api, cm, model, data, K, C, dev)
+    N = data["s"].shape[0]
+
+    def merit(Xv, Uv, sv):
+        with torch.no_grad():
+            out = api.defects(cm, Xv, Uv, sv, p.detach(), K)
+            inc = out["xprop"][model.n:] - Xv[model.n:, :N]
+            return float(0.5 * (out["d"] ** 2).sum() + inc.sum())
+
+    Xd, Ud, sd = X.detach(), U.detach(), s.detach()
+    J0 = merit(Xd, Ud, sd)
+    rng = np.random.default_rng(205)
+    picks = ([("X", (int(rng.integers(model.nx)), int(rng.integers(N + 1)))) for _ in range(10)] +
+             [("U", (int(rng.integers(model.m)), int(rng.integers(N + 1)))) for _ in range(10)] +
+             [("s", (int(rng.integers(N)),)) for _ in range(10)])
+    grads = {"X": X.grad, "U": U.grad, "s": s.grad}
+    base = {"X": Xd, "U": Ud, "s": sd}
+    worst = 0.0
+    for name, idx in picks:
+        v = float(base[name][idx])
+        h = 1e-6 * max(1.0, abs(v))
+        args_p = {k: t.clone() for k, t in base.items()}
+        args_m = {k: t.clone() for k, t in base.items()}
+        args_p[name][idx] += h
+        args_m[name][idx] -= h
+        fd = (merit(args_p["X"], args_p["U"], args_p["s"]) -
+              merit(args_m["X"], args_m["U"], args_m["s"])) / (2 * h)
+        g = float(grads[name][idx])
+        tol = 1e-6 * max(1.0, abs(g)) + 64 * 2.2e-16 * abs(J0) / h
+        assert abs(fd - g) <= tol, (name, idx, fd, g, tol)
+        worst = max(worst, abs(fd - g) / max(1.0, abs(g)))
+    _say(f"  worst |FD - grad| / max(1, |grad|) = {worst:.2e}")
+
+
+def test_adjoint_bitwise_reproducible():
+    """Run-to-run: the reverse sweep and its reductions in fixed order give
+    bit-identical gX, gU, gs and gp on repeated calls, single trajectory and
+    batch plan."""
+    from paper_2604_09993_amd import api
+    _say("[gpu] adjoint run-to-run bitwise: cheetah7 N=50 K=20 C=5; mixed plan of 6 trajectories")
+    model, data, K = synth.make_workload("cheetah7_N50_K20_ckpt5")
+    C = synth.WORKLOADS["cheetah7_N50_K20_ckpt5"]["ckpt"]
+    dev = torch.device("cuda:0")
+    cm = api.CisModel(model)
+    X, U, s, p = _dev_inputs(api, data, dev)
+    fw = api.defects(cm, X, U, s, p, K, ckpt_every=C)
+    seed = torch.randn(fw["d"].shape, generator=torch.Generator().manual_seed(5),
+                       dtype=torch.float64).to(dev)
+    runs = [api.adjoint(cm, X, U, s, p, K, fw["ckpt"], C, seed) for _ in range(3)]
+    torch.cuda.synchronize()
+    for r in runs[1:]:
+        for key in ("gX", "gU", "gs", "gp"):
+            assert torch.equal(r[key], runs[0][key]), key
+    batch = synth.mixed_batch()[:6]
+    trajs = []
+    for m_, d_, k_ in batch:
+        c_ = api.CisModel(m_)
+        Nt = d_["s"].shape[0]
+        trajs.append(dict(cm=c_, K=k_, X=api.to_device_soa(d_["X"], dev, ld=Nt + 1),
+                          U=api.to_device_soa(d_["U"], dev, ld=Nt + 1),
+                          s=torch.tensor(d_["s"], device=dev),
+                          params=torch.tensor(d_["p"], device=dev)))
+    plan = api.BatchPlan(trajs, ("adjoint",), sched="tune", graph=True)
+    gen = torch.Generator().manual_seed(6)
+    for o in plan.out:
+        o["seed"].copy_(torch.randn(o["seed"].shape, generator=gen, dtype=torch.float64))
+    outs = []
+    for _ in range(3):
+        plan.run("adjoint", graph=True)
+        torch.cuda.synchronize()
+        outs.append([{k: o[k].clone() for k in ("gX", "gU", "gs", "gp")} for o in plan.out])
+    for o in outs[1:]:
+        for a_, b_ in zip(o, outs[0]):
+            for key in a_:
+                assert torch.equal(a_[key], b_[key]), key
+    plan.close()
