@@ -271,6 +271,33 @@ def gen_nodes(model: Model, N: int, rng: np.random.Generator,
     return {"X": X, "U": U, "s": s, "p": model.params()}
 
 
+def gen_impact_nodes(model: Model, n_nodes: int, rng: np.random.Generator,
+                     pose_sigma: float = 1e-3, impulse_range=(0.0, 5.0)):
+    """Seeded node variables of the impact map at an SCP iterate (not feasible in
+    general): pre-impact augmented states x~- as in gen_nodes (closed joints,
+    integral states U(0, 0.1)); post-impact states with the pose perturbed by
+    N(0, pose_sigma), velocities x- + N(0, 0.5) and integral states x- + U(0, 0.1);
+    per contact impulses Phi_n ~ U(impulse_range), Phi_t ~ U(-mu Phi_n, mu Phi_n)
+    (inside the friction cone), multipliers Gamma ~ U(0, 1).
+
+    Returns a dict with Xm, Xp [n_nodes, n~], Phi [n_nodes, 2 nc] (t, n per
+    contact), Gamma [n_nodes, nc], p [P] (float64, node-major).
+    """
+    nb, nc = model.nb, model.nc
+    Xm = gen_nodes(model, max(n_nodes - 1, 1), rng)["X"][:n_nodes].copy()
+    Xm[:, 6 * nb:] = rng.uniform(0.0, 0.1, size=(n_nodes, model.ny))
+    Xp = Xm.copy()
+    Xp[:, :3 * nb] += rng.normal(0.0, pose_sigma, size=(n_nodes, 3 * nb))
+    Xp[:, 3 * nb:6 * nb] += rng.normal(0.0, 0.5, size=(n_nodes, 3 * nb))
+    Xp[:, 6 * nb:] += rng.uniform(0.0, 0.1, size=(n_nodes, model.ny))
+    p = model.params()
+    pn = rng.uniform(*impulse_range, size=(n_nodes, nc))
+    pt = rng.uniform(-1.0, 1.0, size=(n_nodes, nc)) * p[0] * pn
+    Phi = np.stack([pt, pn], axis=2).reshape(n_nodes, 2 * nc)
+    Gam = rng.uniform(0.0, 1.0, size=(n_nodes, nc))
+    return {"Xm": Xm, "Xp": Xp, "Phi": Phi, "Gamma": Gam, "p": p}
+
+
 # Workload recipes (model, N, substeps) of the benchmark configurations.
 # The benchmark workloads by name: model, intervals N, substeps K, and the
 # seed of their node data (batch: trajectories; ckpt: substeps between the
