@@ -403,6 +403,67 @@ cis_status cis_batch_plan_discretize_form(const cis_batch_plan *plan, int32_t g,
 /* Release a plan (NULL accepted); synchronizes the device first. */
 void cis_batch_plan_destroy(cis_batch_plan *plan);
 
+/* Sizes of the impact-map outputs of a model: n_theta = 10 nc rows of Theta,
+ * n_jgv_cols = 7 nb + 2 nc columns of JGv, n_jtc_cols = 14 columns of JTc
+ * (any output pointer may be NULL). */
+cis_status cis_impact_dims(const cis_model *model, int32_t *n_theta, int32_t *n_jgv_cols,
+                           int32_t *n_jtc_cols);
+
+/*
+ * Node constraints of the transcribed problem and their Jacobians, for
+ * n_nodes nodes at once (Sec. IV-C, eq. cito-impulse and the families
+ * Theta^delta, Psi^{delta,eps}; impact model of Sec. II-B, eq. impulse-dynamics).
+ * FP64 only.  Per node k, with x~+ = (q+, v+, y+) and x~- = (q-, v-, y-):
+ *
+ *  G~_k = (q+ - q-, v+ - v*, y+ - y-)                       [nx]
+ *    v* = v- + M^-1 (J^T R Phi + grad h^T Lambda), the velocity after the
+ *    impact of eq. impulse-dynamics:velocity-change, with the joint impulse
+ *    Lambda eliminated by imposing grad h(q) v* = 0 after the impact (the
+ *    elimination stated after eq. impulse-dynamics).  Every geometric term
+ *    (grad h, J, the contact frame R = [t n]) is taken at the post-impact
+ *    pose q+; M = diag(m, m, m L^2/12) per body.
+ *  Theta_k, 10 rows per contact i (eq. impulse-dynamics:no-penetration,
+ *    eq. elasticity-impact, eq. max-diss-impulse-KKT:stationarity,
+ *    eq. impulse-friction-cone, relaxed with FB^delta(a, b) =
+ *    a + b - sqrt(a^2 + b^2 + delta) of eq. FB-relax):
+ *      FB(Phi_n, sd), FB(Phi_n, w), Phi_n lam - delta, -Phi_n lam - delta,
+ *      FB(Gamma, rho), -Phi_n, -sd, -w, -Gamma, -rho          (all <= 0)
+ *    with w = n^T J (v+ + e v-), lam = t^T J v+ + Gamma Phi_t / sqrt(Phi_t^2 + 1),
+ *    rho = |mu Phi_n|_s - |Phi_t|_s, |a|_s = sqrt(a^2 + 1) - 1.
+ *  Psi_k (k < n_nodes - 1) = (y-_{k+1} - y+_k) - (delta for the nc
+ *    cross-complementarity states, eps for the violation state)   [ny]
+ *
+ * Inputs (DEVICE, FP64, node index contiguous like X of cis_discretize):
+ *   Xp, Xm [nx][ld_node]   post- and pre-impact augmented states
+ *   Phi    [2 nc][ld_node] (Phi_t, Phi_n) of contact 0, then contact 1, ...
+ *   Gamma  [nc][ld_node]   friction multipliers
+ *   params [P] = (mu, e, masses)
+ * Outputs (DEVICE, FP64, node-major, packed; every entry written):
+ *   G     [n_nodes][nx]
+ *   Theta [n_nodes][10 nc]
+ *   JGv   [n_nodes][3 nb][7 nb + 2 nc]  dG~_{velocity rows} / d w with
+ *         w = (q+ [3 nb], v- [3 nb], Phi [2 nc], masses [nb])
+ *   JTc   [n_nodes][10 nc][14]  dTheta_{10 i + r} / d w_i with
+ *         w_i = (q+_b [3], v+_b [3], v-_b [3], Phi_t_i, Phi_n_i, Gamma_i, mu, e),
+ *         b the body of contact i
+ *   Psi   [n_nodes - 1][ny], or NULL to skip
+ * Entries of the full Jacobians outside these blocks are the same for every
+ * node and are not written: dG~/d(x~+, x~-) is +I / -I on the pose and
+ * integral-state rows, dG~_v/dv+ = I, and every other derivative of G~
+ * (v+ rows by q-, y+, y-, Gamma, mu, e) and of Theta (by q-, y+, y-, and the
+ * other contacts' variables) is 0; dPsi_k/dy+_k = -I, dPsi_k/dy-_{k+1} = I.
+ *
+ * delta > 0 and finite, eps finite; ld_node >= max(n_nodes, 1); n_nodes = 0
+ * enqueues nothing and checks no pointer.  Phi, Gamma, Theta and JTc may be NULL when nc = 0.
+ * Errors: CIS_ERR_NULL, CIS_ERR_DIM, CIS_ERR_LAYOUT (pointers must be 8-byte
+ * aligned), CIS_ERR_UNSUPPORTED, CIS_ERR_HIP.
+ */
+cis_status cis_impact_linearize(const cis_model *model, int32_t n_nodes, int64_t ld_node,
+                                const double *Xp, const double *Xm, const double *Phi,
+                                const double *Gamma, const double *params, double delta,
+                                double eps, double *G, double *Theta, double *JGv, double *JTc,
+                                double *Psi, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

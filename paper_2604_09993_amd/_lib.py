@@ -51,7 +51,7 @@ EXPORTS = [
     "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
     "cis_blocked_workspace_size", "cis_discretize_blocked", "cis_discretize_adjoint_noalloc",
     "cis_split_workspace_size", "cis_discretize_split", "cis_batch_plan_discretize_form",
-    "cis_batch_run_part",
+    "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize",
 ]
 
 
@@ -151,6 +151,11 @@ def load(build_if_missing: bool = True):
     lib.cis_batch_plan_discretize_form.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.cis_batch_plan_destroy.restype = None
     lib.cis_batch_plan_destroy.argtypes = [P]
+    lib.cis_impact_dims.restype = St
+    lib.cis_impact_dims.argtypes = [P] + [ctypes.POINTER(I32)] * 3
+    lib.cis_impact_linearize.restype = St
+    lib.cis_impact_linearize.argtypes = ([P, I32, ctypes.c_int64] + [P] * 5
+                                         + [ctypes.c_double, ctypes.c_double] + [P] * 6)
     _lib = lib
     return lib
 

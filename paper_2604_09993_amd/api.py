@@ -306,6 +306,65 @@ class CisDefects(torch.autograd.Function):
         return gX, gU, g["gs"], g["gp"], None, None, None
 
 
+def impact_dims(cm: CisModel):
+    """(rows of Theta, columns of JGv, columns of JTc) of a model."""
+    d = [ctypes.c_int32() for _ in range(3)]
+    _lib.check(_lib.load().cis_impact_dims(cm.handle, *[ctypes.byref(v) for v in d]))
+    return tuple(v.value for v in d)
+
+
+def impact_columns(model):
+    """Where the columns of the compact impact Jacobians sit in the node vector
+    z = (x~+ [nx], x~- [nx], Phi [2 nc], Gamma [nc], p [P]): an index array
+    [7 nb + 2 nc] for JGv and [nc, 14] for JTc (layout of include/cis.h)."""
+    nb, nc, nx = model.nb, model.nc, model.nx
+    nq = 3 * nb
+    phi0, gam0, p0 = 2 * nx, 2 * nx + 2 * nc, 2 * nx + 3 * nc
+    jgv = np.concatenate([np.arange(nq), nx + nq + np.arange(nq), phi0 + np.arange(2 * nc),
+                          p0 + 2 + np.arange(nb)])
+    jtc = np.zeros((nc, 14), dtype=np.int64)
+    for i in range(nc):
+        b = int(model.contact_body[i])
+        jtc[i] = np.concatenate([3 * b + np.arange(3), nq + 3 * b + np.arange(3),
+                                 nx + nq + 3 * b + np.arange(3),
+                                 [phi0 + 2 * i, phi0 + 2 * i + 1, gam0 + i, p0, p0 + 1]])
+    return jgv, jtc
+
+
+def impact_linearize(cm: CisModel, Xp, Xm, Phi, Gamma, params, delta, eps=0.0, *, n_nodes=None,
+                     with_psi=True, stream=None):
+    """Node residuals G~, Theta (and Psi) with the compact Jacobians JGv, JTc of
+    n_nodes nodes (FP64).  Xp, Xm [nx, ld], Phi [2 nc, ld], Gamma [nc, ld] share
+    one row stride ld; outputs are node-major (include/cis.h)."""
+    if Xp.device.type != "cuda" or Xp.dtype != torch.float64:
+        raise ValueError("inputs must be float64 GPU tensors")
+    n = Xp.shape[1] if n_nodes is None else int(n_nodes)
+    ld = Xp.stride(0)
+    nth, ncv, nct = impact_dims(cm)
+    nc = nth // 10
+    for t, rows in ((Xp, cm.nx), (Xm, cm.nx), (Phi, 2 * nc), (Gamma, nc)):
+        if nc == 0 and rows == 0:
+            continue
+        if (t.device != Xp.device or t.dtype != torch.float64 or t.dim() != 2 or t.shape[0] != rows
+                or t.stride(1) != 1 or t.stride(0) != ld or t.shape[1] < n):
+            raise ValueError("Xp, Xm, Phi, Gamma must be float64 [rows, >= n_nodes] with one stride")
+    if params.numel() != cm.np or not params.is_contiguous() or params.dtype != torch.float64:
+        raise ValueError("params must hold P contiguous float64 values")
+    nq = cm.n // 2
+    kw = dict(device=Xp.device, dtype=torch.float64)
+    with _alloc_on(stream):
+        out = dict(G=torch.empty((n, cm.nx), **kw), Theta=torch.empty((n, nth), **kw),
+                   JGv=torch.empty((n, nq, ncv), **kw), JTc=torch.empty((n, nth, nct), **kw),
+                   Psi=torch.empty((max(n - 1, 0), cm.ny), **kw) if with_psi else None)
+    lib = _lib.load()
+    _lib.check(lib.cis_impact_linearize(
+        cm.handle, n, max(ld, 1), _ptr(Xp), _ptr(Xm), _ptr(Phi if nc else None),
+        _ptr(Gamma if nc else None), _ptr(params), float(delta), float(eps), _ptr(out["G"]),
+        _ptr(out["Theta"] if nc else None), _ptr(out["JGv"]), _ptr(out["JTc"] if nc else None),
+        _ptr(out["Psi"]), _stream(stream)))
+    return out
+
+
 def as_interval_major(out):
     """[N, ...] views of the outputs (A[N,nx,nx], Bm/Bp[N,nx,m], S/d/F~[N,nx])."""
     v = {}

@@ -319,6 +319,22 @@ def make_workload(name: str, traj_id: int = 0):
     return model, data, cfg["K"]
 
 
+# Node batches of the impact map: the nodes of a batched workload (every node
+# of every trajectory, (N + 1) x batch), drawn by gen_impact_nodes with `seed`.
+IMPACT_WORKLOADS = {
+    "quad13_x64": dict(workload="quad13_N200_K20_x64", seed=6),
+}
+
+
+def impact_workload(name: str):
+    """Model and node variables of a named impact-map batch."""
+    cfg = IMPACT_WORKLOADS[name]
+    w = WORKLOADS[cfg["workload"]]
+    model, _, _ = make_workload(cfg["workload"], 0)
+    n = (w["N"] + 1) * w.get("batch", 1)
+    return model, gen_impact_nodes(model, n, np.random.default_rng(cfg["seed"]))
+
+
 # Model mix of the uneven multi-trajectory batch (trajectories per 256).
 BATCH_MIX = (("hopper", 128), ("cheetah7", 77), ("biped5", 51))
 

@@ -158,6 +158,24 @@ def test_entry_points_validate_before_launch():
     assert b"cis_discretize_adjoint_noalloc" in lib.cis_last_error()
     assert lib.cis_discretize_adjoint_noalloc(h, None, P(8), P(8), P(8), P(8), P(8), 2, P(8),
                                               P(8), P(8), P(8), P(8), None) == _lib.CIS_ERR_NULL
+    # impact map: sizes, delta, required pointers, alignment; n_nodes = 0 is a no-op
+    imp = lambda n, ld, dl=1e-3, eps=0.0, ptrs=(8,) * 10: lib.cis_impact_linearize(
+        h, n, ld, *[P(v) if v else None for v in ptrs[:5]], dl, eps,
+        *[P(v) if v else None for v in ptrs[5:]], None)
+    assert imp(4, 3) == _lib.CIS_ERR_DIM                       # ld_node < n_nodes
+    assert imp(-1, 3) == _lib.CIS_ERR_DIM
+    assert imp(4, 4, dl=0.0) == _lib.CIS_ERR_DIM
+    assert imp(4, 4, dl=float("nan")) == _lib.CIS_ERR_DIM
+    assert imp(4, 4, eps=float("inf")) == _lib.CIS_ERR_DIM
+    assert imp(4, 4, ptrs=(8, 8, 0, 8, 8, 8, 8, 8, 8, 8)) == _lib.CIS_ERR_NULL   # Phi, nc > 0
+    assert imp(4, 4, ptrs=(8, 8, 8, 8, 8, 8, 8, 0, 8, 8)) == _lib.CIS_ERR_NULL   # JGv
+    assert imp(4, 4, ptrs=(8, 8, 8, 8, 8, 8, 8, 8, 12, 8)) == _lib.CIS_ERR_LAYOUT
+    assert imp(0, 1, ptrs=(0,) * 10) == 0
+    assert lib.cis_impact_linearize(None, 4, 4, *[P(8)] * 5, 1e-3, 0.0, *[P(8)] * 5,
+                                    None) == _lib.CIS_ERR_NULL
+    dims = [ctypes.c_int32() for _ in range(3)]
+    assert lib.cis_impact_dims(h, *[ctypes.byref(d) for d in dims]) == 0
+    assert [d.value for d in dims] == [10 * model.nc, 7 * model.nb + 2 * model.nc, 14]
     lib.cis_model_destroy(h)
 
 

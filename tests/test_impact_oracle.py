@@ -211,3 +211,16 @@ def test_point_mass_tangential_impulse_and_friction_sign():
     assert gam > 0.0
     assert abs(th[2] + delta) <= 1e-15 and abs(th[3] + delta) <= 1e-15
     assert abs(th[9]) <= 1e-15                      # rho = 0 on the cone boundary
+
+
+@pytest.mark.parametrize("name", ["point1", "hopper", "biped3s", "cheetah7", "quad13"])
+def test_compact_layout_holds_every_varying_entry(name):
+    """The compact blocks of include/cis.h plus its constant entries rebuild the
+    oracle's dense Jacobians exactly: no entry outside the blocks varies."""
+    import impact_layout
+    model, d = _rand_case(name, 16)
+    lin = impact.linearize(model, d["Xp"], d["Xm"], d["Phi"], d["Gamma"], d["p"], 1e-2)
+    JGv, JTc = impact_layout.compact_from_dense(model, lin["JG"], lin["JT"])
+    JG, JT = impact_layout.dense_from_compact(model, JGv, JTc)
+    assert np.array_equal(JG, lin["JG"])
+    assert np.array_equal(JT, lin["JT"])
