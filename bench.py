@@ -382,6 +382,58 @@ def main():
         del plan32, trajs
         torch.cuda.empty_cache()
 
+        # node-level impact map over every node of the headline batch (64 x 201
+        # nodes, one launch): G~, Theta, Psi and the compact Jacobians
+        from paper_2604_09993_amd.profiling import impact_bytes
+        imodel, idata = synth.impact_workload("quad13_x64")
+        icm = api.CisModel(imodel)
+        soa = lambda a: torch.from_numpy(np.ascontiguousarray(a.T)).to(dev)
+        iin = [soa(idata[k]) for k in ("Xp", "Xm", "Phi", "Gamma")]
+        ip = torch.tensor(idata["p"], device=dev)
+        n_nodes = iin[0].shape[1]
+        iout = api.impact_linearize(icm, *iin, ip, 1e-2, 1e-4, stream=stream)
+        iargv = ([icm.handle, n_nodes, iin[0].stride(0)]
+                 + [ctypes.c_void_p(t.data_ptr()) for t in iin + [ip]] + [1e-2, 1e-4]
+                 + [ctypes.c_void_p(iout[k].data_ptr()) for k in ("G", "Theta", "JGv", "JTc", "Psi")]
+                 + [ctypes.c_void_p(stream.cuda_stream)])
+
+        def launch_impact():
+            st = lib.cis_impact_linearize(*iargv)
+            if st != 0:
+                _lib.check(st)
+        ms_imp, _ = timed(launch_impact, 5 * args.extra_steps, 5)
+        ibytes = n_nodes * impact_bytes(imodel)
+        iname = f"k_impact<ImpTopo<{imodel.legs}, {imodel.depth}>>"
+        progress(f"impact map quad13 {n_nodes} nodes {ms_imp * 1e3:.1f} us/launch")
+        extras["impact_quad13x64_f64"] = {
+            "value": n_nodes / (ms_imp * 1e-3), "unit": "nodes/s", "ms_per_launch": ms_imp,
+            "nodes": n_nodes, "kernel": iname,
+            "roofline": {"bound": "hbm", "achieved": ibytes / (ms_imp * 1e-3) / 1e9,
+                         "peak": 8000.0, "unit": "GB/s",
+                         "frac": ibytes / (ms_imp * 1e-3) / 8e12,
+                         "traffic": committed_traffic(iname),
+                         "algorithmic_bytes_per_launch": ibytes},
+            "timing": "HIP events on the launch stream around cis_impact_linearize calls"}
+        if not args.no_cpu_baseline:
+            picks = [0, 5000, n_nodes - 1]
+            got_i = {k: iout[k][picks].cpu().numpy() for k in ("G", "Theta", "JGv", "JTc")}
+
+            def run_impact():
+                from oracle import impact as oimp
+                from parity import PHI64, block_err
+                import impact_layout
+                lin = oimp.linearize(imodel, idata["Xp"][picks], idata["Xm"][picks],
+                                     idata["Phi"][picks], idata["Gamma"][picks], idata["p"], 1e-2)
+                JGv, JTc = impact_layout.compact_from_dense(imodel, lin["JG"], lin["JT"])
+                ref = dict(G=lin["G"], Theta=lin["Theta"], JGv=JGv, JTc=JTc)
+                worst = max(block_err(got_i[k], ref[k], PHI64) for k in ref)
+                parity["impact_quad13x64_f64"] = {
+                    "max_rel_err_vs_oracle": worst, "metric": "per-entry (phi = 1e-3)",
+                    "bar": 1e-10, "sample": f"nodes {picks} (G, Theta, JGv, JTc)"}
+            pending.append(run_impact)
+        del iin, iout
+        torch.cuda.empty_cache()
+
         # uneven batch of 256 trajectories over three models
         mb = synth.mixed_batch()
         m_int = sum(d["s"].shape[0] for _, d, _ in mb)

@@ -26,7 +26,6 @@
 #include "cis_model.hpp"
 
 namespace cis {
-namespace {
 
 template <int L_, int D_>
 struct ImpTopo {
@@ -471,7 +470,6 @@ cis_status launch_impact(const cis_model* m, const ImpactArgs& args, hipStream_t
                                   hipGetErrorString(e));
 }
 
-}  // namespace
 }  // namespace cis
 
 using namespace cis;

@@ -158,6 +158,9 @@ def bench_algorithmic_bytes():
             tan = sum(n * split_bytes(m_, ds)[1] for m_, n, k in items)
             out[f"k_coefrec_batch<{tn}, {t}"] = rec
             out[f"k_tangent_batch<{tn}, {t}"] = tan
+    imodel, idata = synth.impact_workload("quad13_x64")
+    out[f"k_impact<ImpTopo<{imodel.legs}, {imodel.depth}>"] = \
+        idata["Xp"].shape[0] * impact_bytes(imodel)
     qb = synth.workload_batch("quad13_N200_K20_x64")
     t = _topo(qb[0][0])
     out[f"k_discretize_batch<double, {t}"] = sum(d["s"].shape[0] * interval_bytes(m_, k, "discretize")
@@ -183,6 +186,16 @@ def split_bytes(model, dsize=8):
     rec = dsize * ((2 * nx + 2 * m + 1 + P) + 3 * nx + nx * (nx - n))
     tan = dsize * (nx * n + 2 * nx * m)
     return rec, tan
+
+
+def impact_bytes(model, dsize=8):
+    """Algorithmic bytes of one node of the impact map: it reads x~+, x~-,
+    Phi and Gamma of the node and writes G~, Theta, Psi and the compact
+    Jacobians JGv [3 nb][7 nb + 2 nc] and JTc [10 nc][14]."""
+    nx, nb, nc, ny = model.nx, model.nb, model.nc, model.ny
+    read = 2 * nx + 3 * nc
+    write = nx + 10 * nc + ny + 3 * nb * (7 * nb + 2 * nc) + 140 * nc
+    return dsize * (read + write)
 
 
 PHI_FJ = {2: 300, 5: 700, 7: 1000, 13: 2000}   # per-stage RHS + Jacobian FLOP by body count
