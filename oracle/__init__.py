@@ -56,6 +56,12 @@ def _load():
                                         ctypes.c_int]
         _lib.oracle_adjoint.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, P, P,
                                         P, P, P, P, ctypes.c_int]
+        _lib.oracle_rkf_tableau.argtypes = [P, P, P, P]
+        _lib.oracle_integrate_erk.argtypes = ([P, P, P, P, ctypes.c_double, P, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_int]
+                                              + [P] * 10)
+        _lib.oracle_discretize_rkf.argtypes = [P, ctypes.c_int, ctypes.c_int] + [P] * 11 + [
+            ctypes.c_int]
     return _lib
 
 
@@ -190,3 +196,58 @@ def adjoint(model, X, U, s, p, K, lam, nthreads=0):
     lib.oracle_adjoint(om.ref, N, int(K), _ptr(X), _ptr(U), _ptr(s), _ptr(p), _ptr(lam),
                        _ptr(gX), _ptr(gU), _ptr(gs), _ptr(gp), int(nthreads))
     return dict(gX=gX, gU=gU[:, :m], gs=gs, gp=gp)
+
+
+def rkf_tableau():
+    """The Fehlberg 4(5) tableau the oracle integrates with: c[6], a[6, 6], b[6]
+    (propagated, fourth order), bh[6] (embedded, fifth order)."""
+    lib = _load()
+    c, a, b, bh = np.zeros(6), np.zeros((6, 6)), np.zeros(6), np.zeros(6)
+    lib.oracle_rkf_tableau(_ptr(c), _ptr(a), _ptr(b), _ptr(bh))
+    return c, a, b, bh
+
+
+def integrate_erk(model, x0, Uk, Uk1, s, p, K, c, a, b, bh=None, tau0=0.0, tau1=1.0):
+    """One interval with K steps of an explicit Runge-Kutta tableau and the
+    variational equations: dict xf, Phi, Bm, Bp, S, err."""
+    om = OracleModel(model)
+    lib = _load()
+    nx, m = om.nx, om.m
+    c, a, b = _f64(c), _f64(a), _f64(b)
+    bh = None if bh is None else _f64(bh)
+    x0, p = _f64(x0), _f64(p)
+    Uk = _f64(Uk) if m else np.zeros(1)
+    Uk1 = _f64(Uk1) if m else np.zeros(1)
+    out = dict(xf=np.zeros(nx), Phi=np.zeros((nx, nx)), Bm=np.zeros((nx, max(m, 1))),
+               Bp=np.zeros((nx, max(m, 1))), S=np.zeros(nx))
+    err = np.zeros(1)
+    lib.oracle_integrate_erk(om.ref, _ptr(x0), _ptr(Uk), _ptr(Uk1), float(s), _ptr(p),
+                             float(tau0), float(tau1), int(K), int(c.size), _ptr(c), _ptr(a),
+                             _ptr(b), _ptr(bh), _ptr(out["xf"]), _ptr(out["Phi"]),
+                             _ptr(out["Bm"]), _ptr(out["Bp"]), _ptr(out["S"]), _ptr(err))
+    out["Bm"] = out["Bm"][:, :m]
+    out["Bp"] = out["Bp"][:, :m]
+    out["err"] = float(err[0])
+    return out
+
+
+def discretize_rkf(model, X, U, s, p, K, nthreads=0):
+    """All intervals with K Fehlberg steps each: A, Bm, Bp, S, d, xprop as in
+    discretize, and err[N] (largest embedded estimate over the steps)."""
+    om = OracleModel(model)
+    lib = _load()
+    X, s, p = _f64(X), _f64(s), _f64(p)
+    N = X.shape[0] - 1
+    nx, m = om.nx, om.m
+    U = _f64(U) if m else np.zeros((N + 1, 1))
+    mm = max(m, 1)
+    out = dict(A=np.zeros((N, nx, nx)), Bm=np.zeros((N, nx, mm)), Bp=np.zeros((N, nx, mm)),
+               S=np.zeros((N, nx)), d=np.zeros((N, nx)), xprop=np.zeros((N, nx)),
+               err=np.zeros(N))
+    lib.oracle_discretize_rkf(om.ref, N, int(K), _ptr(X), _ptr(U), _ptr(s), _ptr(p),
+                              _ptr(out["A"]), _ptr(out["Bm"]) if m else None,
+                              _ptr(out["Bp"]) if m else None, _ptr(out["S"]), _ptr(out["d"]),
+                              _ptr(out["xprop"]), _ptr(out["err"]), int(nthreads))
+    out["Bm"] = out["Bm"][:, :, :m]
+    out["Bp"] = out["Bp"][:, :, :m]
+    return out

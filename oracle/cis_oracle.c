@@ -7,8 +7,10 @@
  *
  * Plain, slow and dense on purpose: the right-hand side, its Jacobians (filled
  * entry by entry from hand-derived formulas), classical RK4 with the
- * variational equations on dense matrices, the reverse sweep of the discrete
- * map, and forward parameter sensitivities.  Every quantity is double.
+ * variational equations on dense matrices, the same for any explicit
+ * Runge-Kutta tableau (the Fehlberg 4(5) pair of the paper's transcription),
+ * the reverse sweep of the discrete map, and forward parameter
+ * sensitivities.  Every quantity is double.
  *
  * What it follows (arxiv 2604.09993):
  *  - planar maximal-coordinate dynamics  q' = v,  M v' = W + J^T R phi + grad h^T lambda
@@ -567,5 +569,160 @@ int oracle_adjoint(const omodel *M, int N, int K, const double *X, const double 
         gp[c] = acc;
     }
     free(ukb); free(uk1b); free(pb);
+    return 0;
+}
+
+/* ==========================================================================
+ * Runge-Kutta-Fehlberg transcription (Sec. VI: the custom Runge-Kutta-Fehlberg
+ * integrator with internal numerical differentiation, a fixed number of steps
+ * per interval).
+ *
+ * Any explicit Runge-Kutta method with a strictly lower-triangular tableau
+ * (stage nodes c_i, coefficients a_ij, weights b_i and, optionally, embedded
+ * weights bh_i):
+ *     K_i = h F~(tau_j + c_i h, x_j + h sum_{l<i} a_il K_l)   (here h = 1/K on tau)
+ *     x_{j+1} = x_j + sum_i b_i K_i,   e_j = sum_i (bh_i - b_i) K_i
+ * with the same stages applied to the variational equations (every Jacobian
+ * at the stage state), so the sensitivities are the exact derivatives of the
+ * discrete map.  The tableau used by oracle_discretize_rkf is the 4(5) pair of
+ * Fehlberg (1969): the fourth-order solution is propagated and the
+ * fifth-order one gives the embedded error estimate; every interval reports
+ * max_j max_r |e_j[r]| over its steps and all augmented rows.
+ * ========================================================================== */
+#define RKF_S 6
+static const double RKF_C[RKF_S] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+static const double RKF_A[RKF_S][RKF_S] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0, 0}};
+static const double RKF_B4[RKF_S] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0,
+                                     -1.0 / 5.0, 0.0};
+static const double RKF_B5[RKF_S] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0,
+                                     -9.0 / 50.0, 2.0 / 55.0};
+
+/* The Fehlberg tableau as used (c[6], a[6][6] row-major, b[6], bh[6]). */
+void oracle_rkf_tableau(double *c, double *a, double *b, double *bh) {
+    for (int i = 0; i < RKF_S; ++i) {
+        c[i] = RKF_C[i];
+        b[i] = RKF_B4[i];
+        bh[i] = RKF_B5[i];
+        for (int l = 0; l < RKF_S; ++l) a[i * RKF_S + l] = RKF_A[i][l];
+    }
+}
+
+/*
+ * One interval [tau0, tau1] with K steps of the explicit method (S stages,
+ * tableau c, a (S x S row-major), b, bh (may be NULL)), with the variational
+ * equations of oracle_integrate for Z = [Phi | Bm | Bp | Sv]; *err receives
+ * the largest |e| (0 when bh is NULL).  Outputs other than xf may be NULL.
+ */
+void oracle_integrate_erk(const omodel *M, const double *x0, const double *Uk, const double *Uk1,
+                          double s, const double *p, double tau0, double tau1, int K, int S,
+                          const double *c, const double *a, const double *b, const double *bh,
+                          double *xf, double *Phi, double *Bm, double *Bp, double *Sv,
+                          double *err) {
+    const int nx = o_nx(M), m = o_m(M), np = o_np(M);
+    const int nz = nx + 2 * m + 1;
+    const int oB = nx, oP = nx + m, oS = nx + 2 * m;
+    const size_t NZ = (size_t)nx * nz;
+    const double h = (tau1 - tau0) / K;
+    double *x = malloc(sizeof(double) * nx), *xs = malloc(sizeof(double) * nx);
+    double *kx = malloc(sizeof(double) * nx * S);          /* K_i of the state, [S][nx] */
+    double *Z = calloc(NZ, sizeof(double)), *Zs = malloc(sizeof(double) * NZ);
+    double *KZ = malloc(sizeof(double) * NZ * S);          /* K_i of Z, [S][nx][nz] */
+    double *Fv = malloc(sizeof(double) * nx), *Jx = malloc(sizeof(double) * nx * nx);
+    double *Ju = malloc(sizeof(double) * nx * (m + 1)), *Jub = malloc(sizeof(double) * nx * (m + 1));
+    double *Jp = malloc(sizeof(double) * nx * np);
+    double *u = malloc(sizeof(double) * (m + 1)), *ub = malloc(sizeof(double) * (m + 1));
+    double emax = 0.0;
+    for (int r = 0; r < nx; ++r) { x[r] = x0[r]; Z[(size_t)r * nz + r] = 1.0; }
+    for (int q = 0; q < m; ++q) ub[q] = 0.5 * (Uk[q] + Uk1[q]);
+    for (int j = 0; j < K; ++j) {
+        for (int i = 0; i < S; ++i) {
+            const double tau = tau0 + (j + c[i]) * h;
+            /* stage input */
+            for (int r = 0; r < nx; ++r) {
+                double acc = 0.0;
+                for (int l = 0; l < i; ++l) acc += a[i * S + l] * kx[(size_t)l * nx + r];
+                xs[r] = x[r] + acc;
+            }
+            for (size_t e = 0; e < NZ; ++e) {
+                double acc = 0.0;
+                for (int l = 0; l < i; ++l) acc += a[i * S + l] * KZ[(size_t)l * NZ + e];
+                Zs[e] = Z[e] + acc;
+            }
+            for (int q = 0; q < m; ++q) u[q] = (1.0 - tau) * Uk[q] + tau * Uk1[q];
+            oracle_rhs_jac(M, xs, u, ub, p, Fv, Jx, Ju, Jub, Jp);
+            /* K_i = h (s Jx Zs + forcing), forcing as in oracle_integrate */
+            double *KZi = KZ + (size_t)i * NZ;
+            matmul(nx, nx, nz, Jx, Zs, KZi);
+            for (size_t e = 0; e < NZ; ++e) KZi[e] *= s;
+            for (int r = 0; r < nx; ++r) {
+                for (int q = 0; q < m; ++q) {
+                    KZi[(size_t)r * nz + oB + q] += s * (Ju[(size_t)r * m + q] * (1.0 - tau) + 0.5 * Jub[(size_t)r * m + q]);
+                    KZi[(size_t)r * nz + oP + q] += s * (Ju[(size_t)r * m + q] * tau + 0.5 * Jub[(size_t)r * m + q]);
+                }
+                KZi[(size_t)r * nz + oS] += Fv[r];
+            }
+            for (size_t e = 0; e < NZ; ++e) KZi[e] *= h;
+            for (int r = 0; r < nx; ++r) kx[(size_t)i * nx + r] = h * s * Fv[r];
+        }
+        if (bh) {
+            for (int r = 0; r < nx; ++r) {
+                double e = 0.0;
+                for (int i = 0; i < S; ++i) e += (bh[i] - b[i]) * kx[(size_t)i * nx + r];
+                if (fabs(e) > emax) emax = fabs(e);
+            }
+        }
+        for (int r = 0; r < nx; ++r) {
+            double acc = 0.0;
+            for (int i = 0; i < S; ++i) acc += b[i] * kx[(size_t)i * nx + r];
+            x[r] += acc;
+        }
+        for (size_t e = 0; e < NZ; ++e) {
+            double acc = 0.0;
+            for (int i = 0; i < S; ++i) acc += b[i] * KZ[(size_t)i * NZ + e];
+            Z[e] += acc;
+        }
+    }
+    memcpy(xf, x, sizeof(double) * nx);
+    for (int r = 0; r < nx; ++r) {
+        if (Phi) for (int q = 0; q < nx; ++q) Phi[(size_t)r * nx + q] = Z[(size_t)r * nz + q];
+        if (Bm) for (int q = 0; q < m; ++q) Bm[(size_t)r * m + q] = Z[(size_t)r * nz + oB + q];
+        if (Bp) for (int q = 0; q < m; ++q) Bp[(size_t)r * m + q] = Z[(size_t)r * nz + oP + q];
+        if (Sv) Sv[r] = Z[(size_t)r * nz + oS];
+    }
+    if (err) *err = emax;
+    free(x); free(xs); free(kx); free(Z); free(Zs); free(KZ); free(Fv); free(Jx); free(Ju);
+    free(Jub); free(Jp); free(u); free(ub);
+}
+
+/* Multiple shooting with the Fehlberg pair: outputs of oracle_discretize
+ * (without Pi) plus err[N], the embedded estimate of each interval. */
+int oracle_discretize_rkf(const omodel *M, int N, int K, const double *X, const double *U,
+                          const double *s, const double *p, double *A, double *Bm, double *Bp,
+                          double *S, double *defect, double *xprop, double *err, int nthreads) {
+    const int nx = o_nx(M), m = o_m(M);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int k = 0; k < N; ++k) {
+        double *xf = malloc(sizeof(double) * nx);
+        oracle_integrate_erk(M, X + (size_t)k * nx, U + (size_t)k * m, U + (size_t)(k + 1) * m,
+                             s[k], p, 0.0, 1.0, K, RKF_S, RKF_C, &RKF_A[0][0], RKF_B4, RKF_B5, xf,
+                             A ? A + (size_t)k * nx * nx : NULL,
+                             Bm ? Bm + (size_t)k * nx * m : NULL,
+                             Bp ? Bp + (size_t)k * nx * m : NULL,
+                             S ? S + (size_t)k * nx : NULL, err ? err + k : NULL);
+        for (int r = 0; r < nx; ++r) {
+            if (xprop) xprop[(size_t)k * nx + r] = xf[r];
+            if (defect) defect[(size_t)k * nx + r] = xf[r] - X[(size_t)(k + 1) * nx + r];
+        }
+        free(xf);
+    }
     return 0;
 }
