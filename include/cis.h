@@ -227,6 +227,32 @@ cis_status cis_discretize_split(const cis_model *model, const cis_shape *shape, 
                                 void *defect, void *xprop, void *ws, size_t ws_bytes,
                                 void *stream);
 
+/* Bytes of device workspace cis_discretize_rkf needs for this shape (the
+ * model must have legs with links, else CIS_ERR_UNSUPPORTED). */
+cis_status cis_rkf_workspace_size(const cis_model *model, const cis_shape *shape,
+                                  size_t *bytes);
+
+/*
+ * The discretize step with the Runge-Kutta-Fehlberg integrator of the paper's
+ * transcription (Sec. VI) in place of classical RK4: K fixed steps of
+ * Fehlberg's 4(5) pair per interval (stage nodes 0, 1/4, 3/8, 12/13, 1, 1/2
+ * of the step), the fourth-order solution propagated, with the variational
+ * equations integrated through the same stages (internal numerical
+ * differentiation), so A, Bm, Bp and S are the exact derivatives of that
+ * discrete map; defect and xprop as for cis_discretize.  err (may be NULL;
+ * [N], element type of the shape): for each interval the largest embedded
+ * error estimate |h sum_i (bh_i - b_i) K_i| over its steps and all nx rows,
+ * bh the fifth-order weights.  Two launches (stage records, then tangent
+ * columns) as cis_discretize_split; waves (1 or 2): register budget of the
+ * second launch.  ws must hold cis_rkf_workspace_size bytes, 8-byte aligned;
+ * its contents are scratch.  dtype CIS_F64 or CIS_F32.  Models without legs
+ * with links: CIS_ERR_UNSUPPORTED.
+ */
+cis_status cis_discretize_rkf(const cis_model *model, const cis_shape *shape, const void *X,
+                              const void *U, const void *s, const void *params, int32_t waves,
+                              void *A, void *Bm, void *Bp, void *S, void *defect, void *xprop,
+                              void *err, void *ws, size_t ws_bytes, void *stream);
+
 /* Composition of the substep blocks of cis_discretize_blocked. */
 enum { CIS_COMPOSE_VALU = 0, CIS_COMPOSE_MFMA = 1 };
 

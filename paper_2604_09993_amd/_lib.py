@@ -51,7 +51,8 @@ EXPORTS = [
     "cis_batch_run", "cis_batch_graph_run", "cis_batch_plan_info", "cis_batch_plan_destroy",
     "cis_blocked_workspace_size", "cis_discretize_blocked", "cis_discretize_adjoint_noalloc",
     "cis_split_workspace_size", "cis_discretize_split", "cis_batch_plan_discretize_form",
-    "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize",
+    "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize", "cis_rkf_workspace_size",
+    "cis_discretize_rkf",
 ]
 
 
@@ -151,6 +152,11 @@ def load(build_if_missing: bool = True):
     lib.cis_batch_plan_discretize_form.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.cis_batch_plan_destroy.restype = None
     lib.cis_batch_plan_destroy.argtypes = [P]
+    lib.cis_rkf_workspace_size.restype = St
+    lib.cis_rkf_workspace_size.argtypes = [P, ctypes.POINTER(Shape), ctypes.POINTER(ctypes.c_size_t)]
+    lib.cis_discretize_rkf.restype = St
+    lib.cis_discretize_rkf.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, I32]
+                                       + [P] * 8 + [ctypes.c_size_t, P])
     lib.cis_impact_dims.restype = St
     lib.cis_impact_dims.argtypes = [P] + [ctypes.POINTER(I32)] * 3
     lib.cis_impact_linearize.restype = St

@@ -222,6 +222,39 @@ def discretize_split(cm: CisModel, X, U, s, params, K, *, waves=1, with_xprop=Tr
     return out
 
 
+def rkf_workspace_bytes(cm: CisModel, N, K, dtype=torch.float64):
+    sh = _lib.Shape(N, int(K), _dtype_code(dtype), 0, N + 1, N)
+    nb = ctypes.c_size_t()
+    _lib.check(_lib.load().cis_rkf_workspace_size(cm.handle, ctypes.byref(sh), ctypes.byref(nb)))
+    return nb.value
+
+
+def discretize_rkf(cm: CisModel, X, U, s, params, K, *, waves=1, with_xprop=True, ws=None,
+                   stream=None):
+    """The discretize outputs with K Runge-Kutta-Fehlberg steps per interval
+    (fourth-order solution propagated) and err[N], the embedded estimate."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    kw = dict(device=X.device, dtype=X.dtype)
+    nbytes = rkf_workspace_bytes(cm, N, K, X.dtype)
+    with _alloc_on(stream):
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw), err=torch.empty((N,), **kw))
+        out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty((nbytes,), device=X.device, dtype=torch.uint8)
+    sh = _shape(X, s, K)
+    lib = _lib.load()
+    _lib.check(lib.cis_discretize_rkf(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                      _ptr(params), int(waves), _ptr(out["A"]),
+                                      _ptr(out["Bm"] if m else None),
+                                      _ptr(out["Bp"] if m else None), _ptr(out["S"]),
+                                      _ptr(out["d"]), _ptr(out["xprop"]), _ptr(out["err"]),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
 def defects(cm: CisModel, X, U, s, params, K, *, ckpt_every=None, stream=None):
     """F~ and defects only; optional substep checkpoints [K/C, n, N] for the adjoint."""
     _check_inputs(cm, X, U, s, params)

@@ -194,24 +194,18 @@ __device__ __forceinline__ Frame<T> terrain(const MC& mc, T Px, T Py) {
     return f;
 }
 
-// ---------------------------------------------------------------------------
-// State wave: one stage.  bs.xs holds the stage input of the lane's body.
-// Writes the next stage input (or the new substep state after stage 3) into
-// bs.xs and into ring[NX], the body rotation into cs_out[NB][2] and the
-// accelerations into fv_out[3 NB].
-// ---------------------------------------------------------------------------
-template <class T, class TP, int ST>
-__device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
-                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
-                                            const BodyConst<T, TP>& c, BodyRK<T>& bs, T tau,
-                                            T* ring, T (*cs_out)[2], T* fv_out, int lane) {
-    constexpr int st = ST;   // RK stage, known at compile time
-    constexpr int NB = TP::NB, NQ = TP::NQ;
+// Accelerations fv (x, y, theta) of the lane's body at the stage input xs
+// (its six rows; the parent's and children's rows come through DPP and lane
+// reads) at stage time tau, and the body rotation (cb, sb).
+template <class T, class TP>
+__device__ __forceinline__ void body_accel(const Interval<T, TP>& iv,
+                                           const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                           const BodyConst<T, TP>& c, const T (&xs)[6], T tau,
+                                           T (&fv)[3], T& cb, T& sb) {
     const T omt = T(1) - tau;
-    T sb, cb;
-    sincos_t(bs.xs[2], &sb, &cb);
+    sincos_t(xs[2], &sb, &cb);
     const bool pt = c.p == 0;
-    const T thp = from_parent<TP>(bs.xs[2], pt), omp = from_parent<TP>(bs.xs[5], pt);
+    const T thp = from_parent<TP>(xs[2], pt), omp = from_parent<TP>(xs[5], pt);
     const T sp = from_parent<TP>(sb, pt), cp = from_parent<TP>(cb, pt);
     T Fx = T(0), Fy = T(0), Tq = T(0);
     T wx = T(0), wy = T(0), wt = T(0);   // parent-side wrench of the own joint
@@ -221,7 +215,7 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
         const T tq = omt * c.uk[0] + tau * c.uk1[0];
         const T lx = omt * c.uk[1] + tau * c.uk1[1];
         const T ly = omt * c.uk[2] + tau * c.uk1[2];
-        const T tt = tq - c.kj * (bs.xs[2] - thp) - c.dj * (bs.xs[5] - omp);
+        const T tt = tq - c.kj * (xs[2] - thp) - c.dj * (xs[5] - omp);
         Fx -= lx;
         Fy -= ly;
         Tq += -(acx * ly - acy * lx) + tt;
@@ -231,7 +225,7 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
     }
     if (c.contact) {
         const T ax = cb * c.rx - sb * c.ry, ay = sb * c.rx + cb * c.ry;
-        const Frame<T> f = terrain<T>(mc, bs.xs[0] + ax, bs.xs[1] + ay);
+        const Frame<T> f = terrain<T>(mc, xs[0] + ax, xs[1] + ay);
         const T ln = omt * c.ck[0] + tau * c.ck1[0];
         const T ft = (omt * c.ck[1] + tau * c.ck1[1]) - (omt * c.ck[2] + tau * c.ck1[2]);
         const T fx = f.tx * ft + f.nx * ln, fy = f.ty * ft + f.ny * ln;
@@ -243,7 +237,25 @@ __device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
     Fx += from_children<TP>(wx, c.b);
     Fy += from_children<TP>(wy, c.b);
     Tq += from_children<TP>(wt, c.b);
-    const T fv[3] = {Fx * c.mi, Fy * c.mi - T(mc.g), Tq * c.ii};
+    fv[0] = Fx * c.mi;
+    fv[1] = Fy * c.mi - T(mc.g);
+    fv[2] = Tq * c.ii;
+}
+
+// ---------------------------------------------------------------------------
+// State wave: one stage.  bs.xs holds the stage input of the lane's body.
+// Writes the next stage input (or the new substep state after stage 3) into
+// bs.xs and into ring[NX], the body rotation into cs_out[NB][2] and the
+// accelerations into fv_out[3 NB].
+template <class T, class TP, int ST>
+__device__ __forceinline__ void state_stage(const Interval<T, TP>& iv,
+                                            const MConst<TP::NB, TP::NJ, TP::NC>& mc,
+                                            const BodyConst<T, TP>& c, BodyRK<T>& bs, T tau,
+                                            T* ring, T (*cs_out)[2], T* fv_out, int lane) {
+    constexpr int st = ST;   // RK stage, known at compile time
+    constexpr int NB = TP::NB, NQ = TP::NQ;
+    T fv[3], cb, sb;
+    body_accel<T, TP>(iv, mc, c, bs.xs, tau, fv, cb, sb);
     const T s = iv.s, h = iv.h;
     const T an = (st == 2) ? h : T(0.5) * h;
 #pragma unroll
@@ -470,19 +482,22 @@ struct SLane {
     T ycc[NCL], yct;
 };
 
-template <class T, class TP, int ST, class LY = CoefDense<TP>>
-__device__ __forceinline__ void s_stage(const Interval<T, TP>& iv, const BodyConst<T, TP>& c,
-                                        SLane<T, TP>& z, const T* __restrict__ cf, int lane) {
+// Derivative of the S column on the lane's body at the stage input zs: the
+// velocity rows kv, the lane's cross-complementarity rows kcc and its part of
+// the violation row kct (the pose rows are s zs_v + F~, formed by the caller).
+template <class T, class TP, class LY>
+__device__ __forceinline__ void s_rhs(const Interval<T, TP>& iv, const BodyConst<T, TP>& c,
+                                      const T (&zs)[6], const T* __restrict__ cf, int lane,
+                                      T (&kv)[3], T (&kcc)[SLane<T, TP>::NCL], T& kct) {
     constexpr int NB = TP::NB, NQ = TP::NQ, NX = TP::NX, D = TP::D, L = TP::L;
     constexpr int NCL = SLane<T, TP>::NCL;
-    const T s = iv.s, h = iv.h;
     const int b = c.b;
-    const T x = z.zs[0], y = z.zs[1], th = z.zs[2];
-    const T vx = z.zs[3], vy = z.zs[4], om = z.zs[5];
-    T kv[3] = {cf[LY::f(NQ + 3 * b)], cf[LY::f(NQ + 3 * b + 1)],
-               cf[LY::f(NQ + 3 * b + 2)] + cf[LY::cth(b)] * th};
-    T kct = lane < NB ? cf[LY::ctp(b)] : T(0);
-    T kcc[NCL];
+    const T x = zs[0], y = zs[1], th = zs[2];
+    const T vx = zs[3], vy = zs[4], om = zs[5];
+    kv[0] = cf[LY::f(NQ + 3 * b)];
+    kv[1] = cf[LY::f(NQ + 3 * b + 1)];
+    kv[2] = cf[LY::f(NQ + 3 * b + 2)] + cf[LY::cth(b)] * th;
+    kct = lane < NB ? cf[LY::ctp(b)] : T(0);
 #pragma unroll
     for (int l = 0; l < NCL; ++l) kcc[l] = T(0);
     if constexpr (D >= 1) {
@@ -521,6 +536,16 @@ __device__ __forceinline__ void s_stage(const Interval<T, TP>& iv, const BodyCon
             }
         }
     }
+}
+
+template <class T, class TP, int ST, class LY = CoefDense<TP>>
+__device__ __forceinline__ void s_stage(const Interval<T, TP>& iv, const BodyConst<T, TP>& c,
+                                        SLane<T, TP>& z, const T* __restrict__ cf, int lane) {
+    constexpr int NCL = SLane<T, TP>::NCL;
+    const T s = iv.s, h = iv.h;
+    const int b = c.b;
+    T kv[3], kcc[NCL], kct;
+    s_rhs<T, TP, LY>(iv, c, z.zs, cf, lane, kv, kcc, kct);
     // classical RK4 combination (stage ST known at compile time)
     constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
     const T an = (ST == 2) ? h : T(0.5) * h;

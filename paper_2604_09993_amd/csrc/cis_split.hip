@@ -30,38 +30,9 @@
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
 #include "cis_model.hpp"
+#include "cis_split.hpp"
 
 namespace cis {
-
-// Layout of an interval's part of the split workspace (elements of T):
-//   [0, CRS)                        s, h, h/6, 0 x5, then k/I terms kc[j][4]
-//   CRS + t * GLOBAL, t < 4 K       stage record t (CoefRec<TP> prefix)
-template <class TP>
-struct SplitRec {
-    using R = CoefRec<TP>;
-    static constexpr int CRS = (8 + 4 * TP::NJ + 7) / 8 * 8;
-    static constexpr int GLOBAL = R::GLOBAL;
-    static constexpr int64_t per_interval(int K) { return CRS + (int64_t)4 * K * GLOBAL; }
-    static constexpr int NCOLT = TP::NX + 2 * TP::M;      // tangent columns of k_tangent
-    static constexpr int NBLK = (NCOLT + 63) / 64;        // column blocks of 64 lanes
-};
-
-// Constant entries of a compact record (joint blocks) and its zero.
-template <class T, class TP>
-__device__ __forceinline__ void coefrec_constants(const Interval<T, TP>& iv, T* cf, int tid,
-                                                  int nth) {
-    using R = CoefRec<TP>;
-    const T s = iv.s;
-    for (int j = tid; j < TP::NJ; j += nth) {
-        const int p = TP::parent(j), c = j + 1;
-        T* jb = cf + R::JB + 8 * j;
-        jb[4] = s * iv.minv[p];
-        jb[5] = -s * iv.minv[c];
-        jb[6] = -s * iv.iinv[p];
-        jb[7] = s * iv.iinv[c];
-    }
-    if (tid == 0) cf[R::ZERO] = T(0);
-}
 
 template <class T, class TP>
 struct RecShared {
@@ -241,28 +212,9 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
 }
 
 // ---------------------------------------------------------------------------
-// k_tangent: one stage of a leg wave.  Local body lb = 0 is the torso, lb =
-// 1..D the links of leg `leg`; rows z[3 lb + k] (q) and z[3 LB + 3 lb + k] (v).
-// lr: the wave's leg block of the stage record; rs: the whole stage record
-// (forcing entries, read per lane at offsets off[], offcc).
+// k_tangent: one classical RK4 stage of a leg wave (derivative from
+// tangent_split_rhs, then the RK4 combination).
 // ---------------------------------------------------------------------------
-template <class T, class TP>
-struct TanLane {
-    static constexpr int LB = TP::D + 1;
-    T zb[6 * LB], za[6 * LB], zs[6 * LB];
-    T ycc, yct;
-};
-
-// One element of a raw buffer at byte offset `off` (offsets within the
-// resource's byte range only).
-template <class T>
-__device__ __forceinline__ T buffer_elem(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-
 template <class T, class TP, int ST, bool FORCE>
 __device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* __restrict__ cr,
                                                     const T* __restrict__ lr,
@@ -270,72 +222,11 @@ __device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* 
                                                     int lane, T tau, T wbm, T wbp,
                                                     const unsigned (&off)[3 * (TP::D + 1)],
                                                     unsigned offcc) {
-    constexpr int LB = TP::D + 1, D = TP::D, L = TP::L;
+    constexpr int LB = TP::D + 1;
     const T s = cr[0], h = cr[1], h6 = cr[2];
-#define ZQ(lb, k) z.zs[3 * (lb) + (k)]
-#define ZV(lb, k) z.zs[3 * LB + 3 * (lb) + (k)]
-    // forcing of B-/B+ columns (zero offsets and weights elsewhere): issued
-    // first, used last; buffer loads at per-lane byte offsets from the stage
-    // record (a scalar resource, so no per-lane 64-bit addresses)
-    T g[3 * LB];
-    T gcc = T(0);
-    if constexpr (FORCE) {
-        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<T*>(rs), (short)0, (int)(CoefRec<TP>::GLOBAL * sizeof(T)), 0x00020000);
-#pragma unroll
-        for (int r = 0; r < 3 * LB; ++r) g[r] = buffer_elem<T>(rsrc, off[r]);
-        gcc = buffer_elem<T>(rsrc, offcc);
-    }
-    // hip stiffness and damping of this leg on the torso, exchanged
-    const T* kcl = cr + 8 + 4 * leg * D;   // kc[j][4] of the leg's joints
-    T hip = kcl[0] * (ZQ(1, 2) - ZQ(0, 2)) + kcl[1] * (ZV(1, 2) - ZV(0, 2));
-    if constexpr (L > 1) {
-        xch[leg * 64 + lane] = hip;
-        __syncthreads();
-        hip = xch[lane];
-#pragma unroll
-        for (int l = 1; l < L; ++l) hip += xch[l * 64 + lane];
-    }
-    T kv[3 * LB];
-    kv[0] = T(0);
-    kv[1] = T(0);
-    kv[2] = lr[0] * ZQ(0, 2) + hip;
-#pragma unroll
-    for (int lb = 1; lb <= D; ++lb) {
-        kv[3 * lb] = T(0);
-        kv[3 * lb + 1] = T(0);
-        kv[3 * lb + 2] = lr[lb] * ZQ(lb, 2);
-    }
-    T kct = T(0), kcc;
-#pragma unroll
-    for (int lb = 1; lb <= D; ++lb) {
-        const T* kc = kcl + 4 * (lb - 1);
-        const T dth = ZQ(lb, 2) - ZQ(lb - 1, 2);
-        const T dom = ZV(lb, 2) - ZV(lb - 1, 2);
-        if (lb >= 2) kv[3 * (lb - 1) + 2] += kc[0] * dth + kc[1] * dom;
-        kv[3 * lb + 2] -= kc[2] * dth + kc[3] * dom;
-        const T* jh = lr + 1 + D + 4 * (lb - 1);
-        kct += jh[0] * (ZQ(lb - 1, 0) - ZQ(lb, 0)) + jh[1] * (ZQ(lb - 1, 1) - ZQ(lb, 1)) +
-               jh[2] * ZQ(lb - 1, 2) + jh[3] * ZQ(lb, 2);
-    }
-    {
-        const T* ct = lr + 1 + 5 * D;   // contact terms C_AX .. C_ZPY of the leg's contact
-        constexpr int lb = D;
-        const T dPx = ZQ(lb, 0) - ct[C_AY] * ZQ(lb, 2);
-        const T dPy = ZQ(lb, 1) + ct[C_AX] * ZQ(lb, 2);
-        kv[3 * lb] += ct[C_FXP] * dPx;
-        kv[3 * lb + 1] += ct[C_FYP] * dPx;
-        kv[3 * lb + 2] += ct[C_TP] * dPx;
-        kcc = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * ZV(lb, 0) + ct[C_EYD] * ZV(lb, 1) +
-              ct[C_EOM] * ZV(lb, 2) + ct[C_ETH] * ZQ(lb, 2);
-        kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
-    }
-    if constexpr (FORCE) {
-        const T wB = wbm * (T(1) - tau) + wbp * tau;
-#pragma unroll
-        for (int r = 0; r < 3 * LB; ++r) kv[r] += wB * g[r];
-        kcc += (wbm + wbp) * gcc;
-    }
+    T kv[3 * LB], kcc, kct;
+    tangent_split_rhs<T, TP, FORCE>(z.zs, cr, lr, rs, xch, leg, lane, tau, wbm, wbp, off, offcc,
+                                    kv, kcc, kct);
     // classical RK4 combination (stage ST known at compile time)
     constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
     const T an = (ST == 2) ? h : T(0.5) * h;
@@ -362,33 +253,6 @@ __device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* 
             z.zs[r] = z.zb[r];
         }
     }
-#undef ZQ
-#undef ZV
-}
-
-// Record offset of the forcing entry of control `ctrl` in row k (0: x, 1: y,
-// 2: theta) of body gb, or the zero entry (Sec. IV-B FOH: dF~/du of the
-// joint torques, joint forces and contact forces).
-template <class TP>
-__device__ __forceinline__ int forcing_offset(int ctrl, int gb, int k) {
-    using R = CoefRec<TP>;
-    constexpr int NJ = TP::NJ;
-    if (ctrl < NJ) {
-        const int j = ctrl, p = TP::parent(j), c = j + 1;
-        if (k == 2 && gb == p) return R::JB + 8 * j + 6;
-        if (k == 2 && gb == c) return R::JB + 8 * j + 7;
-        return R::ZERO;
-    }
-    if (ctrl < 3 * NJ) {
-        const int j = (ctrl - NJ) >> 1, ax = (ctrl - NJ) & 1, p = TP::parent(j), c = j + 1;
-        if (k == ax && gb == p) return R::JB + 8 * j + 4;
-        if (k == ax && gb == c) return R::JB + 8 * j + 5;
-        if (k == 2 && gb == p) return R::JB + 8 * j + ax;
-        if (k == 2 && gb == c) return R::JB + 8 * j + 2 + ax;
-        return R::ZERO;
-    }
-    const int i = (ctrl - 3 * NJ) / 3, q = (ctrl - 3 * NJ) % 3;
-    return gb == TP::cbody(i) ? R::CB + 12 * i + 3 * k + q : R::ZERO;
 }
 
 template <class T, class TP, bool FORCE>
@@ -425,39 +289,13 @@ __device__ __forceinline__ void tangent_split_loop(TanLane<T, TP>& z, const T* _
 template <class T, class TP>
 __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __restrict__ rec,
                                              const int k, const int cb, T* xch) {
-    constexpr int NX = TP::NX, NXT = TP::NXT, NQ = TP::NQ, M = TP::M, NC = TP::NC;
-    constexpr int D = TP::D, L = TP::L, LB = D + 1;
+    constexpr int D = TP::D, LB = D + 1;
     using SR = SplitRec<TP>;
     const int tid = threadIdx.x, lane = tid & 63;
     const int leg = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int col = cb * 64 + lane;
-    const bool active = col < SR::NCOLT;
-    auto gbody = [&](int lb) { return lb == 0 ? 0 : 1 + leg * D + lb - 1; };
-    T wbm = T(0), wbp = T(0);
-    int ctrl = 0;
-    if (col >= NX && col < NX + M) { wbm = T(1); ctrl = col - NX; }
-    else if (col >= NX + M && col < NX + 2 * M) { wbp = T(1); ctrl = col - NX - M; }
-    const bool bcol = wbm != T(0) || wbp != T(0);
-    // byte offsets of the forcing entries of the lane's control in a stage record
-    unsigned off[3 * LB];
-#pragma unroll
-    for (int lb = 0; lb < LB; ++lb)
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk)
-            off[3 * lb + kk] = sizeof(T) * (unsigned)(bcol ? forcing_offset<TP>(ctrl, gbody(lb), kk)
-                                                           : CoefRec<TP>::ZERO);
-    unsigned offcc = sizeof(T) * (unsigned)CoefRec<TP>::ZERO;
-    if (bcol && ctrl >= 3 * TP::NJ && (ctrl - 3 * TP::NJ) / 3 == leg)
-        offcc = sizeof(T) * (unsigned)CoefRec<TP>::gc(leg, (ctrl - 3 * TP::NJ) % 3);
+    T wbm, wbp;
     TanLane<T, TP> z;
-#pragma unroll
-    for (int lb = 0; lb < LB; ++lb)
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-            const int gq = 3 * gbody(lb) + kk;
-            z.zb[3 * lb + kk] = (gq == col) ? T(1) : T(0);
-            z.zb[3 * LB + 3 * lb + kk] = (NQ + gq == col) ? T(1) : T(0);
-        }
+    const TanCol<TP> tc = tangent_column<T, TP>(cb, leg, lane, wbm, wbp, z.zb);
 #pragma unroll
     for (int r = 0; r < 6 * LB; ++r) {
         z.zs[r] = z.zb[r];
@@ -468,38 +306,13 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
     const T* cr = rec;
     const T* rec0 = rec + SR::CRS;
     // blocks holding no B-/B+ column skip the forcing code (uniform branch)
-    if ((cb + 1) * 64 <= NX) tangent_split_loop<T, TP, false>(z, cr, rec0, xch, leg, lane, a.K,
-                                                             wbm, wbp, off, offcc);
-    else tangent_split_loop<T, TP, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, off, offcc);
-    // violation row: sum of the legs' parts in leg order
-    T yct = z.yct;
-    if constexpr (L > 1) {
-        __syncthreads();
-        xch[leg * 64 + lane] = z.yct;
-        __syncthreads();
-        yct = xch[lane];
-#pragma unroll
-        for (int l = 1; l < L; ++l) yct += xch[l * 64 + lane];
-    }
-    if (!active) return;
-    const int64_t ldi = a.ldi;
-    T* out;
-    int64_t cstride, c0;   // element (row, column) at out[(row * cstride + c0) * ldi + k]
-    if (col < NX) { out = a.A; cstride = NXT; c0 = col; }
-    else if (col < NX + M) { out = a.Bm; cstride = M; c0 = col - NX; }
-    else { out = a.Bp; cstride = M; c0 = col - NX - M; }
-#pragma unroll
-    for (int lb = 0; lb < LB; ++lb) {
-        if (lb == 0 && leg != 0) continue;
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-            const int gq = 3 * gbody(lb) + kk;
-            out[((int64_t)gq * cstride + c0) * ldi + k] = z.zb[3 * lb + kk];
-            out[((int64_t)(NQ + gq) * cstride + c0) * ldi + k] = z.zb[3 * LB + 3 * lb + kk];
-        }
-    }
-    out[((int64_t)(NX + leg) * cstride + c0) * ldi + k] = z.ycc;
-    if (leg == 0) out[((int64_t)(NX + NC) * cstride + c0) * ldi + k] = yct;
+    if ((cb + 1) * 64 <= TP::NX)
+        tangent_split_loop<T, TP, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                         tc.offcc);
+    else
+        tangent_split_loop<T, TP, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                        tc.offcc);
+    tangent_store<T, TP>(a, k, leg, lane, tc, z.zb, z.ycc, z.yct, xch);
 }
 
 // Single trajectory: rec holds N interval parts of per_interval(K) elements.
