@@ -60,6 +60,19 @@ def split_flops_per_interval(model, K):
     return total - tangent, tangent
 
 
+def rkf_flops_per_interval(model, K):
+    """Per-interval FLOPs of the Runge-Kutta-Fehlberg form (K steps of the 4(5)
+    pair): K [10 nnz(J) c + 28 nx c + 6 phi_fJ] -- five propagated stages of
+    the tangent product, 14 FMAs per tangent element and step for the stage
+    inputs and the solution (partial sums), six right-hand side and Jacobian
+    evaluations per step (the sixth for the estimate)."""
+    nb, nj, nc = model.nb, model.nj, model.nc
+    nnz = 2 * 3 * nb + 2 * nb + 4 * nj + 4 * nc
+    c = model.n + 2 * model.m + 1
+    phi = PHI_FJ.get(nb, 1000)
+    return K * (10 * nnz * c + 28 * model.nx * c + 6 * phi)
+
+
 def adjoint_flops_per_interval(model, K):
     """Per-interval FLOPs of one gradient step (defects pass + reverse sweep):
     K [6 phi_fJ + 8 (nnz(J) + nnz(J_u, J_ubar) + nnz(J_p)) + 14 nx] + 2 K phi_fJ.
@@ -432,6 +445,66 @@ def main():
                     "bar": 1e-10, "sample": f"nodes {picks} (G, Theta, JGv, JTc)"}
             pending.append(run_impact)
         del iin, iout
+        torch.cuda.empty_cache()
+
+        # Runge-Kutta-Fehlberg form: the 12800 quad13 intervals of the batch as
+        # one trajectory (cis_discretize_rkf), beside the RK4 split form on the
+        # same intervals (cis_discretize_split)
+        rmodel, rdata, rK = synth.make_workload("quad13_N12800_K20")
+        rN = rdata["s"].shape[0]
+        rcm = api.CisModel(rmodel)
+        rX = api.to_device_soa(rdata["X"], dev)
+        rU = api.to_device_soa(rdata["U"], dev)
+        rs = torch.tensor(rdata["s"], device=dev)
+        rp = torch.tensor(rdata["p"], device=dev)
+        rout = api.discretize_rkf(rcm, rX, rU, rs, rp, rK, stream=stream)
+        rws = torch.empty((api.rkf_workspace_bytes(rcm, rN, rK),), device=dev, dtype=torch.uint8)
+        rsh = _lib.Shape(rN, rK, _lib.CIS_F64, 0, rX.stride(0), rN)
+        vpr = lambda t: ctypes.c_void_p(None if t is None else t.data_ptr())
+        rargs = [vpr(t) for t in (rX, rU, rs, rp)]
+        routs = [vpr(rout[k]) for k in ("A", "Bm", "Bp", "S", "d", "xprop")]
+        st_r = ctypes.c_void_p(stream.cuda_stream)
+
+        def launch_rkf():
+            _lib.check(lib.cis_discretize_rkf(rcm.handle, ctypes.byref(rsh), *rargs, 1, *routs,
+                                              vpr(rout["err"]), vpr(rws), rws.numel(), st_r))
+
+        def launch_rk4_split():
+            _lib.check(lib.cis_discretize_split(rcm.handle, ctypes.byref(rsh), *rargs, 1, *routs,
+                                                vpr(rws), rws.numel(), st_r))
+        ms_rkf, _ = timed(launch_rkf, args.extra_steps, 2)
+        ms_rk4s, _ = timed(launch_rk4_split, args.extra_steps, 2)
+        launch_rkf()
+        torch.cuda.synchronize()
+        rkf_fl = rkf_flops_per_interval(rmodel, rK) * rN
+        progress(f"rkf quad13 N={rN} K={rK}: {ms_rkf:.3f} ms (rk4 split {ms_rk4s:.3f} ms)")
+        extras["rkf_quad13_N12800_K20_f64"] = {
+            "value": rN / (ms_rkf * 1e-3), "unit": "intervals/s", "ms_per_step": ms_rkf,
+            "rk4_split_ms_same_intervals": ms_rk4s,
+            "roofline": {"bound": "alu", "achieved": rkf_fl / (ms_rkf * 1e-3) / 1e12,
+                         "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": rkf_fl / (ms_rkf * 1e-3) / PEAK_FP64_VALU,
+                         "algorithmic_flop_per_step": rkf_fl},
+            "step": "cis_discretize_rkf: Fehlberg 4(5), K=20 steps, records + tangent launches"}
+        if not args.no_cpu_baseline:
+            rks = [0, 6400, rN - 1]
+            got_r = {k: api.as_interval_major({k: rout[k]})[k][rks].double().cpu().numpy()
+                     for k in ("A", "Bm", "Bp", "S", "d", "xprop")}
+
+            def run_rkf():
+                import oracle
+                from parity import PHI64, block_err
+                worst = 0.0
+                for i, kk in enumerate(rks):
+                    ref = oracle.discretize_rkf(rmodel, rdata["X"][kk:kk + 2], rdata["U"][kk:kk + 2],
+                                                rdata["s"][kk:kk + 1], rdata["p"], rK)
+                    for key in ("A", "Bm", "Bp", "S", "d", "xprop"):
+                        worst = max(worst, block_err(got_r[key][i:i + 1], ref[key], PHI64))
+                parity["rkf_quad13_N12800_K20_f64"] = {
+                    "max_rel_err_vs_oracle": worst, "metric": "per-entry (phi = 1e-3)",
+                    "bar": 1e-10, "sample": f"intervals {rks}"}
+            pending.append(run_rkf)
+        del rout, rws, rX, rU
         torch.cuda.empty_cache()
 
         # uneven batch of 256 trajectories over three models

@@ -307,6 +307,9 @@ WORKLOADS = {
     "cheetah7_N50_K20": dict(model="cheetah7", N=50, K=20, seed=2),
     "cheetah7_N50_K20_ckpt5": dict(model="cheetah7", N=50, K=20, ckpt=5, seed=3),
     "quad13_N200_K20_x64": dict(model="quad13", N=200, K=20, batch=64, seed=5),
+    # the 64 x 200 intervals of the batch as one trajectory (same interval
+    # lengths: T scaled with N)
+    "quad13_N12800_K20": dict(model="quad13", N=12800, K=20, T=64.0, seed=7),
 }
 
 
@@ -315,7 +318,7 @@ def make_workload(name: str, traj_id: int = 0):
     cfg = WORKLOADS[name]
     rng = np.random.default_rng([cfg["seed"], traj_id])
     model = MODEL_MAKERS[cfg["model"]](rng)
-    data = gen_nodes(model, cfg["N"], rng)
+    data = gen_nodes(model, cfg["N"], rng, T=cfg.get("T", 1.0))
     return model, data, cfg["K"]
 
 
