@@ -298,6 +298,30 @@ def gen_impact_nodes(model: Model, n_nodes: int, rng: np.random.Generator,
     return {"Xm": Xm, "Xp": Xp, "Phi": Phi, "Gamma": Gam, "p": p}
 
 
+def gen_paper_nodes(model: Model, N: int, rng: np.random.Generator, T: float = 1.0,
+                    vel_sigma: float = 0.5, contact_range=(0.0, 30.0)):
+    """Seeded node data of the paper-faithful dynamics variant (joint forces
+    eliminated, n_y = 4 nc + 1): poses and velocities as gen_nodes, integral
+    states zero; u = (tau ~ N(0, torque_sigma), per contact phi_t, phi_n, gamma)
+    with phi_n ~ U(contact_range), phi_t ~ U(-mu phi_n, mu phi_n) (inside the
+    friction cone), gamma ~ U(0, 1).
+
+    Returns a dict with X[N+1, 6 nb + 4 nc + 1], U[N+1, nj + 3 nc], s[N], p[P].
+    """
+    base = gen_nodes(model, N, rng, vel_sigma=vel_sigma, T=T)
+    nb, nj, nc = model.nb, model.nj, model.nc
+    X = np.zeros((N + 1, 6 * nb + 4 * nc + 1))
+    X[:, :6 * nb] = base["X"][:, :6 * nb]
+    U = np.zeros((N + 1, nj + 3 * nc))
+    U[:, :nj] = rng.normal(0.0, model.torque_sigma, size=(N + 1, nj))
+    p = model.params()
+    pn = rng.uniform(*contact_range, size=(N + 1, nc))
+    U[:, nj::3] = rng.uniform(-1.0, 1.0, size=(N + 1, nc)) * p[0] * pn
+    U[:, nj + 1::3] = pn
+    U[:, nj + 2::3] = rng.uniform(0.0, 1.0, size=(N + 1, nc))
+    return {"X": X, "U": U, "s": base["s"], "p": p}
+
+
 # Workload recipes (model, N, substeps) of the benchmark configurations.
 # The benchmark workloads by name: model, intervals N, substeps K, and the
 # seed of their node data (batch: trajectories; ckpt: substeps between the
