@@ -253,6 +253,42 @@ cis_status cis_discretize_rkf(const cis_model *model, const cis_shape *shape, co
                               void *A, void *Bm, void *Bp, void *S, void *defect, void *xprop,
                               void *err, void *ws, size_t ws_bytes, void *stream);
 
+/* Sizes of the paper-faithful dynamics variant of a model: nx = 6 nb + 4 nc + 1
+ * augmented states and m = nj + 3 nc controls (any output pointer may be NULL). */
+cis_status cis_paper_dims(const cis_model *model, int32_t *nx, int32_t *m);
+
+/* Bytes of device workspace cis_discretize_paper needs (FP64; models with legs
+ * with links, else CIS_ERR_UNSUPPORTED). */
+cis_status cis_paper_workspace_size(const cis_model *model, const cis_shape *shape,
+                                    size_t *bytes);
+
+/*
+ * The discretize step of the paper-faithful dynamics variant, FP64:
+ *  - joint reaction forces are not controls: they are eliminated at the
+ *    acceleration level (Sec. II-A, eq. joint-cnstr-acc):
+ *      lambda = -(grad h M^-1 grad h^T)^-1 (grad h M^-1 (W + J^T R phi) + c),
+ *      c_j = v^T grad^2 h_j v = -w_p^2 a_p + w_c^2 a_c;
+ *  - controls u = (tau_0 .. tau_{nj-1}, then (phi_t, phi_n, gamma) per
+ *    contact), m = nj + 3 nc, with R phi = t phi_t + n phi_n;
+ *  - integral states (eq. aux-dynamics): per contact the integrals of phi_n,
+ *    lambda_c = t^T J v + gamma phi_t / sqrt(phi_t^2 + 1), gamma and
+ *    rho_c = |mu phi_n|_s - |phi_t|_s, then one violation state integrating
+ *    sum_i ramp_s(-phi_n) + ramp_s(-sd) + ramp_s(-gamma) + ramp_s(-rho_c)
+ *    (one row of all ones as the mixing matrix); nx = 6 nb + 4 nc + 1;
+ *  - classical RK4 with K substeps and FOH controls as cis_discretize, with
+ *    the variational equations through the same stages (Sec. IV-B, Sec. VI).
+ * Arrays as in the header comment with these nx and m: X [nx][ld_node],
+ * U [m][ld_node], A [nx][nx][ld_int], Bm/Bp [nx][m][ld_int], S, defect,
+ * xprop [nx][ld_int] (xprop may be NULL).  Two launches (a stage record per
+ * interval, then tangent columns); ws must hold cis_paper_workspace_size
+ * bytes, 8-byte aligned (scratch).  Errors as for cis_discretize_split;
+ * dtype other than CIS_F64: CIS_ERR_DTYPE.
+ */
+cis_status cis_discretize_paper(const cis_model *model, const cis_shape *shape, const void *X,
+                                const void *U, const void *s, const void *params, void *A,
+                                void *Bm, void *Bp, void *S, void *defect, void *xprop, void *ws,
+                                size_t ws_bytes, void *stream);
+
 /* Composition of the substep blocks of cis_discretize_blocked. */
 enum { CIS_COMPOSE_VALU = 0, CIS_COMPOSE_MFMA = 1 };
 

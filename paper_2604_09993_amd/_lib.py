@@ -52,7 +52,7 @@ EXPORTS = [
     "cis_blocked_workspace_size", "cis_discretize_blocked", "cis_discretize_adjoint_noalloc",
     "cis_split_workspace_size", "cis_discretize_split", "cis_batch_plan_discretize_form",
     "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize", "cis_rkf_workspace_size",
-    "cis_discretize_rkf",
+    "cis_discretize_rkf", "cis_paper_dims", "cis_paper_workspace_size", "cis_discretize_paper",
 ]
 
 
@@ -157,6 +157,14 @@ def load(build_if_missing: bool = True):
     lib.cis_discretize_rkf.restype = St
     lib.cis_discretize_rkf.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, I32]
                                        + [P] * 8 + [ctypes.c_size_t, P])
+    lib.cis_paper_dims.restype = St
+    lib.cis_paper_dims.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.cis_paper_workspace_size.restype = St
+    lib.cis_paper_workspace_size.argtypes = [P, ctypes.POINTER(Shape),
+                                             ctypes.POINTER(ctypes.c_size_t)]
+    lib.cis_discretize_paper.restype = St
+    lib.cis_discretize_paper.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P]
+                                         + [P] * 7 + [ctypes.c_size_t, P])
     lib.cis_impact_dims.restype = St
     lib.cis_impact_dims.argtypes = [P] + [ctypes.POINTER(I32)] * 3
     lib.cis_impact_linearize.restype = St

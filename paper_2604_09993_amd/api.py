@@ -255,6 +255,43 @@ def discretize_rkf(cm: CisModel, X, U, s, params, K, *, waves=1, with_xprop=True
     return out
 
 
+def paper_dims(cm: CisModel):
+    """(nx, m) of the paper-faithful dynamics variant of a model."""
+    nx, m = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(_lib.load().cis_paper_dims(cm.handle, ctypes.byref(nx), ctypes.byref(m)))
+    return nx.value, m.value
+
+
+def discretize_paper(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None):
+    """The discretize outputs of the paper-faithful dynamics variant (joint
+    forces eliminated, controls (tau, phi_t, phi_n, gamma), nx = 6 nb + 4 nc + 1),
+    FP64: X [nx, ld_node], U [m, ld_node]."""
+    nx, m = paper_dims(cm)
+    if X.dtype != torch.float64 or X.device.type != "cuda":
+        raise ValueError("inputs must be float64 GPU tensors")
+    N = s.shape[0]
+    if (X.shape[0] != nx or U.shape[0] != m or X.stride(1) != 1 or U.stride(1) != 1
+            or U.stride(0) != X.stride(0) or X.shape[1] < N + 1 or U.shape[1] < N + 1):
+        raise ValueError("X must be [nx, >= N+1] and U [m, >= N+1] with one ld_node")
+    kw = dict(device=X.device, dtype=X.dtype)
+    sh = _lib.Shape(N, int(K), _lib.CIS_F64, 0, X.stride(0), N)
+    nb_ = ctypes.c_size_t()
+    lib = _lib.load()
+    _lib.check(lib.cis_paper_workspace_size(cm.handle, ctypes.byref(sh), ctypes.byref(nb_)))
+    with _alloc_on(stream):
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw))
+        out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+        ws = torch.empty((nb_.value,), device=X.device, dtype=torch.uint8)
+    _lib.check(lib.cis_discretize_paper(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
+                                        _ptr(params), _ptr(out["A"]), _ptr(out["Bm"]),
+                                        _ptr(out["Bp"]), _ptr(out["S"]), _ptr(out["d"]),
+                                        _ptr(out["xprop"]), _ptr(ws), ws.numel(),
+                                        _stream(stream)))
+    return out
+
+
 def defects(cm: CisModel, X, U, s, params, K, *, ckpt_every=None, stream=None):
     """F~ and defects only; optional substep checkpoints [K/C, n, N] for the adjoint."""
     _check_inputs(cm, X, U, s, params)

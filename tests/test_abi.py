@@ -173,6 +173,26 @@ def test_entry_points_validate_before_launch():
     assert imp(0, 1, ptrs=(0,) * 10) == 0
     assert lib.cis_impact_linearize(None, 4, 4, *[P(8)] * 5, 1e-3, 0.0, *[P(8)] * 5,
                                     None) == _lib.CIS_ERR_NULL
+    # paper-dynamics form: FP64 only, workspace checked
+    need = ctypes.c_size_t(0)
+    assert lib.cis_paper_workspace_size(h, ctypes.byref(good), ctypes.byref(need)) == 0
+    sh32 = _lib.Shape(5, 4, _lib.CIS_F32, 0, 6, 5)
+    pap = lambda sh, ws, nb: lib.cis_discretize_paper(h, ctypes.byref(sh), P(8), P(8), P(8), P(8),
+                                                      P(8), P(8), P(8), P(8), P(8), None, ws, nb,
+                                                      None)
+    assert pap(sh32, P(8), need.value) == _lib.CIS_ERR_DTYPE
+    assert pap(good, None, need.value) == _lib.CIS_ERR_WORKSPACE
+    assert pap(good, P(8), need.value - 8) == _lib.CIS_ERR_WORKSPACE
+    pd = [ctypes.c_int32() for _ in range(2)]
+    assert lib.cis_paper_dims(h, *[ctypes.byref(d) for d in pd]) == 0
+    assert [d.value for d in pd] == [6 * model.nb + 4 * model.nc + 1, model.nj + 3 * model.nc]
+    # RKF form: workspace checked
+    assert lib.cis_rkf_workspace_size(h, ctypes.byref(good), ctypes.byref(need)) == 0
+    rkf = lambda ws, nb: lib.cis_discretize_rkf(h, ctypes.byref(good), P(8), P(8), P(8), P(8), 1,
+                                                P(8), P(8), P(8), P(8), P(8), None, None, ws, nb,
+                                                None)
+    assert rkf(None, need.value) == _lib.CIS_ERR_WORKSPACE
+    assert rkf(P(8), need.value - 8) == _lib.CIS_ERR_WORKSPACE
     dims = [ctypes.c_int32() for _ in range(3)]
     assert lib.cis_impact_dims(h, *[ctypes.byref(d) for d in dims]) == 0
     assert [d.value for d in dims] == [10 * model.nc, 7 * model.nb + 2 * model.nc, 14]
