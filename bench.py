@@ -73,6 +73,22 @@ def rkf_flops_per_interval(model, K):
     return K * (10 * nnz * c + 28 * model.nx * c + 6 * phi)
 
 
+def paper_flops_per_interval(model, K):
+    """Per-interval FLOPs of the paper-faithful dynamics variant:
+    4K [c (2 n_q 2 n_j + 2 nnz(J) + 14 nx) + 2 (2 n_j)^2 (2 n_j + n_q + 1)] with
+    c = 6 n_b + 2 m + 1 tangent columns (m = n_j + 3 n_c, nx = 6 n_b + 4 n_c + 1):
+    per stage and column the dense joint coupling Wm b, the sparse local terms
+    and the RK4 combination; per stage the Gauss-Jordan elimination of
+    [A | grad h M^-1 | r]."""
+    nb, nj, nc = model.nb, model.nj, model.nc
+    nq = 3 * nb
+    nnz = 2 * nq + 2 * nb + 4 * nj + 4 * nc
+    nx = 6 * nb + 4 * nc + 1
+    c = 6 * nb + 2 * (nj + 3 * nc) + 1
+    return 4 * K * (c * (2 * nq * 2 * nj + 2 * nnz + 14 * nx)
+                    + 2 * (2 * nj) ** 2 * (2 * nj + nq + 1))
+
+
 def adjoint_flops_per_interval(model, K):
     """Per-interval FLOPs of one gradient step (defects pass + reverse sweep):
     K [6 phi_fJ + 8 (nnz(J) + nnz(J_u, J_ubar) + nnz(J_p)) + 14 nx] + 2 K phi_fJ.
@@ -505,6 +521,59 @@ def main():
                     "bar": 1e-10, "sample": f"intervals {rks}"}
             pending.append(run_rkf)
         del rout, rws, rX, rU
+        torch.cuda.empty_cache()
+
+        # paper-faithful dynamics variant (joint forces eliminated): 12800
+        # quad13 intervals as one trajectory, K = 20
+        pmodel = rmodel
+        prng = np.random.default_rng(8)
+        pdata = synth.gen_paper_nodes(pmodel, rN, prng, T=64.0)
+        pcm = api.CisModel(pmodel)
+        pX = api.to_device_soa(pdata["X"], dev)
+        pU = api.to_device_soa(pdata["U"], dev)
+        ps = torch.tensor(pdata["s"], device=dev)
+        pp = torch.tensor(pdata["p"], device=dev)
+        pout = api.discretize_paper(pcm, pX, pU, ps, pp, rK, stream=stream)
+        psh = _lib.Shape(rN, rK, _lib.CIS_F64, 0, pX.stride(0), rN)
+        pnb = ctypes.c_size_t()
+        _lib.check(lib.cis_paper_workspace_size(pcm.handle, ctypes.byref(psh), ctypes.byref(pnb)))
+        pws = torch.empty((pnb.value,), device=dev, dtype=torch.uint8)
+        pargs = [vpr(t) for t in (pX, pU, ps, pp)]
+        pouts = [vpr(pout[k]) for k in ("A", "Bm", "Bp", "S", "d", "xprop")]
+
+        def launch_paper():
+            _lib.check(lib.cis_discretize_paper(pcm.handle, ctypes.byref(psh), *pargs, *pouts,
+                                                vpr(pws), pws.numel(), st_r))
+        ms_pap, _ = timed(launch_paper, max(args.extra_steps // 4, 3), 1)
+        pap_fl = paper_flops_per_interval(pmodel, rK) * rN
+        progress(f"paper dynamics quad13 N={rN} K={rK}: {ms_pap:.3f} ms")
+        extras["paper_dynamics_quad13_N12800_K20_f64"] = {
+            "value": rN / (ms_pap * 1e-3), "unit": "intervals/s", "ms_per_step": ms_pap,
+            "roofline": {"bound": "alu", "achieved": pap_fl / (ms_pap * 1e-3) / 1e12,
+                         "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": pap_fl / (ms_pap * 1e-3) / PEAK_FP64_VALU,
+                         "algorithmic_flop_per_step": pap_fl},
+            "step": "cis_discretize_paper: joint forces eliminated, RK4 K=20, record + tangent "
+                    "launches"}
+        if not args.no_cpu_baseline:
+            pks = [0, rN - 1]
+            got_p = {k: api.as_interval_major({k: pout[k]})[k][pks].cpu().numpy()
+                     for k in ("A", "Bm", "Bp", "S", "d", "xprop")}
+
+            def run_paper():
+                from oracle import paper_dynamics as pdyn
+                from parity import PHI64, block_err
+                worst = 0.0
+                for i, kk in enumerate(pks):
+                    ref = pdyn.discretize(pmodel, pdata["X"][kk:kk + 2], pdata["U"][kk:kk + 2],
+                                          pdata["s"][kk:kk + 1], pdata["p"], rK)
+                    for key in ("A", "Bm", "Bp", "S", "d", "xprop"):
+                        worst = max(worst, block_err(got_p[key][i:i + 1], ref[key], PHI64))
+                parity["paper_dynamics_quad13_N12800_K20_f64"] = {
+                    "max_rel_err_vs_oracle": worst, "metric": "per-entry (phi = 1e-3)",
+                    "bar": 1e-10, "sample": f"intervals {pks}"}
+            pending.append(run_paper)
+        del pout, pws, pX, pU
         torch.cuda.empty_cache()
 
         # uneven batch of 256 trajectories over three models
