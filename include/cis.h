@@ -456,6 +456,22 @@ cis_status cis_batch_plan_info(const cis_batch_plan *plan, int32_t g, int32_t *g
                                int32_t *persist_blocks, int32_t *adjoint_waves,
                                int32_t *waves_per_simd, int32_t *defects_waves);
 
+/*
+ * Tuning cache.  With CIS_SCHED_TUNE and the environment variable
+ * CIS_TUNE_CACHE naming a file, cis_batch_plan_create looks up each model
+ * group's choices (discretize form and register budget, grid or persistent
+ * launch, defects form, reverse-sweep waves) under a key made of the device
+ * (architecture, compute units), the topology, dtype, operations, the
+ * group's number of intervals, its substep range and, with the reverse sweep,
+ * its largest checkpoint spacing.  Found: the choices are used without timing.
+ * Not found: the group is timed and its choices are added to the file (JSON,
+ * written through a temporary file; a missing or unreadable file counts as
+ * empty).  *from_cache = 1 when every tuned choice of group g came from the
+ * file.  Errors: CIS_ERR_NULL, CIS_ERR_DIM (g out of range).
+ */
+cis_status cis_batch_plan_tuned_from_cache(const cis_batch_plan *plan, int32_t g,
+                                           int32_t *from_cache);
+
 /* Discretize form of group g (0 <= g < groups): *split = 1 when it runs in
  * the split form, with *tangent_waves its register budget (waves per SIMD),
  * else 0 and 0.  Any output pointer may be NULL; g out of range: CIS_ERR_DIM. */

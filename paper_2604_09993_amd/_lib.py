@@ -53,6 +53,7 @@ EXPORTS = [
     "cis_split_workspace_size", "cis_discretize_split", "cis_batch_plan_discretize_form",
     "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize", "cis_rkf_workspace_size",
     "cis_discretize_rkf", "cis_paper_dims", "cis_paper_workspace_size", "cis_discretize_paper",
+    "cis_batch_plan_tuned_from_cache",
 ]
 
 
@@ -157,6 +158,8 @@ def load(build_if_missing: bool = True):
     lib.cis_discretize_rkf.restype = St
     lib.cis_discretize_rkf.argtypes = ([P, ctypes.POINTER(Shape), P, P, P, P, I32]
                                        + [P] * 8 + [ctypes.c_size_t, P])
+    lib.cis_batch_plan_tuned_from_cache.restype = St
+    lib.cis_batch_plan_tuned_from_cache.argtypes = [P, I32, ctypes.POINTER(I32)]
     lib.cis_paper_dims.restype = St
     lib.cis_paper_dims.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.cis_paper_workspace_size.restype = St

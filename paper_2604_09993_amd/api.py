@@ -563,13 +563,14 @@ class BatchPlan:
         for g in range(ng.value):
             v = [ctypes.c_int32() for _ in range(7)]
             _lib.check(lib.cis_batch_plan_info(self._h, g, None, *[ctypes.byref(x) for x in v]))
-            sp, tw = ctypes.c_int32(), ctypes.c_int32()
+            sp, tw, fc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
             _lib.check(lib.cis_batch_plan_discretize_form(self._h, g, ctypes.byref(sp),
                                                           ctypes.byref(tw)))
+            _lib.check(lib.cis_batch_plan_tuned_from_cache(self._h, g, ctypes.byref(fc)))
             res.append(dict(n_traj=v[0].value, n_items=v[1].value, units_per_item=v[2].value,
                             persist_blocks=v[3].value, adjoint_waves=v[4].value,
                             waves_per_simd=v[5].value, defects_waves=v[6].value,
-                            split=sp.value))
+                            split=sp.value, from_cache=fc.value))
         return res
 
     def close(self):

@@ -4,7 +4,13 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "../../include/cis.h"
@@ -36,7 +42,131 @@ struct Group {
     std::vector<int64_t> rec_off;
     BatchGroupDev dev{};
     KLaunch disc, disc_b, def, adj;   // disc_b: tangent launch of the split form
+    bool from_cache = false;          // every tuned choice came from the tuning cache
 };
+
+// ---------------------------------------------------------------------------
+// Tuning cache: the choices CIS_SCHED_TUNE makes per model group, kept in the
+// JSON file named by CIS_TUNE_CACHE (no variable: no cache) as
+//   {"version": 1, "entries": {"<key>": {"split": s, "waves": w, "persist": p,
+//                                        "def_lane": d, "adj_waves": a}, ...}}
+// keyed by device (architecture, compute units), topology, dtype, operations,
+// work-list length and substep range (and checkpoint spacing with the reverse
+// sweep); -1 marks a choice that was not made.  A missing or unreadable file
+// is an empty cache; writes replace the file through a temporary.
+// ---------------------------------------------------------------------------
+struct TuneChoice {
+    int split = -1, waves = -1, persist = -1, def_lane = -1, adj_waves = -1;
+};
+
+std::mutex g_cache_mu;
+
+// minimal reader of the cache's own format (objects, strings, integers)
+struct CacheParser {
+    const std::string& t;
+    size_t i = 0;
+    explicit CacheParser(const std::string& s) : t(s) {}
+    void ws() { while (i < t.size() && std::strchr(" \t\r\n", t[i])) ++i; }
+    bool lit(char c) { ws(); if (i < t.size() && t[i] == c) { ++i; return true; } return false; }
+    bool str(std::string& out) {
+        ws();
+        if (i >= t.size() || t[i] != '"') return false;
+        const size_t j = t.find('"', i + 1);
+        if (j == std::string::npos) return false;
+        out = t.substr(i + 1, j - i - 1);
+        i = j + 1;
+        return true;
+    }
+    bool num(long& v) {
+        ws();
+        char* end = nullptr;
+        v = std::strtol(t.c_str() + i, &end, 10);
+        if (end == t.c_str() + i) return false;
+        i = end - t.c_str();
+        return true;
+    }
+    // {"name": int, ...}
+    bool choice(TuneChoice& c) {
+        if (!lit('{')) return false;
+        if (lit('}')) return true;
+        do {
+            std::string k;
+            long v = 0;
+            if (!str(k) || !lit(':') || !num(v)) return false;
+            if (k == "split") c.split = (int)v;
+            else if (k == "waves") c.waves = (int)v;
+            else if (k == "persist") c.persist = (int)v;
+            else if (k == "def_lane") c.def_lane = (int)v;
+            else if (k == "adj_waves") c.adj_waves = (int)v;
+        } while (lit(','));
+        return lit('}');
+    }
+    bool file(std::map<std::string, TuneChoice>& m) {
+        if (!lit('{')) return false;
+        if (lit('}')) return true;
+        do {
+            std::string k;
+            if (!str(k) || !lit(':')) return false;
+            if (k == "entries") {
+                if (!lit('{')) return false;
+                if (lit('}')) continue;
+                do {
+                    std::string key;
+                    TuneChoice c;
+                    if (!str(key) || !lit(':') || !choice(c)) return false;
+                    m[key] = c;
+                } while (lit(','));
+                if (!lit('}')) return false;
+            } else {
+                long v = 0;
+                if (!num(v)) return false;
+            }
+        } while (lit(','));
+        return lit('}');
+    }
+};
+
+std::map<std::string, TuneChoice> cache_read(const std::string& path) {
+    std::map<std::string, TuneChoice> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string text = ss.str();
+    CacheParser cp(text);
+    if (!cp.file(m)) m.clear();
+    return m;
+}
+
+bool cache_write(const std::string& path, const std::map<std::string, TuneChoice>& m) {
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return false;
+        f << "{\"version\": 1, \"entries\": {";
+        bool first = true;
+        for (const auto& kv : m) {
+            const TuneChoice& c = kv.second;
+            f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": {\"split\": " << c.split
+              << ", \"waves\": " << c.waves << ", \"persist\": " << c.persist
+              << ", \"def_lane\": " << c.def_lane << ", \"adj_waves\": " << c.adj_waves << "}";
+            first = false;
+        }
+        f << "\n}}\n";
+        if (!f) return false;
+    }
+    return std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+std::string device_tag(int dev) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%s/%dcu", pr.gcnArchName, pr.multiProcessorCount);
+    for (char* c = buf; *c; ++c)
+        if (*c == '"' || *c == '\\') *c = '_';
+    return buf;
+}
 
 int auto_ckpt(int K) {
     for (int c = 8; c > 1; --c)
@@ -427,6 +557,20 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         return fail(CIS_ERR_HIP, "cis_batch_plan_create: upload: %s", hipGetErrorString(e));
     }
 
+    // tuning cache (CIS_SCHED_TUNE only)
+    std::string cpath;
+    std::map<std::string, TuneChoice> cache;
+    bool cache_dirty = false;
+    std::string dtag;
+    if (sched == CIS_SCHED_TUNE) {
+        const char* cp = std::getenv("CIS_TUNE_CACHE");
+        if (cp && *cp) {
+            cpath = cp;
+            dtag = device_tag(p->device);
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            cache = cache_read(cpath);
+        }
+    }
     // launch records
     int ncu = 0;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -440,6 +584,24 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
         g.dev.rec = g.split_ok ? (void*)(p->recmem + g.rec_base * es) : nullptr;
         g.dev.rec_off = g.split_ok ? (const int64_t*)(d + g.recoff_off) : nullptr;
         cis_status st;
+        std::string key;
+        TuneChoice want, made;
+        bool cached_all = !cpath.empty();
+        if (!cpath.empty()) {
+            int kmin = 1 << 30, kmax = 0, cmx = 1;
+            for (int i : g.trajs) {
+                kmin = std::min(kmin, trajs[i].substeps);
+                kmax = std::max(kmax, trajs[i].substeps);
+                cmx = std::max(cmx, p->ckpt_every[i]);
+            }
+            char kb[256];
+            std::snprintf(kb, sizeof(kb), "%s|L%dD%d|%s|ops%d|items%zu|K%d-%d|C%d", dtag.c_str(),
+                          g.model->L, g.model->D, dtype == CIS_F64 ? "f64" : "f32", (int)ops,
+                          g.items.size(), kmin, kmax, (ops & CIS_BATCH_ADJOINT) ? cmx : 0);
+            key = kb;
+            auto it = cache.find(key);
+            if (it != cache.end()) want = it->second;
+        }
         if (ops & CIS_BATCH_DISCRETIZE) {
             // candidates: (grid | persistent) x register budget (1 or 2 waves
             // per SIMD; FP64 only has the second); the schedule bits fix some
@@ -492,7 +654,18 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
                 }
             }
             size_t best = 0;
-            if (cands.size() > 1) {
+            bool hit = false;
+            if (cands.size() > 1 && want.split >= 0) {
+                for (size_t c = 0; c < cands.size(); ++c)
+                    if ((cands[c].split ? 1 : 0) == want.split && cands[c].waves == want.waves &&
+                        (cands[c].pblocks > 0 ? 1 : 0) == want.persist) {
+                        best = c;
+                        hit = true;
+                        break;
+                    }
+            }
+            if (cands.size() > 1 && !hit) {
+                cached_all = false;
                 float tbest = -1.f;
                 for (size_t c = 0; c < cands.size(); ++c) {
                     const float t = cands[c].split ? time_pair(cands[c].l, cands[c].lb, hs, 3)
@@ -512,6 +685,9 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             g.disc = cands[best].l;
             g.split = cands[best].split;
             if (g.split) g.disc_b = cands[best].lb;
+            made.split = g.split ? 1 : 0;
+            made.waves = g.disc_waves;
+            made.persist = g.persist_blocks > 0 ? 1 : 0;
         }
         if (ops & CIS_BATCH_ADJOINT) {
             BatchGroupDev dd = g.dev;
@@ -520,7 +696,10 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             st = prep_defects_batch(g.model, dtype, dd, true, &def_body);
             if (st == CIS_OK) st = prep_defects_batch(g.model, dtype, dd, false, &def_lane);
             g.def = def_force == 2 ? def_lane : def_body;
-            if (st == CIS_OK && sched == CIS_SCHED_TUNE && !def_force) {
+            if (st == CIS_OK && sched == CIS_SCHED_TUNE && !def_force && want.def_lane >= 0) {
+                g.def = want.def_lane ? def_lane : def_body;
+            } else if (st == CIS_OK && sched == CIS_SCHED_TUNE && !def_force) {
+                cached_all = false;
                 const float tb = time_launch(def_body, hs, 3);
                 const float tl = time_launch(def_lane, hs, 3);
                 if (tb < 0.f || tl < 0.f) {
@@ -540,8 +719,12 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
                 plan_free(p);
                 return st;
             }
+            made.def_lane = g.def.func == def_lane.func ? 1 : 0;
             int best = adj_force ? 4 - adj_force : 1;
-            if (sched == CIS_SCHED_TUNE && !adj_force) {
+            if (sched == CIS_SCHED_TUNE && !adj_force && want.adj_waves >= 1 && want.adj_waves <= 4) {
+                best = 4 - want.adj_waves;
+            } else if (sched == CIS_SCHED_TUNE && !adj_force) {
+                cached_all = false;
                 if (g.def.launch(hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess) {
                     plan_free(p);
                     return fail(CIS_ERR_HIP, "cis_batch_plan_create: tuning launch failed");
@@ -563,7 +746,22 @@ extern "C" cis_status cis_batch_plan_create(const cis_traj* trajs, int32_t n_tra
             g.adj = adjv[best];
             g.adj_waves = adjv[best].block.x / 64;
             g.def_waves = g.def.block.x / 64;
+            made.adj_waves = 4 - best;
         }
+        if (!cpath.empty()) {
+            g.from_cache = cached_all;
+            if (!cached_all) {
+                cache[key] = made;
+                cache_dirty = true;
+            }
+        }
+    }
+    if (cache_dirty) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        // merge with entries other plans wrote meanwhile, then replace the file
+        std::map<std::string, TuneChoice> cur = cache_read(cpath);
+        for (const auto& kv : cache) cur[kv.first] = kv.second;
+        (void)cache_write(cpath, cur);
     }
     if (p->recmem) {
         bool used = false;
@@ -688,6 +886,15 @@ extern "C" cis_status cis_batch_plan_discretize_form(const cis_batch_plan* p, in
     const Group& gr = p->groups[g];
     if (split) *split = gr.split ? 1 : 0;
     if (tangent_waves) *tangent_waves = gr.split ? gr.disc_waves : 0;
+    return CIS_OK;
+}
+
+extern "C" cis_status cis_batch_plan_tuned_from_cache(const cis_batch_plan* p, int32_t g,
+                                                      int32_t* from_cache) {
+    if (!p || !from_cache) return fail(CIS_ERR_NULL, "cis_batch_plan_tuned_from_cache: null argument");
+    if (g < 0 || g >= (int32_t)p->groups.size())
+        return fail(CIS_ERR_DIM, "cis_batch_plan_tuned_from_cache: group %d out of range", g);
+    *from_cache = p->groups[g].from_cache ? 1 : 0;
     return CIS_OK;
 }
 
