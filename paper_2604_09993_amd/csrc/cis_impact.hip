@@ -41,6 +41,7 @@ struct ImpTopo {
     static constexpr int NIN = 2 * NXT + 3 * NC;       // node inputs (x+, x-, Phi, Gamma)
     static_assert(NJ2 + NQ + 1 <= 64, "one lane per column of the augmented system");
     static_assert(NCT * NC <= 64, "one lane per (contact, variable)");
+    static_assert(32 + 5 * NC <= 64, "one lane per (contact, wrench direction)");
     __host__ __device__ static constexpr int parent(int j) {
         return D == 0 ? 0 : ((j % D == 0) ? 0 : j);
     }
@@ -150,6 +151,7 @@ struct ImpShared {
     double vs[TP::NQ];                  // v*
     double lam[cmax(TP::NJ2, 1)];       // Lambda
     double X[cmax(TP::NJ2, 1)][TP::NQP];   // A^-1 grad h M^-1
+    double dw[cmax(TP::NC, 1)][5][3];   // d(contact wrench)/d(x_b, y_b, th_b, Phi_t, Phi_n)
 };
 
 // value of v in lane `src` (wave-uniform), in every lane
@@ -233,14 +235,22 @@ __global__ void __launch_bounds__(64) k_impact(ImpactArgs a, MConst<TP::NB, TP::
         }
     }
     if constexpr (NC > 0) {
-        if (lane >= 32 && lane < 32 + NC) {
-            const int i = lane - 32, b = TP::cbody(i);
+        // lane 32 + 5 i + d: the wrench of contact i and its derivative along
+        // direction d of (x_b, y_b, th_b, Phi_t, Phi_n)
+        if (lane >= 32 && lane < 32 + 5 * NC) {
+            const int i = (lane - 32) / 5, d = lane - 32 - 5 * i, b = TP::cbody(i);
             Dual Fx, Fy, Tq;
-            contact_wrench(mc, i, dn(qp[3 * b]), dn(qp[3 * b + 1]), dn(qp[3 * b + 2]),
-                           dn(phi[2 * i]), dn(phi[2 * i + 1]), Fx, Fy, Tq);
-            sh.cw[i][0] = Fx.v;
-            sh.cw[i][1] = Fy.v;
-            sh.cw[i][2] = Tq.v;
+            contact_wrench(mc, i, dn(qp[3 * b], d == 0), dn(qp[3 * b + 1], d == 1),
+                           dn(qp[3 * b + 2], d == 2), dn(phi[2 * i], d == 3),
+                           dn(phi[2 * i + 1], d == 4), Fx, Fy, Tq);
+            if (d == 0) {
+                sh.cw[i][0] = Fx.v;
+                sh.cw[i][1] = Fy.v;
+                sh.cw[i][2] = Tq.v;
+            }
+            sh.dw[i][d][0] = Fx.d;
+            sh.dw[i][d][1] = Fy.d;
+            sh.dw[i][d][2] = Tq.d;
         }
     }
     lds_sync();
@@ -348,18 +358,9 @@ __global__ void __launch_bounds__(64) k_impact(ImpactArgs a, MConst<TP::NB, TP::
         if constexpr (NC > 0) {
             const int i = TP::contact_at(b);
             if (i >= 0 && (kind == 0 || kind == 2)) {
-                const double sx = kind == 0 && comp == 0 ? 1.0 : 0.0;
-                const double sy = kind == 0 && comp == 1 ? 1.0 : 0.0;
-                const double st = kind == 0 && comp == 2 ? 1.0 : 0.0;
-                const double sft = kind == 2 && (comp & 1) == 0 ? 1.0 : 0.0;
-                const double sfn = kind == 2 && (comp & 1) == 1 ? 1.0 : 0.0;
-                Dual Fx, Fy, Tq;
-                contact_wrench(mc, i, dn(qp[3 * b], sx), dn(qp[3 * b + 1], sy),
-                               dn(qp[3 * b + 2], st), dn(phi[2 * i], sft), dn(phi[2 * i + 1], sfn),
-                               Fx, Fy, Tq);
-                du[0] = sh.minv[3 * b] * Fx.d;
-                du[1] = sh.minv[3 * b + 1] * Fy.d;
-                du[2] = sh.minv[3 * b + 2] * Tq.d;
+                const int d = kind == 0 ? comp : 3 + (comp & 1);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) du[q] = sh.minv[3 * b + q] * sh.dw[i][d][q];
             }
         }
         if (kind == 1) du[comp] = 1.0;
