@@ -406,3 +406,56 @@ def workload_batch(name: str, n_traj=None):
         MODEL_MAKERS[cfg["model"]](r)   # same stream position as make_workload
         out.append((model, gen_nodes(model, cfg["N"], r), K))
     return out
+
+
+def standing_state(model: Model, x0: float, th0: float = 0.0, joint_angles=None,
+                   clearance: float = 0.0):
+    """Augmented state of the model at rest with its lowest contact `clearance`
+    above the terrain: torso at horizontal position x0 and angle th0, relative
+    joint angles (default zero), velocities and integral states zero."""
+    ja = np.zeros(model.nj) if joint_angles is None else np.asarray(joint_angles, float)
+    pos, th = _place(model, x0, 0.0, th0, ja)
+    gap = _lowest_clearance(model, pos, th)
+    pos[:, 1] += (clearance - gap) if gap is not None else 1.0
+    x = np.zeros(model.nx)
+    x[:3 * model.nb] = np.column_stack([pos[:, 0], pos[:, 1], th]).reshape(-1)
+    return x
+
+
+def scp_initial_guess(model: Model, N: int, x_init, x_final, s0: float,
+                      rng: np.random.Generator, force_range=(0.0, 20.0),
+                      impulse_range=(0.0, 1.0)):
+    """Naive starting point of the contact-implicit SCP (the initialization of
+    the paper's experiments, Sec. VI): node poses interpolated linearly between
+    the boundary states, velocities, integral states, joint torques and joint
+    forces zero, contact forces and impulses drawn inside the friction cone
+    (lambda_n ~ U(force_range), lambda_t+ + lambda_t- <= mu lambda_n;
+    Phi_n ~ U(impulse_range), |Phi_t| <= mu Phi_n), multipliers Gamma ~ U(0, 1).
+
+    Returns node-major Xp, Xm [N+1, nx], Phi [N+1, 2 nc], Gamma [N+1, nc],
+    interval controls Ua, Ub [N, m] (discontinuous first-order hold) and S [N].
+    """
+    nb, nj, nc, nx, m = model.nb, model.nj, model.nc, model.nx, model.m
+    mu = model.params()[0]
+    w = np.linspace(0.0, 1.0, N + 1)[:, None]
+    X = np.zeros((N + 1, nx))
+    X[:, :3 * nb] = (1.0 - w) * np.asarray(x_init)[:3 * nb] + w * np.asarray(x_final)[:3 * nb]
+    Xm, Xp = X.copy(), X.copy()
+
+    def controls():
+        U = np.zeros((N, m))
+        ln = rng.uniform(*force_range, size=(N, nc))
+        frac = rng.uniform(0.0, 1.0, size=(N, nc, 2))
+        frac /= np.maximum(1.0, frac.sum(axis=2, keepdims=True))
+        U[:, 3 * nj::3] = ln
+        U[:, 3 * nj + 1::3] = frac[:, :, 0] * mu * ln
+        U[:, 3 * nj + 2::3] = frac[:, :, 1] * mu * ln
+        return U
+
+    Ua, Ub = controls(), controls()
+    pn = rng.uniform(*impulse_range, size=(N + 1, nc))
+    pt = rng.uniform(-1.0, 1.0, size=(N + 1, nc)) * mu * pn
+    Phi = np.stack([pt, pn], axis=2).reshape(N + 1, 2 * nc)
+    Gam = rng.uniform(0.0, 1.0, size=(N + 1, nc))
+    return {"Xp": Xp, "Xm": Xm, "Phi": Phi, "Gamma": Gam, "Ua": Ua, "Ub": Ub,
+            "S": np.full(N, float(s0))}
