@@ -542,6 +542,45 @@ cis_status cis_impact_linearize(const cis_model *model, int32_t n_nodes, int64_t
                                 double eps, double *G, double *Theta, double *JGv, double *JTc,
                                 double *Psi, void *stream);
 
+/*
+ * Sparse LDL^T factorization of a symmetric quasi-definite matrix (host
+ * memory, host code): the reduced KKT system [P + G^T D G + r I, A^T; A, -r I]
+ * that the interior-point solver of the SCP driver's convex subproblems
+ * factors at every iteration (the prox-linear subproblem of Sec. V, solved in
+ * canonical form as in Sec. VI).  Quasi-definite matrices factor in any
+ * symmetric order without pivoting, so the caller chooses the elimination
+ * order (fill-reducing) and passes the permuted matrix.
+ *
+ * The matrix (n x n) is given by its upper triangle, diagonal included, in
+ * compressed sparse columns: column k holds rows Ai[Ap[k] .. Ap[k+1]-1]
+ * (each <= k, any order, no duplicates) with values Ax.
+ *
+ * cis_ldl_symbolic: elimination tree parent[n] (-1 at roots) and the number
+ * of entries Lnz[n] of each column of the unit lower factor L (diagonal
+ * excluded); work[n] is scratch.  Returns nnz(L) >= 0, -1 on a NULL pointer
+ * or n < 0, -2 on an entry below the diagonal.
+ *
+ * cis_ldl_numeric: L (columns Lp[n+1], Li/Lx[nnz(L)], strictly lower) and
+ * D[n] with A = L D L^T; iwork[3n] and y[n] are scratch.  With sign[n]
+ * (+1 / -1: the expected sign of each pivot, e.g. +1 on the primal block and
+ * -1 on the multiplier block of a KKT matrix) a pivot d with sign * d <= eps
+ * is replaced by sign * delta (dynamic regularization; the factor is then
+ * that of a nearby matrix); sign may be NULL (no replacement).  Returns the
+ * number of replaced pivots, -1 on a NULL pointer, -2 on a NaN pivot or (sign
+ * NULL) a zero pivot.
+ *
+ * cis_ldl_solve: x <- (L D L^T)^-1 x in place (x[n]).
+ * All arrays are caller-owned; nothing is allocated or retained.
+ */
+int64_t cis_ldl_symbolic(int32_t n, const int32_t *Ap, const int32_t *Ai, int32_t *parent,
+                         int32_t *Lnz, int32_t *work);
+int32_t cis_ldl_numeric(int32_t n, const int32_t *Ap, const int32_t *Ai, const double *Ax,
+                        const int32_t *parent, const int32_t *Lnz, const int8_t *sign, double eps,
+                        double delta, int32_t *Lp, int32_t *Li, double *Lx, double *D,
+                        int32_t *iwork, double *y);
+void cis_ldl_solve(int32_t n, const int32_t *Lp, const int32_t *Li, const double *Lx,
+                   const double *D, double *x);
+
 #ifdef __cplusplus
 }
 #endif

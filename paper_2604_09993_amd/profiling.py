@@ -29,11 +29,13 @@ COPY_ELEMS = 64 * 1024 * 1024   # doubles per calibration copy
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of the kernel sources and the ABI header (identifies measured kernels)."""
+    """Hash of the device-code sources (the .hip files and the headers they
+    include): identifies the measured kernels.  Host-only files (.cpp) and the
+    ABI header's declarations do not change a kernel and are left out."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".cpp")))
-    for f in files + [os.path.join("..", "..", "include", "cis.h")]:
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())

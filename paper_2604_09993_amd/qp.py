@@ -16,18 +16,27 @@ reduced quasi-definite system
     [ P + G^T D G + r I   A^T  ] [dx]   [r1]
     [ A                  -r I  ] [dy] = [r2],      D = diag(z / s),
 
-once (sparse LU of SciPy) and solves it twice (affine and corrected
-directions), with a few steps of iterative refinement against the
-unregularized matrix.  Rows of A and G are scaled to unit infinity norm
-before the solve (the row normalization of the canonical form).
+once and solves it twice (affine and corrected directions), with a few
+steps of iterative refinement against the unregularized matrix.  The
+factorization is the native sparse LDL^T of libcis (cis_ldl_*) in a
+fill-reducing symmetric order (minimum degree on the pattern, taken from
+SciPy's SuperLU once per sparsity pattern); the pattern of the reduced
+matrix, the order and the elimination tree are computed once per pattern and
+can be kept across solves (`cache`).  Rows of A and G are scaled to unit
+infinity norm before the solve (the row normalization of the canonical form).
 """
 from __future__ import annotations
 
 from dataclasses import dataclass
 
+import ctypes
+import hashlib
+
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
+
+from . import _lib
 
 
 @dataclass
@@ -54,6 +63,132 @@ def _row_scale(M, v):
     return sp.diags(sc) @ M, v * sc, sc
 
 
+def _vp(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class _Kkt:
+    """The reduced KKT matrix K(D) = [P + G^T D G + r I, A^T; A, -r I] of one
+    sparsity pattern of (P, A, G): its upper triangle in a fill-reducing
+    symmetric order (CSC), where every entry comes from (the constants of P,
+    A and r, and the D-weighted products of pairs of entries of one row of
+    G), and the native symbolic factorization.  Values are set per solve."""
+
+    def __init__(self, P, A, G, reg):
+        n, me = P.shape[0], A.shape[0]
+        N = n + me
+        self.n, self.me, self.N, self.reg = n, me, N, reg
+        # constants: upper triangle of P, A^T above the diagonal, the diagonal
+        Pc = P.tocoo()
+        self.p_up = np.nonzero(Pc.row <= Pc.col)[0]
+        Ac = A.tocoo()
+        d = np.arange(N)
+        cr = np.concatenate([Pc.row[self.p_up], Ac.col, d]).astype(np.int64)
+        cc = np.concatenate([Pc.col[self.p_up], n + Ac.row, d]).astype(np.int64)
+        self.regdiag = np.concatenate([np.full(n, reg), np.full(me, -reg)])
+        # pairs (a <= b) of entries of each row of G, as positions in G.data
+        lens = np.diff(G.indptr)
+        pa, pb, pr = [], [], []
+        for k in np.unique(lens):
+            if k == 0:
+                continue
+            rows = np.nonzero(lens == k)[0]
+            ia, ib = np.triu_indices(k)
+            base = G.indptr[rows][:, None]
+            pa.append((base + ia[None, :]).ravel())
+            pb.append((base + ib[None, :]).ravel())
+            pr.append(np.repeat(rows, ia.size))
+        cat = lambda x: np.concatenate(x).astype(np.int64) if x else np.zeros(0, np.int64)
+        self.pa, self.pb, self.gr = cat(pa), cat(pb), cat(pr)
+        ga, gb = G.indices[self.pa].astype(np.int64), G.indices[self.pb].astype(np.int64)
+        # fill-reducing order from the symmetric pattern (values at D = 1)
+        cv = self._const_values(P, A)
+        gw = G.data[self.pa] * G.data[self.pb]
+        Kfull = sp.csc_matrix((np.concatenate([cv, cv, gw, gw]),
+                               (np.concatenate([cr, cc, ga, gb]), np.concatenate([cc, cr, gb, ga]))),
+                              shape=(N, N))
+        Kfull.sum_duplicates()
+        lu = spla.splu(Kfull, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                       options=dict(SymmetricMode=True))
+        best = None
+        for perm in (lu.perm_c, np.argsort(lu.perm_c)):
+            st = self._structure(np.asarray(perm, np.int64), cr, cc, ga, gb)
+            if best is None or st["lnz"] < best["lnz"]:
+                best = st
+        self.__dict__.update(best)
+        self.Lp = np.zeros(N + 1, np.int32)
+        self.Li = np.zeros(max(self.lnz, 1), np.int32)
+        self.Lx = np.zeros(max(self.lnz, 1))
+        self.Dl = np.zeros(N)
+        self.iwork = np.zeros(3 * N, np.int32)
+        self.y = np.zeros(N)
+        # expected pivot signs in the elimination order: + on the primal block,
+        # - on the multipliers of the equalities
+        self.sign = np.where(self.perm < n, 1, -1).astype(np.int8)
+        self.replaced = 0
+
+    def _const_values(self, P, A):
+        return np.concatenate([P.tocoo().data[self.p_up], A.tocoo().data, self.regdiag])
+
+    def set_values(self, P, A, G):
+        """Constants and pair products of this solve's matrices (same pattern)."""
+        self.const = np.bincount(self.inv_c, weights=self._const_values(P, A),
+                                 minlength=self.nnz)
+        self.gw = G.data[self.pa] * G.data[self.pb]
+
+    def _structure(self, perm, cr, cc, ga, gb):
+        N = self.N
+        pinv = np.empty(N, np.int64)
+        pinv[perm] = np.arange(N)
+
+        def key(r, c):
+            pr, pc = pinv[r], pinv[c]
+            return np.minimum(pr, pc) + N * np.maximum(pr, pc)
+        kc, kg = key(cr, cc), key(ga, gb)
+        uniq, inv = np.unique(np.concatenate([kc, kg]), return_inverse=True)
+        Ai = (uniq % N).astype(np.int32)
+        colk = uniq // N
+        Ap = np.zeros(N + 1, np.int32)
+        np.cumsum(np.bincount(colk, minlength=N), out=Ap[1:])
+        parent = np.zeros(N, np.int32)
+        Lnz = np.zeros(N, np.int32)
+        work = np.zeros(N, np.int32)
+        lnz = _lib.load().cis_ldl_symbolic(N, _vp(Ap), _vp(Ai), _vp(parent), _vp(Lnz), _vp(work))
+        if lnz < 0:
+            raise RuntimeError(f"cis_ldl_symbolic failed ({lnz})")
+        return dict(perm=perm, Ap=Ap, Ai=Ai, nnz=uniq.size, inv_c=inv[:kc.size],
+                    inv_g=inv[kc.size:], parent=parent, Lnz=Lnz, lnz=int(lnz))
+
+    def factor(self, D):
+        Ax = self.const + np.bincount(self.inv_g, weights=self.gw * D[self.gr],
+                                      minlength=self.nnz)
+        st = _lib.load().cis_ldl_numeric(self.N, _vp(self.Ap), _vp(self.Ai), _vp(Ax),
+                                         _vp(self.parent), _vp(self.Lnz), _vp(self.sign),
+                                         ctypes.c_double(1e-13), ctypes.c_double(1e-7),
+                                         _vp(self.Lp), _vp(self.Li), _vp(self.Lx),
+                                         _vp(self.Dl), _vp(self.iwork), _vp(self.y))
+        if st < 0:
+            raise RuntimeError(f"cis_ldl_numeric failed ({st})")
+        self.replaced = st
+
+    def solve(self, rhs):
+        x = np.ascontiguousarray(rhs[self.perm])
+        _lib.load().cis_ldl_solve(self.N, _vp(self.Lp), _vp(self.Li), _vp(self.Lx), _vp(self.Dl),
+                                  _vp(x))
+        out = np.empty_like(x)
+        out[self.perm] = x
+        return out
+
+
+def _pattern_key(*mats):
+    h = hashlib.sha1()
+    for M in mats:
+        h.update(np.asarray(M.shape, np.int64).tobytes())
+        h.update(M.indptr.tobytes())
+        h.update(M.indices.tobytes())
+    return h.hexdigest()
+
+
 def _max_step(v, dv):
     """Largest a in (0, 1] with v + a dv >= 0 (v > 0)."""
     neg = dv < 0.0
@@ -63,7 +198,7 @@ def _max_step(v, dv):
 
 
 def solve_qp(P, q, A=None, b=None, G=None, h=None, *, tol=1e-8, max_iter=80, reg=1e-11,
-             refine=2, min_step=1e-8) -> QPResult:
+             refine=2, min_step=1e-8, cache=None) -> QPResult:
     """Solve the convex QP above.  P [n, n] symmetric positive semidefinite
     (sparse or dense), q [n]; A [me, n], b [me]; G [mi, n], h [mi] (either pair
     may be None).  The problem must be feasible with a bounded optimum.
@@ -71,10 +206,12 @@ def solve_qp(P, q, A=None, b=None, G=None, h=None, *, tol=1e-8, max_iter=80, reg
     below tol; status "stalled" reports a stop on a step shorter than min_step
     (the reduced system has lost the accuracy to go further: the last iterate
     is returned with its residuals), "max_iter" one that ran out of
-    iterations."""
+    iterations.  `cache` (a dict) keeps the ordering and symbolic
+    factorization for the next solve with the same sparsity pattern."""
     q = np.asarray(q, dtype=np.float64)
     n = q.size
     P = sp.csr_matrix(P, shape=(n, n), dtype=np.float64)
+    P.sum_duplicates()
     A = sp.csr_matrix((0, n)) if A is None else sp.csr_matrix(A, dtype=np.float64)
     b = np.zeros(0) if b is None else np.asarray(b, dtype=np.float64)
     G = sp.csr_matrix((0, n)) if G is None else sp.csr_matrix(G, dtype=np.float64)
@@ -88,18 +225,31 @@ def solve_qp(P, q, A=None, b=None, G=None, h=None, *, tol=1e-8, max_iter=80, reg
     nq, nb, nh = max(1.0, np.abs(q).max(initial=0.0)), max(1.0, np.abs(b).max(initial=0.0)), \
         max(1.0, np.abs(h).max(initial=0.0))
 
-    def factor(D):
-        H = (P + Gt @ sp.diags(D) @ G).tocsr()
-        K0 = sp.bmat([[H, At], [A, sp.csr_matrix((me, me))]], format="csc")
-        Kr = (K0 + sp.diags(np.concatenate([np.full(n, reg), np.full(me, -reg)]))).tocsc()
-        return K0, spla.splu(Kr, permc_spec="MMD_AT_PLUS_A")
+    for M in (P, A, G):
+        M.sum_duplicates()
+        M.sort_indices()
+    key = _pattern_key(P, A, G) + repr(reg)
+    kkt = cache.get(key) if cache is not None else None
+    if kkt is None:
+        kkt = _Kkt(P, A, G, reg)
+        if cache is not None:
+            cache.clear()
+            cache[key] = kkt
+    kkt.set_values(P, A, G)
 
-    def solve(fac, r1, r2):
-        K0, lu = fac
+    def factor(D):
+        kkt.factor(D)
+        return D
+
+    def solve(D, r1, r2):
+        # K(D) without the regularization, applied for the refinement steps
+        def K0(v):
+            v1, v2 = v[:n], v[n:]
+            return np.concatenate([P @ v1 + Gt @ (D * (G @ v1)) + At @ v2, A @ v1])
         rhs = np.concatenate([r1, r2])
-        sol = lu.solve(rhs)
+        sol = kkt.solve(rhs)
         for _ in range(refine):
-            sol = sol + lu.solve(rhs - K0 @ sol)
+            sol = sol + kkt.solve(rhs - K0(sol))
         return sol[:n], sol[n:]
 
     # starting point: the least-squares point of the constraints with D = I,

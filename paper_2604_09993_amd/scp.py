@@ -457,6 +457,7 @@ class ScpDriver:
         self.w_px, self.w_ep = float(w_px), float(w_ep)
         self.hom = homotopy if homotopy is not None else DeltaHomotopy()
         self.qp_tol = qp_tol
+        self.qp_cache = {}     # ordering and symbolic factorization of the KKT pattern
         self.history: list[ScpIteration] = []
 
     def subproblem(self, z, delta):
@@ -467,7 +468,8 @@ class ScpDriver:
         t1 = time.perf_counter()
         sub = assemble(pb, z, tr, self.w_px, self.w_ep)
         t2 = time.perf_counter()
-        r = solve_qp(sub.P, sub.q, sub.A, sub.b, sub.G, sub.h, tol=self.qp_tol)
+        r = solve_qp(sub.P, sub.q, sub.A, sub.b, sub.G, sub.h, tol=self.qp_tol,
+                     cache=self.qp_cache)
         t3 = time.perf_counter()
         dzh = r.x[:sub.n_z]
         z_next = z + pb.zscale * dzh
