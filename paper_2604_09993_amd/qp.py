@@ -17,7 +17,8 @@ reduced quasi-definite system
     [ A                  -r I  ] [dy] = [r2],      D = diag(z / s),
 
 once and solves it twice (affine and corrected directions), with a few
-steps of iterative refinement against the unregularized matrix.  The
+steps of iterative refinement against the unregularized matrix.  The cost is scaled so that its largest coefficient
+is 1 (multipliers are returned unscaled).  The
 factorization is the native sparse LDL^T of libcis (cis_ldl_*) in a
 fill-reducing symmetric order (minimum degree on the pattern, taken from
 SciPy's SuperLU once per sparsity pattern); the pattern of the reduced
@@ -189,6 +190,10 @@ def _pattern_key(*mats):
     return h.hexdigest()
 
 
+D_MIN, D_MAX = 1e-24, 1e24   # bounds of the slack scaling z / s
+TINY = 1e-300                # floor of slacks and multipliers after a step
+
+
 def _max_step(v, dv):
     """Largest a in (0, 1] with v + a dv >= 0 (v > 0)."""
     neg = dv < 0.0
@@ -221,6 +226,11 @@ def solve_qp(P, q, A=None, b=None, G=None, h=None, *, tol=1e-8, max_iter=80, reg
         raise ValueError("inconsistent QP dimensions")
     A, b, sca = _row_scale(A, b)
     G, h, scg = _row_scale(G, h)
+    # cost scaling: the largest entry of P and q becomes 1, so that the
+    # multipliers (and the slack scaling z / s) stay near unit size
+    cs = max(np.abs(q).max(initial=0.0), np.abs(P.data).max(initial=0.0))
+    cs = 1.0 / cs if cs > 0.0 else 1.0
+    P, q = P * cs, q * cs
     At, Gt = A.T.tocsr(), G.T.tocsr()
     nq, nb, nh = max(1.0, np.abs(q).max(initial=0.0)), max(1.0, np.abs(b).max(initial=0.0)), \
         max(1.0, np.abs(h).max(initial=0.0))
@@ -280,8 +290,14 @@ def solve_qp(P, q, A=None, b=None, G=None, h=None, *, tol=1e-8, max_iter=80, reg
         if rd <= tol and rp <= tol and gap <= tol:
             status = "optimal"
             break
-        D = z / s if mi else np.zeros(0)
-        fac = factor(D)
+        # scaling of the slacks, bounded so that the reduced matrix stays
+        # finite when a slack or multiplier has reached the rounding level
+        D = np.clip(z / s, D_MIN, D_MAX) if mi else np.zeros(0)
+        try:
+            fac = factor(D)
+        except RuntimeError:
+            status = "stalled"
+            break
 
         def direction(r_c):
             dx, dy = solve(fac, -r_d - Gt @ (D * r_i - r_c / s), -r_p)
@@ -305,7 +321,10 @@ def solve_qp(P, q, A=None, b=None, G=None, h=None, *, tol=1e-8, max_iter=80, reg
             status = "stalled"
             break
         x, y, z, s = x + a * dx, y + a * dy, z + a * dz, s + a * ds
-    obj = 0.5 * float(x @ (P @ x)) + float(q @ x)
-    # undo the row scaling of the multipliers
-    return QPResult(x=x, y=y * sca, z=z * scg, s=s / scg if mi else s, status=status, iters=it,
-                    obj=obj, res_primal=float(rp), res_dual=float(rd), gap=float(gap))
+        if mi:
+            np.maximum(z, TINY, out=z)
+            np.maximum(s, TINY, out=s)
+    obj = (0.5 * float(x @ (P @ x)) + float(q @ x)) / cs
+    # undo the cost scaling and the row scaling of the multipliers
+    return QPResult(x=x, y=y * sca / cs, z=z * scg / cs, s=s / scg if mi else s, status=status,
+                    iters=it, obj=obj, res_primal=float(rp), res_dual=float(rd), gap=float(gap))
