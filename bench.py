@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="time the headline workload only (profiling runs)")
     ap.add_argument("--extra-steps", type=int, default=20)
+    ap.add_argument("--scp-max-iter", type=int, default=1500,
+                    help="iteration cap of the end-to-end SCP run on the monoped")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs every kernel on a single GPU "
@@ -716,24 +718,30 @@ def main():
         htr = scp.GpuTranscriber(hpb)
         htr(hpb.unpack(hz0), 1.0)                       # warm-up transcription
         hdrv = scp.ScpDriver(hpb, htr)
-        n_scp = max(10, args.extra_steps)
         t_scp = time.perf_counter()
-        hdrv.run(hz0, max_iter=n_scp)
+        hdrv.run(hz0, max_iter=args.scp_max_iter,
+                 callback=lambda rec, z: rec.j % 100 == 99 and progress(
+                     f"scp iteration {rec.j + 1}: delta {rec.delta:.3g}, J_px {rec.J_px:.2e}, "
+                     f"J_ep {rec.J_ep:.2e}"))
         t_scp = time.perf_counter() - t_scp
         hh = hdrv.history
         ms_it = 1e3 * t_scp / len(hh)
         extras["scp_monoped_N14_K10"] = {
             "value": len(hh) / t_scp, "unit": "SCP iterations/s", "ms_per_iteration": ms_it,
-            "iterations": len(hh),
+            "iterations": len(hh), "converged": bool(hdrv.hom.done()), "wall_s": t_scp,
+            "final": {"delta": hdrv.hom.delta[-1], "J_px": hh[-1].J_px, "J_ep": hh[-1].J_ep,
+                      "cost": hh[-1].cost},
+            "qp_status_counts": {st: sum(r.qp_status == st for r in hh)
+                                 for st in sorted({r.qp_status for r in hh})},
             "transcribe_ms": 1e3 * float(np.mean([r.t_transcribe for r in hh])),
             "assemble_ms": 1e3 * float(np.mean([r.t_assemble for r in hh])),
             "qp_solve_ms": 1e3 * float(np.mean([r.t_solve for r in hh])),
             "qp_iterations_mean": float(np.mean([r.qp_iters for r in hh])),
-            "J_ep_first_last": [hh[0].J_ep, hh[-1].J_ep], "delta_last": hh[-1].delta,
             "step": "transcription (cis_discretize over the node-doubled discontinuous hold + "
                     "cis_impact_linearize, host copies included), subproblem assembly, QP solve, "
                     "Alg. 1 update"}
-        progress(f"scp monoped: {len(hh)} iterations, {ms_it:.1f} ms/iteration "
+        progress(f"scp monoped: {len(hh)} iterations in {t_scp:.1f} s (converged "
+                 f"{extras['scp_monoped_N14_K10']['converged']}), {ms_it:.1f} ms/iteration "
                  f"(transcribe {extras['scp_monoped_N14_K10']['transcribe_ms']:.2f}, "
                  f"assemble {extras['scp_monoped_N14_K10']['assemble_ms']:.2f}, "
                  f"solve {extras['scp_monoped_N14_K10']['qp_solve_ms']:.2f} ms)")

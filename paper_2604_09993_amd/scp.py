@@ -61,6 +61,8 @@ class CitoProblem:
     s_max: float = 0.10
     eps_ctcs: float = 1e-4             # bound of the violation-state increment
     w_cost: float = 1.0                # weight of the squared scaled torques
+    mu: float = 1.0                    # friction coefficient (the experiments' value, Sec. VI)
+    e: float = 0.0                     # restitution (the experiments' value, Sec. VI)
     scales: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -71,7 +73,7 @@ class CitoProblem:
         self.NB = 2 * self.nx + 3 * self.nc          # node block
         self.IB = 2 * self.m + 1                      # interval block
         self.nz = (self.N + 1) * self.NB + self.N * self.IB
-        self.p = m.params()
+        self.p = m.params(mu=self.mu, e=self.e)
         sc = dict(q=1.0, v=2.0, y=1.0, phi=1.0, gam=1.0, tau=self.tau_max / 2.0,
                   jf=20.0, cf=20.0, s=0.05)
         sc.update(self.scales)

@@ -424,19 +424,18 @@ def standing_state(model: Model, x0: float, th0: float = 0.0, joint_angles=None,
 
 def scp_initial_guess(model: Model, N: int, x_init, x_final, s0: float,
                       rng: np.random.Generator, force_range=(0.0, 20.0),
-                      impulse_range=(0.0, 1.0)):
+                      impulse_range=(0.0, 1.0), mu: float = 1.0):
     """Naive starting point of the contact-implicit SCP (the initialization of
     the paper's experiments, Sec. VI): node poses interpolated linearly between
     the boundary states, velocities, integral states, joint torques and joint
-    forces zero, contact forces and impulses drawn inside the friction cone
-    (lambda_n ~ U(force_range), lambda_t+ + lambda_t- <= mu lambda_n;
+    forces zero, contact forces and impulses drawn inside the friction cone of
+    coefficient mu (lambda_n ~ U(force_range), lambda_t+ + lambda_t- <= mu lambda_n;
     Phi_n ~ U(impulse_range), |Phi_t| <= mu Phi_n), multipliers Gamma ~ U(0, 1).
 
     Returns node-major Xp, Xm [N+1, nx], Phi [N+1, 2 nc], Gamma [N+1, nc],
     interval controls Ua, Ub [N, m] (discontinuous first-order hold) and S [N].
     """
     nb, nj, nc, nx, m = model.nb, model.nj, model.nc, model.nx, model.m
-    mu = model.params()[0]
     w = np.linspace(0.0, 1.0, N + 1)[:, None]
     X = np.zeros((N + 1, nx))
     X[:, :3 * nb] = (1.0 - w) * np.asarray(x_init)[:3 * nb] + w * np.asarray(x_final)[:3 * nb]
