@@ -47,3 +47,24 @@ def test_scp_iterations_with_gpu_transcription_match_the_oracle():
     assert dg == do
     for a, b in zip(zg, zo):
         assert np.max(np.abs(a - b) / pb.zscale) <= 1e-6
+
+
+def test_scp_monoped_converges_to_a_solution_of_the_relaxed_problem():
+    """Alg. 1 to its own termination with GPU transcription; the final iterate
+    is then checked with the oracle's nonlinear residuals at the delta of the
+    last subproblem: dynamics defects and node equalities vanish, Theta and
+    Psi hold, and the boundary states are met."""
+    pb, z0 = _problem()
+    print("scp hopper N=14 K=10 rk4 to termination", flush=True)
+    drv = scp.ScpDriver(pb, scp.GpuTranscriber(pb))
+    z = drv.run(z0, max_iter=1500)
+    assert drv.hom.done() and len(drv.history) < 1500
+    assert drv.hom.delta[-1] <= drv.hom.delta_min
+    delta = drv.hom.delta[-2]
+    r = oracle_transcriber(pb)(pb.unpack(z), delta)
+    assert np.abs(r["d"] / pb.xscale).max() <= 1e-6
+    assert np.abs(r["G"] / pb.xscale).max() <= 1e-6
+    assert np.max(r["Theta"]) <= 1e-6 and np.max(r["Psi"]) <= 1e-6
+    v = pb.unpack(z)
+    assert np.abs(v["Xm"][0] - pb.x_init).max() <= 1e-9
+    assert np.abs(v["Xp"][-1][:2 * pb.nq] - pb.x_final[:2 * pb.nq]).max() <= 1e-9
