@@ -215,18 +215,23 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
 // k_tangent: one classical RK4 stage of a leg wave (derivative from
 // tangent_split_rhs, then the RK4 combination).
 // ---------------------------------------------------------------------------
-template <class T, class TP, int ST, bool FORCE>
+template <class T, class TP, int ST, bool FORCE, bool LDSF>
 __device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* __restrict__ cr,
                                                     const T* __restrict__ lr,
                                                     const T* __restrict__ rs, T* xch, int leg,
                                                     int lane, T tau, T wbm, T wbp,
                                                     const unsigned (&off)[3 * (TP::D + 1)],
-                                                    unsigned offcc) {
+                                                    unsigned offcc, T* fbuf,
+                                                    const T* rs_next) {
     constexpr int LB = TP::D + 1;
+    constexpr int FBUF = SplitRec<TP>::FBUF;
     const T s = cr[0], h = cr[1], h6 = cr[2];
     T kv[3 * LB], kcc, kct;
-    tangent_split_rhs<T, TP, FORCE>(z.zs, cr, lr, rs, xch, leg, lane, tau, wbm, wbp, off, offcc,
-                                    kv, kcc, kct);
+    // forcing regions alternate between the two LDS buffers stage by stage
+    // (4 stages per substep, so the parity of the stage is that of ST)
+    tangent_split_rhs<T, TP, FORCE, LDSF>(z.zs, cr, lr, rs, xch, leg, lane, tau, wbm, wbp, off,
+                                          offcc, kv, kcc, kct, fbuf + (ST & 1) * FBUF, rs_next,
+                                          fbuf + ((ST + 1) & 1) * FBUF);
     // classical RK4 combination (stage ST known at compile time)
     constexpr int WK = (ST == 0 || ST == 3) ? 1 : 2;
     const T an = (ST == 2) ? h : T(0.5) * h;
@@ -255,12 +260,12 @@ __device__ __forceinline__ void tangent_split_stage(TanLane<T, TP>& z, const T* 
     }
 }
 
-template <class T, class TP, bool FORCE>
+template <class T, class TP, bool FORCE, bool LDSF>
 __device__ __forceinline__ void tangent_split_loop(TanLane<T, TP>& z, const T* __restrict__ cr,
                                                    const T* __restrict__ rec0, T* xch, int leg,
                                                    int lane, int K, T wbm, T wbp,
                                                    const unsigned (&off)[3 * (TP::D + 1)],
-                                                   unsigned offcc) {
+                                                   unsigned offcc, T* fbuf) {
     using R = CoefRec<TP>;
     constexpr int LEGB = R::LEGB, GL = R::GLOBAL, L = TP::L;
     const T Kt = T(K);
@@ -270,17 +275,19 @@ __device__ __forceinline__ void tangent_split_loop(TanLane<T, TP>& z, const T* _
         const T tau0 = jt / Kt, tauh = (jt + T(0.5)) / Kt, tau1 = (jt + T(1)) / Kt;
         T* x0 = xch;
         T* x1 = xch + L * 64;
-        tangent_split_stage<T, TP, 0, FORCE>(z, cr, rs + leg * LEGB, rs, x0, leg, lane, tau0,
-                                             wbm, wbp, off, offcc);
+        tangent_split_stage<T, TP, 0, FORCE, LDSF>(z, cr, rs + leg * LEGB, rs, x0, leg, lane,
+                                                   tau0, wbm, wbp, off, offcc, fbuf, rs + GL);
         rs += GL;
-        tangent_split_stage<T, TP, 1, FORCE>(z, cr, rs + leg * LEGB, rs, x1, leg, lane, tauh,
-                                             wbm, wbp, off, offcc);
+        tangent_split_stage<T, TP, 1, FORCE, LDSF>(z, cr, rs + leg * LEGB, rs, x1, leg, lane,
+                                                   tauh, wbm, wbp, off, offcc, fbuf, rs + GL);
         rs += GL;
-        tangent_split_stage<T, TP, 2, FORCE>(z, cr, rs + leg * LEGB, rs, x0, leg, lane, tauh,
-                                             wbm, wbp, off, offcc);
+        tangent_split_stage<T, TP, 2, FORCE, LDSF>(z, cr, rs + leg * LEGB, rs, x0, leg, lane,
+                                                   tauh, wbm, wbp, off, offcc, fbuf, rs + GL);
         rs += GL;
-        tangent_split_stage<T, TP, 3, FORCE>(z, cr, rs + leg * LEGB, rs, x1, leg, lane, tau1,
-                                             wbm, wbp, off, offcc);
+        // the last stage of the interval copies its own region (never read)
+        tangent_split_stage<T, TP, 3, FORCE, LDSF>(z, cr, rs + leg * LEGB, rs, x1, leg, lane,
+                                                   tau1, wbm, wbp, off, offcc, fbuf,
+                                                   j + 1 < K ? rs + GL : rs);
         rs += GL;
     }
 }
@@ -288,7 +295,7 @@ __device__ __forceinline__ void tangent_split_loop(TanLane<T, TP>& z, const T* _
 // Columns [64 cb, 64 cb + 64) of interval k, wave `leg` (all waves of the block).
 template <class T, class TP>
 __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __restrict__ rec,
-                                             const int k, const int cb, T* xch) {
+                                             const int k, const int cb, T* xch, T* fbuf) {
     constexpr int D = TP::D, LB = D + 1;
     using SR = SplitRec<TP>;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -306,12 +313,23 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
     const T* cr = rec;
     const T* rec0 = rec + SR::CRS;
     // blocks holding no B-/B+ column skip the forcing code (uniform branch)
-    if ((cb + 1) * 64 <= TP::NX)
-        tangent_split_loop<T, TP, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
-                                         tc.offcc);
-    else
-        tangent_split_loop<T, TP, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
-                                        tc.offcc);
+    if ((cb + 1) * 64 <= TP::NX) {
+        tangent_split_loop<T, TP, false, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                                tc.offcc, fbuf);
+    } else if constexpr (TP::L > 1) {
+        // forcing from LDS: offsets from the start of the forcing region
+        constexpr unsigned base = sizeof(T) * CoefRec<TP>::JB;
+        unsigned offl[3 * LB];
+#pragma unroll
+        for (int r = 0; r < 3 * LB; ++r) offl[r] = tc.off[r] - base;
+        // stage 0's region, ordered before its reads by stage 0's barrier
+        fbuf[forcing_slot<TP>(leg, lane)] = forcing_load<T, TP>(rec0, leg, lane);
+        tangent_split_loop<T, TP, true, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, offl,
+                                              tc.offcc - base, fbuf);
+    } else {
+        tangent_split_loop<T, TP, true, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                               tc.offcc, fbuf);
+    }
     tangent_store<T, TP>(a, k, leg, lane, tc, z.zb, z.ycc, z.yct, xch);
 }
 
@@ -329,9 +347,11 @@ template <class T, class TP, int WAVES>
 __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu(WAVES)))
     k_tangent(FwdArgs<T> a, const T* __restrict__ rec) {
     __shared__ T xch[2 * TP::L * 64];
+    __shared__ T fbuf[2 * SplitRec<TP>::FBUF];
     int item, cb;
     unit_item(xcd_slot(blockIdx.x, gridDim.x), a.N, SplitRec<TP>::NBLK, item, cb);
-    tangent_item<T, TP>(a, rec + (int64_t)item * SplitRec<TP>::per_interval(a.K), item, cb, xch);
+    tangent_item<T, TP>(a, rec + (int64_t)item * SplitRec<TP>::per_interval(a.K), item, cb, xch,
+                        fbuf);
 }
 
 // Batches: one launch per model over the work list; rec_off[item] is the
@@ -352,11 +372,12 @@ __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu
     k_tangent_batch(BatchArgs<FwdArgs<T>> b, const T* __restrict__ rec,
                     const int64_t* __restrict__ rec_off) {
     __shared__ T xch[2 * TP::L * 64];
+    __shared__ T fbuf[2 * SplitRec<TP>::FBUF];
     int item, cb;
     unit_item(xcd_slot(blockIdx.x, gridDim.x), b.n_items, SplitRec<TP>::NBLK, item, cb);
     const int2 it = b.items[item];
     const FwdArgs<T> a = b.descs[it.x];
-    tangent_item<T, TP>(a, rec + rec_off[item], it.y, cb, xch);
+    tangent_item<T, TP>(a, rec + rec_off[item], it.y, cb, xch, fbuf);
 }
 
 // ---------------------------------------------------------------------------

@@ -25,6 +25,10 @@ struct SplitRec {
     }
     static constexpr int NCOLT = TP::NX + 2 * TP::M;      // tangent columns of k_tangent
     static constexpr int NBLK = (NCOLT + 63) / 64;        // column blocks of 64 lanes
+    // forcing region of a stage record: [JB, GLOBAL) (joint and contact
+    // blocks, the zero entry), staged in LDS by k_tangent in buffers of FBUF
+    static constexpr int FREG = GLOBAL - CoefRec<TP>::JB;
+    static constexpr int FBUF = 64 * TP::L;
 };
 
 // Constant entries of a compact record (joint blocks) and its zero.
@@ -68,6 +72,23 @@ __device__ __forceinline__ T buffer_elem(__amdgpu_buffer_rsrc_t r, unsigned off)
 }
 
 
+// Forcing region of a stage record (elements [JB, GLOBAL): joint and contact
+// blocks, the zero entry) staged in LDS one stage ahead: thread t of the
+// workgroup (leg wave `leg`, lane `lane`) carries element t of the region
+// (index clamped into the region, so every thread loads and stores without a
+// branch; the LDS buffers are padded to 64 L elements).
+template <class TP>
+__device__ __forceinline__ int forcing_slot(int leg, int lane) {
+    return leg * 64 + lane;
+}
+
+template <class T, class TP>
+__device__ __forceinline__ T forcing_load(const T* rs, int leg, int lane) {
+    constexpr int FREG = SplitRec<TP>::FREG;
+    const int c = forcing_slot<TP>(leg, lane);
+    return rs[CoefRec<TP>::JB + (c < FREG ? c : FREG - 1)];
+}
+
 // Derivative of the lane's column on its rows at the stage input zs (local
 // body lb = 0 the torso, lb = 1..D the links of leg `leg`; rows zs[3 lb + k]
 // (q) and zs[3 LB + 3 lb + k] (v)): kv for the velocity rows, kcc for the
@@ -75,7 +96,14 @@ __device__ __forceinline__ T buffer_elem(__amdgpu_buffer_rsrc_t r, unsigned off)
 // row (the pose rows are s zs_v).  lr: the wave's leg block of the stage
 // record; rs: the whole stage record (forcing entries, read per lane at
 // offsets off[], offcc).  Contains one workgroup barrier when L > 1.
-template <class T, class TP, bool FORCE>
+//
+// LDSF (L > 1 only): the forcing entries come from this stage's forcing
+// region in LDS (fcur; off[] and offcc are then byte offsets from the
+// region's start), stored there during the previous stage; this stage loads
+// its thread's element of the next stage's region (rs_next) at its start and
+// stores it to fnext after its barrier (rs_next = rs for the last stage:
+// loaded and stored, never read).
+template <class T, class TP, bool FORCE, bool LDSF = false>
 __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)],
                                                   const T* __restrict__ cr,
                                                   const T* __restrict__ lr,
@@ -83,8 +111,13 @@ __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)]
                                                   int lane, T tau, T wbm, T wbp,
                                                   const unsigned (&off)[3 * (TP::D + 1)],
                                                   unsigned offcc, T (&kv)[3 * (TP::D + 1)],
-                                                  T& kcc, T& kct) {
+                                                  T& kcc, T& kct, const T* fcur = nullptr,
+                                                  const T* rs_next = nullptr,
+                                                  T* fnext = nullptr) {
     constexpr int LB = TP::D + 1, D = TP::D, L = TP::L;
+    static_assert(!LDSF || L > 1, "the LDS forcing path rides on the hip-exchange barrier");
+    T fpre = T(0);
+    if constexpr (FORCE && LDSF) fpre = forcing_load<T, TP>(rs_next, leg, lane);
 #define ZQ(lb, k) zs[3 * (lb) + (k)]
 #define ZV(lb, k) zs[3 * LB + 3 * (lb) + (k)]
     // forcing of B-/B+ columns (zero offsets and weights elsewhere): issued
@@ -92,7 +125,7 @@ __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)]
     // record (a scalar resource, so no per-lane 64-bit addresses)
     T g[3 * LB];
     T gcc = T(0);
-    if constexpr (FORCE) {
+    if constexpr (FORCE && !LDSF) {
         const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<T*>(rs), (short)0, (int)(CoefRec<TP>::GLOBAL * sizeof(T)), 0x00020000);
 #pragma unroll
@@ -105,6 +138,9 @@ __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)]
     if constexpr (L > 1) {
         xch[leg * 64 + lane] = hip;
         __syncthreads();
+        // every wave has passed its reads of the previous stage's region,
+        // which the next stage's region replaces
+        if constexpr (FORCE && LDSF) fnext[forcing_slot<TP>(leg, lane)] = fpre;
         hip = xch[lane];
 #pragma unroll
         for (int l = 1; l < L; ++l) hip += xch[l * 64 + lane];
@@ -141,6 +177,13 @@ __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)]
         kcc = ct[C_EPX] * dPx + ct[C_EPY] * dPy + ct[C_EXD] * ZV(lb, 0) + ct[C_EYD] * ZV(lb, 1) +
               ct[C_EOM] * ZV(lb, 2) + ct[C_ETH] * ZQ(lb, 2);
         kct += ct[C_ZPX] * dPx + ct[C_ZPY] * dPy;
+    }
+    if constexpr (FORCE && LDSF) {
+        // read where used (after this stage's barrier)
+        const char* fb = (const char*)fcur;
+#pragma unroll
+        for (int r = 0; r < 3 * LB; ++r) g[r] = *(const T*)(fb + off[r]);
+        gcc = *(const T*)(fb + offcc);
     }
     if constexpr (FORCE) {
         const T wB = wbm * (T(1) - tau) + wbp * tau;
