@@ -393,18 +393,19 @@ __device__ __forceinline__ void rkf_combine(T& za, T& zs, T& p2, T& p3, T& p4, T
 static_assert(Fehlberg45::b(1) == 0.0 && Fehlberg45::b(5) == 0.0,
               "the tangent stages assume the propagated weights of Fehlberg's pair");
 
-template <class T, class TP, int I, bool FORCE>
+template <class T, class TP, int I, bool FORCE, bool LDSF>
 __device__ __forceinline__ void tangent_rkf_stage(RkfLane<T, TP>& z, const T* __restrict__ cr,
                                                   const T* __restrict__ lr,
                                                   const T* __restrict__ rs, T* xch, int leg,
                                                   int lane, T tau, T wbm, T wbp,
                                                   const unsigned (&off)[3 * (TP::D + 1)],
-                                                  unsigned offcc) {
+                                                  unsigned offcc, const T* fcur,
+                                                  const T* rs_next, T* fnext) {
     constexpr int LB = TP::D + 1;
     const T s = cr[0], h = cr[1];
     T kv[3 * LB], kcc, kct;
-    tangent_split_rhs<T, TP, FORCE>(z.zs, cr, lr, rs, xch, leg, lane, tau, wbm, wbp, off, offcc,
-                                    kv, kcc, kct);
+    tangent_split_rhs<T, TP, FORCE, LDSF>(z.zs, cr, lr, rs, xch, leg, lane, tau, wbm, wbp, off,
+                                          offcc, kv, kcc, kct, fcur, rs_next, fnext);
 #pragma unroll
     for (int r = 0; r < 3 * LB; ++r) {
         const T hk = h * (s * z.zs[3 * LB + r]);
@@ -421,26 +422,30 @@ __device__ __forceinline__ void tangent_rkf_stage(RkfLane<T, TP>& z, const T* __
     }
 }
 
-template <class T, class TP, bool FORCE>
+template <class T, class TP, bool FORCE, bool LDSF>
 __device__ __forceinline__ void tangent_rkf_loop(RkfLane<T, TP>& z, const T* __restrict__ cr,
                                                  const T* __restrict__ rec0, T* xch, int leg,
                                                  int lane, int K, T wbm, T wbp,
                                                  const unsigned (&off)[3 * (TP::D + 1)],
-                                                 unsigned offcc) {
+                                                 unsigned offcc, T* fbuf) {
     using R = CoefRec<TP>;
-    constexpr int LEGB = R::LEGB, GL = R::GLOBAL, L = TP::L;
+    constexpr int LEGB = R::LEGB, GL = R::GLOBAL, L = TP::L, FBUF = SplitRec<TP>::FBUF;
     const T Kt = T(K);
     const T* rs = rec0;
     T* xb[2] = {xch, xch + L * 64};
-    int par = 0;   // exchange buffer of the stage (alternates stage by stage)
+    T* fb[2] = {fbuf, fbuf + FBUF};
+    int par = 0;   // exchange and forcing buffers of the stage (alternate stage by stage)
     for (int j = 0; j < K; ++j) {
         const T jt = T(j);
         [&]<int... Is>(std::integer_sequence<int, Is...>) {
             ([&] {
                 constexpr int I = Is;
-                tangent_rkf_stage<T, TP, I, FORCE>(z, cr, rs + leg * LEGB, rs, xb[par], leg, lane,
-                                                   (jt + T(RKF::c(I))) / Kt, wbm, wbp, off,
-                                                   offcc);
+                // the interval's last stage copies its own forcing region (never read)
+                const T* rsn = (I == RKF::R - 1 && j + 1 == K) ? rs : rs + GL;
+                tangent_rkf_stage<T, TP, I, FORCE, LDSF>(z, cr, rs + leg * LEGB, rs, xb[par], leg,
+                                                         lane, (jt + T(RKF::c(I))) / Kt, wbm,
+                                                         wbp, off, offcc, fb[par], rsn,
+                                                         fb[par ^ 1]);
                 rs += GL;
                 par ^= 1;
             }(), ...);
@@ -450,7 +455,7 @@ __device__ __forceinline__ void tangent_rkf_loop(RkfLane<T, TP>& z, const T* __r
 
 template <class T, class TP>
 __device__ __forceinline__ void rkf_tangent_item(const FwdArgs<T>& a, const T* __restrict__ rec,
-                                                 const int k, const int cb, T* xch) {
+                                                 const int k, const int cb, T* xch, T* fbuf) {
     constexpr int LB = TP::D + 1;
     using SR = SplitRec<TP>;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -464,12 +469,23 @@ __device__ __forceinline__ void rkf_tangent_item(const FwdArgs<T>& a, const T* _
     z.yct = T(0);
     const T* cr = rec;
     const T* rec0 = rec + SR::CRS;
-    if ((cb + 1) * 64 <= TP::NX)
-        tangent_rkf_loop<T, TP, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
-                                       tc.offcc);
-    else
-        tangent_rkf_loop<T, TP, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
-                                      tc.offcc);
+    if ((cb + 1) * 64 <= TP::NX) {
+        tangent_rkf_loop<T, TP, false, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                              tc.offcc, fbuf);
+    } else if constexpr (TP::L > 1) {
+        // forcing from LDS (offsets from the start of the forcing region),
+        // stage 0's region stored before the first barrier
+        constexpr unsigned base = sizeof(T) * CoefRec<TP>::JB;
+        unsigned offl[3 * LB];
+#pragma unroll
+        for (int r = 0; r < 3 * LB; ++r) offl[r] = tc.off[r] - base;
+        fbuf[forcing_slot<TP>(leg, lane)] = forcing_load<T, TP>(rec0, leg, lane);
+        tangent_rkf_loop<T, TP, true, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, offl,
+                                            tc.offcc - base, fbuf);
+    } else {
+        tangent_rkf_loop<T, TP, true, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                             tc.offcc, fbuf);
+    }
     tangent_store<T, TP>(a, k, leg, lane, tc, z.za, z.ycc, z.yct, xch);
 }
 
@@ -487,10 +503,11 @@ template <class T, class TP, int WAVES>
 __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu(WAVES)))
     k_rkf_tan(FwdArgs<T> a, const T* __restrict__ rec) {
     __shared__ T xch[2 * TP::L * 64];
+    __shared__ T fbuf[2 * SplitRec<TP>::FBUF];
     int item, cb;
     unit_item(xcd_slot(blockIdx.x, gridDim.x), a.N, SplitRec<TP>::NBLK, item, cb);
     rkf_tangent_item<T, TP>(a, rec + (int64_t)item * SplitRec<TP>::per_interval(a.K, RKF::R),
-                            item, cb, xch);
+                            item, cb, xch, fbuf);
 }
 
 // ---------------------------------------------------------------------------
