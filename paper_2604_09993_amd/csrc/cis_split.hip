@@ -313,19 +313,19 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
     const T* cr = rec;
     const T* rec0 = rec + SR::CRS;
     // blocks holding no B-/B+ column skip the forcing code (uniform branch)
+    if constexpr (TP::L > 1) {
+        // every block stages the records (in blocks without B-/B+ columns
+        // only to bring the leg blocks into the L2 cache a stage early)
+        stage_store<T, TP>(fbuf, stage_load<T, TP>(rec0, leg, lane), leg, lane);
+    }
     if ((cb + 1) * 64 <= TP::NX) {
-        tangent_split_loop<T, TP, false, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
-                                                tc.offcc, fbuf);
+        tangent_split_loop<T, TP, false, (TP::L > 1)>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp,
+                                                      tc.off, tc.offcc, fbuf);
     } else if constexpr (TP::L > 1) {
-        // forcing from LDS: offsets from the start of the forcing region
-        constexpr unsigned base = sizeof(T) * CoefRec<TP>::JB;
-        unsigned offl[3 * LB];
-#pragma unroll
-        for (int r = 0; r < 3 * LB; ++r) offl[r] = tc.off[r] - base;
-        // stage 0's region, ordered before its reads by stage 0's barrier
-        fbuf[forcing_slot<TP>(leg, lane)] = forcing_load<T, TP>(rec0, leg, lane);
-        tangent_split_loop<T, TP, true, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, offl,
-                                              tc.offcc - base, fbuf);
+        // forcing from the stage records staged in LDS (stage 0's record
+        // stored above, ordered before its reads by stage 0's barrier)
+        tangent_split_loop<T, TP, true, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                              tc.offcc, fbuf);
     } else {
         tangent_split_loop<T, TP, true, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
                                                tc.offcc, fbuf);

@@ -25,10 +25,10 @@ struct SplitRec {
     }
     static constexpr int NCOLT = TP::NX + 2 * TP::M;      // tangent columns of k_tangent
     static constexpr int NBLK = (NCOLT + 63) / 64;        // column blocks of 64 lanes
-    // forcing region of a stage record: [JB, GLOBAL) (joint and contact
-    // blocks, the zero entry), staged in LDS by k_tangent in buffers of FBUF
-    static constexpr int FREG = GLOBAL - CoefRec<TP>::JB;
-    static constexpr int FBUF = 64 * TP::L;
+    // a stage record staged in LDS by the tangent kernels: SPT elements per
+    // thread of the L-wave workgroup, buffers of FBUF elements
+    static constexpr int SPT = (GLOBAL + 64 * TP::L - 1) / (64 * TP::L);
+    static constexpr int FBUF = SPT * 64 * TP::L;
 };
 
 // Constant entries of a compact record (joint blocks) and its zero.
@@ -72,21 +72,35 @@ __device__ __forceinline__ T buffer_elem(__amdgpu_buffer_rsrc_t r, unsigned off)
 }
 
 
-// Forcing region of a stage record (elements [JB, GLOBAL): joint and contact
-// blocks, the zero entry) staged in LDS one stage ahead: thread t of the
-// workgroup (leg wave `leg`, lane `lane`) carries element t of the region
-// (index clamped into the region, so every thread loads and stores without a
-// branch; the LDS buffers are padded to 64 L elements).
-template <class TP>
-__device__ __forceinline__ int forcing_slot(int leg, int lane) {
-    return leg * 64 + lane;
+// A stage record staged in LDS one stage ahead: thread t of the workgroup
+// (leg wave `leg`, lane `lane`) carries elements t + 64 L e, e < SPT, of the
+// record (indices clamped into the record, so every thread loads and stores
+// without a branch; the buffers are padded to FBUF elements).  The forcing
+// entries are read from the copy; the same loads bring the leg blocks, which
+// the leg waves read with scalar loads, into the L2 cache a stage early.
+template <class T, class TP>
+struct StagedRec {
+    T v[SplitRec<TP>::SPT];
+};
+
+template <class T, class TP>
+__device__ __forceinline__ StagedRec<T, TP> stage_load(const T* rs, int leg, int lane) {
+    constexpr int GL = CoefRec<TP>::GLOBAL, NT = 64 * TP::L;
+    StagedRec<T, TP> r;
+#pragma unroll
+    for (int e = 0; e < SplitRec<TP>::SPT; ++e) {
+        const int c = e * NT + leg * 64 + lane;
+        r.v[e] = rs[c < GL ? c : GL - 1];
+    }
+    return r;
 }
 
 template <class T, class TP>
-__device__ __forceinline__ T forcing_load(const T* rs, int leg, int lane) {
-    constexpr int FREG = SplitRec<TP>::FREG;
-    const int c = forcing_slot<TP>(leg, lane);
-    return rs[CoefRec<TP>::JB + (c < FREG ? c : FREG - 1)];
+__device__ __forceinline__ void stage_store(T* lbuf, const StagedRec<T, TP>& r, int leg,
+                                            int lane) {
+    constexpr int NT = 64 * TP::L;
+#pragma unroll
+    for (int e = 0; e < SplitRec<TP>::SPT; ++e) lbuf[e * NT + leg * 64 + lane] = r.v[e];
 }
 
 // Derivative of the lane's column on its rows at the stage input zs (local
@@ -97,12 +111,12 @@ __device__ __forceinline__ T forcing_load(const T* rs, int leg, int lane) {
 // record; rs: the whole stage record (forcing entries, read per lane at
 // offsets off[], offcc).  Contains one workgroup barrier when L > 1.
 //
-// LDSF (L > 1 only): the forcing entries come from this stage's forcing
-// region in LDS (fcur; off[] and offcc are then byte offsets from the
-// region's start), stored there during the previous stage; this stage loads
-// its thread's element of the next stage's region (rs_next) at its start and
-// stores it to fnext after its barrier (rs_next = rs for the last stage:
-// loaded and stored, never read).
+// LDSF (L > 1 only): the forcing entries come from this stage's record
+// staged in LDS (fcur, the same byte offsets as in the record), stored there
+// during the previous stage; this stage loads its thread's elements of the
+// next stage's record (rs_next) at its start and stores them to fnext after
+// its barrier (rs_next = rs for the last stage: loaded and stored, never
+// read).
 template <class T, class TP, bool FORCE, bool LDSF = false>
 __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)],
                                                   const T* __restrict__ cr,
@@ -116,8 +130,8 @@ __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)]
                                                   T* fnext = nullptr) {
     constexpr int LB = TP::D + 1, D = TP::D, L = TP::L;
     static_assert(!LDSF || L > 1, "the LDS forcing path rides on the hip-exchange barrier");
-    T fpre = T(0);
-    if constexpr (FORCE && LDSF) fpre = forcing_load<T, TP>(rs_next, leg, lane);
+    StagedRec<T, TP> fpre;
+    if constexpr (LDSF) fpre = stage_load<T, TP>(rs_next, leg, lane);
 #define ZQ(lb, k) zs[3 * (lb) + (k)]
 #define ZV(lb, k) zs[3 * LB + 3 * (lb) + (k)]
     // forcing of B-/B+ columns (zero offsets and weights elsewhere): issued
@@ -140,7 +154,7 @@ __device__ __forceinline__ void tangent_split_rhs(const T (&zs)[6 * (TP::D + 1)]
         __syncthreads();
         // every wave has passed its reads of the previous stage's region,
         // which the next stage's region replaces
-        if constexpr (FORCE && LDSF) fnext[forcing_slot<TP>(leg, lane)] = fpre;
+        if constexpr (LDSF) stage_store<T, TP>(fnext, fpre, leg, lane);
         hip = xch[lane];
 #pragma unroll
         for (int l = 1; l < L; ++l) hip += xch[l * 64 + lane];
