@@ -440,14 +440,33 @@ struct PLane {
     double yc[5];
 };
 
+// Threads of a tangent workgroup and the elements of a stage record each of
+// them loads one stage ahead (into the LDS area `sink`, never read: the loads
+// bring the record, which the leg waves then read with scalar loads, into the
+// L2 cache before it is needed).
+template <class TP>
+struct PWarm {
+    static constexpr int NT = 64 * TP::L;
+    static constexpr int PW = (PRec<TP>::STAGE + NT - 1) / NT;
+};
+
 template <class TP>
 __device__ __forceinline__ void paper_tangent_stage(PLane<TP>& z, const double* __restrict__ hd,
                                                     const double* __restrict__ sr, double* xch,
                                                     int leg, int lane, int st, double tau,
                                                     double wbm, double wbp, int ctrl,
-                                                    double fsel) {
+                                                    double fsel,
+                                                    const double* __restrict__ sr_next,
+                                                    double* sink) {
     constexpr int D = TP::D, L = TP::L, LB = TP::LB, NJ = TP::NJ, NJ2 = TP::NJ2, NQ = TP::NQ;
     using R = PRec<TP>;
+    constexpr int NT = PWarm<TP>::NT, PW = PWarm<TP>::PW;
+    double warm[PW];
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+        const int c = e * NT + leg * 64 + lane;
+        warm[e] = sr_next[c < R::STAGE ? c : R::STAGE - 1];
+    }
     const double s = hd[0], h = hd[1], h6 = hd[2];
     const double* minv = hd + 8;
     const double* kd = hd + 8 + NQ;
@@ -508,6 +527,8 @@ __device__ __forceinline__ void paper_tangent_stage(PLane<TP>& z, const double* 
     } else {
         u[2] += hip;
     }
+#pragma unroll
+    for (int e = 0; e < PW; ++e) sink[e * NT + leg * 64 + lane] = warm[e];
     // ---- b on the leg's joints: grad h M^-1 u + dgrad_h v' + dc ----
     double y[3 * LB];
 #pragma unroll
@@ -626,6 +647,7 @@ __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu
     constexpr int NX = TP::NX, NC = TP::NC;
     using R = PRec<TP>;
     __shared__ double xch[(TP::L + 2 * TP::NJ) * 64];
+    __shared__ double sink[PWarm<TP>::PW * PWarm<TP>::NT];
     int k, cb;
     unit_item(xcd_slot(blockIdx.x, gridDim.x), a.N, TP::NBLK, k, cb);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -659,9 +681,13 @@ __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu
     for (int t = 0; t < 4 * a.K; ++t) {
         const int st = t & 3, j = t >> 2;
         const double tau = (double(j) + (st == 0 ? 0.0 : (st == 3 ? 1.0 : 0.5))) * h;
-        paper_tangent_stage<TP>(z, hd, hd + R::HDR + (int64_t)t * R::STAGE, xch, leg, lane, st,
-                                tau, wbm, wbp, ctrl, fsel);
+        const double* sr = hd + R::HDR + (int64_t)t * R::STAGE;
+        paper_tangent_stage<TP>(z, hd, sr, xch, leg, lane, st, tau, wbm, wbp, ctrl, fsel,
+                                t + 1 < 4 * a.K ? sr + R::STAGE : sr, sink);
     }
+    // the warm-up copies are never read; a read on a path that never runs
+    // (K >= 1 is checked on the host) keeps their stores
+    if (a.K <= 0) xch[tid] = sink[tid];
     // violation row: the legs' shares in leg order
     double yct = z.yc[4];
     if constexpr (L > 1) {

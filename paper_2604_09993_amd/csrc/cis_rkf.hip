@@ -469,19 +469,19 @@ __device__ __forceinline__ void rkf_tangent_item(const FwdArgs<T>& a, const T* _
     z.yct = T(0);
     const T* cr = rec;
     const T* rec0 = rec + SR::CRS;
+    if constexpr (TP::L > 1) {
+        // every block stages the records (in blocks without B-/B+ columns
+        // only to bring the leg blocks into the L2 cache a stage early)
+        stage_store<T, TP>(fbuf, stage_load<T, TP>(rec0, leg, lane), leg, lane);
+    }
     if ((cb + 1) * 64 <= TP::NX) {
-        tangent_rkf_loop<T, TP, false, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
-                                              tc.offcc, fbuf);
+        tangent_rkf_loop<T, TP, false, (TP::L > 1)>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp,
+                                                    tc.off, tc.offcc, fbuf);
     } else if constexpr (TP::L > 1) {
-        // forcing from LDS (offsets from the start of the forcing region),
-        // stage 0's region stored before the first barrier
-        constexpr unsigned base = sizeof(T) * CoefRec<TP>::JB;
-        unsigned offl[3 * LB];
-#pragma unroll
-        for (int r = 0; r < 3 * LB; ++r) offl[r] = tc.off[r] - base;
-        fbuf[forcing_slot<TP>(leg, lane)] = forcing_load<T, TP>(rec0, leg, lane);
-        tangent_rkf_loop<T, TP, true, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, offl,
-                                            tc.offcc - base, fbuf);
+        // forcing from the stage records staged in LDS (stage 0's record
+        // stored above, ordered before its reads by stage 0's barrier)
+        tangent_rkf_loop<T, TP, true, true>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
+                                            tc.offcc, fbuf);
     } else {
         tangent_rkf_loop<T, TP, true, false>(z, cr, rec0, xch, leg, lane, a.K, wbm, wbp, tc.off,
                                              tc.offcc, fbuf);
