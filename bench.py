@@ -601,7 +601,22 @@ def main():
                            args.extra_steps, 2)
         check_adjoint("mixed256_f64_adjoint", mb, planm, lams_m,
                       sorted(set(first.values()) | {5, 100, 200}))
-        progress(f"mixed256 fp64 discretize {ms_m:.3f} ms, gradient step {ms_madj:.3f} ms")
+        # each model's trajectories alone (same kernels, tuned the same way): the
+        # mixed graph runs the groups concurrently, so its time against the
+        # slowest group alone bounds what one launch switching on the model
+        # could still gain by overlapping them
+        alone = {}
+        by_model = {}
+        for i, (m_, _, _) in enumerate(mb):
+            by_model.setdefault(m_.name, []).append(i)
+        for name_, idx in by_model.items():
+            pl = api.BatchPlan([trajs[i] for i in idx], ("discretize",), sched="tune", graph=True,
+                               stream=stream)
+            alone[name_], _ = timed(lambda: pl.run("discretize", graph=True, stream=stream),
+                                    args.extra_steps, 2)
+            pl.close()
+        progress(f"mixed256 fp64 discretize {ms_m:.3f} ms, gradient step {ms_madj:.3f} ms; "
+                 f"groups alone {alone}")
         extras["mixed256_f64"] = {
             "trajectories": len(mb), "intervals": m_int,
             "discretize": {"value": m_int / (ms_m * 1e-3), "unit": "intervals/s",
@@ -610,7 +625,9 @@ def main():
             "gradient_step": {"value": m_int / (ms_madj * 1e-3), "unit": "interval grads/s",
                               "ms_per_step": ms_madj,
                               "roofline_frac": m_adj / (ms_madj * 1e-3) / PEAK_FP64_VALU},
-            "groups": planm.groups()}
+            "groups": planm.groups(),
+            "groups_alone_ms": alone, "sum_alone_ms": sum(alone.values()),
+            "max_alone_ms": max(alone.values())}
         planm.close()
         del planm, trajs
         torch.cuda.empty_cache()
@@ -715,49 +732,51 @@ def main():
         hpb = scp.CitoProblem(hmodel, 14, hx0, hx1, K=10)
         hg = synth.scp_initial_guess(hmodel, 14, hx0, hx1, 0.05, np.random.default_rng(1))
         hz0 = hpb.pack(hg["Xp"], hg["Xm"], hg["Phi"], hg["Gamma"], hg["Ua"], hg["Ub"], hg["S"])
-        htr = scp.GpuTranscriber(hpb)
-        htr(hpb.unpack(hz0), 1.0)                       # warm-up transcription
-        hdrv = scp.ScpDriver(hpb, htr)
-        t_scp = time.perf_counter()
-        hdrv.run(hz0, max_iter=args.scp_max_iter,
-                 callback=lambda rec, z: rec.j % 100 == 99 and progress(
-                     f"scp iteration {rec.j + 1}: delta {rec.delta:.3g}, J_px {rec.J_px:.2e}, "
-                     f"J_ep {rec.J_ep:.2e}"))
-        t_scp = time.perf_counter() - t_scp
-        hh = hdrv.history
-        ms_it = 1e3 * t_scp / len(hh)
-        extras["scp_monoped_N14_K10"] = {
-            "value": len(hh) / t_scp, "unit": "SCP iterations/s", "ms_per_iteration": ms_it,
-            "iterations": len(hh), "converged": bool(hdrv.hom.done()), "wall_s": t_scp,
-            "final": {"delta": hdrv.hom.delta[-1], "J_px": hh[-1].J_px, "J_ep": hh[-1].J_ep,
-                      "cost": hh[-1].cost},
-            "qp_status_counts": {st: sum(r.qp_status == st for r in hh)
-                                 for st in sorted({r.qp_status for r in hh})},
-            "transcribe_ms": 1e3 * float(np.mean([r.t_transcribe for r in hh])),
-            "assemble_ms": 1e3 * float(np.mean([r.t_assemble for r in hh])),
-            "qp_solve_ms": 1e3 * float(np.mean([r.t_solve for r in hh])),
-            "qp_iterations_mean": float(np.mean([r.qp_iters for r in hh])),
-            "step": "transcription (cis_discretize over the node-doubled discontinuous hold + "
-                    "cis_impact_linearize, host copies included), subproblem assembly, QP solve, "
-                    "Alg. 1 update"}
-        progress(f"scp monoped: {len(hh)} iterations in {t_scp:.1f} s (converged "
-                 f"{extras['scp_monoped_N14_K10']['converged']}), {ms_it:.1f} ms/iteration "
-                 f"(transcribe {extras['scp_monoped_N14_K10']['transcribe_ms']:.2f}, "
-                 f"assemble {extras['scp_monoped_N14_K10']['assemble_ms']:.2f}, "
-                 f"solve {extras['scp_monoped_N14_K10']['qp_solve_ms']:.2f} ms)")
-        if not args.no_cpu_baseline:
-            got_h = htr(hpb.unpack(hz0), 0.5)
+        for integ, key in (("rk4", "scp_monoped_N14_K10"), ("rkf", "scp_monoped_N14_K10_rkf")):
+            htr = scp.GpuTranscriber(hpb, integ)
+            htr(hpb.unpack(hz0), 1.0)                   # warm-up transcription
+            hdrv = scp.ScpDriver(hpb, htr)
+            t_scp = time.perf_counter()
+            hdrv.run(hz0, max_iter=args.scp_max_iter,
+                     callback=lambda rec, z: rec.j % 100 == 99 and progress(
+                         f"scp ({integ}) iteration {rec.j + 1}: delta {rec.delta:.3g}, "
+                         f"J_px {rec.J_px:.2e}, J_ep {rec.J_ep:.2e}"))
+            t_scp = time.perf_counter() - t_scp
+            hh = hdrv.history
+            ms_it = 1e3 * t_scp / len(hh)
+            ex = {
+                "value": len(hh) / t_scp, "unit": "SCP iterations/s", "ms_per_iteration": ms_it,
+                "iterations": len(hh), "converged": bool(hdrv.hom.done()), "wall_s": t_scp,
+                "integrator": {"rk4": "classical RK4", "rkf": "Fehlberg 4(5)"}[integ],
+                "final": {"delta": hdrv.hom.delta[-1], "J_px": hh[-1].J_px, "J_ep": hh[-1].J_ep,
+                          "cost": hh[-1].cost},
+                "qp_status_counts": {st: sum(r.qp_status == st for r in hh)
+                                     for st in sorted({r.qp_status for r in hh})},
+                "transcribe_ms": 1e3 * float(np.mean([r.t_transcribe for r in hh])),
+                "assemble_ms": 1e3 * float(np.mean([r.t_assemble for r in hh])),
+                "qp_solve_ms": 1e3 * float(np.mean([r.t_solve for r in hh])),
+                "qp_iterations_mean": float(np.mean([r.qp_iters for r in hh])),
+                "step": "transcription (cis_discretize or cis_discretize_rkf over the "
+                        "node-doubled discontinuous hold + cis_impact_linearize, host copies "
+                        "included), subproblem assembly, QP solve, Alg. 1 update"}
+            extras[key] = ex
+            progress(f"scp monoped ({integ}): {len(hh)} iterations in {t_scp:.1f} s (converged "
+                     f"{ex['converged']}), {ms_it:.1f} ms/iteration (transcribe "
+                     f"{ex['transcribe_ms']:.2f}, assemble {ex['assemble_ms']:.2f}, solve "
+                     f"{ex['qp_solve_ms']:.2f} ms)")
+            if not args.no_cpu_baseline:
+                got_h = htr(hpb.unpack(hz0), 0.5)
 
-            def run_scp():
-                from parity import PHI64, block_err
-                from scp_oracle import oracle_transcriber
-                ref = oracle_transcriber(hpb)(hpb.unpack(hz0), 0.5)
-                worst = max(block_err(got_h[k], ref[k], PHI64) for k in ref)
-                parity["scp_monoped_transcription"] = {
-                    "max_rel_err_vs_oracle": worst, "metric": "per-entry (phi = 1e-3)",
-                    "bar": 1e-10, "sample": "initial iterate, every interval and node "
-                    "(A, B-, B+, S, d, G~, Theta, Psi and their node Jacobians), delta = 0.5"}
-            pending.append(run_scp)
+                def run_scp(got_h=got_h, integ=integ, key=key):
+                    from parity import PHI64, block_err
+                    from scp_oracle import oracle_transcriber
+                    ref = oracle_transcriber(hpb, integ)(hpb.unpack(hz0), 0.5)
+                    worst = max(block_err(got_h[k], ref[k], PHI64) for k in ref)
+                    parity[key + "_transcription"] = {
+                        "max_rel_err_vs_oracle": worst, "metric": "per-entry (phi = 1e-3)",
+                        "bar": 1e-10, "sample": "initial iterate, every interval and node "
+                        "(A, B-, B+, S, d, G~, Theta, Psi and their node Jacobians), delta = 0.5"}
+                pending.append(run_scp)
 
     line["extras"] = extras
 
