@@ -44,11 +44,11 @@ struct RecShared {
 };
 
 // ---------------------------------------------------------------------------
-// k_coefrec: interval k by three waves, one workgroup barrier per step:
-//   wave 0 (state)       : stage t at step t;
-//   wave 1 (coefficients): stage t-1 at step t, into coef[(t-1) & 1];
-//   wave 2 (S column)    : stage t-2 at step t from coef[(t-2) & 1], and the
-//                          copy of that record to device memory.
+// k_coefrec: interval k by two waves, one workgroup barrier per step:
+//   wave 0 (state, S column): stage t of the nominal recursion at step t, and
+//                          the S column's stage t-2 from coef[(t-2) & 1] with
+//                          the copy of that record to device memory;
+//   wave 1 (coefficients): stage t-1 at step t, into coef[(t-1) & 1].
 // ---------------------------------------------------------------------------
 template <class T, class TP>
 __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs<T>& a,
@@ -59,7 +59,7 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
     using R = CoefRec<TP>;
     using SR = SplitRec<TP>;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    constexpr int nth = 192;
+    constexpr int nth = 128;
     load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
     for (int e = tid; e < 2 * R::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
     __syncthreads();
@@ -80,7 +80,7 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
     __syncthreads();
 
     if (wave == 0) {
-        // ---------------- state wave: stage t at step t ----------------
+        // ---- state wave: stage t at step t; S column: stage t-2 at step t ----
         const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
         BodyRK<T> bs;
 #pragma unroll
@@ -93,23 +93,43 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
             bs.xs[kk] = bs.xb[kk];
             bs.xa[kk] = T(0);
         }
+        SLane<T, TP> z;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) z.zs[r] = z.zb[r] = z.za[r] = T(0);
+#pragma unroll
+        for (int l = 0; l < SLane<T, TP>::NCL; ++l) z.ycc[l] = T(0);
+        z.yct = T(0);
         const T Kt = T(a.K);
-        for (int j = 0; j < a.K; ++j) {
-            const T jt = T(j);
-            state_stage<T, TP, 0>(sh.iv, mc, c, bs, jt / Kt, sh.xring[1], sh.csring[0],
-                                  sh.fring[0], lane);
+        T* out = rec + SR::CRS;
+        // steps t = 4 j + ST, t < nsteps: one barrier each (both stage indices
+        // known at compile time inside the unrolled substep)
+        auto step = [&](auto st_c, int j) {
+            constexpr int ST = decltype(st_c)::value;
+            constexpr int SS = (ST + 2) & 3;   // S stage of this step
+            const int t = 4 * j + ST;
+            if (t < nst) {
+                const T jt = T(j);
+                const T tau = ST == 0 ? jt / Kt : (ST == 3 ? (jt + T(1)) / Kt : (jt + T(0.5)) / Kt);
+                state_stage<T, TP, ST>(sh.iv, mc, c, bs, tau, sh.xring[(ST + 1) & 3],
+                                       sh.csring[ST], sh.fring[ST], lane);
+            }
+            if (t >= 2) {
+                const T* cf = sh.coef[SS & 1];
+                s_stage<T, TP, SS, R>(sh.iv, c, z, cf, lane);
+#pragma unroll
+                for (int e = lane; e < R::GLOBAL; e += 64) out[e] = cf[e];
+                out += R::GLOBAL;
+            }
             __syncthreads();
-            state_stage<T, TP, 1>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[2], sh.csring[1],
-                                  sh.fring[1], lane);
-            __syncthreads();
-            state_stage<T, TP, 2>(sh.iv, mc, c, bs, (jt + T(0.5)) / Kt, sh.xring[3], sh.csring[2],
-                                  sh.fring[2], lane);
-            __syncthreads();
-            state_stage<T, TP, 3>(sh.iv, mc, c, bs, (jt + T(1)) / Kt, sh.xring[0], sh.csring[3],
-                                  sh.fring[3], lane);
-            __syncthreads();
+        };
+        for (int j = 0; 4 * j < nsteps; ++j) {
+            step(std::integral_constant<int, 0>{}, j);
+            step(std::integral_constant<int, 1>{}, j);
+            if (4 * j + 2 < nsteps) {
+                step(std::integral_constant<int, 2>{}, j);
+                step(std::integral_constant<int, 3>{}, j);
+            }
         }
-        for (int t = nst; t < nsteps; ++t) __syncthreads();
         if (lane < NB) {
 #pragma unroll
             for (int kk = 0; kk < 6; ++kk) {
@@ -118,7 +138,19 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
                 a.defect[r * ldi + k] = bs.xb[kk] - sh.iv.xk1[r];
             }
         }
-    } else if (wave == 1) {
+        T yct = T(0);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) yct += lane_value(z.yct, e);
+        if (lane < NB) {
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                a.S[(int64_t)(3 * c.b + kk) * ldi + k] = z.zb[kk];
+                a.S[(int64_t)(NQ + 3 * c.b + kk) * ldi + k] = z.zb[3 + kk];
+            }
+            if (c.contact) a.S[(int64_t)(NX + c.i) * ldi + k] = z.ycc[0];
+            if (lane == 0) a.S[(int64_t)(NX + NC) * ldi + k] = yct;
+        }
+    } else {
         // ------- coefficient wave: stage tc at step tc + 1; integral rows -------
         const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
         const int ycc_row = NX + c.i;
@@ -168,47 +200,9 @@ __device__ __forceinline__ void coefrec_item(RecShared<T, TP>& sh, const FwdArgs
             const int r = e / NY, cc = NX + e % NY;
             a.A[((int64_t)r * NXT + cc) * ldi + k] = (r == cc) ? T(1) : T(0);
         }
-    } else {
-        // ---- S wave: stage t-2 at step t on body lanes; record copy ----
-        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
-        SLane<T, TP> z;
-#pragma unroll
-        for (int r = 0; r < 6; ++r) z.zs[r] = z.zb[r] = z.za[r] = T(0);
-#pragma unroll
-        for (int l = 0; l < SLane<T, TP>::NCL; ++l) z.ycc[l] = T(0);
-        z.yct = T(0);
-        __syncthreads();
-        __syncthreads();
-        T* out = rec + SR::CRS;
-        for (int j = 0; j < a.K; ++j) {
-#pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const T* cf = sh.coef[st & 1];
-                if (st == 0) s_stage<T, TP, 0, R>(sh.iv, c, z, cf, lane);
-                else if (st == 1) s_stage<T, TP, 1, R>(sh.iv, c, z, cf, lane);
-                else if (st == 2) s_stage<T, TP, 2, R>(sh.iv, c, z, cf, lane);
-                else s_stage<T, TP, 3, R>(sh.iv, c, z, cf, lane);
-#pragma unroll
-                for (int e = lane; e < R::GLOBAL; e += 64) out[e] = cf[e];
-                out += R::GLOBAL;
-                __syncthreads();
-            }
-        }
-        T yct = T(0);
-#pragma unroll
-        for (int e = 0; e < NB; ++e) yct += lane_value(z.yct, e);
-        if (lane < NB) {
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-                a.S[(int64_t)(3 * c.b + kk) * ldi + k] = z.zb[kk];
-                a.S[(int64_t)(NQ + 3 * c.b + kk) * ldi + k] = z.zb[3 + kk];
-            }
-            if (c.contact) a.S[(int64_t)(NX + c.i) * ldi + k] = z.ycc[0];
-            if (lane == 0) a.S[(int64_t)(NX + NC) * ldi + k] = yct;
-        }
-        (void)L;
-        (void)D;
     }
+    (void)L;
+    (void)D;
 }
 
 // ---------------------------------------------------------------------------
@@ -335,7 +329,7 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
 
 // Single trajectory: rec holds N interval parts of per_interval(K) elements.
 template <class T, class TP>
-__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
     k_coefrec(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc,
                                                  T* __restrict__ rec) {
     __shared__ RecShared<T, TP> sh;
@@ -357,7 +351,7 @@ __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu
 // Batches: one launch per model over the work list; rec_off[item] is the
 // element offset of the item's part of the workspace.
 template <class T, class TP>
-__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
     k_coefrec_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc,
                     T* __restrict__ rec, const int64_t* __restrict__ rec_off) {
     __shared__ RecShared<T, TP> sh;
@@ -431,7 +425,7 @@ static cis_status launch_split_t(const cis_model* m, const cis_shape* sh, const 
         a.C = 1;
         T* rec = (T*)ws;
         void* args_a[] = {&a, &mc, &rec};
-        hipError_t e = hipLaunchKernel((const void*)&k_coefrec<T, TP>, dim3(sh->N), dim3(192),
+        hipError_t e = hipLaunchKernel((const void*)&k_coefrec<T, TP>, dim3(sh->N), dim3(128),
                                        args_a, 0, stream);
         if (e != hipSuccess) return fail(CIS_ERR_HIP, "k_coefrec launch: %s", hipGetErrorString(e));
         const T* crec = rec;
@@ -462,7 +456,7 @@ static cis_status prep_split_t(const cis_model* m, const BatchGroupDev& g, int w
         ka->arg(g.rec_off);
         ka->func = (const void*)&k_coefrec_batch<T, TP>;
         ka->grid = dim3(g.n_items);
-        ka->block = dim3(192);
+        ka->block = dim3(128);
         kb->arg(b);
         kb->arg((const T*)g.rec);
         kb->arg(g.rec_off);
