@@ -11,7 +11,7 @@
 // rows.  The stage times tau = (j + c_i) / K feed the FOH controls.
 //
 // Two kernels in the split layout (cis_split.hpp):
-//   k_rkf_rec : per interval three waves, the nominal steps on body lanes
+//   k_rkf_rec : per interval two waves, the nominal steps on body lanes
 //               (with the sixth stage for the estimate), the Jacobian
 //               coefficients of the five propagated stages into compact
 //               records, the integral rows, and the dilation column S;
@@ -90,14 +90,14 @@ __device__ __forceinline__ T next_input(const T (&kd)[RKF::R][NR], int r) {
 }
 
 // ---------------------------------------------------------------------------
-// k_rkf_rec: interval k by three waves, one workgroup barrier per step (five
+// k_rkf_rec: interval k by two waves, one workgroup barrier per step (five
 // steps per RKF step):
-//   wave 0 (state)       : record stage t at step t; at the fifth stage also
-//                          the sixth (estimate) and the step's end;
+//   wave 0 (state, S)    : record stage t at step t; at the fifth stage also
+//                          the sixth (estimate) and the step's end; then the
+//                          S column's record stage t-2 and the copy of that
+//                          record to device memory;
 //   wave 1 (coefficients): record stage t-1 at step t, into coef[(t-1) & 1];
-//                          the integral rows and their estimate;
-//   wave 2 (S column)    : record stage t-2 at step t, and the copy of that
-//                          record to device memory.
+//                          the integral rows and their estimate.
 // ---------------------------------------------------------------------------
 template <class T, class TP>
 __device__ __forceinline__ void rkf_rec_item(RkfShared<T, TP>& sh, const FwdArgs<T>& a,
@@ -109,7 +109,7 @@ __device__ __forceinline__ void rkf_rec_item(RkfShared<T, TP>& sh, const FwdArgs
     using SR = SplitRec<TP>;
     constexpr int NR = RKF::R;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    constexpr int nth = 192;
+    constexpr int nth = 128;
     load_interval<T, TP>(sh.iv, a, mc, k, tid, nth);
     for (int e = tid; e < 2 * R::SIZE; e += nth) (&sh.coef[0][0])[e] = T(0);
     __syncthreads();
@@ -128,7 +128,8 @@ __device__ __forceinline__ void rkf_rec_item(RkfShared<T, TP>& sh, const FwdArgs
     __syncthreads();
 
     if (wave == 0) {
-        // ---------------- state wave ----------------
+        // ------- state wave (record stage t at step t) and S column (record
+        // stage t-2 at step t, then the copy of that record) -------
         const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
         T xb[6], xs[6], kd[NR][6];
 #pragma unroll
@@ -139,69 +140,114 @@ __device__ __forceinline__ void rkf_rec_item(RkfShared<T, TP>& sh, const FwdArgs
 #pragma unroll
         for (int q = 0; q < 6; ++q) xs[q] = xb[q];
         T emax = T(0);
-        for (int j = 0; j < a.K; ++j) {
+        constexpr int NCL = SLane<T, TP>::NCL;
+        T zb[6], zs[6], skd[NR][6], ycc[NCL], yct = T(0);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) zb[q] = zs[q] = T(0);
+#pragma unroll
+        for (int l = 0; l < NCL; ++l) ycc[l] = T(0);
+        T* out = rec + SR::CRS;
+        const int nst = NR * a.K, nsteps = nst + 2;
+        for (int j = 0; NR * j < nsteps; ++j) {
             const T jt = T(j);
             [&]<int... Is>(std::integer_sequence<int, Is...>) {
                 ([&] {
                     constexpr int I = Is;
                     const int t = NR * j + I;
-                    T fv[3], cb, sb;
-                    body_accel<T, TP>(sh.iv, mc, c, xs, (jt + T(RKF::c(I))) / Kt, fv, cb, sb);
+                    if (t >= nsteps) return;
+                    if (t < nst) {
+                        T fv[3], cb, sb;
+                        body_accel<T, TP>(sh.iv, mc, c, xs, (jt + T(RKF::c(I))) / Kt, fv, cb, sb);
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) kd[I][q] = s * (q < 3 ? xs[3 + q] : fv[q - 3]);
-                    if (lane < NB) {
+                        for (int q = 0; q < 6; ++q) kd[I][q] = s * (q < 3 ? xs[3 + q] : fv[q - 3]);
+                        if (lane < NB) {
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) sh.fring[t & 3][3 * c.b + q] = fv[q];
-                        sh.csring[t & 3][c.b][0] = cb;
-                        sh.csring[t & 3][c.b][1] = sb;
-                    }
-                    if constexpr (I < NR - 1) {
+                            for (int q = 0; q < 3; ++q) sh.fring[t & 3][3 * c.b + q] = fv[q];
+                            sh.csring[t & 3][c.b][0] = cb;
+                            sh.csring[t & 3][c.b][1] = sb;
+                        }
+                        if constexpr (I < NR - 1) {
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) xs[q] = xb[q] + h * next_input<I>(kd, q);
-                    } else {
-                        // sixth stage (estimate only), then the step's end
-                        T x6[6];
+                            for (int q = 0; q < 6; ++q) xs[q] = xb[q] + h * next_input<I>(kd, q);
+                        } else {
+                            // sixth stage (estimate only), then the step's end
+                            T x6[6];
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) x6[q] = xb[q] + h * next_input<I>(kd, q);
-                        T f6[3], c6, s6;
-                        body_accel<T, TP>(sh.iv, mc, c, x6, (jt + T(RKF::c(5))) / Kt, f6, c6, s6);
+                            for (int q = 0; q < 6; ++q) x6[q] = xb[q] + h * next_input<I>(kd, q);
+                            T f6[3], c6, s6;
+                            body_accel<T, TP>(sh.iv, mc, c, x6, (jt + T(RKF::c(5))) / Kt, f6, c6,
+                                              s6);
+                            if (lane < NB) {
+#pragma unroll
+                                for (int q = 0; q < 3; ++q) {
+                                    sh.x6[3 * c.b + q] = x6[q];
+                                    sh.x6[NQ + 3 * c.b + q] = x6[3 + q];
+                                    sh.f6[3 * c.b + q] = f6[q];
+                                }
+                                sh.cs6[c.b][0] = c6;
+                                sh.cs6[c.b][1] = s6;
+                            }
+#pragma unroll
+                            for (int q = 0; q < 6; ++q) {
+                                const T k6 = s * (q < 3 ? x6[3 + q] : f6[q - 3]);
+                                T ev = T(RKF::e(5)) * k6, xn = T(0);
+#pragma unroll
+                                for (int l = 0; l < NR; ++l) {
+                                    if (RKF::e(l) != 0.0) ev += T(RKF::e(l)) * kd[l][q];
+                                    if (RKF::b(l) != 0.0) xn += T(RKF::b(l)) * kd[l][q];
+                                }
+                                emax = fmax(emax, fabs(h * ev));
+                                xb[q] += h * xn;
+                                xs[q] = xb[q];
+                            }
+                        }
                         if (lane < NB) {
 #pragma unroll
                             for (int q = 0; q < 3; ++q) {
-                                sh.x6[3 * c.b + q] = x6[q];
-                                sh.x6[NQ + 3 * c.b + q] = x6[3 + q];
-                                sh.f6[3 * c.b + q] = f6[q];
+                                sh.xring[(t + 1) & 3][3 * c.b + q] = xs[q];
+                                sh.xring[(t + 1) & 3][NQ + 3 * c.b + q] = xs[3 + q];
                             }
-                            sh.cs6[c.b][0] = c6;
-                            sh.cs6[c.b][1] = s6;
-                        }
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            const T k6 = s * (q < 3 ? x6[3 + q] : f6[q - 3]);
-                            T ev = T(RKF::e(5)) * k6, xn = T(0);
-#pragma unroll
-                            for (int l = 0; l < NR; ++l) {
-                                if (RKF::e(l) != 0.0) ev += T(RKF::e(l)) * kd[l][q];
-                                if (RKF::b(l) != 0.0) xn += T(RKF::b(l)) * kd[l][q];
-                            }
-                            emax = fmax(emax, fabs(h * ev));
-                            xb[q] += h * xn;
-                            xs[q] = xb[q];
                         }
                     }
-                    if (lane < NB) {
+                    if (t >= 2) {
+                        // the S column's record stage t - 2 (its index within
+                        // the step known at compile time)
+                        constexpr int J = (I + NR - 2) % NR;
+                        const T* cf = sh.coef[(t - 2) & 1];
+                        T kv[3], kcc[NCL], kct;
+                        s_rhs<T, TP, R>(sh.iv, c, zs, cf, lane, kv, kcc, kct);
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
-                            sh.xring[(t + 1) & 3][3 * c.b + q] = xs[q];
-                            sh.xring[(t + 1) & 3][NQ + 3 * c.b + q] = xs[3 + q];
+                            skd[J][q] = s * zs[3 + q] + cf[R::f(3 * c.b + q)];
+                            skd[J][3 + q] = kv[q];
                         }
+                        if constexpr (RKF::b(J) != 0.0) {
+#pragma unroll
+                            for (int l = 0; l < NCL; ++l) ycc[l] += (h * T(RKF::b(J))) * kcc[l];
+                            yct += (h * T(RKF::b(J))) * kct;
+                        }
+                        if constexpr (J < NR - 1) {
+#pragma unroll
+                            for (int q = 0; q < 6; ++q) zs[q] = zb[q] + h * next_input<J>(skd, q);
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 6; ++q) {
+                                T xn = T(0);
+#pragma unroll
+                                for (int l = 0; l < NR; ++l)
+                                    if (RKF::b(l) != 0.0) xn += T(RKF::b(l)) * skd[l][q];
+                                zb[q] += h * xn;
+                                zs[q] = zb[q];
+                            }
+                        }
+#pragma unroll
+                        for (int e = lane; e < R::GLOBAL; e += 64) out[e] = cf[e];
+                        out += R::GLOBAL;
                     }
                     __syncthreads();
                 }(), ...);
             }(std::make_integer_sequence<int, NR>{});
         }
-        __syncthreads();
-        __syncthreads();
         if (lane < NB) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
@@ -214,7 +260,19 @@ __device__ __forceinline__ void rkf_rec_item(RkfShared<T, TP>& sh, const FwdArgs
 #pragma unroll
         for (int e = 0; e < NB; ++e) m = fmax(m, lane_value(emax, e));
         if (lane == 0) sh.emax[0] = m;
-    } else if (wave == 1) {
+        T yt = T(0);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) yt += lane_value(yct, e);
+        if (lane < NB) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                a.S[(int64_t)(3 * c.b + q) * ldi + k] = zb[q];
+                a.S[(int64_t)(NQ + 3 * c.b + q) * ldi + k] = zb[3 + q];
+            }
+            if (c.contact) a.S[(int64_t)(NX + c.i) * ldi + k] = ycc[0];
+            if (lane == 0) a.S[(int64_t)(NX + NC) * ldi + k] = yt;
+        }
+    } else {
         // ------- coefficient wave: record stage tc at step tc + 1; integral rows -------
         const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
         const int ycc_row = NX + c.i;
@@ -284,69 +342,6 @@ __device__ __forceinline__ void rkf_rec_item(RkfShared<T, TP>& sh, const FwdArgs
 #pragma unroll
         for (int e = 0; e < NB; ++e) m = fmax(m, lane_value(emax, e));
         if (lane == 0) sh.emax[1] = m;
-    } else {
-        // ---- S wave: record stage t-2 at step t on body lanes; record copy ----
-        const BodyConst<T, TP> c = body_const<T, TP>(sh.iv, mc, lane);
-        constexpr int NCL = SLane<T, TP>::NCL;
-        T zb[6], zs[6], kd[NR][6], ycc[NCL], yct = T(0);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) zb[q] = zs[q] = T(0);
-#pragma unroll
-        for (int l = 0; l < NCL; ++l) ycc[l] = T(0);
-        __syncthreads();
-        __syncthreads();
-        T* out = rec + SR::CRS;
-        for (int j = 0; j < a.K; ++j) {
-            [&]<int... Is>(std::integer_sequence<int, Is...>) {
-                ([&] {
-                    constexpr int I = Is;
-                    const int t = NR * j + I;
-                    const T* cf = sh.coef[t & 1];
-                    T kv[3], kcc[NCL], kct;
-                    s_rhs<T, TP, R>(sh.iv, c, zs, cf, lane, kv, kcc, kct);
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        kd[I][q] = s * zs[3 + q] + cf[R::f(3 * c.b + q)];
-                        kd[I][3 + q] = kv[q];
-                    }
-                    if constexpr (RKF::b(I) != 0.0) {
-#pragma unroll
-                        for (int l = 0; l < NCL; ++l) ycc[l] += (h * T(RKF::b(I))) * kcc[l];
-                        yct += (h * T(RKF::b(I))) * kct;
-                    }
-                    if constexpr (I < NR - 1) {
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) zs[q] = zb[q] + h * next_input<I>(kd, q);
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            T xn = T(0);
-#pragma unroll
-                            for (int l = 0; l < NR; ++l)
-                                if (RKF::b(l) != 0.0) xn += T(RKF::b(l)) * kd[l][q];
-                            zb[q] += h * xn;
-                            zs[q] = zb[q];
-                        }
-                    }
-#pragma unroll
-                    for (int e = lane; e < R::GLOBAL; e += 64) out[e] = cf[e];
-                    out += R::GLOBAL;
-                    __syncthreads();
-                }(), ...);
-            }(std::make_integer_sequence<int, NR>{});
-        }
-        T yt = T(0);
-#pragma unroll
-        for (int e = 0; e < NB; ++e) yt += lane_value(yct, e);
-        if (lane < NB) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                a.S[(int64_t)(3 * c.b + q) * ldi + k] = zb[q];
-                a.S[(int64_t)(NQ + 3 * c.b + q) * ldi + k] = zb[3 + q];
-            }
-            if (c.contact) a.S[(int64_t)(NX + c.i) * ldi + k] = ycc[0];
-            if (lane == 0) a.S[(int64_t)(NX + NC) * ldi + k] = yt;
-        }
     }
     __syncthreads();
     if (err && tid == 0) err[k] = fmax(sh.emax[0], sh.emax[1]);
@@ -490,7 +485,7 @@ __device__ __forceinline__ void rkf_tangent_item(const FwdArgs<T>& a, const T* _
 }
 
 template <class T, class TP>
-__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
     k_rkf_rec(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc, T* __restrict__ rec,
               T* __restrict__ err) {
     __shared__ RkfShared<T, TP> sh;
@@ -555,7 +550,7 @@ static cis_status launch_rkf_t(const cis_model* m, const cis_shape* sh, const vo
         T* rec = (T*)ws;
         T* e = (T*)err;
         void* args_a[] = {&a, &mc, &rec, &e};
-        hipError_t st = hipLaunchKernel((const void*)&k_rkf_rec<T, TP>, dim3(sh->N), dim3(192),
+        hipError_t st = hipLaunchKernel((const void*)&k_rkf_rec<T, TP>, dim3(sh->N), dim3(128),
                                         args_a, 0, stream);
         if (st != hipSuccess) return fail(CIS_ERR_HIP, "k_rkf_rec launch: %s", hipGetErrorString(st));
         const T* crec = rec;
