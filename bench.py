@@ -503,7 +503,11 @@ def main():
             "roofline": {"bound": "alu", "achieved": rkf_fl / (ms_rkf * 1e-3) / 1e12,
                          "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                          "frac": rkf_fl / (ms_rkf * 1e-3) / PEAK_FP64_VALU,
-                         "algorithmic_flop_per_step": rkf_fl},
+                         "algorithmic_flop_per_step": rkf_fl,
+                         "traffic": {"records": committed_traffic(
+                                         f"k_rkf_rec<double, Topo<{rmodel.legs}, {rmodel.depth}, 6, 1, false>>"),
+                                     "tangent": committed_traffic(
+                                         f"k_rkf_tan<double, Topo<{rmodel.legs}, {rmodel.depth}, 6, 1, false>, 1>")}},
             "step": "cis_discretize_rkf: Fehlberg 4(5), K=20 steps, records + tangent launches"}
         if not args.no_cpu_baseline:
             rks = [0, 6400, rN - 1]
@@ -555,7 +559,11 @@ def main():
             "roofline": {"bound": "alu", "achieved": pap_fl / (ms_pap * 1e-3) / 1e12,
                          "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                          "frac": pap_fl / (ms_pap * 1e-3) / PEAK_FP64_VALU,
-                         "algorithmic_flop_per_step": pap_fl},
+                         "algorithmic_flop_per_step": pap_fl,
+                         "traffic": {"records": committed_traffic(
+                                         f"k_paper_rec<PTopo<{rmodel.legs}, {rmodel.depth}>>"),
+                                     "tangent": committed_traffic(
+                                         f"k_paper_tan<PTopo<{rmodel.legs}, {rmodel.depth}>>")}},
             "step": "cis_discretize_paper: joint forces eliminated, RK4 K=20, record + tangent "
                     "launches"}
         if not args.no_cpu_baseline:
