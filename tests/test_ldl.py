@@ -91,3 +91,14 @@ def test_entries_below_the_diagonal_are_rejected():
     Ai = np.array([0, 1, 1], np.int32)                # row 1 in column 0
     parent, Lnz, work = (np.zeros(2, np.int32) for _ in range(3))
     assert lib.cis_ldl_symbolic(2, _vp(Ap), _vp(Ai), _vp(parent), _vp(Lnz), _vp(work)) == -2
+
+
+def test_zero_pivot_without_signs_is_an_error_and_null_pointers_are_refused():
+    K = np.array([[1.0, 1.0], [1.0, 1.0]])          # singular: second pivot exactly 0
+    st, _, _, _ = _factor(K)
+    assert st == -2
+    lib = _lib.load()
+    assert lib.cis_ldl_symbolic(2, None, None, None, None, None) == -1
+    assert lib.cis_ldl_numeric(2, None, None, None, None, None, None, ctypes.c_double(0.0),
+                               ctypes.c_double(0.0), None, None, None, None, None, None) == -1
+    assert lib.cis_ldl_symbolic(0, _vp(np.zeros(1, np.int32)), None, None, None, None) == 0
