@@ -12,8 +12,8 @@ from scp_oracle import oracle_transcriber
 pytestmark = pytest.mark.gpu
 
 
-def _problem(N=14, K=10, seed=0):
-    model = synth.make_hopper(np.random.default_rng(seed))
+def _problem(N=14, K=10, seed=0, model="hopper"):
+    model = synth.MODEL_MAKERS[model](np.random.default_rng(seed))
     xi = synth.standing_state(model, 0.0)
     xf = synth.standing_state(model, 0.3)
     pb = scp.CitoProblem(model, N, xi, xf, K=K)
@@ -68,3 +68,32 @@ def test_scp_monoped_converges_to_a_solution_of_the_relaxed_problem():
     v = pb.unpack(z)
     assert np.abs(v["Xm"][0] - pb.x_init).max() <= 1e-9
     assert np.abs(v["Xp"][-1][:2 * pb.nq] - pb.x_final[:2 * pb.nq]).max() <= 1e-9
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "rkf"])
+def test_biped_transcription_on_the_sinusoid_matches_the_oracle(integrator):
+    """The paper's second robot class: a 5-body biped with two feet on the
+    sinusoidal terrain (two contacts, joint chains of depth two)."""
+    pb, z = _problem(model="biped5")
+    v = pb.unpack(z)
+    print(f"scp transcription biped5 N=14 K=10 {integrator}", flush=True)
+    got = scp.GpuTranscriber(pb, integrator)(v, 0.3)
+    ref = oracle_transcriber(pb, integrator)(v, 0.3)
+    for key in ("A", "Bm", "Bp", "S", "d", "G", "Theta", "Psi", "JG", "JT"):
+        err = block_err(got[key], ref[key], PHI64)
+        assert err <= TOL64, (key, err)
+
+
+def test_biped_scp_iterations_with_gpu_transcription_match_the_oracle():
+    pb, z0 = _problem(model="biped5")
+    print("scp iterations biped5 N=14 K=10 rk4 x2", flush=True)
+    runs = []
+    for tr in (scp.GpuTranscriber(pb), oracle_transcriber(pb)):
+        drv = scp.ScpDriver(pb, tr)
+        zs = []
+        drv.run(z0, max_iter=2, callback=lambda rec, z: zs.append(z.copy()))
+        runs.append((zs, drv.hom.delta))
+    (zg, dg), (zo, do) = runs
+    assert dg == do
+    for a, b in zip(zg, zo):
+        assert np.max(np.abs(a - b) / pb.zscale) <= 1e-6
