@@ -728,8 +728,13 @@ def main():
                 ms_b, _ = timed(lambda: api.discretize_blocked(cmq, Xq, Uq, sq, pq, K, B, mode,
                                                                ws=wsb, stream=stream), 10, 2)
                 blk[f"B{B}_{mode}_ms"] = ms_b
+        _, tb, tc, _ = api.blocked_tune(cmq, Xq, Uq, sq, pq, K, stream=stream)
+        blk["tuned"] = {"blocks": tb, "compose": tc if tb > 1 else None,
+                        "candidates": "one-launch form and blocks 2..8 dividing K, VALU and MFMA "
+                                      "composition, timed on these inputs (cis_blocked_tune)"}
         extras["quad13_N200_K20_single_blocking"] = blk
-        progress("blocking: " + ", ".join(f"{k} {v:.3f}" for k, v in blk.items()))
+        progress("blocking: " + ", ".join(f"{k} {v:.3f}" for k, v in blk.items()
+                                          if isinstance(v, float)) + f"; tuned {blk['tuned']}")
 
         # the SCP driver end to end on the monoped (hopper; the paper's grid of
         # 15 nodes, 10 integration steps per interval): GPU transcription, host

@@ -319,6 +319,25 @@ cis_status cis_discretize_blocked(const cis_model *model, const cis_shape *shape
                                   void *S, void *defect, void *xprop, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/*
+ * Substep-blocking tuner of one trajectory shape (FP64): times the one-launch
+ * form (cis_discretize, reported as blocks = 1) and cis_discretize_blocked for
+ * every block count 2..8 dividing the substep count with both compositions on
+ * the caller's inputs (best of three runs each, HIP events on `stream`), and
+ * returns the fastest as (*blocks, *compose); the outputs then hold that
+ * configuration's results.  With CIS_TUNE_CACHE naming a file the choice is
+ * looked up first and recorded after tuning under (device, topology, N, K);
+ * *from_cache (may be NULL) reports a hit, in which case nothing is timed.
+ * NOT a hot call: allocates the largest blocked workspace, synchronizes the
+ * stream and frees it.  Arguments as for cis_discretize_blocked.
+ * Errors: those of cis_discretize / cis_discretize_blocked, CIS_ERR_NULL for
+ * missing blocks or compose, CIS_ERR_DTYPE for FP32, CIS_ERR_HIP.
+ */
+cis_status cis_blocked_tune(const cis_model *model, const cis_shape *shape, const void *X,
+                            const void *U, const void *s, const void *params, void *A, void *Bm,
+                            void *Bp, void *S, void *defect, void *xprop, int32_t *blocks,
+                            int32_t *compose, int32_t *from_cache, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches of trajectories (multiple shooting over many trajectories at once,
  * Sec. VI): the per-interval work of every trajectory is put on one device

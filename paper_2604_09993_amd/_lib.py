@@ -54,6 +54,7 @@ EXPORTS = [
     "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize", "cis_rkf_workspace_size",
     "cis_discretize_rkf", "cis_paper_dims", "cis_paper_workspace_size", "cis_discretize_paper",
     "cis_batch_plan_tuned_from_cache", "cis_ldl_symbolic", "cis_ldl_numeric", "cis_ldl_solve",
+    "cis_blocked_tune",
 ]
 
 
@@ -173,6 +174,9 @@ def load(build_if_missing: bool = True):
     lib.cis_impact_linearize.restype = St
     lib.cis_impact_linearize.argtypes = ([P, I32, ctypes.c_int64] + [P] * 5
                                          + [ctypes.c_double, ctypes.c_double] + [P] * 6)
+    lib.cis_blocked_tune.restype = St
+    lib.cis_blocked_tune.argtypes = [P, ctypes.POINTER(Shape)] + [P] * 10 + \
+        [ctypes.POINTER(I32)] * 3 + [P]
     lib.cis_ldl_symbolic.restype = ctypes.c_int64
     lib.cis_ldl_symbolic.argtypes = [I32] + [P] * 5
     lib.cis_ldl_numeric.restype = I32

@@ -187,6 +187,30 @@ def discretize_blocked(cm: CisModel, X, U, s, params, K, blocks, compose="valu",
     return out
 
 
+def blocked_tune(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None):
+    """Substep-blocking tuner (FP64): the fastest of the one-launch form
+    (blocks = 1) and the blocked forms on these inputs.  Returns (outputs of
+    the chosen form, blocks, compose name, whether the choice came from the
+    CIS_TUNE_CACHE file)."""
+    _check_inputs(cm, X, U, s, params)
+    N, nx, m = s.shape[0], cm.nx, cm.m
+    kw = dict(device=X.device, dtype=X.dtype)
+    with _alloc_on(stream):
+        out = dict(A=torch.empty((nx, nx, N), **kw), Bm=torch.empty((nx, m, N), **kw),
+                   Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
+                   d=torch.empty((nx, N), **kw))
+        out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
+    sh = _shape(X, s, K)
+    b, c, hit = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(_lib.load().cis_blocked_tune(
+        cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s), _ptr(params), _ptr(out["A"]),
+        _ptr(out["Bm"] if m else None), _ptr(out["Bp"] if m else None), _ptr(out["S"]),
+        _ptr(out["d"]), _ptr(out["xprop"]), ctypes.byref(b), ctypes.byref(c), ctypes.byref(hit),
+        _stream(stream)))
+    compose = "mfma" if c.value == _lib.CIS_COMPOSE_MFMA else "valu"
+    return out, b.value, compose, bool(hit.value)
+
+
 def split_workspace_bytes(cm: CisModel, N, K, dtype=torch.float64):
     sh = _lib.Shape(N, int(K), _dtype_code(dtype), 0, N + 1, N)
     nbytes = ctypes.c_size_t()

@@ -45,20 +45,22 @@ struct Group {
     bool from_cache = false;          // every tuned choice came from the tuning cache
 };
 
+}  // namespace
+
+namespace cis {
+
 // ---------------------------------------------------------------------------
-// Tuning cache: the choices CIS_SCHED_TUNE makes per model group, kept in the
-// JSON file named by CIS_TUNE_CACHE (no variable: no cache) as
+// Tuning cache: the choices CIS_SCHED_TUNE makes per model group (and the
+// substep-blocking tuner per trajectory shape), kept in the JSON file named by
+// CIS_TUNE_CACHE (no variable: no cache) as
 //   {"version": 1, "entries": {"<key>": {"split": s, "waves": w, "persist": p,
-//                                        "def_lane": d, "adj_waves": a}, ...}}
+//                                        "def_lane": d, "adj_waves": a,
+//                                        "blocks": b, "compose": c}, ...}}
 // keyed by device (architecture, compute units), topology, dtype, operations,
 // work-list length and substep range (and checkpoint spacing with the reverse
 // sweep); -1 marks a choice that was not made.  A missing or unreadable file
 // is an empty cache; writes replace the file through a temporary.
 // ---------------------------------------------------------------------------
-struct TuneChoice {
-    int split = -1, waves = -1, persist = -1, def_lane = -1, adj_waves = -1;
-};
-
 std::mutex g_cache_mu;
 
 // minimal reader of the cache's own format (objects, strings, integers)
@@ -98,6 +100,8 @@ struct CacheParser {
             else if (k == "persist") c.persist = (int)v;
             else if (k == "def_lane") c.def_lane = (int)v;
             else if (k == "adj_waves") c.adj_waves = (int)v;
+            else if (k == "blocks") c.blocks = (int)v;
+            else if (k == "compose") c.compose = (int)v;
         } while (lit(','));
         return lit('}');
     }
@@ -149,7 +153,8 @@ bool cache_write(const std::string& path, const std::map<std::string, TuneChoice
             const TuneChoice& c = kv.second;
             f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": {\"split\": " << c.split
               << ", \"waves\": " << c.waves << ", \"persist\": " << c.persist
-              << ", \"def_lane\": " << c.def_lane << ", \"adj_waves\": " << c.adj_waves << "}";
+              << ", \"def_lane\": " << c.def_lane << ", \"adj_waves\": " << c.adj_waves
+              << ", \"blocks\": " << c.blocks << ", \"compose\": " << c.compose << "}";
             first = false;
         }
         f << "\n}}\n";
@@ -167,6 +172,10 @@ std::string device_tag(int dev) {
         if (*c == '"' || *c == '\\') *c = '_';
     return buf;
 }
+
+}  // namespace cis
+
+namespace {
 
 int auto_ckpt(int K) {
     for (int c = 8; c > 1; --c)

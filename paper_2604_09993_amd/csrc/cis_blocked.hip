@@ -12,6 +12,9 @@
 // the vector ALUs or on FP64 MFMA (v_mfma_f64_16x16x4).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/cis.h"
@@ -335,4 +338,121 @@ extern "C" cis_status cis_discretize_blocked(const cis_model* model, const cis_s
     CIS_TOPOLOGIES(CIS_COMPOSE)
 #undef CIS_COMPOSE
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_blocked: topology has no compiled kernel");
+}
+
+// ---------------------------------------------------------------------------
+// Substep-blocking tuner of one trajectory shape: the one-launch kernel
+// (blocks = 1) against every blocked configuration, timed on the caller's data.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Best of `reps` timed runs (HIP events on the stream) after one untimed run.
+template <class F>
+float time_ms(F run, hipStream_t hs, int reps, cis_status& st) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = fail(CIS_ERR_HIP, "cis_blocked_tune: event creation failed");
+        return 0.0f;
+    }
+    float best = -1.0f;
+    st = run();
+    for (int r = 0; r < reps && st == CIS_OK; ++r) {
+        hipEventRecord(e0, hs);
+        st = run();
+        hipEventRecord(e1, hs);
+        if (hipEventSynchronize(e1) != hipSuccess) st = fail(CIS_ERR_HIP, "cis_blocked_tune: sync failed");
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (best < 0.0f || ms < best) best = ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return best;
+}
+
+}  // namespace
+
+extern "C" cis_status cis_blocked_tune(const cis_model* model, const cis_shape* shape,
+                                       const void* X, const void* U, const void* s,
+                                       const void* params, void* A, void* Bm, void* Bp, void* S,
+                                       void* defect, void* xprop, int32_t* blocks,
+                                       int32_t* compose, int32_t* from_cache, void* stream) {
+    cis_status st = check_common(model, shape, X, U, s, params);
+    if (st != CIS_OK) return st;
+    if (!blocks || !compose)
+        return fail(CIS_ERR_NULL, "cis_blocked_tune: blocks and compose outputs are required");
+    if (shape->dtype != CIS_F64)
+        return fail(CIS_ERR_DTYPE, "cis_blocked_tune: only CIS_F64 is offered");
+    hipStream_t hs = (hipStream_t)stream;
+    const int K = shape->substeps;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CIS_ERR_HIP, "cis_blocked_tune: no device");
+    // cache lookup
+    const char* cpath = std::getenv("CIS_TUNE_CACHE");
+    char key[256];
+    std::snprintf(key, sizeof(key), "blocked|%s|L%dD%d|f64|N%d|K%d", device_tag(dev).c_str(),
+                  model->L, model->D, shape->N, K);
+    bool hit = false;
+    if (from_cache) *from_cache = 0;
+    if (cpath && *cpath) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        const auto cache = cache_read(cpath);
+        const auto it = cache.find(key);
+        if (it != cache.end() && it->second.blocks >= 1 &&
+            (it->second.blocks == 1 || K % it->second.blocks == 0) &&
+            (it->second.compose == CIS_COMPOSE_VALU || it->second.compose == CIS_COMPOSE_MFMA)) {
+            *blocks = it->second.blocks;
+            *compose = it->second.compose;
+            hit = true;
+            if (from_cache) *from_cache = 1;
+        }
+    }
+    // workspace for the largest blocked candidate
+    size_t wsz = 0;
+    for (int b = 2; b <= 8 && b <= K; ++b)
+        if (K % b == 0) wsz = std::max(wsz, blocked_layout(model, shape, b).total);
+    void* ws = nullptr;
+    if (wsz && hipMalloc(&ws, wsz) != hipSuccess)
+        return fail(CIS_ERR_HIP, "cis_blocked_tune: workspace of %zu bytes", wsz);
+    auto run = [&](int b, int c) -> cis_status {
+        if (b == 1)
+            return cis_discretize(model, shape, X, U, s, params, A, Bm, Bp, S, defect, xprop, stream);
+        return cis_discretize_blocked(model, shape, X, U, s, params, b, c, A, Bm, Bp, S, defect,
+                                      xprop, ws, wsz, stream);
+    };
+    if (!hit) {
+        int best_b = 1, best_c = CIS_COMPOSE_VALU;
+        float best = time_ms([&] { return run(1, CIS_COMPOSE_VALU); }, hs, 3, st);
+        for (int b = 2; b <= 8 && b <= K && st == CIS_OK; ++b) {
+            if (K % b != 0) continue;
+            for (int c = CIS_COMPOSE_VALU; c <= CIS_COMPOSE_MFMA && st == CIS_OK; ++c) {
+                const float ms = time_ms([&] { return run(b, c); }, hs, 3, st);
+                if (st == CIS_OK && ms < best) {
+                    best = ms;
+                    best_b = b;
+                    best_c = c;
+                }
+            }
+        }
+        if (st != CIS_OK) {
+            if (ws) (void)hipFree(ws);
+            return st;
+        }
+        *blocks = best_b;
+        *compose = best_c;
+        if (cpath && *cpath) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto cur = cache_read(cpath);
+            TuneChoice& tc = cur[key];
+            tc.blocks = best_b;
+            tc.compose = best_c;
+            (void)cache_write(cpath, cur);
+        }
+    }
+    // the outputs hold the chosen configuration's results
+    st = run(*blocks, *compose);
+    if (st == CIS_OK && hipStreamSynchronize(hs) != hipSuccess)
+        st = fail(CIS_ERR_HIP, "cis_blocked_tune: stream synchronization failed");
+    if (ws) (void)hipFree(ws);
+    return st;
 }

@@ -3,6 +3,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/cis.h"
@@ -29,5 +32,17 @@ inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // Checks shared by every entry point: model, shape, and the input pointers.
 cis_status check_common(const cis_model* m, const cis_shape* sh, const void* X, const void* U,
                         const void* s, const void* params);
+
+// Tuning cache (CIS_TUNE_CACHE): choices per key, -1 where not made; the file
+// is read and rewritten under g_cache_mu.
+struct TuneChoice {
+    int split = -1, waves = -1, persist = -1, def_lane = -1, adj_waves = -1;
+    int blocks = -1, compose = -1;
+};
+extern std::mutex g_cache_mu;
+std::map<std::string, TuneChoice> cache_read(const std::string& path);
+bool cache_write(const std::string& path, const std::map<std::string, TuneChoice>& m);
+// "<architecture>/<compute units>cu" of a device
+std::string device_tag(int dev);
 
 }  // namespace cis

@@ -77,3 +77,32 @@ def test_blocked_rejects_bad_block_counts():
             api.discretize_blocked(cm, X, U, s, p, 4, B)
     with pytest.raises(_lib.CisError):
         api.discretize_blocked(cm, X.float(), U.float(), s.float(), p.float(), 4, 2)
+
+
+def test_blocking_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypatch):
+    """The substep-blocking tuner (one-launch form against every blocked
+    configuration) returns one of its candidates, its outputs are that
+    configuration's (checked against the oracle), and a second call reads the
+    same choice back from the CIS_TUNE_CACHE file."""
+    import oracle
+    from paper_2604_09993_amd import api, synth
+    from parity import PHI64, TOL64, block_err
+    print("blocked tune cheetah7 N=8 K=8", flush=True)
+    rng = np.random.default_rng(41)
+    model = synth.make_cheetah7(rng)
+    d = synth.gen_nodes(model, 8, rng, T=0.16)
+    K = 8
+    cm = api.CisModel(model)
+    X, U = api.to_device_soa(d["X"]), api.to_device_soa(d["U"])
+    s = torch.tensor(d["s"], device="cuda")
+    p = torch.tensor(d["p"], device="cuda")
+    monkeypatch.setenv("CIS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    out, b, c, hit = api.blocked_tune(cm, X, U, s, p, K)
+    assert not hit and b in (1, 2, 4, 8) and c in ("valu", "mfma")
+    ref = oracle.discretize(model, d["X"], d["U"], d["s"], d["p"], K)
+    got = api.as_interval_major(out)
+    for key in ("A", "Bm", "Bp", "S", "d", "xprop"):
+        assert block_err(got[key].cpu().numpy(), ref[key], PHI64) <= TOL64, key
+    out2, b2, c2, hit2 = api.blocked_tune(cm, X, U, s, p, K)
+    assert hit2 and (b2, c2) == (b, c)
+    assert '"blocks"' in (tmp_path / "tune.json").read_text()
