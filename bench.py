@@ -668,10 +668,13 @@ def main():
             fake = type("P", (), {"out": [out]})()
             check_intervals(f"{name}_{'f64' if dtype == torch.float64 else 'f32'}", wrap, fake,
                             [(0, 0, N)], dtype == torch.float32)
+            # the tuner's pick among layouts and forms on these inputs (best of three)
+            _, ch = api.single_tune(cm, X, U, s, p, K, stream=stream)
+            tuned = {k: ch[k] for k in ("form", "layout", "waves", "blocks", "compose", "ms")}
             return dict(value=N / (ms * 1e-3), unit="intervals/s", ms_per_step=ms,
                         roofline_frac=algorithmic_flops_per_interval(model, K) * N / (ms * 1e-3) /
-                        (PEAK_FP64_VALU if dtype == torch.float64 else PEAK_FP32_VALU)), \
-                (cm, X, U, s, p, N, K)
+                        (PEAK_FP64_VALU if dtype == torch.float64 else PEAK_FP32_VALU),
+                        tuned=tuned), (cm, X, U, s, p, N, K)
 
         extras["cheetah7_N50_K20_f64"], keep = single("cheetah7_N50_K20", torch.float64)
         extras["cheetah7_N50_K20_f32"], _ = single("cheetah7_N50_K20", torch.float32)
@@ -728,10 +731,15 @@ def main():
                 ms_b, _ = timed(lambda: api.discretize_blocked(cmq, Xq, Uq, sq, pq, K, B, mode,
                                                                ws=wsb, stream=stream), 10, 2)
                 blk[f"B{B}_{mode}_ms"] = ms_b
-        _, tb, tc, _ = api.blocked_tune(cmq, Xq, Uq, sq, pq, K, stream=stream)
-        blk["tuned"] = {"blocks": tb, "compose": tc if tb > 1 else None,
-                        "candidates": "one-launch form and blocks 2..8 dividing K, VALU and MFMA "
-                                      "composition, timed on these inputs (cis_blocked_tune)"}
+        for lay in ("latency", "latency_s", "narrow", "throughput"):
+            ms_l, _ = timed(lambda: api.discretize(cmq, Xq, Uq, sq, pq, K, layout=lay,
+                                                   stream=stream), 10, 2)
+            blk[f"layout_{lay}_ms"] = ms_l
+        _, ch = api.single_tune(cmq, Xq, Uq, sq, pq, K, stream=stream)
+        blk["tuned"] = {k: ch[k] for k in ("form", "layout", "waves", "blocks", "compose")}
+        blk["tuned"]["candidates"] = ("one-launch layouts, split form with 1 and 2 waves, blocks "
+                                      "2..8 dividing K with VALU and MFMA composition, timed on "
+                                      "these inputs (cis_single_tune)")
         extras["quad13_N200_K20_single_blocking"] = blk
         progress("blocking: " + ", ".join(f"{k} {v:.3f}" for k, v in blk.items()
                                           if isinstance(v, float)) + f"; tuned {blk['tuned']}")

@@ -114,7 +114,10 @@ typedef struct {
     int32_t N;
     int32_t substeps;        /* 1 <= K <= 4096                               */
     int32_t dtype;           /* cis_dtype                                    */
-    int32_t reserved;        /* must be 0                                    */
+    int32_t layout;          /* cis_discretize, one trajectory: workgroup     */
+                             /* layout, 0 = by rule (see cis_discretize),     */
+                             /* 1 latency, 2 latency with S on leg lanes,     */
+                             /* 3 narrow, 4 throughput; other calls ignore it */
     int64_t ld_node;         /* >= N + 1                                     */
     int64_t ld_int;          /* >= N                                         */
 } cis_shape;
@@ -319,24 +322,37 @@ cis_status cis_discretize_blocked(const cis_model *model, const cis_shape *shape
                                   void *S, void *defect, void *xprop, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/* Forms of the discretize step for one trajectory, as chosen by cis_single_tune. */
+enum { CIS_FORM_ONE_LAUNCH = 0, CIS_FORM_SPLIT = 1, CIS_FORM_BLOCKED = 2 };
+typedef struct {
+    int32_t form;            /* CIS_FORM_*                                     */
+    int32_t layout;          /* one-launch form: cis_shape.layout (1..4)       */
+    int32_t waves;           /* split form: register budget (1 or 2)          */
+    int32_t blocks;          /* blocked form: substep blocks (divides K)      */
+    int32_t compose;         /* blocked form: CIS_COMPOSE_*                   */
+    int32_t from_cache;      /* 1: read from the CIS_TUNE_CACHE file           */
+    float ms;                /* time of the choice (best of three), 0 on a hit */
+} cis_single_choice;
+
 /*
- * Substep-blocking tuner of one trajectory shape (FP64): times the one-launch
- * form (cis_discretize, reported as blocks = 1) and cis_discretize_blocked for
- * every block count 2..8 dividing the substep count with both compositions on
- * the caller's inputs (best of three runs each, HIP events on `stream`), and
- * returns the fastest as (*blocks, *compose); the outputs then hold that
- * configuration's results.  With CIS_TUNE_CACHE naming a file the choice is
- * looked up first and recorded after tuning under (device, topology, N, K);
- * *from_cache (may be NULL) reports a hit, in which case nothing is timed.
- * NOT a hot call: allocates the largest blocked workspace, synchronizes the
- * stream and frees it.  Arguments as for cis_discretize_blocked.
- * Errors: those of cis_discretize / cis_discretize_blocked, CIS_ERR_NULL for
- * missing blocks or compose, CIS_ERR_DTYPE for FP32, CIS_ERR_HIP.
+ * Tuner of the discretize step for one trajectory shape: times, on the
+ * caller's inputs, the one-launch kernel in each of its four workgroup
+ * layouts (the threads-per-interval mapping), the split form with one and two
+ * waves per SIMD (models with legs with links), and (FP64) the substep-blocked
+ * form for every block count 2..8 dividing K with VALU and MFMA composition;
+ * each candidate best of three runs (HIP events on `stream`).  Returns the
+ * fastest in *choice and leaves its outputs in A, Bm, Bp, S, defect, xprop.
+ * With CIS_TUNE_CACHE naming a file the choice is looked up first (then
+ * nothing is timed) and recorded after tuning, keyed by device, topology,
+ * dtype, N and K.  NOT a hot call: allocates the largest workspace any
+ * candidate needs, synchronizes the stream and frees it.  shape->layout must
+ * be 0.  Errors: those of the candidates' entry points, CIS_ERR_NULL for a
+ * missing choice, CIS_ERR_HIP.
  */
-cis_status cis_blocked_tune(const cis_model *model, const cis_shape *shape, const void *X,
-                            const void *U, const void *s, const void *params, void *A, void *Bm,
-                            void *Bp, void *S, void *defect, void *xprop, int32_t *blocks,
-                            int32_t *compose, int32_t *from_cache, void *stream);
+cis_status cis_single_tune(const cis_model *model, const cis_shape *shape, const void *X,
+                           const void *U, const void *s, const void *params, void *A, void *Bm,
+                           void *Bp, void *S, void *defect, void *xprop, cis_single_choice *choice,
+                           void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches of trajectories (multiple shooting over many trajectories at once,

@@ -42,6 +42,9 @@ CIS_SCHED_SPLIT = 0x800
 CIS_SCHED_FUSED = 0x1000
 CIS_COMPOSE_VALU = 0
 CIS_COMPOSE_MFMA = 1
+CIS_FORM_ONE_LAUNCH = 0
+CIS_FORM_SPLIT = 1
+CIS_FORM_BLOCKED = 2
 
 # every symbol include/cis.h declares
 EXPORTS = [
@@ -54,7 +57,7 @@ EXPORTS = [
     "cis_batch_run_part", "cis_impact_dims", "cis_impact_linearize", "cis_rkf_workspace_size",
     "cis_discretize_rkf", "cis_paper_dims", "cis_paper_workspace_size", "cis_discretize_paper",
     "cis_batch_plan_tuned_from_cache", "cis_ldl_symbolic", "cis_ldl_numeric", "cis_ldl_solve",
-    "cis_blocked_tune",
+    "cis_single_tune",
 ]
 
 
@@ -74,8 +77,15 @@ class ModelDesc(ctypes.Structure):
 
 class Shape(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("substeps", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("ld_node", ctypes.c_int64), ("ld_int", ctypes.c_int64)]
+
+
+class SingleChoice(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("compose", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
 
 
 class Traj(ctypes.Structure):
@@ -174,9 +184,9 @@ def load(build_if_missing: bool = True):
     lib.cis_impact_linearize.restype = St
     lib.cis_impact_linearize.argtypes = ([P, I32, ctypes.c_int64] + [P] * 5
                                          + [ctypes.c_double, ctypes.c_double] + [P] * 6)
-    lib.cis_blocked_tune.restype = St
-    lib.cis_blocked_tune.argtypes = [P, ctypes.POINTER(Shape)] + [P] * 10 + \
-        [ctypes.POINTER(I32)] * 3 + [P]
+    lib.cis_single_tune.restype = St
+    lib.cis_single_tune.argtypes = [P, ctypes.POINTER(Shape)] + [P] * 10 + \
+        [ctypes.POINTER(SingleChoice), P]
     lib.cis_ldl_symbolic.restype = ctypes.c_int64
     lib.cis_ldl_symbolic.argtypes = [I32] + [P] * 5
     lib.cis_ldl_numeric.restype = I32

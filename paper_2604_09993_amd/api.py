@@ -82,11 +82,14 @@ def _dtype_code(dtype):
     raise TypeError(f"unsupported dtype {dtype}")
 
 
-def _shape(X, s, K, ld_int=None):
+LAYOUTS = {"rule": 0, "latency": 1, "latency_s": 2, "narrow": 3, "throughput": 4}
+
+
+def _shape(X, s, K, ld_int=None, layout="rule"):
     if X.dim() != 2 or X.stride(1) != 1:
         raise ValueError("X must be [nx, ld_node] with unit stride along nodes")
     N = s.shape[0]
-    return _lib.Shape(N, int(K), _dtype_code(X.dtype), 0, X.stride(0),
+    return _lib.Shape(N, int(K), _dtype_code(X.dtype), LAYOUTS[layout], X.stride(0),
                       N if ld_int is None else int(ld_int))
 
 
@@ -106,8 +109,10 @@ def _check_inputs(cm, X, U, s, params):
         raise ValueError("params must hold P contiguous values and s must be contiguous")
 
 
-def discretize(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None):
-    """A, Bm, Bp, S, defect (and F~) of every interval, written by one kernel launch."""
+def discretize(cm: CisModel, X, U, s, params, K, *, with_xprop=True, layout="rule",
+               stream=None):
+    """A, Bm, Bp, S, defect (and F~) of every interval, written by one kernel launch.
+    layout: one of LAYOUTS ("rule": chosen from N and the device's CU count)."""
     _check_inputs(cm, X, U, s, params)
     N, nx, m = s.shape[0], cm.nx, cm.m
     kw = dict(device=X.device, dtype=X.dtype)
@@ -116,7 +121,7 @@ def discretize(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None
                    Bp=torch.empty((nx, m, N), **kw), S=torch.empty((nx, N), **kw),
                    d=torch.empty((nx, N), **kw))
         out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
-    sh = _shape(X, s, K)
+    sh = _shape(X, s, K, layout=layout)
     lib = _lib.load()
     _lib.check(lib.cis_discretize(cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s),
                                   _ptr(params), _ptr(out["A"]), _ptr(out["Bm"] if m else None),
@@ -187,11 +192,15 @@ def discretize_blocked(cm: CisModel, X, U, s, params, K, blocks, compose="valu",
     return out
 
 
-def blocked_tune(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None):
-    """Substep-blocking tuner (FP64): the fastest of the one-launch form
-    (blocks = 1) and the blocked forms on these inputs.  Returns (outputs of
-    the chosen form, blocks, compose name, whether the choice came from the
-    CIS_TUNE_CACHE file)."""
+FORMS = {_lib.CIS_FORM_ONE_LAUNCH: "one_launch", _lib.CIS_FORM_SPLIT: "split",
+         _lib.CIS_FORM_BLOCKED: "blocked"}
+
+
+def single_tune(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=None):
+    """Tuner of the discretize step for one trajectory shape: the fastest of
+    the one-launch layouts, the split form (1 or 2 waves) and the FP64 blocked
+    forms on these inputs.  Returns (outputs of the chosen configuration, a
+    dict describing it: form, layout, waves, blocks, compose, from_cache, ms)."""
     _check_inputs(cm, X, U, s, params)
     N, nx, m = s.shape[0], cm.nx, cm.m
     kw = dict(device=X.device, dtype=X.dtype)
@@ -201,14 +210,17 @@ def blocked_tune(cm: CisModel, X, U, s, params, K, *, with_xprop=True, stream=No
                    d=torch.empty((nx, N), **kw))
         out["xprop"] = torch.empty((nx, N), **kw) if with_xprop else None
     sh = _shape(X, s, K)
-    b, c, hit = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _lib.check(_lib.load().cis_blocked_tune(
+    ch = _lib.SingleChoice()
+    _lib.check(_lib.load().cis_single_tune(
         cm.handle, ctypes.byref(sh), _ptr(X), _ptr(U), _ptr(s), _ptr(params), _ptr(out["A"]),
         _ptr(out["Bm"] if m else None), _ptr(out["Bp"] if m else None), _ptr(out["S"]),
-        _ptr(out["d"]), _ptr(out["xprop"]), ctypes.byref(b), ctypes.byref(c), ctypes.byref(hit),
-        _stream(stream)))
-    compose = "mfma" if c.value == _lib.CIS_COMPOSE_MFMA else "valu"
-    return out, b.value, compose, bool(hit.value)
+        _ptr(out["d"]), _ptr(out["xprop"]), ctypes.byref(ch), _stream(stream)))
+    names = {v: k for k, v in LAYOUTS.items()}
+    choice = dict(form=FORMS[ch.form], layout=names.get(ch.layout, "rule"), waves=ch.waves,
+                  blocks=ch.blocks,
+                  compose="mfma" if ch.compose == _lib.CIS_COMPOSE_MFMA else "valu",
+                  from_cache=bool(ch.from_cache), ms=float(ch.ms))
+    return out, choice
 
 
 def split_workspace_bytes(cm: CisModel, N, K, dtype=torch.float64):

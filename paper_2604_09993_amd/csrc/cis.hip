@@ -782,9 +782,10 @@ static cis_status launch_discretize_as(const cis_model* m, const cis_shape* sh, 
     return CIS_OK;
 }
 
-// One trajectory: the first layout whose (interval, column group) workgroups
-// can all be resident at once, one per CU: latency (S group of its own), the
-// latency layout with S on leg lanes, narrow; the throughput layout beyond.
+// One trajectory: unless cis_shape.layout names one, the first layout whose
+// (interval, column group) workgroups can all be resident at once, one per CU:
+// latency (S group of its own), the latency layout with S on leg lanes,
+// narrow; the throughput layout beyond.
 template <class T, int L, int D>
 static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, const void* X,
                                     const void* U, const void* s, const void* prm, void* A,
@@ -794,6 +795,14 @@ static cis_status launch_discretize(const cis_model* m, const cis_shape* sh, con
     using TLS = LatencyTopoS<T, L, D>;
     using TN = NarrowTopo<T, L, D>;
     using TT = ThroughputTopo<T, L, D>;
+    // an explicit layout (cis_shape.layout 1..4) overrides the rule
+    switch (sh->layout) {
+    case 1: return launch_discretize_as<T, TL>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    case 2: return launch_discretize_as<T, TLS>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    case 3: return launch_discretize_as<T, TN>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    case 4: return launch_discretize_as<T, TT>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);
+    default: break;
+    }
     const int cus = device_cus();
     if ((int64_t)sh->N * TL::NGRP <= cus)
         return launch_discretize_as<T, TL>(m, sh, X, U, s, prm, A, Bm, Bp, S, d, xp, stream);

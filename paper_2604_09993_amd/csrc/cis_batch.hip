@@ -51,11 +51,12 @@ namespace cis {
 
 // ---------------------------------------------------------------------------
 // Tuning cache: the choices CIS_SCHED_TUNE makes per model group (and the
-// substep-blocking tuner per trajectory shape), kept in the JSON file named by
-// CIS_TUNE_CACHE (no variable: no cache) as
+// single-trajectory tuner per trajectory shape), kept in the JSON file named
+// by CIS_TUNE_CACHE (no variable: no cache) as
 //   {"version": 1, "entries": {"<key>": {"split": s, "waves": w, "persist": p,
 //                                        "def_lane": d, "adj_waves": a,
-//                                        "blocks": b, "compose": c}, ...}}
+//                                        "blocks": b, "compose": c,
+//                                        "form": f, "layout": l}, ...}}
 // keyed by device (architecture, compute units), topology, dtype, operations,
 // work-list length and substep range (and checkpoint spacing with the reverse
 // sweep); -1 marks a choice that was not made.  A missing or unreadable file
@@ -102,6 +103,8 @@ struct CacheParser {
             else if (k == "adj_waves") c.adj_waves = (int)v;
             else if (k == "blocks") c.blocks = (int)v;
             else if (k == "compose") c.compose = (int)v;
+            else if (k == "form") c.form = (int)v;
+            else if (k == "layout") c.layout = (int)v;
         } while (lit(','));
         return lit('}');
     }
@@ -154,7 +157,8 @@ bool cache_write(const std::string& path, const std::map<std::string, TuneChoice
             f << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": {\"split\": " << c.split
               << ", \"waves\": " << c.waves << ", \"persist\": " << c.persist
               << ", \"def_lane\": " << c.def_lane << ", \"adj_waves\": " << c.adj_waves
-              << ", \"blocks\": " << c.blocks << ", \"compose\": " << c.compose << "}";
+              << ", \"blocks\": " << c.blocks << ", \"compose\": " << c.compose
+              << ", \"form\": " << c.form << ", \"layout\": " << c.layout << "}";
             first = false;
         }
         f << "\n}}\n";

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "../../include/cis.h"
 #include "cis_host.hpp"
@@ -341,8 +342,8 @@ extern "C" cis_status cis_discretize_blocked(const cis_model* model, const cis_s
 }
 
 // ---------------------------------------------------------------------------
-// Substep-blocking tuner of one trajectory shape: the one-launch kernel
-// (blocks = 1) against every blocked configuration, timed on the caller's data.
+// Tuner of the discretize step for one trajectory shape: one-launch layouts,
+// split form, blocked forms, timed on the caller's data.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -351,7 +352,7 @@ template <class F>
 float time_ms(F run, hipStream_t hs, int reps, cis_status& st) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        st = fail(CIS_ERR_HIP, "cis_blocked_tune: event creation failed");
+        st = fail(CIS_ERR_HIP, "cis_single_tune: event creation failed");
         return 0.0f;
     }
     float best = -1.0f;
@@ -360,7 +361,7 @@ float time_ms(F run, hipStream_t hs, int reps, cis_status& st) {
         hipEventRecord(e0, hs);
         st = run();
         hipEventRecord(e1, hs);
-        if (hipEventSynchronize(e1) != hipSuccess) st = fail(CIS_ERR_HIP, "cis_blocked_tune: sync failed");
+        if (hipEventSynchronize(e1) != hipSuccess) st = fail(CIS_ERR_HIP, "cis_single_tune: sync failed");
         float ms = 0.0f;
         hipEventElapsedTime(&ms, e0, e1);
         if (best < 0.0f || ms < best) best = ms;
@@ -370,89 +371,125 @@ float time_ms(F run, hipStream_t hs, int reps, cis_status& st) {
     return best;
 }
 
+bool valid_choice(const cis_single_choice& c, const cis_model* m, const cis_shape* sh) {
+    const bool legs = m->L >= 1 && m->D >= 1;
+    switch (c.form) {
+    case CIS_FORM_ONE_LAUNCH: return c.layout >= 1 && c.layout <= 4;
+    case CIS_FORM_SPLIT: return legs && (c.waves == 1 || c.waves == 2);
+    case CIS_FORM_BLOCKED:
+        return sh->dtype == CIS_F64 && c.blocks >= 2 && c.blocks <= 8 &&
+               sh->substeps % c.blocks == 0 &&
+               (c.compose == CIS_COMPOSE_VALU || c.compose == CIS_COMPOSE_MFMA);
+    default: return false;
+    }
+}
+
 }  // namespace
 
-extern "C" cis_status cis_blocked_tune(const cis_model* model, const cis_shape* shape,
-                                       const void* X, const void* U, const void* s,
-                                       const void* params, void* A, void* Bm, void* Bp, void* S,
-                                       void* defect, void* xprop, int32_t* blocks,
-                                       int32_t* compose, int32_t* from_cache, void* stream) {
+extern "C" cis_status cis_single_tune(const cis_model* model, const cis_shape* shape,
+                                      const void* X, const void* U, const void* s,
+                                      const void* params, void* A, void* Bm, void* Bp, void* S,
+                                      void* defect, void* xprop, cis_single_choice* choice,
+                                      void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
-    if (!blocks || !compose)
-        return fail(CIS_ERR_NULL, "cis_blocked_tune: blocks and compose outputs are required");
-    if (shape->dtype != CIS_F64)
-        return fail(CIS_ERR_DTYPE, "cis_blocked_tune: only CIS_F64 is offered");
+    if (!choice) return fail(CIS_ERR_NULL, "cis_single_tune: choice output is required");
+    if (shape->layout != 0) return fail(CIS_ERR_DIM, "cis_single_tune: shape->layout must be 0");
     hipStream_t hs = (hipStream_t)stream;
     const int K = shape->substeps;
+    const bool f64 = shape->dtype == CIS_F64;
+    const bool legs = model->L >= 1 && model->D >= 1;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return fail(CIS_ERR_HIP, "cis_blocked_tune: no device");
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CIS_ERR_HIP, "cis_single_tune: no device");
+    std::memset(choice, 0, sizeof(*choice));
     // cache lookup
     const char* cpath = std::getenv("CIS_TUNE_CACHE");
     char key[256];
-    std::snprintf(key, sizeof(key), "blocked|%s|L%dD%d|f64|N%d|K%d", device_tag(dev).c_str(),
-                  model->L, model->D, shape->N, K);
+    std::snprintf(key, sizeof(key), "single|%s|L%dD%d|%s|N%d|K%d", device_tag(dev).c_str(),
+                  model->L, model->D, f64 ? "f64" : "f32", shape->N, K);
     bool hit = false;
-    if (from_cache) *from_cache = 0;
     if (cpath && *cpath) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         const auto cache = cache_read(cpath);
         const auto it = cache.find(key);
-        if (it != cache.end() && it->second.blocks >= 1 &&
-            (it->second.blocks == 1 || K % it->second.blocks == 0) &&
-            (it->second.compose == CIS_COMPOSE_VALU || it->second.compose == CIS_COMPOSE_MFMA)) {
-            *blocks = it->second.blocks;
-            *compose = it->second.compose;
-            hit = true;
-            if (from_cache) *from_cache = 1;
+        if (it != cache.end()) {
+            cis_single_choice c{};
+            c.form = it->second.form;
+            c.layout = it->second.layout;
+            c.waves = it->second.waves;
+            c.blocks = it->second.blocks;
+            c.compose = it->second.compose;
+            if (valid_choice(c, model, shape)) {
+                *choice = c;
+                choice->from_cache = 1;
+                hit = true;
+            }
         }
     }
-    // workspace for the largest blocked candidate
+    // workspace for the largest candidate (split records, blocked passes)
     size_t wsz = 0;
-    for (int b = 2; b <= 8 && b <= K; ++b)
+    if (legs) {
+        size_t b = 0;
+        st = cis_split_workspace_size(model, shape, &b);
+        if (st != CIS_OK) return st;
+        wsz = std::max(wsz, b);
+    }
+    for (int b = 2; f64 && b <= 8 && b <= K; ++b)
         if (K % b == 0) wsz = std::max(wsz, blocked_layout(model, shape, b).total);
     void* ws = nullptr;
     if (wsz && hipMalloc(&ws, wsz) != hipSuccess)
-        return fail(CIS_ERR_HIP, "cis_blocked_tune: workspace of %zu bytes", wsz);
-    auto run = [&](int b, int c) -> cis_status {
-        if (b == 1)
-            return cis_discretize(model, shape, X, U, s, params, A, Bm, Bp, S, defect, xprop, stream);
-        return cis_discretize_blocked(model, shape, X, U, s, params, b, c, A, Bm, Bp, S, defect,
-                                      xprop, ws, wsz, stream);
+        return fail(CIS_ERR_HIP, "cis_single_tune: workspace of %zu bytes", wsz);
+    auto run = [&](const cis_single_choice& c) -> cis_status {
+        if (c.form == CIS_FORM_SPLIT)
+            return cis_discretize_split(model, shape, X, U, s, params, c.waves, A, Bm, Bp, S,
+                                        defect, xprop, ws, wsz, stream);
+        if (c.form == CIS_FORM_BLOCKED)
+            return cis_discretize_blocked(model, shape, X, U, s, params, c.blocks, c.compose, A,
+                                          Bm, Bp, S, defect, xprop, ws, wsz, stream);
+        cis_shape sh = *shape;
+        sh.layout = c.layout;
+        return cis_discretize(model, &sh, X, U, s, params, A, Bm, Bp, S, defect, xprop, stream);
     };
     if (!hit) {
-        int best_b = 1, best_c = CIS_COMPOSE_VALU;
-        float best = time_ms([&] { return run(1, CIS_COMPOSE_VALU); }, hs, 3, st);
-        for (int b = 2; b <= 8 && b <= K && st == CIS_OK; ++b) {
-            if (K % b != 0) continue;
-            for (int c = CIS_COMPOSE_VALU; c <= CIS_COMPOSE_MFMA && st == CIS_OK; ++c) {
-                const float ms = time_ms([&] { return run(b, c); }, hs, 3, st);
-                if (st == CIS_OK && ms < best) {
-                    best = ms;
-                    best_b = b;
-                    best_c = c;
-                }
+        std::vector<cis_single_choice> cands;
+        for (int l = 1; l <= 4; ++l) cands.push_back({CIS_FORM_ONE_LAUNCH, l, 0, 0, 0, 0, 0.0f});
+        if (legs)
+            for (int w = 1; w <= 2; ++w) cands.push_back({CIS_FORM_SPLIT, 0, w, 0, 0, 0, 0.0f});
+        for (int b = 2; f64 && b <= 8 && b <= K; ++b)
+            if (K % b == 0)
+                for (int c = CIS_COMPOSE_VALU; c <= CIS_COMPOSE_MFMA; ++c)
+                    cands.push_back({CIS_FORM_BLOCKED, 0, 0, b, c, 0, 0.0f});
+        int best = -1;
+        float best_ms = 0.0f;
+        for (int i = 0; i < (int)cands.size() && st == CIS_OK; ++i) {
+            const float ms = time_ms([&] { return run(cands[i]); }, hs, 3, st);
+            if (st == CIS_OK && (best < 0 || ms < best_ms)) {
+                best = i;
+                best_ms = ms;
             }
         }
         if (st != CIS_OK) {
             if (ws) (void)hipFree(ws);
             return st;
         }
-        *blocks = best_b;
-        *compose = best_c;
+        *choice = cands[best];
+        choice->ms = best_ms;
         if (cpath && *cpath) {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto cur = cache_read(cpath);
             TuneChoice& tc = cur[key];
-            tc.blocks = best_b;
-            tc.compose = best_c;
+            tc.form = choice->form;
+            tc.layout = choice->layout;
+            tc.waves = choice->waves;
+            tc.blocks = choice->blocks;
+            tc.compose = choice->compose;
             (void)cache_write(cpath, cur);
         }
     }
     // the outputs hold the chosen configuration's results
-    st = run(*blocks, *compose);
+    st = run(*choice);
     if (st == CIS_OK && hipStreamSynchronize(hs) != hipSuccess)
-        st = fail(CIS_ERR_HIP, "cis_blocked_tune: stream synchronization failed");
+        st = fail(CIS_ERR_HIP, "cis_single_tune: stream synchronization failed");
     if (ws) (void)hipFree(ws);
     return st;
 }

@@ -29,7 +29,8 @@ cis_status check_common(const cis_model* m, const cis_shape* sh, const void* X, 
     if (!m || !sh) return fail(CIS_ERR_NULL, "model and shape are required");
     if (sh->dtype != CIS_F64 && sh->dtype != CIS_F32)
         return fail(CIS_ERR_DTYPE, "unknown dtype %d", sh->dtype);
-    if (sh->reserved != 0) return fail(CIS_ERR_DIM, "cis_shape.reserved must be 0");
+    if (sh->layout < 0 || sh->layout > 4)
+        return fail(CIS_ERR_DIM, "cis_shape.layout=%d outside [0, 4]", sh->layout);
     if (sh->N < 1) return fail(CIS_ERR_DIM, "N=%d must be >= 1", sh->N);
     if (sh->substeps < 1 || sh->substeps > 4096)
         return fail(CIS_ERR_DIM, "substeps=%d outside [1, 4096]", sh->substeps);

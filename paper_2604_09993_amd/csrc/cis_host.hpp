@@ -37,7 +37,7 @@ cis_status check_common(const cis_model* m, const cis_shape* sh, const void* X, 
 // is read and rewritten under g_cache_mu.
 struct TuneChoice {
     int split = -1, waves = -1, persist = -1, def_lane = -1, adj_waves = -1;
-    int blocks = -1, compose = -1;
+    int blocks = -1, compose = -1, form = -1, layout = -1;
 };
 extern std::mutex g_cache_mu;
 std::map<std::string, TuneChoice> cache_read(const std::string& path);

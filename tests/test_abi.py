@@ -120,7 +120,8 @@ def test_entry_points_validate_before_launch():
     assert _call_discretize(h, _lib.Shape(5, 4, 0, 0, 5, 5)) == _lib.CIS_ERR_DIM   # ld_node < N+1
     assert _call_discretize(h, _lib.Shape(5, 4, 0, 0, 6, 4)) == _lib.CIS_ERR_DIM   # ld_int < N
     assert _call_discretize(h, _lib.Shape(5, 4, 7, 0, 6, 5)) == _lib.CIS_ERR_DTYPE
-    assert _call_discretize(h, _lib.Shape(5, 4, 0, 1, 6, 5)) == _lib.CIS_ERR_DIM   # reserved
+    assert _call_discretize(h, _lib.Shape(5, 4, 0, 5, 6, 5)) == _lib.CIS_ERR_DIM   # layout > 4
+    assert _call_discretize(h, _lib.Shape(5, 4, 0, -1, 6, 5)) == _lib.CIS_ERR_DIM
     assert _call_discretize(h, good, X=0) == _lib.CIS_ERR_NULL
     assert _call_discretize(h, good, U=0) == _lib.CIS_ERR_NULL                      # m > 0
     assert _call_discretize(h, good, X=12) == _lib.CIS_ERR_LAYOUT                   # misaligned
@@ -149,14 +150,14 @@ def test_entry_points_validate_before_launch():
                                                     P(8), P(8), None, ws, nb, None)
     assert blk(None, need.value) == _lib.CIS_ERR_WORKSPACE
     assert blk(P(8), need.value - 8) == _lib.CIS_ERR_WORKSPACE
-    # the blocking tuner: outputs for the choice are required, FP32 is refused
-    bi, ci = ctypes.c_int32(), ctypes.c_int32()
-    tune = lambda sh, b, c: lib.cis_blocked_tune(h, ctypes.byref(sh), P(8), P(8), P(8), P(8),
-                                                 P(8), P(8), P(8), P(8), P(8), None, b, c, None,
-                                                 None)
-    assert tune(sh4, None, ctypes.byref(ci)) == _lib.CIS_ERR_NULL
-    sh32 = _lib.Shape(5, 4, _lib.CIS_F32, 0, 6, 5)
-    assert tune(sh32, ctypes.byref(bi), ctypes.byref(ci)) == _lib.CIS_ERR_DTYPE
+    # the single-trajectory tuner: the choice output is required, the shape
+    # names no layout (the tuner picks it)
+    ch = _lib.SingleChoice()
+    tune = lambda sh, c: lib.cis_single_tune(h, ctypes.byref(sh), P(8), P(8), P(8), P(8), P(8),
+                                             P(8), P(8), P(8), P(8), None, c, None)
+    assert tune(sh4, None) == _lib.CIS_ERR_NULL
+    assert tune(_lib.Shape(5, 4, _lib.CIS_F64, 3, 6, 5), ctypes.byref(ch)) == _lib.CIS_ERR_DIM
+    assert tune(_lib.Shape(5, 4, 7, 0, 6, 5), ctypes.byref(ch)) == _lib.CIS_ERR_DTYPE
     # the allocation-free reverse sweep holds (2 m + P) N <= 2^20 doubles
     big = (1 << 20) // (2 * model.m + model.n_params) + 1
     shb = _lib.Shape(big, 4, _lib.CIS_F64, 0, big + 1, big)

@@ -79,30 +79,73 @@ def test_blocked_rejects_bad_block_counts():
         api.discretize_blocked(cm, X.float(), U.float(), s.float(), p.float(), 4, 2)
 
 
-def test_blocking_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypatch):
-    """The substep-blocking tuner (one-launch form against every blocked
-    configuration) returns one of its candidates, its outputs are that
+def _check_choice(choice, K, dtype):
+    if choice["form"] == "one_launch":
+        assert choice["layout"] in ("latency", "latency_s", "narrow", "throughput")
+    elif choice["form"] == "split":
+        assert choice["waves"] in (1, 2)
+    else:
+        assert dtype == torch.float64 and 2 <= choice["blocks"] <= 8
+        assert K % choice["blocks"] == 0 and choice["compose"] in ("valu", "mfma")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypatch, dtype):
+    """The single-trajectory tuner (one-launch layouts, split form, blocked
+    forms) returns one of its candidates, its outputs are that
     configuration's (checked against the oracle), and a second call reads the
     same choice back from the CIS_TUNE_CACHE file."""
     import oracle
     from paper_2604_09993_amd import api, synth
-    from parity import PHI64, TOL64, block_err
-    print("blocked tune cheetah7 N=8 K=8", flush=True)
+    from parity import PHI32, PHI64, TOL32, TOL64, block_err
+    print(f"single tune cheetah7 N=8 K=8 {dtype}", flush=True)
     rng = np.random.default_rng(41)
     model = synth.make_cheetah7(rng)
     d = synth.gen_nodes(model, 8, rng, T=0.16)
     K = 8
     cm = api.CisModel(model)
+    X, U = api.to_device_soa(d["X"], dtype=dtype), api.to_device_soa(d["U"], dtype=dtype)
+    s = torch.tensor(d["s"], device="cuda", dtype=dtype)
+    p = torch.tensor(d["p"], device="cuda", dtype=dtype)
+    monkeypatch.setenv("CIS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    out, choice = api.single_tune(cm, X, U, s, p, K)
+    assert not choice["from_cache"] and choice["ms"] > 0
+    _check_choice(choice, K, dtype)
+    # FP32: the oracle runs on the same FP32-rounded inputs
+    r = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if dtype == torch.float32 \
+        else (lambda a: a)
+    ref = oracle.discretize(model, r(d["X"]), r(d["U"]), r(d["s"]), r(d["p"]), K)
+    got = api.as_interval_major(out)
+    phi, tol = (PHI64, TOL64) if dtype == torch.float64 else (PHI32, TOL32)
+    for key in ("A", "Bm", "Bp", "S", "d", "xprop"):
+        assert block_err(got[key].double().cpu().numpy(), ref[key], phi) <= tol, key
+    out2, choice2 = api.single_tune(cm, X, U, s, p, K)
+    assert choice2["from_cache"]
+    for f in ("form", "layout", "waves", "blocks", "compose"):
+        assert choice2[f] == choice[f], f
+    got2 = api.as_interval_major(out2)
+    for key in ("A", "S", "d"):
+        assert torch.equal(got2[key], got[key]), key
+    assert '"form"' in (tmp_path / "tune.json").read_text()
+
+
+@pytest.mark.parametrize("layout", ["latency", "latency_s", "narrow", "throughput"])
+def test_every_one_launch_layout_matches_the_oracle(layout):
+    """cis_shape.layout forces each workgroup layout of the one-launch kernel;
+    every one gives the oracle's results (FP64, quadruped with a ragged N)."""
+    import oracle
+    from paper_2604_09993_amd import api, synth
+    from parity import PHI64, TOL64, block_err
+    print(f"layout {layout} quad13 N=7 K=6", flush=True)
+    rng = np.random.default_rng(43)
+    model = synth.make_quad13(rng)
+    d = synth.gen_nodes(model, 7, rng, T=0.14)
+    K = 6
+    cm = api.CisModel(model)
     X, U = api.to_device_soa(d["X"]), api.to_device_soa(d["U"])
     s = torch.tensor(d["s"], device="cuda")
     p = torch.tensor(d["p"], device="cuda")
-    monkeypatch.setenv("CIS_TUNE_CACHE", str(tmp_path / "tune.json"))
-    out, b, c, hit = api.blocked_tune(cm, X, U, s, p, K)
-    assert not hit and b in (1, 2, 4, 8) and c in ("valu", "mfma")
+    got = api.as_interval_major(api.discretize(cm, X, U, s, p, K, layout=layout))
     ref = oracle.discretize(model, d["X"], d["U"], d["s"], d["p"], K)
-    got = api.as_interval_major(out)
     for key in ("A", "Bm", "Bp", "S", "d", "xprop"):
         assert block_err(got[key].cpu().numpy(), ref[key], PHI64) <= TOL64, key
-    out2, b2, c2, hit2 = api.blocked_tune(cm, X, U, s, p, K)
-    assert hit2 and (b2, c2) == (b, c)
-    assert '"blocks"' in (tmp_path / "tune.json").read_text()
