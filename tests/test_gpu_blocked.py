@@ -129,23 +129,29 @@ def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypa
     assert '"form"' in (tmp_path / "tune.json").read_text()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("layout", ["latency", "latency_s", "narrow", "throughput"])
-def test_every_one_launch_layout_matches_the_oracle(layout):
+def test_every_one_launch_layout_matches_the_oracle(layout, dtype):
     """cis_shape.layout forces each workgroup layout of the one-launch kernel;
-    every one gives the oracle's results (FP64, quadruped with a ragged N)."""
+    every one gives the oracle's results (quadruped with a ragged N; FP32
+    against the oracle on the same FP32-rounded inputs)."""
     import oracle
     from paper_2604_09993_amd import api, synth
-    from parity import PHI64, TOL64, block_err
-    print(f"layout {layout} quad13 N=7 K=6", flush=True)
+    from parity import PHI32, PHI64, TOL32, TOL64, block_err
+    print(f"layout {layout} quad13 N=7 K=6 {dtype}", flush=True)
     rng = np.random.default_rng(43)
     model = synth.make_quad13(rng)
     d = synth.gen_nodes(model, 7, rng, T=0.14)
     K = 6
     cm = api.CisModel(model)
-    X, U = api.to_device_soa(d["X"]), api.to_device_soa(d["U"])
-    s = torch.tensor(d["s"], device="cuda")
-    p = torch.tensor(d["p"], device="cuda")
+    X = api.to_device_soa(d["X"], dtype=dtype)
+    U = api.to_device_soa(d["U"], dtype=dtype)
+    s = torch.tensor(d["s"], device="cuda", dtype=dtype)
+    p = torch.tensor(d["p"], device="cuda", dtype=dtype)
     got = api.as_interval_major(api.discretize(cm, X, U, s, p, K, layout=layout))
-    ref = oracle.discretize(model, d["X"], d["U"], d["s"], d["p"], K)
+    r = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if dtype == torch.float32 \
+        else (lambda a: a)
+    ref = oracle.discretize(model, r(d["X"]), r(d["U"]), r(d["s"]), r(d["p"]), K)
+    phi, tol = (PHI64, TOL64) if dtype == torch.float64 else (PHI32, TOL32)
     for key in ("A", "Bm", "Bp", "S", "d", "xprop"):
-        assert block_err(got[key].cpu().numpy(), ref[key], PHI64) <= TOL64, key
+        assert block_err(got[key].double().cpu().numpy(), ref[key], phi) <= tol, key
