@@ -47,6 +47,19 @@
  * synchronization.  A cis_model is an immutable host object and may be used
  * from several threads and streams at once.  On any returned error nothing
  * has been enqueued and no output has been written.
+ *
+ * Non-finite values (NaN, +-inf) in the inputs propagate through the
+ * arithmetic and are not checked.  Debug mode: with the environment variable
+ * CIS_DEBUG_FINITE set (non-empty, not "0"), cis_discretize,
+ * cis_discretize_split, cis_discretize_blocked, cis_discretize_rkf,
+ * cis_discretize_paper, cis_defects and cis_discretize_adjoint, after a
+ * successful launch, count the non-finite values of every input and output
+ * array (the blocks the call reads or writes; checkpoints and workspaces
+ * excluded), synchronize the stream, and return CIS_ERR_NONFINITE, with
+ * cis_last_error naming each such array and its count ("input X 3, output A
+ * 120"); the outputs are then written.  Debug mode allocates, copies and
+ * synchronizes: it is not for hot loops, and the allocation-free entry point
+ * does not take part in it.
  */
 #ifndef CIS_H
 #define CIS_H
@@ -67,7 +80,8 @@ typedef enum {
     CIS_ERR_WORKSPACE = 5,    /* workspace missing or too small              */
     CIS_ERR_MODEL = 6,        /* malformed model description                 */
     CIS_ERR_HIP = 7,          /* the HIP runtime rejected a launch           */
-    CIS_ERR_UNSUPPORTED = 8   /* topology with no compiled kernel            */
+    CIS_ERR_UNSUPPORTED = 8,  /* topology with no compiled kernel            */
+    CIS_ERR_NONFINITE = 9     /* debug mode only: non-finite input or output */
 } cis_status;
 
 typedef enum { CIS_F64 = 0, CIS_F32 = 1 } cis_dtype;

@@ -23,6 +23,7 @@ CIS_ERR_WORKSPACE = 5
 CIS_ERR_MODEL = 6
 CIS_ERR_HIP = 7
 CIS_ERR_UNSUPPORTED = 8
+CIS_ERR_NONFINITE = 9
 CIS_F64 = 0
 CIS_F32 = 1
 CIS_BATCH_DISCRETIZE = 1

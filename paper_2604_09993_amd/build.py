@@ -9,9 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcis.so")
 SOURCES = ["cis.hip", "cis_adjoint.hip", "cis_batch.hip", "cis_blocked.hip", "cis_split.hip",
-           "cis_impact.hip", "cis_rkf.hip", "cis_paper.hip",
+           "cis_impact.hip", "cis_rkf.hip", "cis_paper.hip", "cis_debug.hip",
            "cis_host.cpp", "cis_ldl.cpp"]
 HEADERS = ["cis_model.hpp", "cis_body.hpp", "cis_host.hpp", "cis_launch.hpp", "cis_split.hpp",
+           "cis_debug.hpp",
            os.path.join("..", "..", "include", "cis.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

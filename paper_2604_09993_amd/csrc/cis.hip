@@ -18,6 +18,7 @@
 #include "../../include/cis.h"
 #include "cis_model.hpp"
 #include "cis_body.hpp"
+#include "cis_debug.hpp"
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
 
@@ -979,10 +980,10 @@ int discretize_units_per_item(const cis_model* m, int32_t dtype) {
 
 using namespace cis;
 
-extern "C" cis_status cis_discretize(const cis_model* model, const cis_shape* shape,
-                                     const void* X, const void* U, const void* s,
-                                     const void* params, void* A, void* Bm, void* Bp, void* S,
-                                     void* defect, void* xprop, void* stream) {
+static cis_status discretize_impl(const cis_model* model, const cis_shape* shape,
+                                  const void* X, const void* U, const void* s,
+                                  const void* params, void* A, void* Bm, void* Bp, void* S,
+                                  void* defect, void* xprop, void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
     const size_t es = elem_size(shape->dtype);
@@ -1005,10 +1006,22 @@ extern "C" cis_status cis_discretize(const cis_model* model, const cis_shape* sh
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize: topology has no compiled kernel");
 }
 
-extern "C" cis_status cis_defects(const cis_model* model, const cis_shape* shape, const void* X,
-                                  const void* U, const void* s, const void* params,
-                                  void* defect, void* xprop, void* ckpt, int32_t ckpt_every,
-                                  void* stream) {
+// Debug mode (CIS_DEBUG_FINITE): the non-finite scan after the launch.
+extern "C" cis_status cis_discretize(const cis_model* model, const cis_shape* shape,
+                                     const void* X, const void* U, const void* s,
+                                     const void* params, void* A, void* Bm, void* Bp, void* S,
+                                     void* defect, void* xprop, void* stream) {
+    const cis_status st =
+        discretize_impl(model, shape, X, U, s, params, A, Bm, Bp, S, defect, xprop, stream);
+    if (st != CIS_OK || !debug_finite_enabled()) return st;
+    return debug_scan_forward("cis_discretize", model, shape, model->nx, model->m, X, U, s,
+                              params, A, Bm, Bp, S, defect, xprop, nullptr, stream);
+}
+
+static cis_status defects_impl(const cis_model* model, const cis_shape* shape, const void* X,
+                               const void* U, const void* s, const void* params,
+                               void* defect, void* xprop, void* ckpt, int32_t ckpt_every,
+                               void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
     const size_t es = elem_size(shape->dtype);
@@ -1030,4 +1043,15 @@ extern "C" cis_status cis_defects(const cis_model* model, const cis_shape* shape
     CIS_TOPOLOGIES(CIS_DISPATCH_DEF)
 #undef CIS_DISPATCH_DEF
     return fail(CIS_ERR_UNSUPPORTED, "cis_defects: topology has no compiled kernel");
+}
+
+extern "C" cis_status cis_defects(const cis_model* model, const cis_shape* shape, const void* X,
+                                  const void* U, const void* s, const void* params,
+                                  void* defect, void* xprop, void* ckpt, int32_t ckpt_every,
+                                  void* stream) {
+    const cis_status st =
+        defects_impl(model, shape, X, U, s, params, defect, xprop, ckpt, ckpt_every, stream);
+    if (st != CIS_OK || !debug_finite_enabled()) return st;
+    return debug_scan_forward("cis_defects", model, shape, model->nx, model->m, X, U, s, params,
+                              nullptr, nullptr, nullptr, nullptr, defect, xprop, nullptr, stream);
 }

@@ -20,6 +20,7 @@
 #include <mutex>
 
 #include "../../include/cis.h"
+#include "cis_debug.hpp"
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
 #include "cis_body.hpp"
@@ -943,12 +944,12 @@ extern "C" cis_status cis_adjoint_workspace_size(const cis_model* m, const cis_s
     return CIS_OK;
 }
 
-extern "C" cis_status cis_discretize_adjoint(const cis_model* model, const cis_shape* shape,
-                                             const void* X, const void* U, const void* s,
-                                             const void* params, const void* ckpt,
-                                             int32_t ckpt_every, const void* seed, void* gX,
-                                             void* gU, void* gs, void* gparams, void* ws,
-                                             size_t ws_bytes, void* stream) {
+static cis_status discretize_adjoint_impl(const cis_model* model, const cis_shape* shape,
+                                          const void* X, const void* U, const void* s,
+                                          const void* params, const void* ckpt,
+                                          int32_t ckpt_every, const void* seed, void* gX,
+                                          void* gU, void* gs, void* gparams, void* ws,
+                                          size_t ws_bytes, void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
     if (shape->dtype != CIS_F64)
@@ -976,6 +977,28 @@ extern "C" cis_status cis_discretize_adjoint(const cis_model* model, const cis_s
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_adjoint: topology has no compiled kernel");
 }
 
+extern "C" cis_status cis_discretize_adjoint(const cis_model* model, const cis_shape* shape,
+                                             const void* X, const void* U, const void* s,
+                                             const void* params, const void* ckpt,
+                                             int32_t ckpt_every, const void* seed, void* gX,
+                                             void* gU, void* gs, void* gparams, void* ws,
+                                             size_t ws_bytes, void* stream) {
+    const cis_status st = discretize_adjoint_impl(model, shape, X, U, s, params, ckpt,
+                                                  ckpt_every, seed, gX, gU, gs, gparams, ws,
+                                                  ws_bytes, stream);
+    if (st != CIS_OK || !debug_finite_enabled()) return st;
+    const int64_t N = shape->N, ln = shape->ld_node, li = shape->ld_int;
+    const DebugArr arr[] = {
+        {"X", X, model->nx, N + 1, ln, false},   {"U", U, model->m, N + 1, ln, false},
+        {"s", s, 1, N, N, false},                {"params", params, 1, model->np, model->np, false},
+        {"seed", seed, model->nx, N, li, false}, {"gX", gX, model->nx, N + 1, ln, true},
+        {"gU", gU, model->m, N + 1, ln, true},   {"gs", gs, 1, N, N, true},
+        {"gparams", gparams, 1, model->np, model->np, true},
+    };
+    return debug_scan("cis_discretize_adjoint", CIS_F64, stream, arr,
+                      (int)(sizeof(arr) / sizeof(arr[0])));
+}
+
 extern "C" cis_status cis_discretize_adjoint_noalloc(const cis_model* model,
                                                      const cis_shape* shape, const void* X,
                                                      const void* U, const void* s,
@@ -996,6 +1019,6 @@ extern "C" cis_status cis_discretize_adjoint_noalloc(const cis_model* model,
     if (st != CIS_OK) return st;
     // same validation and kernels as cis_discretize_adjoint, with the device
     // array as the workspace
-    return cis_discretize_adjoint(model, shape, X, U, s, params, ckpt, ckpt_every, seed, gX, gU,
-                                  gs, gparams, ws, NOALLOC_DOUBLES * sizeof(double), stream);
+    return discretize_adjoint_impl(model, shape, X, U, s, params, ckpt, ckpt_every, seed, gX,
+                                   gU, gs, gparams, ws, NOALLOC_DOUBLES * sizeof(double), stream);
 }

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/cis.h"
+#include "cis_debug.hpp"
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
 #include "cis_model.hpp"
@@ -289,12 +290,12 @@ extern "C" cis_status cis_blocked_workspace_size(const cis_model* model, const c
     return CIS_OK;
 }
 
-extern "C" cis_status cis_discretize_blocked(const cis_model* model, const cis_shape* shape,
-                                             const void* X, const void* U, const void* s,
-                                             const void* params, int32_t blocks,
-                                             int32_t compose, void* A, void* Bm, void* Bp,
-                                             void* S, void* defect, void* xprop, void* ws,
-                                             size_t ws_bytes, void* stream) {
+static cis_status discretize_blocked_impl(const cis_model* model, const cis_shape* shape,
+                                          const void* X, const void* U, const void* s,
+                                          const void* params, int32_t blocks,
+                                          int32_t compose, void* A, void* Bm, void* Bp,
+                                          void* S, void* defect, void* xprop, void* ws,
+                                          size_t ws_bytes, void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
     if (shape->dtype != CIS_F64)
@@ -339,6 +340,20 @@ extern "C" cis_status cis_discretize_blocked(const cis_model* model, const cis_s
     CIS_TOPOLOGIES(CIS_COMPOSE)
 #undef CIS_COMPOSE
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_blocked: topology has no compiled kernel");
+}
+
+extern "C" cis_status cis_discretize_blocked(const cis_model* model, const cis_shape* shape,
+                                             const void* X, const void* U, const void* s,
+                                             const void* params, int32_t blocks,
+                                             int32_t compose, void* A, void* Bm, void* Bp,
+                                             void* S, void* defect, void* xprop, void* ws,
+                                             size_t ws_bytes, void* stream) {
+    const cis_status st = discretize_blocked_impl(model, shape, X, U, s, params, blocks, compose,
+                                                  A, Bm, Bp, S, defect, xprop, ws, ws_bytes,
+                                                  stream);
+    if (st != CIS_OK || !debug_finite_enabled()) return st;
+    return debug_scan_forward("cis_discretize_blocked", model, shape, model->nx, model->m, X, U,
+                              s, params, A, Bm, Bp, S, defect, xprop, nullptr, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,6 +64,7 @@ extern "C" const char* cis_status_string(cis_status st) {
         case CIS_ERR_MODEL: return "malformed model description";
         case CIS_ERR_HIP: return "HIP runtime error";
         case CIS_ERR_UNSUPPORTED: return "topology has no compiled kernel";
+        case CIS_ERR_NONFINITE: return "non-finite values (debug mode)";
     }
     return "unknown status";
 }

@@ -31,6 +31,7 @@
 #include <utility>
 
 #include "../../include/cis.h"
+#include "cis_debug.hpp"
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
 #include "cis_model.hpp"
@@ -776,11 +777,11 @@ extern "C" cis_status cis_paper_workspace_size(const cis_model* m, const cis_sha
     return CIS_OK;
 }
 
-extern "C" cis_status cis_discretize_paper(const cis_model* model, const cis_shape* shape,
-                                           const void* X, const void* U, const void* s,
-                                           const void* params, void* A, void* Bm, void* Bp,
-                                           void* S, void* defect, void* xprop, void* ws,
-                                           size_t ws_bytes, void* stream) {
+static cis_status discretize_paper_impl(const cis_model* model, const cis_shape* shape,
+                                        const void* X, const void* U, const void* s,
+                                        const void* params, void* A, void* Bm, void* Bp,
+                                        void* S, void* defect, void* xprop, void* ws,
+                                        size_t ws_bytes, void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
     if (shape->dtype != CIS_F64)
@@ -817,4 +818,19 @@ extern "C" cis_status cis_discretize_paper(const cis_model* model, const cis_sha
     CIS_TOPOLOGIES(CIS_DISPATCH_PAPER)
 #undef CIS_DISPATCH_PAPER
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_paper: topology has no compiled kernel");
+}
+
+extern "C" cis_status cis_discretize_paper(const cis_model* model, const cis_shape* shape,
+                                           const void* X, const void* U, const void* s,
+                                           const void* params, void* A, void* Bm, void* Bp,
+                                           void* S, void* defect, void* xprop, void* ws,
+                                           size_t ws_bytes, void* stream) {
+    cis_status st = discretize_paper_impl(model, shape, X, U, s, params, A, Bm, Bp, S, defect,
+                                          xprop, ws, ws_bytes, stream);
+    if (st != CIS_OK || !debug_finite_enabled()) return st;
+    int32_t nx = 0, nu = 0;
+    st = cis_paper_dims(model, &nx, &nu);
+    if (st != CIS_OK) return st;
+    return debug_scan_forward("cis_discretize_paper", model, shape, nx, nu, X, U, s, params, A,
+                              Bm, Bp, S, defect, xprop, nullptr, stream);
 }

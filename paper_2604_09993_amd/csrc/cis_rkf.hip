@@ -26,6 +26,7 @@
 
 #include "../../include/cis.h"
 #include "cis_body.hpp"
+#include "cis_debug.hpp"
 #include "cis_host.hpp"
 #include "cis_launch.hpp"
 #include "cis_model.hpp"
@@ -588,11 +589,11 @@ extern "C" cis_status cis_rkf_workspace_size(const cis_model* m, const cis_shape
     return rkf_ws_bytes(m, sh, bytes);
 }
 
-extern "C" cis_status cis_discretize_rkf(const cis_model* model, const cis_shape* shape,
-                                         const void* X, const void* U, const void* s,
-                                         const void* params, int32_t waves, void* A, void* Bm,
-                                         void* Bp, void* S, void* defect, void* xprop, void* err,
-                                         void* ws, size_t ws_bytes, void* stream) {
+static cis_status discretize_rkf_impl(const cis_model* model, const cis_shape* shape,
+                                      const void* X, const void* U, const void* s,
+                                      const void* params, int32_t waves, void* A, void* Bm,
+                                      void* Bp, void* S, void* defect, void* xprop, void* err,
+                                      void* ws, size_t ws_bytes, void* stream) {
     cis_status st = check_common(model, shape, X, U, s, params);
     if (st != CIS_OK) return st;
     if (waves != 1 && waves != 2)
@@ -620,4 +621,16 @@ extern "C" cis_status cis_discretize_rkf(const cis_model* model, const cis_shape
     CIS_TOPOLOGIES(CIS_DISPATCH_RKF)
 #undef CIS_DISPATCH_RKF
     return fail(CIS_ERR_UNSUPPORTED, "cis_discretize_rkf: topology has no compiled kernel");
+}
+
+extern "C" cis_status cis_discretize_rkf(const cis_model* model, const cis_shape* shape,
+                                         const void* X, const void* U, const void* s,
+                                         const void* params, int32_t waves, void* A, void* Bm,
+                                         void* Bp, void* S, void* defect, void* xprop, void* err,
+                                         void* ws, size_t ws_bytes, void* stream) {
+    const cis_status st = discretize_rkf_impl(model, shape, X, U, s, params, waves, A, Bm, Bp, S,
+                                              defect, xprop, err, ws, ws_bytes, stream);
+    if (st != CIS_OK || !debug_finite_enabled()) return st;
+    return debug_scan_forward("cis_discretize_rkf", model, shape, model->nx, model->m, X, U, s,
+                              params, A, Bm, Bp, S, defect, xprop, err, stream);
 }

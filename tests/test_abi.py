@@ -134,6 +134,7 @@ def test_entry_points_validate_before_launch():
     assert lib.cis_defects(h, ctypes.byref(good), P(8), P(8), P(8), P(8), None, None, None, 0,
                            None) == _lib.CIS_ERR_NULL
     assert lib.cis_status_string(_lib.CIS_ERR_DIM) == b"dimension out of range"
+    assert lib.cis_status_string(_lib.CIS_ERR_NONFINITE) == b"non-finite values (debug mode)"
     # workspaces: missing or short workspaces are refused before any launch
     need = ctypes.c_size_t(0)
     assert lib.cis_adjoint_workspace_size(h, ctypes.byref(good), ctypes.byref(need)) == 0
