@@ -89,8 +89,9 @@ def _check_choice(choice, K, dtype):
         assert K % choice["blocks"] == 0 and choice["compose"] in ("valu", "mfma")
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypatch, dtype):
+@pytest.mark.parametrize("name,dtype", [("cheetah7", torch.float64), ("cheetah7", torch.float32),
+                                        ("point1", torch.float64)])
+def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypatch, name, dtype):
     """The single-trajectory tuner (one-launch layouts, split form, blocked
     forms) returns one of its candidates, its outputs are that
     configuration's (checked against the oracle), and a second call reads the
@@ -98,9 +99,9 @@ def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypa
     import oracle
     from paper_2604_09993_amd import api, synth
     from parity import PHI32, PHI64, TOL32, TOL64, block_err
-    print(f"single tune cheetah7 N=8 K=8 {dtype}", flush=True)
+    print(f"single tune {name} N=8 K=8 {dtype}", flush=True)
     rng = np.random.default_rng(41)
-    model = synth.make_cheetah7(rng)
+    model = synth.MODEL_MAKERS[name](rng)
     d = synth.gen_nodes(model, 8, rng, T=0.16)
     K = 8
     cm = api.CisModel(model)
@@ -111,6 +112,8 @@ def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypa
     out, choice = api.single_tune(cm, X, U, s, p, K)
     assert not choice["from_cache"] and choice["ms"] > 0
     _check_choice(choice, K, dtype)
+    if model.nb == 1:
+        assert choice["form"] != "split"   # no legs with links: no split candidate
     # FP32: the oracle runs on the same FP32-rounded inputs
     r = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if dtype == torch.float32 \
         else (lambda a: a)
