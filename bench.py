@@ -483,23 +483,28 @@ def main():
         routs = [vpr(rout[k]) for k in ("A", "Bm", "Bp", "S", "d", "xprop")]
         st_r = ctypes.c_void_p(stream.cuda_stream)
 
-        def launch_rkf():
-            _lib.check(lib.cis_discretize_rkf(rcm.handle, ctypes.byref(rsh), *rargs, 1, *routs,
-                                              vpr(rout["err"]), vpr(rws), rws.numel(), st_r))
+        def launch_rkf(waves=1):
+            _lib.check(lib.cis_discretize_rkf(rcm.handle, ctypes.byref(rsh), *rargs, waves,
+                                              *routs, vpr(rout["err"]), vpr(rws), rws.numel(),
+                                              st_r))
 
         def launch_rk4_split():   # the register budget the batch tuner picks for quad13
             _lib.check(lib.cis_discretize_split(rcm.handle, ctypes.byref(rsh), *rargs, 2, *routs,
                                                 vpr(rws), rws.numel(), st_r))
-        ms_rkf, _ = timed(launch_rkf, args.extra_steps, 2)
+        # both register budgets of the tangent launch; the faster is reported
+        rkf_by_waves = {w: timed(lambda: launch_rkf(w), args.extra_steps, 2)[0] for w in (1, 2)}
+        rkf_w = min(rkf_by_waves, key=rkf_by_waves.get)
+        ms_rkf = rkf_by_waves[rkf_w]
         ms_rk4s, _ = timed(launch_rk4_split, args.extra_steps, 2)
-        launch_rkf()
+        launch_rkf(rkf_w)
         torch.cuda.synchronize()
         rkf_fl = rkf_flops_per_interval(rmodel, rK) * rN
         progress(f"rkf quad13 N={rN} K={rK}: {ms_rkf:.3f} ms (rk4 split {ms_rk4s:.3f} ms)")
         extras["rkf_quad13_N12800_K20_f64"] = {
             "value": rN / (ms_rkf * 1e-3), "unit": "intervals/s", "ms_per_step": ms_rkf,
             "rk4_split_ms_same_intervals": ms_rk4s,
-            "tangent_waves_per_simd": {"rkf": 1, "rk4_split": 2},
+            "tangent_waves_per_simd": {"rkf": rkf_w, "rk4_split": 2},
+            "rkf_ms_by_tangent_waves": {str(w): v for w, v in rkf_by_waves.items()},
             "roofline": {"bound": "alu", "achieved": rkf_fl / (ms_rkf * 1e-3) / 1e12,
                          "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                          "frac": rkf_fl / (ms_rkf * 1e-3) / PEAK_FP64_VALU,
@@ -507,7 +512,7 @@ def main():
                          "traffic": {"records": committed_traffic(
                                          f"k_rkf_rec<double, Topo<{rmodel.legs}, {rmodel.depth}, 6, 1, false>>"),
                                      "tangent": committed_traffic(
-                                         f"k_rkf_tan<double, Topo<{rmodel.legs}, {rmodel.depth}, 6, 1, false>, 1>")}},
+                                         f"k_rkf_tan<double, Topo<{rmodel.legs}, {rmodel.depth}, 6, 1, false>, {rkf_w}>")}},
             "step": "cis_discretize_rkf: Fehlberg 4(5), K=20 steps, records + tangent launches"}
         if not args.no_cpu_baseline:
             rks = [0, 6400, rN - 1]
