@@ -195,7 +195,7 @@ def main():
                     help="iteration cap of the end-to-end SCP run on the monoped")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs every kernel on a single GPU "
+        print("bench.py measures one GPU only: the library runs every kernel on a single GPU "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
