@@ -144,7 +144,8 @@ struct PShared {
 // k_paper_rec: interval k, one wave.
 // ---------------------------------------------------------------------------
 template <class TP>
-__global__ void __launch_bounds__(64) k_paper_rec(PaperArgs a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+    k_paper_rec(PaperArgs a, MConst<TP::NB, TP::NJ, TP::NC> mc) {
     constexpr int NB = TP::NB, NJ = TP::NJ, NC = TP::NC, NQ = TP::NQ, N6 = TP::N6;
     constexpr int NX = TP::NX, NY = TP::NY, M = TP::M, NJ2 = TP::NJ2;
     using R = PRec<TP>;
@@ -642,7 +643,7 @@ __device__ __forceinline__ void paper_tangent_stage(PLane<TP>& z, const double* 
 }
 
 template <class TP>
-__global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu(1)))
+__global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu(2)))
     k_paper_tan(PaperArgs a) {
     constexpr int N6 = TP::N6, NQ = TP::NQ, M = TP::M, D = TP::D, L = TP::L, LB = TP::LB;
     constexpr int NX = TP::NX, NC = TP::NC;
