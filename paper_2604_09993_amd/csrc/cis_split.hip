@@ -330,7 +330,7 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
 
 // Single trajectory: rec holds N interval parts of per_interval(K) elements.
 template <class T, class TP>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_coefrec(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc,
                                                  T* __restrict__ rec) {
     __shared__ RecShared<T, TP> sh;
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu
 // Batches: one launch per model over the work list; rec_off[item] is the
 // element offset of the item's part of the workspace.
 template <class T, class TP>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_coefrec_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc,
                     T* __restrict__ rec, const int64_t* __restrict__ rec_off) {
     __shared__ RecShared<T, TP> sh;
