@@ -485,8 +485,10 @@ __device__ __forceinline__ void rkf_tangent_item(const FwdArgs<T>& a, const T* _
     tangent_store<T, TP>(a, k, leg, lane, tc, z.za, z.ycc, z.yct, xch);
 }
 
+// FP64 at one wave per SIMD: two would spill the stage derivatives to scratch.
 template <class T, class TP>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(128)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 2)))
     k_rkf_rec(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc, T* __restrict__ rec,
               T* __restrict__ err) {
     __shared__ RkfShared<T, TP> sh;

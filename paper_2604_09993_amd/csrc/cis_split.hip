@@ -329,8 +329,10 @@ __device__ __forceinline__ void tangent_item(const FwdArgs<T>& a, const T* __res
 }
 
 // Single trajectory: rec holds N interval parts of per_interval(K) elements.
+// FP32 at four waves per SIMD (128 VGPRs, a few bytes of scratch), FP64 at two.
 template <class T, class TP>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+__global__ void __launch_bounds__(128)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_coefrec(FwdArgs<T> a, MConst<TP::NB, TP::NJ, TP::NC> mc,
                                                  T* __restrict__ rec) {
     __shared__ RecShared<T, TP> sh;
@@ -351,8 +353,10 @@ __global__ void __launch_bounds__(64 * TP::L) __attribute__((amdgpu_waves_per_eu
 
 // Batches: one launch per model over the work list; rec_off[item] is the
 // element offset of the item's part of the workspace.
+// FP32 at four waves per SIMD (128 VGPRs, a few bytes of scratch), FP64 at two.
 template <class T, class TP>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+__global__ void __launch_bounds__(128)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_coefrec_batch(BatchArgs<FwdArgs<T>> b, MConst<TP::NB, TP::NJ, TP::NC> mc,
                     T* __restrict__ rec, const int64_t* __restrict__ rec_off) {
     __shared__ RecShared<T, TP> sh;
