@@ -129,7 +129,21 @@ def test_single_tuner_choice_matches_the_oracle_and_is_cached(tmp_path, monkeypa
     got2 = api.as_interval_major(out2)
     for key in ("A", "S", "d"):
         assert torch.equal(got2[key], got[key]), key
-    assert '"form"' in (tmp_path / "tune.json").read_text()
+    path = tmp_path / "tune.json"
+    assert '"form"' in path.read_text()
+    # an entry naming a configuration that does not exist for this shape is
+    # ignored (the shape is tuned again); a damaged file counts as empty
+    import json
+    cache = json.loads(path.read_text())
+    for entry in cache["entries"].values():
+        entry.update(form=2, blocks=3, compose=0)     # 3 does not divide K = 8
+    path.write_text(json.dumps(cache))
+    _, choice3 = api.single_tune(cm, X, U, s, p, K)
+    assert not choice3["from_cache"]
+    _check_choice(choice3, K, dtype)
+    path.write_text("{not json")
+    _, choice4 = api.single_tune(cm, X, U, s, p, K)
+    assert not choice4["from_cache"] and '"form"' in path.read_text()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
