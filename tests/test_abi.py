@@ -105,6 +105,25 @@ def _gpu_visible():
 
 
 @pytest.mark.skipif("_gpu_visible()", reason="uses fake addresses; run only where no GPU exists")
+def test_debug_mode_keeps_validation_before_launch(monkeypatch):
+    """With CIS_DEBUG_FINITE set, invalid arguments are still refused before
+    any launch and before the non-finite scan (fake addresses, never read)."""
+    monkeypatch.setenv("CIS_DEBUG_FINITE", "1")
+    model = synth.make_hopper(np.random.default_rng(0))
+    st, h = _create(model)
+    assert st == 0
+    good = _lib.Shape(5, 4, _lib.CIS_F64, 0, 6, 5)
+    assert _call_discretize(h, _lib.Shape(5, 4, 0, 0, 5, 5)) == _lib.CIS_ERR_DIM
+    assert _call_discretize(h, good, X=0) == _lib.CIS_ERR_NULL
+    assert _call_discretize(h, good, X=12) == _lib.CIS_ERR_LAYOUT
+    lib = _lib.load()
+    P = lambda v: ctypes.c_void_p(v)
+    assert lib.cis_defects(h, ctypes.byref(good), P(8), P(8), P(8), P(8), None, None, None, 0,
+                           None) == _lib.CIS_ERR_NULL
+    lib.cis_model_destroy(h)
+
+
+@pytest.mark.skipif("_gpu_visible()", reason="uses fake addresses; run only where no GPU exists")
 def test_entry_points_validate_before_launch():
     """Every rejection returns before any HIP call (fake, never-dereferenced addresses)."""
     lib = _lib.load()
